@@ -1,0 +1,300 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (no GPU needed).
+
+Each test checks the oracle against something other than itself: closed forms, invariants of the
+kinetic model stated in the paper, exactness of Gauss-Hermite quadrature, limits with known discrete
+solutions, and the thresholds the paper's Fourier analysis reports.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, field_names
+from oracle import fourier as FA
+from workloads import (BC_WALL, case_cavity, case_fourier_1d, gauss_hermite_grid, mesh_1d, mesh_cavity,
+                       ordinates_hemisphere, ordinates_slab)
+from workloads.cases import Case, Flow, Gas
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden(name):
+    out = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, v = line.split()[:2]
+        out[k] = float(v)
+    return out
+
+
+def He(n, x):
+    """Probabilists' Hermite polynomials (orthogonal under exp(-x^2/2))."""
+    return np.polynomial.hermite_e.hermeval(x, [0] * n + [1])
+
+
+def maxwell(x2, D, T=1.0):
+    return (2 * np.pi * T) ** (-D / 2) * np.exp(-x2 / (2 * T))
+
+
+def _case_1d(n=8, nv=48, no=16, Kn=0.3, k_eff=0.7, sigma_R=0.2, T=(1.0, 1.0), Z=(5.0, 50.0)):
+    c = case_fourier_1d(n=n, nv=nv, no=no, Kn=Kn, tau_opt=k_eff, Z_r=Z[0], Z_v=Z[1], sigma_R=sigma_R,
+                        T_left=T[0], T_right=T[1], T0=1.0)
+    return c
+
+
+def _noneq_state_1d(c, b2=0.05, b3=0.03, h1=0.02, r1=0.04, v1=-0.03, rad=(0.3, 0.2)):
+    """Quadrature-exact non-equilibrium state: u = 0, T_t = T_r = T_v = 1, sigma and q nonzero."""
+    g = c.vgrid
+    x = g.xi[:, 0]
+    M = maxwell(x * x, 1)
+    d_r, d_v = c.gas.d_r, c.gas.d_v
+    G = M * (1 + b2 * He(2, x) + b3 * He(3, x))
+    H = 2 * M * (1 - b2 + h1 * He(1, x))  # keeps 3 rho T_t = sum (x^2 G + H) = 3
+    R = 0.5 * d_r * M * (1 + r1 * He(1, x))
+    V = 0.5 * d_v * M * (1 + v1 * He(1, x))
+    nc = c.mesh.nc
+    f = np.zeros((nc, 4, g.nv))
+    f[:, 0], f[:, 1], f[:, 2], f[:, 3] = G, R, V, H
+    mu = c.ords.omega[:, 0]
+    I = np.tile(c.gas.sigma_R / np.pi * (1 + rad[0] * mu + rad[1]), (nc, 1))
+    return f, I
+
+
+def test_quadrature_exactness():
+    """Gauss-Hermite weights of the workloads integrate Maxwellian moments exactly."""
+    for D, n in ((1, 48), (2, 16)):
+        g = gauss_hermite_grid(n, D)
+        x2 = (g.xi ** 2).sum(axis=1)
+        M = maxwell(x2, D)
+        assert abs((g.w * M).sum() - 1) < 1e-13
+        assert abs((g.w * M * x2).sum() - D) < 1e-12
+        assert abs((g.w * M * x2 * x2).sum() - D * (D + 2)) < 1e-11
+    o = ordinates_slab(16)
+    assert abs(o.w.sum() - 4 * np.pi) < 1e-12
+    h = ordinates_hemisphere(4, 8)
+    assert abs(h.w.sum() - 4 * np.pi) < 1e-12
+    assert abs((h.w * h.omega[:, 0] ** 2).sum() - 4 * np.pi / 3) < 1e-12  # int Omega_x^2 dOmega = 4 pi / 3
+
+
+def test_equilibrium_fixed_point_1d():
+    """Uniform equilibrium between walls at the same temperature: zero residual, no change (P1)."""
+    c = _case_1d(T=(1.0, 1.0))
+    o = Oracle(c)
+    f0, I0 = o.get_state()
+    J = o.collision()
+    assert np.abs(J).max() < 1e-14 * np.abs(f0).max() / 1e-3
+    r = o.kinetic_step(want_residual=True)
+    f1, I1 = o.get_state()
+    scale = np.abs(f0).max()
+    assert np.abs(r).max() < 1e-13 * scale
+    assert np.abs(f1 - f0).max() < 1e-14 * scale
+    assert np.abs(I1 - I0).max() < 1e-15
+    np.testing.assert_allclose(o.rad_source(), 0.0, atol=1e-16)
+
+
+def test_equilibrium_fixed_point_2d():
+    m = mesh_cavity(h=0.1)
+    c = case_cavity(mesh=m, nvx=12, n_theta=2, n_phi=4, u_lid=0.0, T_lid=1.0)
+    o = Oracle(c)
+    f0, _ = o.get_state()
+    r = o.kinetic_step(want_residual=True)
+    assert np.abs(r).max() < 1e-13 * np.abs(f0).max()
+
+
+def _moments_of_J(c, J, JR):
+    g = c.vgrid
+    x = g.xi[:, 0]
+    w = g.w
+    G, R, V, H = J[:, 0], J[:, 1], J[:, 2], J[:, 3]
+    mass = G @ w
+    mom = G @ (w * x)
+    energy = (0.5 * G @ (w * x * x)) + 0.5 * (H @ w) + R @ w + V @ w + JR @ c.ords.w
+    stress = G @ (w * x * x) - (G @ (w * x * x) + H @ w) / 3.0
+    qt = 0.5 * ((G @ (w * x ** 3)) + H @ (w * x))
+    qr = R @ (w * x)
+    qv = V @ (w * x)
+    return mass, mom, energy, stress, qt, qr, qv, R @ w, V @ w
+
+
+def test_collision_invariants_and_relaxation_rates():
+    """Mass, momentum and total energy (gas + radiation) are conserved by the sources; stress relaxes as
+    -sigma/tau and the heat fluxes as -(1/tau) A q with A the Mason matrix (Sec. 2.1, P2)."""
+    c = _case_1d()
+    o = Oracle(c)
+    f, I = _noneq_state_1d(c)
+    o.set_state(f, I)
+    F = o.fields()
+    names = field_names(1)
+    fl = dict(zip(names, F[0]))
+    # the constructed state has unit temperatures, zero velocity, nonzero stress and heat fluxes
+    assert abs(fl["ux"]) < 1e-15 and abs(fl["Tt"] - 1) < 1e-14 and abs(fl["Tr"] - 1) < 1e-14
+    assert abs(fl["sigxx"]) > 1e-2 and abs(fl["qtx"]) > 1e-2
+    J = o.collision()
+    JR = o.rad_source()
+    mass, mom, energy, stress, qt, qr, qv, er, ev = _moments_of_J(c, J, JR)
+    gas = c.gas
+    tau = np.sqrt(2 / np.pi) * c.flow.Kn_gas  # rho = T_t = 1
+    assert np.abs(mass).max() < 1e-13
+    assert np.abs(mom).max() < 1e-13
+    assert np.abs(energy).max() < 1e-13
+    np.testing.assert_allclose(stress, -fl["sigxx"] / tau, rtol=1e-12)
+    A = FA.mason_A(gas.d_r, gas.d_v, gas.Z_r, gas.Z_v, gas.Sc)
+    q = np.array([fl["qtx"], fl["qrx"], fl["qvx"]])
+    np.testing.assert_allclose(np.stack([qt[0], qr[0], qv[0]]), -(A @ q) / tau, rtol=1e-11)
+    # internal-energy exchange: T_r = T_t so no rotational exchange; vibrational exchange with photons only
+    e_R = fl["TR"] ** 4 * 4 * gas.sigma_R
+    e_vR = 4 * gas.sigma_R  # T_v = 1
+    np.testing.assert_allclose(er, 0.0, atol=1e-13)
+    np.testing.assert_allclose(ev, -c.flow.k_eff * (e_vR - e_R), rtol=1e-12)
+
+
+def test_mode_exchange_rates():
+    """int J_1 = (e_tr - e_r)/(Z_r tau) and int J_2 = (e_tv - e_v)/(Z_v tau) - k_eff (e_vR - e_R) with
+    T_r, T_v != T_t (Eq. macroscopic_equation sources); the quadrature is near-exact for these temperatures."""
+    c = _case_1d(nv=64)
+    o = Oracle(c)
+    g = c.vgrid
+    x = g.xi[:, 0]
+    M = maxwell(x * x, 1)
+    Tr, Tv = 1.08, 0.93
+    d_r, d_v = c.gas.d_r, c.gas.d_v
+    f = np.zeros((c.mesh.nc, 4, g.nv))
+    f[:, 0] = M
+    f[:, 3] = 2 * M
+    f[:, 1] = 0.5 * d_r * Tr * M
+    f[:, 2] = 0.5 * d_v * Tv * M
+    I = np.full((c.mesh.nc, c.ords.no), 1.3 * c.gas.sigma_R / np.pi)
+    o.set_state(f, I)
+    J = o.collision()
+    JR = o.rad_source()
+    *_, er, ev = _moments_of_J(c, J, JR)
+    tau = np.sqrt(2 / np.pi) * c.flow.Kn_gas
+    Ttr = (3 + d_r * Tr) / (3 + d_r)
+    Ttv = (3 + d_v * Tv) / (3 + d_v)
+    e_R = 1.3 * c.gas.sigma_R / np.pi * 4 * np.pi
+    np.testing.assert_allclose(er, 0.5 * d_r * (Ttr - Tr) / (c.gas.Z_r * tau), rtol=1e-10)
+    np.testing.assert_allclose(ev, 0.5 * d_v * (Ttv - Tv) / (c.gas.Z_v * tau)
+                               - c.flow.k_eff * (4 * c.gas.sigma_R * Tv ** 4 - e_R), rtol=1e-10)
+
+
+def test_transport_conserves_mass_closed_domain():
+    """Face fluxes telescope and diffuse walls are impermeable: the mass moment of the kinetic residual
+    sums to the (zero) mass moment of the collision term."""
+    m = mesh_cavity(h=0.1)
+    c = case_cavity(mesh=m, nvx=12, n_theta=2, n_phi=4)
+    o = Oracle(c)
+    for _ in range(3):
+        o.iterate(gsis=False)
+    f, I = o.get_state()
+    J = o.collision()
+    r = o.kinetic_step(want_residual=True)
+    w, V = c.vgrid.w, m.vol
+    total_r = (V[:, None] * (r[:, 0, :] * w)).sum()
+    total_J = (V[:, None] * (J[:, 0, :] * w)).sum()
+    assert abs(total_r - total_J) < 1e-12 * np.abs(f).max()
+
+
+def _free_molecular_closed_form(c):
+    g = c.vgrid
+    x = g.xi[:, 0]
+    T1, T2 = c.bcs[0]["T"], c.bcs[1]["T"]
+    M1, M2 = maxwell(x * x, 1, T1), maxwell(x * x, 1, T2)
+    pos, neg = x > 0, x < 0
+    ratio = (g.w[pos] * x[pos] * M1[pos]).sum() / (g.w[neg] * -x[neg] * M2[neg]).sum()  # rho2 / rho1
+    return M1, M2, pos, neg, ratio, T1, T2
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_collisionless_slab(order):
+    """Free-molecular gas between diffuse walls at T = 1 and 2 (P4): each velocity carries its emitting
+    wall's Maxwellian, with wall densities fixed by zero net mass flux, in every cell."""
+    c = _case_1d(n=12, nv=24, Kn=1e14, k_eff=0.0, sigma_R=1e-3, T=(1.0, 2.0))
+    o = Oracle(c, second_order=order, max_inner=5)
+    n, hist = o.solve(gsis=False, tol=1e-13, max_outer=3000)
+    assert 0 < n < 3000
+    f, _ = o.get_state()
+    M1, M2, pos, neg, ratio, T1, T2 = _free_molecular_closed_form(c)
+    G = f[:, 0, :]
+    rho1 = G[0, pos][0] / M1[pos][0]
+    np.testing.assert_allclose(G[:, pos], rho1 * np.tile(M1[pos], (c.mesh.nc, 1)), rtol=1e-9)
+    np.testing.assert_allclose(G[:, neg], ratio * rho1 * np.tile(M2[neg], (c.mesh.nc, 1)), rtol=1e-9)
+    # internal distributions re-emitted at the wall temperature
+    np.testing.assert_allclose(f[:, 1, pos], 0.5 * c.gas.d_r * T1 * G[:, pos], rtol=1e-9)
+    np.testing.assert_allclose(f[:, 3, neg], 2 * T2 * G[:, neg], rtol=1e-9)
+
+
+def test_optically_thin_slab():
+    """No absorption (k_eff = 0): every ordinate carries its black wall's B(T_w) (P5)."""
+    c = _case_1d(n=10, nv=16, Kn=1.0, k_eff=0.0, sigma_R=0.3, T=(1.0, 2.0))
+    o = Oracle(c)
+    for _ in range(120):
+        o.iterate(gsis=False)
+    _, I = o.get_state()
+    mu = c.ords.omega[:, 0]
+    s = c.gas.sigma_R
+    expect = np.where(mu > 0, s * 1.0 / np.pi, s * 16.0 / np.pi)
+    np.testing.assert_allclose(I, np.tile(expect, (c.mesh.nc, 1)), rtol=1e-13)
+    F = o.fields()
+    names = field_names(1)
+    e_R = (c.ords.w * expect).sum()
+    q_R = (c.ords.w * mu * expect).sum()
+    np.testing.assert_allclose(4 * s * F[:, names.index("TR")] ** 4, e_R, rtol=1e-13)
+    np.testing.assert_allclose(F[:, names.index("qRx")], q_R, rtol=1e-12)
+    assert q_R < 0  # radiation flows from the hot wall at x = 1 towards x = 0
+
+
+def test_sync_restores_macro_state():
+    """After the synchronisation step the moments of f equal the macro state (Sec. 3, P11) up to the
+    quadrature error of Maxwellians at the new temperatures on the fixed grid."""
+    c = _case_1d(n=6, nv=64)
+    o = Oracle(c)
+    o.iterate(gsis=False)
+    W = o.macro_state()
+    D = 1
+    rho = W[:, 0] * 1.02
+    u = W[:, 1] / W[:, 0] + 0.01
+    W2 = W.copy()
+    W2[:, 0] = rho
+    W2[:, 1] = rho * u
+    W2[:, 3] *= 1.05  # e_r
+    W2[:, 4] *= 0.97  # e_v
+    W2[:, 5] *= 1.1  # e_R
+    W2[:, 2] = W[:, 2] * 1.03 + (W2[:, 3] - W[:, 3]) + (W2[:, 4] - W[:, 4]) + (W2[:, 5] - W[:, 5])
+    o.sync(W2)
+    W3 = o.macro_state()
+    np.testing.assert_allclose(W3, W2, rtol=1e-10, atol=1e-13)
+
+
+def test_fourier_cis_thresholds():
+    """CIS Fourier analysis (Sec. 4.2): e_max -> 1 as Kn theta -> 0 (case A), divergence for the
+    coupling product 0.05 (cases B and C), and a divergence threshold near 0.03."""
+    p = golden("paper_fourier.txt")
+    gas = dict(d_r=p["gas_d_r"], d_v=p["gas_d_v"], Z_r=p["gas_Z_r"], Z_v=p["gas_Z_v"])
+    e_small = FA.cis_emax(1e-3, 0.01, 0.01, **gas)
+    e_mid = FA.cis_emax(1.0, 0.01, 0.01, **gas)
+    assert 0.999 < e_small < 1.0 and e_mid < 0.9
+    eB = FA.cis_emax(1e-2, p["caseB_ratio"], p["caseB_sigma_R"], **gas)
+    eC = FA.cis_emax(1e-2, p["caseC_ratio"], p["caseC_sigma_R"], **gas)
+    assert eB > 1.05 and eC > 1.05
+    # at large Kn theta the rarefied iteration converges in every case
+    assert FA.cis_emax(10.0, p["caseB_ratio"], p["caseB_sigma_R"], **gas) < 0.5
+    # threshold of the coupling product (Kn_gas/Kn_photon) sigma_R, bisection at ratio 0.1
+    lo, hi = 0.005, 0.1
+    for _ in range(20):
+        mid = 0.5 * (lo + hi)
+        if FA.cis_emax(1e-2, 0.1, mid / 0.1, **gas) > 1.0 + 1e-9:
+            hi = mid
+        else:
+            lo = mid
+    assert 0.5 * p["cis_divergence_product"] < hi < 2.0 * p["cis_divergence_product"]
+
+
+def test_fourier_cis_conserved_modes():
+    """At theta -> 0 the iteration matrix keeps the conserved perturbations (mass, momentum, total
+    energy): five eigenvalues approach 1."""
+    C = FA.cis_matrix(1e-6, 1.0, 1.0, 0.01)
+    ev = np.sort(np.abs(np.linalg.eigvals(C)))[::-1]
+    assert np.all(ev[:5] > 1 - 1e-5)

@@ -1,0 +1,30 @@
+"""Seeded synthetic inputs shared by the HIP path and the oracle.
+
+This package only builds inputs: meshes (geometry and boundary tags),
+velocity and ordinate quadratures, and case parameter sets.  It holds none
+of the kinetic or macroscopic arithmetic of the method; both the product
+path and the oracle receive what it builds as plain arrays.
+"""
+
+from .mesh import Mesh, mesh_1d, mesh_cavity, mesh_annulus, mesh_periodic_1d, mesh_capsule  # noqa: F401
+from .quadrature import (  # noqa: F401
+    VelocityGrid,
+    Ordinates,
+    gauss_hermite_grid,
+    newton_cotes_grid,
+    ordinates_slab,
+    ordinates_hemisphere,
+    ordinates_sphere,
+)
+from .cases import (  # noqa: F401
+    Gas,
+    Flow,
+    Case,
+    BC_WALL,
+    BC_FARFIELD,
+    case_fourier_1d,
+    case_cavity,
+    case_cylinder,
+    case_capsule,
+    warmstart_case_params,
+)

@@ -1,0 +1,141 @@
+"""Case definitions: gas and flow parameters, boundary tags and initial fields.
+
+Each builder returns a :class:`Case` holding only inputs.  Parameter values
+follow the paper's test section where it gives them (gas constants,
+collision numbers, viscosity index) and the synthetic workload recipes
+otherwise; every random draw is seeded.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .mesh import Mesh, mesh_1d, mesh_cavity, mesh_annulus, mesh_capsule
+from .quadrature import (
+    VelocityGrid,
+    Ordinates,
+    gauss_hermite_grid,
+    newton_cotes_grid,
+    ordinates_slab,
+    ordinates_hemisphere,
+    ordinates_sphere,
+)
+
+BC_WALL = 0  # diffuse, fully accommodating wall; black for radiation
+BC_FARFIELD = 1  # prescribed equilibrium state on incoming characteristics
+
+
+@dataclass
+class Gas:
+    d_r: float = 2.0
+    d_v: float = 1.16
+    Z_r: float = 2.67
+    Z_v: float = 26.7
+    omega: float = 0.74
+    Sc: float = 0.8
+    sigma_R: float = 0.01
+
+    @property
+    def gamma(self) -> float:
+        return (5 + self.d_r + self.d_v) / (3 + self.d_r + self.d_v)
+
+
+@dataclass
+class Flow:
+    Kn_gas: float = 0.1
+    k_eff: float = 1.0  # = 1 / Kn_photon (optical thickness per reference length); 0 = no absorption
+    rho_inf: float = 1.0
+    T_inf: float = 1.0
+    u_inf: tuple = (0.0, 0.0, 0.0)
+
+
+@dataclass
+class Case:
+    name: str
+    mesh: Mesh
+    vgrid: VelocityGrid
+    ords: Ordinates
+    gas: Gas
+    flow: Flow
+    bcs: list  # list of dict(kind, rho, T, u=(ux, uy, uz))
+    init_rho: np.ndarray
+    init_u: np.ndarray  # [nc, dim]
+    init_T: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    def bc_arrays(self):
+        kind = np.array([b["kind"] for b in self.bcs], dtype=np.int32)
+        rho = np.array([b.get("rho", 1.0) for b in self.bcs], dtype=np.float64)
+        T = np.array([b["T"] for b in self.bcs], dtype=np.float64)
+        u = np.array([list(b.get("u", (0.0, 0.0, 0.0))) for b in self.bcs], dtype=np.float64)
+        return kind, rho, T, u
+
+
+def _uniform_init(mesh: Mesh, rho: float, u, T: float):
+    nc, dim = mesh.nc, mesh.dim
+    return (np.full(nc, rho), np.tile(np.asarray(u[:dim], dtype=np.float64), (nc, 1)), np.full(nc, T))
+
+
+def case_fourier_1d(n: int = 64, nv: int = 48, no: int = 16, Kn: float = 0.1, tau_opt: float = 1.0,
+                    Z_r: float = 5.0, Z_v: float = 50.0, sigma_R: float = 0.01, T_left: float = 1.0,
+                    T_right: float = 2.0, T0: float = 1.5) -> Case:
+    """Planar radiative Fourier flow between diffuse black walls at rest."""
+    mesh = mesh_1d(n, 0.0, 1.0, 0, 1)
+    gas = Gas(Z_r=Z_r, Z_v=Z_v, sigma_R=sigma_R)
+    flow = Flow(Kn_gas=Kn, k_eff=tau_opt, rho_inf=1.0, T_inf=T0)
+    bcs = [dict(kind=BC_WALL, T=T_left), dict(kind=BC_WALL, T=T_right)]
+    r, u, T = _uniform_init(mesh, 1.0, (0.0, 0.0, 0.0), T0)
+    return Case(f"fourier1d_n{n}_Kn{Kn}_tau{tau_opt}", mesh, gauss_hermite_grid(nv, 1), ordinates_slab(no),
+                gas, flow, bcs, r, u, T)
+
+
+def case_cavity(Kn: float = 0.1, tau_opt: float = 1.0, h: float = 0.0095, nvx: int = 32, n_theta: int = 4,
+                n_phi: int = 8, sigma_R: float = 0.005, u_lid: float = 0.18, T_lid: float = 3.0,
+                seed: int = 0, mesh: Mesh | None = None) -> Case:
+    """Lid-driven, heated cavity with a concentric square obstacle, unstructured triangles."""
+    mesh = mesh if mesh is not None else mesh_cavity(h=h, seed=seed)
+    gas = Gas(sigma_R=sigma_R)
+    flow = Flow(Kn_gas=Kn, k_eff=tau_opt, rho_inf=1.0, T_inf=1.0)
+    bcs = [dict(kind=BC_WALL, T=1.0), dict(kind=BC_WALL, T=T_lid, u=(u_lid, 0.0, 0.0))]
+    r, u, T = _uniform_init(mesh, 1.0, (0.0, 0.0, 0.0), 1.0)
+    return Case(f"cavity_nc{mesh.nc}_Kn{Kn}_tau{tau_opt}", mesh, gauss_hermite_grid(nvx, 2),
+                ordinates_hemisphere(n_theta, n_phi), gas, flow, bcs, r, u, T)
+
+
+def case_cylinder(Kn: float = 0.01, tau_opt: float = 1.0, Ma: float = 5.0, nvx: int = 64, xmax: float = 12.0,
+                  n_theta: int = 4, n_phi: int = 16, sigma_R: float = 0.1, T_w: float = 2.0,
+                  n_theta_mesh: int = 256, n_r_mesh: int = 80, seed: int = 1, mesh: Mesh | None = None) -> Case:
+    """Hypersonic flow past a cylinder of radius 1 in an annulus of outer radius 6."""
+    mesh = mesh if mesh is not None else mesh_annulus(n_theta=n_theta_mesh, n_r=n_r_mesh, seed=seed)
+    gas = Gas(sigma_R=sigma_R)
+    u_inf = Ma * np.sqrt(gas.gamma * 1.0)
+    flow = Flow(Kn_gas=Kn, k_eff=tau_opt, rho_inf=1.0, T_inf=1.0, u_inf=(u_inf, 0.0, 0.0))
+    bcs = [dict(kind=BC_WALL, T=T_w), dict(kind=BC_FARFIELD, rho=1.0, T=1.0, u=(u_inf, 0.0, 0.0))]
+    r, u, T = _uniform_init(mesh, 1.0, (u_inf, 0.0, 0.0), 1.0)
+    return Case(f"cylinder_nc{mesh.nc}_Ma{Ma}_Kn{Kn}_tau{tau_opt}", mesh, newton_cotes_grid(nvx, 2, xmax),
+                ordinates_hemisphere(n_theta, n_phi), gas, flow, bcs, r, u, T, meta=dict(Ma=Ma))
+
+
+def case_capsule(Kn: float = 0.01, tau_opt: float = 1.0, Ma: float = 10.0, nvx: int = 24, xmax: float = 20.0,
+                 n_theta: int = 8, n_phi: int = 12, sigma_R: float = 0.045, T_w: float = 2.0,
+                 mesh_kw: dict | None = None) -> Case:
+    """Hypersonic flow past a blunt capsule (spherical cap + 33 degree cone), tetrahedra, full 3D velocities."""
+    mesh = mesh_capsule(**(mesh_kw or {}))
+    gas = Gas(sigma_R=sigma_R)
+    u_inf = Ma * np.sqrt(gas.gamma * 1.0)
+    flow = Flow(Kn_gas=Kn, k_eff=tau_opt, rho_inf=1.0, T_inf=1.0, u_inf=(u_inf, 0.0, 0.0))
+    bcs = [dict(kind=BC_WALL, T=T_w), dict(kind=BC_FARFIELD, rho=1.0, T=1.0, u=(u_inf, 0.0, 0.0))]
+    r, u, T = _uniform_init(mesh, 1.0, (u_inf, 0.0, 0.0), 1.0)
+    return Case(f"capsule_nc{mesh.nc}_Ma{Ma}_Kn{Kn}", mesh, newton_cotes_grid(nvx, 3, xmax),
+                ordinates_sphere(n_theta, n_phi), gas, flow, bcs, r, u, T, meta=dict(Ma=Ma))
+
+
+def warmstart_case_params(n: int = 256, seed: int = 2):
+    """Seeded (Ma, Kn, optical thickness) draws for the warm-start data set."""
+    rng = np.random.default_rng(seed)
+    Ma = rng.uniform(3.0, 10.0, n)
+    Kn = 10 ** rng.uniform(-3.0, 0.0, n)
+    tau = 10 ** rng.uniform(-2.0, 2.0, n)
+    return np.stack([Ma, Kn, tau], axis=1)

@@ -52,7 +52,7 @@ typedef struct {
 } mom_t;
 
 typedef struct {
-    double Ttr, Ttv, T, tau, q0[3], q1[3], q2[3], evR, B, cs, dt, dtR;
+    double Ttr, Ttv, T, tau, q0[3], q1[3], q2[3], evR, B, cs, dt, dtR, radd;
 } der_t;
 
 typedef struct {
@@ -350,6 +350,11 @@ static void derived(const orc_t *o, const mom_t *m, int64_t c, der_t *d)
     }
     double Tv2 = m->Tv * m->Tv;
     d->evR = 4 * o->sigR * Tv2 * Tv2;
+    /* reading: the emission part of the gas-photon exchange on f2 is treated point-implicitly in the
+     * relaxation: its linearised rate d(k_eff e_vR)/d e_v = 4 k_eff e_vR / e_v joins the diagonal of f2.
+     * This changes the iteration path only (the residual is unchanged) and keeps T_v positive where the
+     * emission rate per unit vibrational energy is large (low density). */
+    d->radd = 4 * o->keff * d->evR / m->ev;
     d->B = o->sigR * Tv2 * Tv2 / PI;
     d->cs = sqrt(5.0 / 3.0 * m->Tt);
     double un = 0;
@@ -615,7 +620,7 @@ static void kinetic_step(orc_t *o, double *fout, double *Iout, double *racc /* o
                 double r = J[sl] - flux[sl] / V;
                 if (racc) racc[(c * ND + sl) * nv + k] = r;
                 rr[(c * ND + sl) * nv + k] = r;
-                fout[(c * ND + sl) * nv + k] = r / dcoef;
+                fout[(c * ND + sl) * nv + k] = r / (dcoef + (sl == DV ? d[c].radd : 0.0));
             }
         }
         for (int64_t q = 0; q < no; ++q) {
@@ -677,7 +682,8 @@ static void kinetic_step(orc_t *o, double *fout, double *Iout, double *racc /* o
                     for (int sl = 0; sl < ND; ++sl) acc[sl] += xn * o->fa[f] * fout[(j * ND + sl) * nv + k];
                 }
                 for (int sl = 0; sl < ND; ++sl)
-                    tmp[(c * ND + sl) * nv + k] = (rr[(c * ND + sl) * nv + k] - acc[sl] / V) / dco[c * nv + k];
+                    tmp[(c * ND + sl) * nv + k] = (rr[(c * ND + sl) * nv + k] - acc[sl] / V) /
+                                                  (dco[c * nv + k] + (sl == DV ? d[c].radd : 0.0));
             }
             for (int64_t q = 0; q < no; ++q) {
                 double acc = 0;
@@ -1190,6 +1196,48 @@ static void boundary_corr(const orc_t *o, const double *W0, double *bcorr)
     }
 }
 
+/* Point solve of the implicit operator in the unknowns U = (rho, rho u, e_gas, e_r, e_v, e_R): diagonal
+ * except for the gas-photon exchange k_eff (e_vR(T_v) - e_R), which couples e_gas, e_v and e_R and is
+ * solved exactly per cell (reading: the printed diagonal Jacobian leaves this coupling lagged, which lets
+ * e_gas and e_v respond inconsistently to strong emission).  With e' = d e_vR / d e_v:
+ *   D_g dg = r_g - k e' dv + k dR,   D_v dv = r_v + k dR,   D_R dR = r_R + k e' dv. */
+static void local_solve(const orc_t *o, const prim_t *p, const double *rhs, const double *Dg, double *dU)
+{
+    int D = o->D, NW = NWof(D);
+    for (int i = 0; i < NW; ++i) dU[i] = rhs[i] / Dg[i];
+    const int ig = D + 1, iv = D + 3, iR = D + 4;
+    const double k = o->keff;
+    const double ep = 32.0 * o->sigR * p->Tv * p->Tv * p->Tv / (o->dv * p->rho);
+    const double dv = (rhs[iv] + k * rhs[iR] / Dg[iR]) / (Dg[iv] - k * k * ep / Dg[iR]);
+    const double dR = (rhs[iR] + k * ep * dv) / Dg[iR];
+    dU[iv] = dv;
+    dU[iR] = dR;
+    dU[ig] = (rhs[ig] - k * ep * dv + k * dR) / Dg[ig];
+}
+
+/* W += alpha dU (the increment of e is dU_egas + dU_eR), alpha = 2^-m the largest factor (m <= 20) keeping
+ * rho, T_t, e_r, e_v and e_R at least half their current values (reading: a positivity safeguard of the
+ * pseudo-time update; it never acts once the solve is near its steady state). */
+static void positive_update(const orc_t *o, double *W, const double *dU)
+{
+    int D = o->D, NW = NWof(D);
+    prim_t p0;
+    prim_of(o, W, &p0);
+    double a = 1.0;
+    for (int m = 0; m <= 20; ++m, a *= 0.5) {
+        double Wn[8];
+        for (int i = 0; i < NW; ++i) Wn[i] = W[i] + a * dU[i];
+        Wn[D + 1] += a * dU[D + 4];
+        prim_t p1;
+        prim_of(o, Wn, &p1);
+        if (Wn[0] >= 0.5 * W[0] && p1.Tt >= 0.5 * p0.Tt && Wn[D + 2] >= 0.5 * W[D + 2] &&
+            Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4]) {
+            for (int i = 0; i < NW; ++i) W[i] = Wn[i];
+            return;
+        }
+    }
+}
+
 /* Solve the synthetic equations (Eq. macroscopic_equation; FV and implicit incremental forms of Sec. 6)
  * with the HoTs fixed, starting from W (in/out [nc*NW]) = W(M^{k+1/2}); m = M^{k+1/2}. */
 static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
@@ -1265,7 +1313,7 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
          * residual is R_e - R_eR, and on e_R separately; the increment of e is their sum. */
         for (int64_t c = 0; c < nc; ++c) {
             R[c * NW + D + 1] -= R[c * NW + D + 4];
-            for (int i = 0; i < NW; ++i) dW[c * NW + i] = R[c * NW + i] / Dg[c * NW + i];
+            local_solve(o, &P[c], R + c * NW, Dg + c * NW, dW + c * NW);
         }
         for (int sw = 0; sw < o->n_sweeps; ++sw) {
 #pragma omp parallel for schedule(static)
@@ -1293,17 +1341,15 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
                     for (int i = 0; i < NW - 1; ++i) acc[i] += (F1[i] - F0[i] - G * dW[j * NW + i]) * o->fa[f];
                     acc[NW - 1] += (-GR * dW[j * NW + NW - 1]) * o->fa[f];
                 }
-                for (int i = 0; i < NW; ++i)
-                    dW2[c * NW + i] = (R[c * NW + i] - acc[i] / (2 * o->vol[c])) / Dg[c * NW + i];
+                double rhs[8];
+                for (int i = 0; i < NW; ++i) rhs[i] = R[c * NW + i] - acc[i] / (2 * o->vol[c]);
+                local_solve(o, &P[c], rhs, Dg + c * NW, dW2 + c * NW);
             }
             double *t = dW;
             dW = dW2;
             dW2 = t;
         }
-        for (int64_t c = 0; c < nc; ++c) {
-            for (int i = 0; i < NW; ++i) W[c * NW + i] += dW[c * NW + i];
-            W[c * NW + D + 1] += dW[c * NW + D + 4];
-        }
+        for (int64_t c = 0; c < nc; ++c) positive_update(o, W + c * NW, dW + c * NW);
     }
     /* reading: in a domain closed by walls the total mass is not fixed by the steady synthetic equations,
      * and neither the point-implicit macro update nor the point relaxation of the kinetic step conserves

@@ -1,0 +1,83 @@
+// Internal declarations of the GSIS / DVM library: device tables, kernel launchers.
+// The C ABI lives in capi.hip; kernels in kinetic.hip (O(N_cells x N_velocities) work) and
+// macro.hip (per-cell synthetic-equation solver).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace gsis {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kWave = 64;
+constexpr int kNHot = 21;  // HoT_sigma (3x3), HoT_qt, HoT_qr, HoT_qv, HoT_qR (3 each)
+
+// Moment vector per cell (FP64), index helpers for dimension D:
+//   rho, u[D], Tt, Tr, Tv, eR, er, ev, sig[D*D] (full), qt[D], qr[D], qv[D], qR[D]
+struct MomLayout {
+    int D;
+    __host__ __device__ constexpr int rho() const { return 0; }
+    __host__ __device__ constexpr int u() const { return 1; }
+    __host__ __device__ constexpr int Tt() const { return 1 + D; }
+    __host__ __device__ constexpr int Tr() const { return 2 + D; }
+    __host__ __device__ constexpr int Tv() const { return 3 + D; }
+    __host__ __device__ constexpr int eR() const { return 4 + D; }
+    __host__ __device__ constexpr int er() const { return 5 + D; }
+    __host__ __device__ constexpr int ev() const { return 6 + D; }
+    __host__ __device__ constexpr int sig() const { return 7 + D; }
+    __host__ __device__ constexpr int qt() const { return 7 + D + D * D; }
+    __host__ __device__ constexpr int qr() const { return 7 + 2 * D + D * D; }
+    __host__ __device__ constexpr int qv() const { return 7 + 3 * D + D * D; }
+    __host__ __device__ constexpr int qR() const { return 7 + 4 * D + D * D; }
+    __host__ __device__ constexpr int size() const { return 7 + 5 * D + D * D; }
+};
+constexpr int kMomMax = 7 + 5 * 3 + 9;
+
+// Physical constants of one run (host struct passed by value to kernels).
+struct Phys {
+    double d_r, d_v, Z_r, Z_v, omega, Sc, sigma_R, Kn, keff;
+    double A[3][3], Q[3][3], K0[3][3];
+};
+
+// Options used by kernels.
+struct KinOpts {
+    double cfl_meso, cfl_v, kin_omega, limK;
+    int kin_sweeps, second_order;
+};
+
+// Boundary tag data on the device.
+struct BcDev {
+    int kind;
+    double rho, T, u[3];
+};
+
+// Mesh tables on the device (all FP64 geometry; int32 connectivity).
+//   per cell-slot (nc * NFM slots): nbr (>= 0 neighbour cell, -(1+bf) boundary face, INT32_MIN unused),
+//   geo[(slot)*4D]: nSV[D] = n_out S / V, dxc[D] = x_f - x_c, dxj[D] = x_f - x_j, lsq[D];
+//   mgeo[(slot)*(2D+2)]: n_out[D], S, dvec[D] (x_j - x_c, or x_f - x_c on a boundary), face id (as double);
+//   per cell: vol, h, eps2 (limiter), nfc (faces), fsign per slot (+1 / -1)
+struct MeshDev {
+    int D = 0, NFM = 0;
+    int64_t nc = 0, nf = 0, nbf = 0;
+    int *nbr = nullptr;
+    double *geo = nullptr;
+    double *mgeo = nullptr;
+    double *vol = nullptr, *h = nullptr, *eps2 = nullptr;
+    int *nfc = nullptr;
+    // boundary faces
+    int *bf_face = nullptr, *bf_cell = nullptr, *bf_tag = nullptr;
+    double *bf_n = nullptr, *bf_dxc = nullptr;  // outward unit normal, x_f - x_c
+    int *bcells = nullptr;                       // distinct cells next to boundary faces
+    int64_t nbcells = 0;
+    // interior faces (for face HoTs / reference dissipation)
+    int *f_L = nullptr, *f_R = nullptr;  // R < 0 on boundary faces
+    double *f_n = nullptr;               // unit normal L -> R, D per face
+    double *f_d = nullptr;               // x_R - x_L, D per face (interior faces)
+    BcDev *bcs = nullptr;
+    int nbc = 0;
+    int closed = 1;
+};
+
+}  // namespace gsis

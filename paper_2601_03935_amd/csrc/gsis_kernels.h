@@ -1,0 +1,136 @@
+// Buffers and launcher declarations shared by the kernel files and the C ABI.
+#pragma once
+
+#include "gsis_dev.h"
+
+#include <vector>
+
+namespace gsis {
+
+// Device buffers of the kinetic state for storage type T (float or double).
+template <typename T>
+struct KinBufs {
+    T *f = nullptr, *f2 = nullptr, *gf = nullptr, *r = nullptr, *dl0 = nullptr, *dl1 = nullptr;
+    T *I = nullptr, *I2 = nullptr, *gI = nullptr, *rI = nullptr, *dI0 = nullptr, *dI1 = nullptr;
+    T *coef = nullptr, *xi = nullptr, *om = nullptr, *rhow = nullptr;
+    double *xi_d = nullptr, *w_d = nullptr, *om_d = nullptr, *wo_d = nullptr;  // om: D components per ordinate
+    double *bflux = nullptr, *bsurf = nullptr;
+};
+
+// Device buffers of the synthetic-equation solver (FP64).
+struct MacroBufs {
+    double *W = nullptr, *W0 = nullptr, *P = nullptr, *fld = nullptr, *gfld = nullptr;
+    double *R = nullptr, *Dg = nullptr, *dU0 = nullptr, *dU1 = nullptr;
+    double *hotf = nullptr, *bcorr = nullptr, *dref = nullptr;
+    double *resc = nullptr, *scal = nullptr;  // per-cell scratch, device scalars (res0, mass, ...)
+    int *flags = nullptr;                     // [0] done, [1] inner count
+};
+
+// Optional per-kernel timing with HIP events on the launch stream.  Kinds (see gsis.h GSIS_K_*):
+// 0 gradients of f, 1 residual, 2 Jacobi sweeps, 3 radiation kernels, 4 moments, 5 wall densities and
+// boundary fluxes, 6 synchronisation, 7 macro solve.
+struct Prof {
+    static constexpr int kKinds = 8;
+    bool on = false;
+    hipStream_t st = nullptr;
+    struct Rec {
+        int kind;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pend;
+    std::vector<hipEvent_t> pool;
+    double ms[kKinds] = {0}, bytes[kKinds] = {0};
+    int64_t n[kKinds] = {0};
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    // returns an index to pass to end(); -1 when profiling is off
+    int begin(int kind, double by)
+    {
+        if (!on) return -1;
+        Rec r{kind, by, get(), get()};
+        (void)hipEventRecord(r.a, st);
+        pend.push_back(r);
+        return (int)pend.size() - 1;
+    }
+    void end(int i)
+    {
+        if (i >= 0) (void)hipEventRecord(pend[i].b, st);
+    }
+    void collect()
+    {
+        if (pend.empty()) return;
+        (void)hipStreamSynchronize(st);
+        for (auto &r : pend) {
+            float t = 0;
+            (void)hipEventElapsedTime(&t, r.a, r.b);
+            ms[r.kind] += t;
+            bytes[r.kind] += r.bytes;
+            n[r.kind] += 1;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pend.clear();
+    }
+    void reset()
+    {
+        collect();
+        for (int i = 0; i < kKinds; ++i) ms[i] = bytes[i] = 0, n[i] = 0;
+    }
+    void destroy()
+    {
+        collect();
+        for (auto e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
+struct MacroOpts {
+    double cfl_macro, inner_tol;
+    int max_inner, n_sweeps;
+};
+
+template <typename T, int D, int NFM>
+void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpts &o, int64_t nv, int64_t no,
+                    hipStream_t st, Prof *pf);
+template <typename T, int D, int NFM>
+void launch_boundary_state(KinBufs<T> &B, const MeshDev &m, const Phys &p, int so, int64_t nv, int64_t no,
+                           hipStream_t st);
+template <typename T, int D>
+void launch_moments(const KinBufs<T> &B, const double *uref, double *mom, int64_t nc, int64_t nv, int64_t no,
+                    const Phys &p, hipStream_t st);
+template <typename T, int D>
+void launch_prologue(const double *mom, T *coef, const double *h, int64_t nc, const Phys &p, double cfl,
+                     hipStream_t st);
+template <typename T, int D>
+void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_t no, const Phys &p, int init,
+                 hipStream_t st);
+
+// synthetic-equation solve from the moments mom (M^{k+1/2}); bflux: boundary flux moments of the same state;
+// mom_mass: moments whose total mass a closed domain keeps.  Returns the inner iteration count
+// (host-synchronising at the end).
+template <int D, int NFM>
+int macro_solve(MacroBufs &Mb, const MeshDev &m, const Phys &p, const MacroOpts &o, const double *mom,
+                const double *bflux, const double *mom_mass, hipStream_t st);
+// per-cell sync parameters [rho, u[D], Tt, Tr, Tv, eR] of the moments (slot 0) and of W (slot 1)
+template <int D>
+void launch_sync_params(const double *mom, const double *W, double *sp, int64_t nc, const Phys &p, int from_W,
+                        hipStream_t st);
+// epsilon contributions per cell between two moment arrays: 7 values (num rho, den rho, num u, den u,
+// num T, den T, V) and their deterministic sum
+template <int D>
+void launch_residual(const double *mom1, const double *mom0, const double *vol, double *cellbuf, double *out7,
+                     int64_t nc, const Phys &p, hipStream_t st);
+// deterministic single-block sum of n values with stride k (k sums)
+void launch_block_sum(const double *in, int64_t n, int k, double *out, hipStream_t st);
+
+}  // namespace gsis

@@ -1,0 +1,1057 @@
+// Kinetic-step kernels for gfx950: limited gradients, residual with upwind fluxes and the relaxation
+// source, Jacobi sweeps of the first-order implicit operator, moments, wall re-emission, boundary flux
+// moments, synchronisation and equilibrium initialisation.
+//
+// Mapping: one wavefront (64 lanes) per cell; lanes run over the discrete velocities (or ordinates) of
+// that cell in chunks of 64, so every row f[cell][slot][0..nv) is read and written with unit stride.
+// Per-cell geometry and coefficients are wave-uniform and live in scalar registers.  Four cells per
+// 256-thread workgroup; workgroups are remapped so that each of the 8 XCDs walks a contiguous range of
+// (Morton-ordered) cells and finds neighbour rows in its own L2.
+#include "gsis_dev.h"
+#include "gsis_kernels.h"
+
+namespace gsis {
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    const int64_t q = nb / 8, r = nb % 8;
+    const int64_t x = b % 8, i = b / 8;
+    return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ int uni_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <typename T>
+__device__ __forceinline__ T dexp(T x);
+template <>
+__device__ __forceinline__ float dexp<float>(float x)
+{
+    return __expf(x);
+}
+template <>
+__device__ __forceinline__ double dexp<double>(double x)
+{
+    return exp(x);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------ limited gradients of f
+template <typename T, int D, int NFM>
+__global__ __launch_bounds__(256) void k_grad(const T *__restrict__ f, T *__restrict__ gf, const MeshDev m,
+                                              const int nd, const int64_t nv, const int second_order,
+                                              const int *__restrict__ cell_list, const int64_t ncl)
+{
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t idx = b * 4 + (threadIdx.x >> 6);
+    if (idx >= ncl) return;
+    const int c = uni_i(cell_list ? cell_list[idx] : (int)idx);
+    const int nfc = uni_i(m.nfc[c]);
+    int nb[NFM];
+    T lsq[NFM][D], dxc[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : -1;
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            dxc[s][a] = (s < nfc) ? (T)g[D + a] : T(0);
+            lsq[s][a] = (s < nfc) ? (T)g[3 * D + a] : T(0);
+        }
+    }
+    const T eps2 = (T)m.eps2[c];
+    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
+        const int64_t k = k0 + lane;
+        if (k >= nv) break;
+        for (int d = 0; d < nd; ++d) {
+            const T fc = f[((int64_t)c * nd + d) * nv + k];
+            T g[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) g[a] = T(0);
+            T dmax = T(0), dmin = T(0);
+#pragma unroll
+            for (int s = 0; s < NFM; ++s) {
+                if (nb[s] >= 0) {
+                    const T df = f[((int64_t)nb[s] * nd + d) * nv + k] - fc;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) g[a] += lsq[s][a] * df;
+                    dmax = df > dmax ? df : dmax;
+                    dmin = df < dmin ? df : dmin;
+                }
+            }
+            T phi = T(0);
+            if (second_order) {
+                phi = T(1);
+#pragma unroll
+                for (int s = 0; s < NFM; ++s) {
+                    if (s < nfc) {
+                        T d2 = T(0);
+#pragma unroll
+                        for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
+                        if (d2 != T(0)) {
+                            const T d1 = d2 > T(0) ? dmax : dmin;
+                            T p = (d1 * d1 + eps2 + T(2) * d1 * d2) / (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2);
+                            p = p > T(1) ? T(1) : p;
+                            phi = p < phi ? p : phi;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) gf[(((int64_t)c * nd + d) * D + a) * nv + k] = phi * g[a];
+        }
+    }
+}
+
+// per-cell coefficient block (written by k_prologue) -------------------------------------------------
+//   [0..D) u, D invtau, D+1 inv_dt, D+2 radc = k_eff (e_vR - e_R)/rho, D+3 B = sigma_R Tv^4/pi,
+//   D+4 inv_dtR, D+5 radd = 4 k_eff e_vR / e_v (extra diagonal of f2), then for X in (t, r, v): inv2T, norm, a[D], gR, bR[D], gV, bV[D], hH
+__host__ __device__ constexpr int coef_x(int D) { return 5 + 3 * D; }
+__host__ __device__ constexpr int coef_size(int D) { return D + 6 + 3 * coef_x(D); }
+
+// relaxation source J for the nd slots at velocity xi (Eq. kinetic_equation with Eq. reference_distribution,
+// reduced to D velocity dimensions)
+template <typename T, int D>
+__device__ __forceinline__ void collision(const T *cf, const T *xi, const T *fk, T *J, const int nd, const T wt,
+                                          const T wr, const T wv)
+{
+    T cc[D], c2 = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        cc[a] = xi[a] - cf[a];
+        c2 += cc[a] * cc[a];
+    }
+    const T aG = T(0.5) * T(2 + D), aH = T(0.5) * T(D);
+    T Ysum[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int X = 0; X < 3; ++X) {
+        const T *p = cf + D + 6 + X * coef_x(D);
+        const T inv2T = p[0], norm = p[1];
+        const T e = norm * dexp<T>(-c2 * inv2T);
+        T s = T(0), br = T(0), bv = T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            s += p[2 + a] * cc[a];
+            br += p[3 + D + a] * cc[a];
+            bv += p[4 + 2 * D + a] * cc[a];
+        }
+        const T q = c2 * inv2T;
+        const T G = e * (T(1) + s * (q - aG));
+        const T R = p[2 + D] * G + br * e;
+        const T V = p[3 + 2 * D] * G + bv * e;
+        const T H = p[4 + 3 * D] * e * (T(1) + s * (q - aH));
+        const T wX = (X == 0) ? wt : ((X == 1) ? wr : wv);
+        Ysum[0] += wX * G;
+        Ysum[1] += wX * R;
+        Ysum[2] += wX * V;
+        Ysum[3] += wX * H;
+    }
+    const T invtau = cf[D];
+    for (int d = 0; d < nd; ++d) J[d] = (Ysum[d] - fk[d]) * invtau;
+    J[2] -= fk[0] * cf[D + 2];
+}
+
+// boundary state on an incoming velocity: equilibrium (rho, u, T) of the tag, rho replaced by the wall
+// re-emission density on walls
+template <typename T, int D>
+__device__ __forceinline__ void boundary_values(const BcDev &bc, const T rho, const T *xi, const T dr, const T dv,
+                                                T *out)
+{
+    T c2 = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const T cc = xi[a] - (T)bc.u[a];
+        c2 += cc * cc;
+    }
+    const T Tb = (T)bc.T;
+    const T two_pi_T = T(2.0 * kPi) * Tb;
+    T norm = T(1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) norm *= two_pi_T;
+    const T G = rho * dexp<T>(-c2 / (T(2) * Tb)) / sqrt(norm);
+    out[0] = G;
+    out[1] = T(0.5) * dr * Tb * G;
+    out[2] = T(0.5) * dv * Tb * G;
+    out[3] = T(3 - D) * Tb * G;
+}
+
+// ------------------------------------------------------------------ residual and first increment
+template <typename T, int D, int NFM>
+__global__ __launch_bounds__(256) void k_residual(const T *__restrict__ f, const T *__restrict__ gf,
+                                                  const T *__restrict__ coef, const T *__restrict__ xi,
+                                                  const T *__restrict__ rhow, T *__restrict__ r,
+                                                  T *__restrict__ dl, T *__restrict__ fout, const MeshDev m,
+                                                  const int64_t nv, const T cflv_fac, const T omega,
+                                                  const T wt, const T wr, const T wv, const T dr, const T dv)
+{
+    constexpr int ND = (D == 3) ? 3 : 4;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t ci = b * 4 + (threadIdx.x >> 6);
+    if (ci >= m.nc) return;
+    const int c = uni_i((int)ci);
+    const int nfc = uni_i(m.nfc[c]);
+    int nb[NFM];
+    T nsv[NFM][D], dxc[NFM][D], dxj[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : INT32_MIN;
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            nsv[s][a] = (s < nfc) ? (T)g[a] : T(0);
+            dxc[s][a] = (s < nfc) ? (T)g[D + a] : T(0);
+            dxj[s][a] = (s < nfc) ? (T)g[2 * D + a] : T(0);
+        }
+    }
+    T cf[coef_size(3)];
+#pragma unroll
+    for (int i = 0; i < coef_size(D); ++i) cf[i] = coef[(int64_t)c * coef_size(D) + i];
+    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
+        const int64_t k = k0 + lane;
+        if (k >= nv) break;
+        T x[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = xi[k * D + a];
+        T fc[ND], gc[ND][D];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            fc[d] = f[((int64_t)c * ND + d) * nv + k];
+#pragma unroll
+            for (int a = 0; a < D; ++a) gc[d][a] = gf[(((int64_t)c * ND + d) * D + a) * nv + k];
+        }
+        T flux[ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) flux[d] = T(0);
+        T dsum = T(0);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) {
+            if (nb[s] == INT32_MIN) continue;
+            T xn = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
+            T fv[4];
+            if (xn > T(0)) {
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    T v = fc[d];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) v += gc[d][a] * dxc[s][a];
+                    fv[d] = v;
+                }
+                dsum += xn;
+            } else if (nb[s] >= 0) {
+                const int64_t j = nb[s];
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    T v = f[(j * ND + d) * nv + k];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) v += gf[((j * ND + d) * D + a) * nv + k] * dxj[s][a];
+                    fv[d] = v;
+                }
+            } else {
+                const int bfi = -nb[s] - 1;
+                const BcDev bc = m.bcs[m.bf_tag[bfi]];
+                const T rho = (bc.kind == 0) ? rhow[bfi] : (T)bc.rho;
+                boundary_values<T, D>(bc, rho, x, dr, dv, fv);
+            }
+#pragma unroll
+            for (int d = 0; d < ND; ++d) flux[d] += xn * fv[d];
+        }
+        T J[4];
+        collision<T, D>(cf, x, fc, J, ND, wt, wr, wv);
+        const T dcoef = cf[D + 1] + cf[D] + dsum * cflv_fac;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const int64_t o = ((int64_t)c * ND + d) * nv + k;
+            const T rr = J[d] - flux[d];
+            const T dd = (d == 2) ? dcoef + cf[D + 5] : dcoef;
+            if (fout) {
+                fout[o] = fc[d] + omega * (rr / dd);
+            } else {
+                r[o] = rr;
+                dl[o] = rr / dd;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ Jacobi sweep of the implicit operator
+template <typename T, int D, int NFM>
+__global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ r, const T *__restrict__ dlin,
+                                               T *__restrict__ dlout, const T *__restrict__ f,
+                                               T *__restrict__ fout, const T *__restrict__ coef,
+                                               const T *__restrict__ xi, const MeshDev m, const int64_t nv,
+                                               const T cflv_fac, const T omega)
+{
+    constexpr int ND = (D == 3) ? 3 : 4;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t ci = b * 4 + (threadIdx.x >> 6);
+    if (ci >= m.nc) return;
+    const int c = uni_i((int)ci);
+    const int nfc = uni_i(m.nfc[c]);
+    int nb[NFM];
+    T nsv[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : INT32_MIN;
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) nsv[s][a] = (s < nfc) ? (T)g[a] : T(0);
+    }
+    const T base = coef[(int64_t)c * coef_size(D) + D + 1] + coef[(int64_t)c * coef_size(D) + D];
+    const T radd = coef[(int64_t)c * coef_size(D) + D + 5];
+    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
+        const int64_t k = k0 + lane;
+        if (k >= nv) break;
+        T x[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = xi[k * D + a];
+        T acc[ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) acc[d] = T(0);
+        T dsum = T(0);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) {
+            if (nb[s] == INT32_MIN) continue;
+            T xn = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
+            if (xn > T(0)) {
+                dsum += xn;
+            } else if (xn < T(0) && nb[s] >= 0) {
+                const int64_t j = nb[s];
+#pragma unroll
+                for (int d = 0; d < ND; ++d) acc[d] += xn * dlin[(j * ND + d) * nv + k];
+            }
+        }
+        const T dcoef = base + dsum * cflv_fac;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const int64_t o = ((int64_t)c * ND + d) * nv + k;
+            const T dn = (r[o] - acc[d]) / ((d == 2) ? dcoef + radd : dcoef);
+            if (fout)
+                fout[o] = f[o] + omega * dn;
+            else
+                dlout[o] = dn;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ radiation: gradients, residual, sweep
+template <typename T, int D, int NFM>
+__global__ __launch_bounds__(256) void k_grad_I(const T *__restrict__ I, T *__restrict__ gI, const MeshDev m,
+                                                const int64_t no, const int second_order,
+                                                const int *__restrict__ cell_list, const int64_t ncl)
+{
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t idx = b * 4 + (threadIdx.x >> 6);
+    if (idx >= ncl) return;
+    const int c = uni_i(cell_list ? cell_list[idx] : (int)idx);
+    const int nfc = uni_i(m.nfc[c]);
+    int nb[NFM];
+    T lsq[NFM][D], dxc[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : -1;
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            dxc[s][a] = (s < nfc) ? (T)g[D + a] : T(0);
+            lsq[s][a] = (s < nfc) ? (T)g[3 * D + a] : T(0);
+        }
+    }
+    const T eps2 = (T)m.eps2[c];
+    for (int64_t q0 = 0; q0 < no; q0 += kWave) {
+        const int64_t q = q0 + lane;
+        if (q >= no) break;
+        const T Ic = I[(int64_t)c * no + q];
+        T g[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) g[a] = T(0);
+        T dmax = T(0), dmin = T(0);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) {
+            if (nb[s] >= 0) {
+                const T df = I[(int64_t)nb[s] * no + q] - Ic;
+#pragma unroll
+                for (int a = 0; a < D; ++a) g[a] += lsq[s][a] * df;
+                dmax = df > dmax ? df : dmax;
+                dmin = df < dmin ? df : dmin;
+            }
+        }
+        T phi = T(0);
+        if (second_order) {
+            phi = T(1);
+#pragma unroll
+            for (int s = 0; s < NFM; ++s) {
+                if (s < nfc) {
+                    T d2 = T(0);
+#pragma unroll
+                    for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
+                    if (d2 != T(0)) {
+                        const T d1 = d2 > T(0) ? dmax : dmin;
+                        T p = (d1 * d1 + eps2 + T(2) * d1 * d2) / (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2);
+                        p = p > T(1) ? T(1) : p;
+                        phi = p < phi ? p : phi;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) gI[((int64_t)c * D + a) * no + q] = phi * g[a];
+    }
+}
+
+template <typename T, int D, int NFM>
+__global__ __launch_bounds__(256) void k_residual_I(const T *__restrict__ I, const T *__restrict__ gI,
+                                                    const T *__restrict__ coef, const T *__restrict__ om,
+                                                    T *__restrict__ r, T *__restrict__ dl, T *__restrict__ Iout,
+                                                    const MeshDev m, const int64_t no, const T cflv_fac,
+                                                    const T omega, const T keff, const T sigR)
+{
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t ci = b * 4 + (threadIdx.x >> 6);
+    if (ci >= m.nc) return;
+    const int c = uni_i((int)ci);
+    const int nfc = uni_i(m.nfc[c]);
+    int nb[NFM];
+    T nsv[NFM][D], dxc[NFM][D], dxj[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : INT32_MIN;
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            nsv[s][a] = (s < nfc) ? (T)g[a] : T(0);
+            dxc[s][a] = (s < nfc) ? (T)g[D + a] : T(0);
+            dxj[s][a] = (s < nfc) ? (T)g[2 * D + a] : T(0);
+        }
+    }
+    const T B = coef[(int64_t)c * coef_size(D) + D + 3];
+    const T inv_dtR = coef[(int64_t)c * coef_size(D) + D + 4];
+    for (int64_t q0 = 0; q0 < no; q0 += kWave) {
+        const int64_t q = q0 + lane;
+        if (q >= no) break;
+        T o[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) o[a] = om[q * D + a];
+        const T Ic = I[(int64_t)c * no + q];
+        T gc[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) gc[a] = gI[((int64_t)c * D + a) * no + q];
+        T flux = T(0), dsum = T(0);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) {
+            if (nb[s] == INT32_MIN) continue;
+            T on = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) on += o[a] * nsv[s][a];
+            T Iv;
+            if (on > T(0)) {
+                Iv = Ic;
+#pragma unroll
+                for (int a = 0; a < D; ++a) Iv += gc[a] * dxc[s][a];
+                dsum += on;
+            } else if (nb[s] >= 0) {
+                const int64_t j = nb[s];
+                Iv = I[j * no + q];
+#pragma unroll
+                for (int a = 0; a < D; ++a) Iv += gI[(j * D + a) * no + q] * dxj[s][a];
+            } else {
+                const T Tb = (T)m.bcs[m.bf_tag[-nb[s] - 1]].T;
+                Iv = sigR * Tb * Tb * Tb * Tb / T(kPi);
+            }
+            flux += on * Iv;
+        }
+        const T rr = keff * (B - Ic) - flux;
+        const T dcoef = inv_dtR + keff + dsum * cflv_fac;
+        const int64_t idx = (int64_t)c * no + q;
+        if (Iout) {
+            Iout[idx] = Ic + omega * (rr / dcoef);
+        } else {
+            r[idx] = rr;
+            dl[idx] = rr / dcoef;
+        }
+    }
+}
+
+template <typename T, int D, int NFM>
+__global__ __launch_bounds__(256) void k_sweep_I(const T *__restrict__ r, const T *__restrict__ dlin,
+                                                 T *__restrict__ dlout, const T *__restrict__ I,
+                                                 T *__restrict__ Iout, const T *__restrict__ coef,
+                                                 const T *__restrict__ om, const MeshDev m, const int64_t no,
+                                                 const T cflv_fac, const T omega, const T keff)
+{
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t ci = b * 4 + (threadIdx.x >> 6);
+    if (ci >= m.nc) return;
+    const int c = uni_i((int)ci);
+    const int nfc = uni_i(m.nfc[c]);
+    int nb[NFM];
+    T nsv[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : INT32_MIN;
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) nsv[s][a] = (s < nfc) ? (T)g[a] : T(0);
+    }
+    const T base = coef[(int64_t)c * coef_size(D) + D + 4] + keff;
+    for (int64_t q0 = 0; q0 < no; q0 += kWave) {
+        const int64_t q = q0 + lane;
+        if (q >= no) break;
+        T acc = T(0), dsum = T(0);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) {
+            if (nb[s] == INT32_MIN) continue;
+            T on = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) on += om[q * D + a] * nsv[s][a];
+            if (on > T(0))
+                dsum += on;
+            else if (on < T(0) && nb[s] >= 0)
+                acc += on * dlin[(int64_t)nb[s] * no + q];
+        }
+        const int64_t idx = (int64_t)c * no + q;
+        const T dn = (r[idx] - acc) / (base + dsum * cflv_fac);
+        if (Iout)
+            Iout[idx] = I[idx] + omega * dn;
+        else
+            dlout[idx] = dn;
+    }
+}
+
+// ------------------------------------------------------------------ moments (Eq. getmoment, reduced form)
+// Raw FP64 moments about a reference velocity u_ref (the cell's previous velocity) reduced across the
+// wave, then shifted to central moments.  mom layout: see MomLayout.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const T *__restrict__ I,
+                                                 const double *__restrict__ xi, const double *__restrict__ w,
+                                                 const double *__restrict__ om, const double *__restrict__ wo,
+                                                 const double *__restrict__ uref, double *__restrict__ mom,
+                                                 const int64_t nc, const int64_t nv, const int64_t no,
+                                                 const double dr, const double dv)
+{
+    constexpr int ND = (D == 3) ? 3 : 4;
+    constexpr MomLayout L{D};
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t ci = b * 4 + (threadIdx.x >> 6);
+    if (ci >= nc) return;
+    const int c = uni_i((int)ci);
+    double ur[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) ur[a] = uref ? uref[(int64_t)c * L.size() + L.u() + a] : 0.0;
+    // accumulators: G: m0, m1[D], m2[D*D], m3[D]; H: h0, h1[D]; R: r0, r1[D]; V: v0, v1[D]
+    double m0 = 0, m1[D], m2[D][D], m3[D], h0 = 0, h1[D], r0 = 0, r1[D], v0 = 0, v1[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        m1[a] = m3[a] = h1[a] = r1[a] = v1[a] = 0;
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) m2[a][bb] = 0;
+    }
+    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
+        const int64_t k = k0 + lane;
+        if (k >= nv) break;
+        const double wk = w[k];
+        double cc[D], c2 = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            cc[a] = xi[k * D + a] - ur[a];
+            c2 += cc[a] * cc[a];
+        }
+        const double G = wk * (double)f[((int64_t)c * ND + 0) * nv + k];
+        const double R = wk * (double)f[((int64_t)c * ND + 1) * nv + k];
+        const double V = wk * (double)f[((int64_t)c * ND + 2) * nv + k];
+        const double H = (ND == 4) ? wk * (double)f[((int64_t)c * ND + (ND == 4 ? 3 : 0)) * nv + k] : 0.0;
+        m0 += G;
+        h0 += H;
+        r0 += R;
+        v0 += V;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            m1[a] += cc[a] * G;
+            m3[a] += cc[a] * c2 * G;
+            h1[a] += cc[a] * H;
+            r1[a] += cc[a] * R;
+            v1[a] += cc[a] * V;
+#pragma unroll
+            for (int bb = 0; bb < D; ++bb) m2[a][bb] += cc[a] * cc[bb] * G;
+        }
+    }
+    m0 = wave_sum(m0);
+    h0 = wave_sum(h0);
+    r0 = wave_sum(r0);
+    v0 = wave_sum(v0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        m1[a] = wave_sum(m1[a]);
+        m3[a] = wave_sum(m3[a]);
+        h1[a] = wave_sum(h1[a]);
+        r1[a] = wave_sum(r1[a]);
+        v1[a] = wave_sum(v1[a]);
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) m2[a][bb] = wave_sum(m2[a][bb]);
+    }
+    double eR = 0, qR[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) qR[a] = 0;
+    for (int64_t q0 = 0; q0 < no; q0 += kWave) {
+        const int64_t q = q0 + lane;
+        if (q >= no) break;
+        const double Iq = wo[q] * (double)I[(int64_t)c * no + q];
+        eR += Iq;
+#pragma unroll
+        for (int a = 0; a < D; ++a) qR[a] += om[q * D + a] * Iq;
+    }
+    eR = wave_sum(eR);
+#pragma unroll
+    for (int a = 0; a < D; ++a) qR[a] = wave_sum(qR[a]);
+    if (lane == 0) {
+        double *M = mom + (int64_t)c * L.size();
+        const double rho = m0;
+        double dl[D], d2 = 0, S2 = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            dl[a] = m1[a] / rho;
+            d2 += dl[a] * dl[a];
+            S2 += m2[a][a];
+        }
+        const double Tt = (S2 - rho * d2 + h0) / (3.0 * rho);
+        M[L.rho()] = rho;
+#pragma unroll
+        for (int a = 0; a < D; ++a) M[L.u() + a] = ur[a] + dl[a];
+        M[L.Tt()] = Tt;
+        M[L.Tr()] = 2.0 * r0 / (dr * rho);
+        M[L.Tv()] = 2.0 * v0 / (dv * rho);
+        M[L.eR()] = eR;
+        M[L.er()] = r0;
+        M[L.ev()] = v0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+#pragma unroll
+            for (int bb = 0; bb < D; ++bb)
+                M[L.sig() + a * D + bb] = m2[a][bb] - rho * dl[a] * dl[bb] - (a == bb ? rho * Tt : 0.0);
+            double t3 = m3[a] - dl[a] * S2 + 2.0 * rho * dl[a] * d2;
+#pragma unroll
+            for (int bb = 0; bb < D; ++bb) t3 -= 2.0 * dl[bb] * m2[a][bb];
+            M[L.qt() + a] = 0.5 * (t3 + h1[a] - dl[a] * h0);
+            M[L.qr() + a] = r1[a] - dl[a] * r0;
+            M[L.qv() + a] = v1[a] - dl[a] * v0;
+            M[L.qR() + a] = qR[a];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ per-cell coefficients (prologue)
+template <typename T, int D>
+__global__ void k_prologue(const double *__restrict__ mom, T *__restrict__ coef, const double *__restrict__ h,
+                           const int64_t nc, const Phys p, const double cfl_meso)
+{
+    constexpr MomLayout L{D};
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double *M = mom + c * L.size();
+    T *cf = coef + c * coef_size(D);
+    const double rho = M[L.rho()], Tt = M[L.Tt()], Tr = M[L.Tr()], Tv = M[L.Tv()], eR = M[L.eR()];
+    const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = (3 * Tt + p.d_v * Tv) / (3 + p.d_v);
+    const double tau = sqrt(2.0 / kPi) * pow(Tt, p.omega - 1.0) * p.Kn / rho;
+    double qt[3] = {0, 0, 0}, qr[3] = {0, 0, 0}, qv[3] = {0, 0, 0}, q0[3], q1[3], q2[3];
+    double un = 0;
+    for (int a = 0; a < D; ++a) {
+        qt[a] = M[L.qt() + a];
+        qr[a] = M[L.qr() + a];
+        qv[a] = M[L.qv() + a];
+        cf[a] = (T)M[L.u() + a];
+        un += M[L.u() + a] * M[L.u() + a];
+    }
+    for (int a = 0; a < 3; ++a) {
+        q0[a] = p.Q[0][0] * qt[a] + p.Q[0][1] * qr[a] + p.Q[0][2] * qv[a];
+        q1[a] = p.Q[1][0] * qt[a] + p.Q[1][1] * qr[a] + p.Q[1][2] * qv[a];
+        q2[a] = p.Q[2][0] * qt[a] + p.Q[2][1] * qr[a] + p.Q[2][2] * qv[a];
+    }
+    const double cs = sqrt(5.0 / 3.0 * Tt);
+    const double Tv4 = Tv * Tv * Tv * Tv;
+    cf[D] = (T)(1.0 / tau);
+    cf[D + 1] = (T)((sqrt(un) + cs) / (cfl_meso * h[c]));
+    cf[D + 2] = (T)(p.keff * (4 * p.sigma_R * Tv4 - eR) / rho);
+    cf[D + 3] = (T)(p.sigma_R * Tv4 / kPi);
+    cf[D + 4] = (T)(1.0 / (cfl_meso * h[c]));
+    // point-implicit rate of the emission part of the gas-photon exchange on f2: 4 k_eff e_vR / e_v
+    cf[D + 5] = (T)(4.0 * p.keff * 4 * p.sigma_R * Tv4 / M[L.ev()]);
+    const double TX[3] = {Tt, Ttr, Ttv};
+    const double *qX[3] = {qt, q0, q0};
+    const double TRX[3] = {Tr, Ttr, Tr};
+    const double *qRX[3] = {qr, q1, q1};
+    const double TVX[3] = {Tv, Tv, Ttv};
+    const double *qVX[3] = {qv, q2, q2};
+    for (int X = 0; X < 3; ++X) {
+        T *px = cf + D + 6 + X * coef_x(D);
+        const double T_ = TX[X];
+        px[0] = (T)(1.0 / (2.0 * T_));
+        px[1] = (T)(rho * pow(2.0 * kPi * T_, -0.5 * D));
+        for (int a = 0; a < D; ++a) {
+            px[2 + a] = (T)(2.0 * qX[X][a] / (15.0 * T_ * rho * T_));
+            px[3 + D + a] = (T)(qRX[X][a] / (T_ * rho));
+            px[4 + 2 * D + a] = (T)(qVX[X][a] / (T_ * rho));
+        }
+        px[2 + D] = (T)(0.5 * p.d_r * TRX[X]);
+        px[3 + 2 * D] = (T)(0.5 * p.d_v * TVX[X]);
+        px[4 + 3 * D] = (T)((3 - D) * T_);
+    }
+}
+
+// ------------------------------------------------------------------ wall re-emission densities
+template <typename T, int D, int NFM>
+__global__ __launch_bounds__(64) void k_wall_density(const T *__restrict__ f, const T *__restrict__ gf,
+                                                     const double *__restrict__ xi, const double *__restrict__ w,
+                                                     T *__restrict__ rhow, const MeshDev m, const int64_t nv)
+{
+    constexpr int ND = (D == 3) ? 3 : 4;
+    const int bfi = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int tag = m.bf_tag[bfi];
+    const BcDev bc = m.bcs[tag];
+    if (bc.kind != 0) {
+        if (lane == 0) rhow[bfi] = (T)0;
+        return;
+    }
+    const int64_t c = m.bf_cell[bfi];
+    double n[D], dx[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        n[a] = m.bf_n[(int64_t)bfi * D + a];
+        dx[a] = m.bf_dxc[(int64_t)bfi * D + a];
+    }
+    double out = 0, in = 0;
+    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
+        const int64_t k = k0 + lane;
+        if (k >= nv) break;
+        double xn = 0, c2 = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            xn += xi[k * D + a] * n[a];
+            const double cc = xi[k * D + a] - bc.u[a];
+            c2 += cc * cc;
+        }
+        if (xn > 0) {
+            T v = f[(c * ND + 0) * nv + k];
+#pragma unroll
+            for (int a = 0; a < D; ++a) v += gf[((c * ND + 0) * D + a) * nv + k] * (T)dx[a];
+            out += w[k] * xn * (double)v;
+        } else {
+            in += w[k] * (-xn) * pow(2 * kPi * bc.T, -0.5 * D) * exp(-c2 / (2 * bc.T));
+        }
+    }
+    out = wave_sum(out);
+    in = wave_sum(in);
+    if (lane == 0) rhow[bfi] = (T)(out / in);
+}
+
+// ------------------------------------------------------------------ boundary flux moments of a state
+// per boundary face: NW outward fluxes (mass, momentum D, total energy, e_r, e_v, e_R) per unit area and
+// the surface output (q_conv, q_rad, p_w)
+template <typename T, int D>
+__global__ __launch_bounds__(64) void k_boundary_flux(const T *__restrict__ f, const T *__restrict__ gf,
+                                                      const T *__restrict__ I, const T *__restrict__ gI,
+                                                      const double *__restrict__ xi, const double *__restrict__ w,
+                                                      const double *__restrict__ om, const double *__restrict__ wo,
+                                                      const T *__restrict__ rhow, double *__restrict__ bflux,
+                                                      double *__restrict__ bsurf, const MeshDev m, const int64_t nv,
+                                                      const int64_t no, const double dr, const double dv,
+                                                      const double sigR)
+{
+    constexpr int ND = (D == 3) ? 3 : 4;
+    constexpr int NW = D + 5;
+    const int bfi = blockIdx.x;
+    const int lane = threadIdx.x;
+    const BcDev bc = m.bcs[m.bf_tag[bfi]];
+    const int64_t c = m.bf_cell[bfi];
+    double n[D], dx[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        n[a] = m.bf_n[(int64_t)bfi * D + a];
+        dx[a] = m.bf_dxc[(int64_t)bfi * D + a];
+    }
+    const double rho_in = (bc.kind == 0) ? (double)rhow[bfi] : bc.rho;
+    double F[NW], qconv = 0, pw = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) F[i] = 0;
+    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
+        const int64_t k = k0 + lane;
+        if (k >= nv) break;
+        double x[D], xn = 0, x2 = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            x[a] = xi[k * D + a];
+            xn += x[a] * n[a];
+            x2 += x[a] * x[a];
+        }
+        double fv[4] = {0, 0, 0, 0};
+        if (xn > 0) {
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                T v = f[(c * ND + d) * nv + k];
+#pragma unroll
+                for (int a = 0; a < D; ++a) v += gf[((c * ND + d) * D + a) * nv + k] * (T)dx[a];
+                fv[d] = (double)v;
+            }
+        } else {
+            double c2 = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) c2 += (x[a] - bc.u[a]) * (x[a] - bc.u[a]);
+            const double G = rho_in * pow(2 * kPi * bc.T, -0.5 * D) * exp(-c2 / (2 * bc.T));
+            fv[0] = G;
+            fv[1] = 0.5 * dr * bc.T * G;
+            fv[2] = 0.5 * dv * bc.T * G;
+            fv[3] = (3 - D) * bc.T * G;
+        }
+        const double wk = w[k];
+        const double hv = (ND == 4) ? fv[3] : 0.0;
+        const double en = 0.5 * x2 * fv[0] + 0.5 * hv + fv[1] + fv[2];
+        F[0] += wk * xn * fv[0];
+#pragma unroll
+        for (int a = 0; a < D; ++a) F[1 + a] += wk * xn * x[a] * fv[0];
+        F[D + 1] += wk * xn * en;
+        F[D + 2] += wk * xn * fv[1];
+        F[D + 3] += wk * xn * fv[2];
+        qconv += wk * xn * en;
+        pw += wk * xn * xn * fv[0];
+    }
+    double qrad = 0;
+    for (int64_t q0 = 0; q0 < no; q0 += kWave) {
+        const int64_t q = q0 + lane;
+        if (q >= no) break;
+        double on = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) on += om[q * D + a] * n[a];
+        double Iv;
+        if (on > 0) {
+            T v = I[c * no + q];
+#pragma unroll
+            for (int a = 0; a < D; ++a) v += gI[(c * D + a) * no + q] * (T)dx[a];
+            Iv = (double)v;
+        } else {
+            Iv = sigR * bc.T * bc.T * bc.T * bc.T / kPi;
+        }
+        qrad += wo[q] * on * Iv;
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) F[i] = wave_sum(F[i]);
+    qconv = wave_sum(qconv);
+    pw = wave_sum(pw);
+    qrad = wave_sum(qrad);
+    if (lane == 0) {
+        double *out = bflux + (int64_t)bfi * NW;
+        for (int i = 0; i < NW; ++i) out[i] = F[i];
+        out[D + 4] = qrad;
+        out[D + 1] += qrad;
+        bsurf[(int64_t)bfi * 3 + 0] = qconv;
+        bsurf[(int64_t)bfi * 3 + 1] = qrad;
+        bsurf[(int64_t)bfi * 3 + 2] = pw;
+    }
+}
+
+// ------------------------------------------------------------------ synchronisation and initialisation
+// f += f^eq(M1) - f^eq(M0) with f^eq the multi-temperature equilibrium; I += (eR1 - eR0)/(4 pi).
+// sp per cell: [rho, u[D], Tt, Tr, Tv, eR] for M0 then M1.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__ I, const double *__restrict__ sp,
+                                              const double *__restrict__ xi, const int64_t nc, const int64_t nv,
+                                              const int64_t no, const double dr, const double dv, const int init)
+{
+    constexpr int ND = (D == 3) ? 3 : 4;
+    constexpr int NS = D + 5;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t ci = b * 4 + (threadIdx.x >> 6);
+    if (ci >= nc) return;
+    const int c = uni_i((int)ci);
+    const double *s0 = sp + (int64_t)c * 2 * NS, *s1 = s0 + NS;
+    const double n0 = s0[0] * pow(2 * kPi * s0[D + 1], -0.5 * D), n1 = s1[0] * pow(2 * kPi * s1[D + 1], -0.5 * D);
+    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
+        const int64_t k = k0 + lane;
+        if (k >= nv) break;
+        double c20 = 0, c21 = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double x = xi[k * D + a];
+            c20 += (x - s0[1 + a]) * (x - s0[1 + a]);
+            c21 += (x - s1[1 + a]) * (x - s1[1 + a]);
+        }
+        const double G0 = init ? 0.0 : n0 * exp(-c20 / (2 * s0[D + 1]));
+        const double G1 = n1 * exp(-c21 / (2 * s1[D + 1]));
+        const double dG[4] = {G1 - G0, 0.5 * dr * (s1[D + 2] * G1 - s0[D + 2] * G0),
+                              0.5 * dv * (s1[D + 3] * G1 - s0[D + 3] * G0),
+                              (3 - D) * (s1[D + 1] * G1 - s0[D + 1] * G0)};
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const int64_t o = ((int64_t)c * ND + d) * nv + k;
+            if (init)
+                f[o] = (T)dG[d];
+            else
+                f[o] = (T)((double)f[o] + dG[d]);
+        }
+    }
+    const double dI = init ? s1[D + 4] / (4 * kPi) : (s1[D + 4] - s0[D + 4]) / (4 * kPi);
+    for (int64_t q0 = 0; q0 < no; q0 += kWave) {
+        const int64_t q = q0 + lane;
+        if (q >= no) break;
+        const int64_t o = (int64_t)c * no + q;
+        if (init)
+            I[o] = (T)dI;
+        else
+            I[o] = (T)((double)I[o] + dI);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static inline int64_t wave_blocks(int64_t n) { return (n + 3) / 4; }
+
+template <typename T, int D, int NFM>
+void launch_grad(const T *f, T *gf, const MeshDev &m, int64_t nv, int so, const int *cells, int64_t ncl,
+                 hipStream_t st)
+{
+    if (ncl <= 0) return;
+    hipLaunchKernelGGL((k_grad<T, D, NFM>), dim3(wave_blocks(ncl)), dim3(256), 0, st, f, gf, m, (D == 3) ? 3 : 4,
+                       nv, so, cells, ncl);
+}
+
+template <typename T, int D, int NFM>
+void launch_grad_I(const T *I, T *gI, const MeshDev &m, int64_t no, int so, const int *cells, int64_t ncl,
+                   hipStream_t st)
+{
+    if (ncl <= 0) return;
+    hipLaunchKernelGGL((k_grad_I<T, D, NFM>), dim3(wave_blocks(ncl)), dim3(256), 0, st, I, gI, m, no, so, cells,
+                       ncl);
+}
+
+template <typename T, int D, int NFM>
+void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpts &o, int64_t nv, int64_t no,
+                    hipStream_t st, Prof *pf)
+{
+    constexpr int ND = (D == 3) ? 3 : 4;
+    const T fac = (T)(1.0 + 1.0 / o.cfl_v);
+    const T om = (T)o.kin_omega;
+    const T wt = (T)(1.0 - 1.0 / p.Z_r - 1.0 / p.Z_v), wr = (T)(1.0 / p.Z_r), wv = (T)(1.0 / p.Z_v);
+    const dim3 grid(wave_blocks(m.nc)), blk(256);
+    // algorithmic bytes of each launch: every array the kernel must touch, once
+    const double es = sizeof(T), cv = (double)m.nc * nv * ND * es, co = (double)m.nc * no * es;
+    Prof dummy;
+    Prof &P = pf ? *pf : dummy;
+    int ev = P.begin(0, cv * (1 + D));
+    launch_grad<T, D, NFM>(B.f, B.gf, m, nv, o.second_order, nullptr, m.nc, st);
+    P.end(ev);
+    ev = P.begin(3, co * (1 + D));
+    launch_grad_I<T, D, NFM>(B.I, B.gI, m, no, o.second_order, nullptr, m.nc, st);
+    P.end(ev);
+    ev = P.begin(5, 0.0);
+    if (m.nbf > 0)
+        hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(64), 0, st, B.f, B.gf, B.xi_d, B.w_d,
+                           B.rhow, m, nv);
+    P.end(ev);
+    const int ks = o.kin_sweeps;
+    ev = P.begin(1, ks == 0 ? cv * (2 + D) : cv * (3 + D));
+    hipLaunchKernelGGL((k_residual<T, D, NFM>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xi, B.rhow, B.r, B.dl0,
+                       ks == 0 ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
+    P.end(ev);
+    ev = P.begin(3, ks == 0 ? co * (2 + D) : co * (3 + D));
+    hipLaunchKernelGGL((k_residual_I<T, D, NFM>), grid, blk, 0, st, B.I, B.gI, B.coef, B.om, B.rI, B.dI0,
+                       ks == 0 ? B.I2 : nullptr, m, no, fac, om, (T)p.keff, (T)p.sigma_R);
+    P.end(ev);
+    T *din = B.dl0, *dout = B.dl1, *dIin = B.dI0, *dIout = B.dI1;
+    for (int s = 0; s < ks; ++s) {
+        const bool last = (s == ks - 1);
+        ev = P.begin(2, last ? 4 * cv : 3 * cv);
+        hipLaunchKernelGGL((k_sweep<T, D, NFM>), grid, blk, 0, st, B.r, din, dout, B.f, last ? B.f2 : nullptr,
+                           B.coef, B.xi, m, nv, fac, om);
+        P.end(ev);
+        ev = P.begin(3, last ? 4 * co : 3 * co);
+        hipLaunchKernelGGL((k_sweep_I<T, D, NFM>), grid, blk, 0, st, B.rI, dIin, dIout, B.I,
+                           last ? B.I2 : nullptr, B.coef, B.om, m, no, fac, om, (T)p.keff);
+        P.end(ev);
+        std::swap(din, dout);
+        std::swap(dIin, dIout);
+    }
+    std::swap(B.f, B.f2);
+    std::swap(B.I, B.I2);
+}
+
+template <typename T, int D>
+void launch_moments(const KinBufs<T> &B, const double *uref, double *mom, int64_t nc, int64_t nv, int64_t no,
+                    const Phys &p, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_moments<T, D>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d,
+                       B.om_d, B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
+}
+
+template <typename T, int D>
+void launch_prologue(const double *mom, T *coef, const double *h, int64_t nc, const Phys &p, double cfl,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL((k_prologue<T, D>), dim3((nc + 255) / 256), dim3(256), 0, st, mom, coef, h, nc, p, cfl);
+}
+
+template <typename T, int D, int NFM>
+void launch_boundary_state(KinBufs<T> &B, const MeshDev &m, const Phys &p, int so, int64_t nv, int64_t no,
+                           hipStream_t st)
+{
+    if (m.nbf <= 0) return;
+    launch_grad<T, D, NFM>(B.f, B.gf, m, nv, so, m.bcells, m.nbcells, st);
+    launch_grad_I<T, D, NFM>(B.I, B.gI, m, no, so, m.bcells, m.nbcells, st);
+    hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(64), 0, st, B.f, B.gf, B.xi_d, B.w_d,
+                       B.rhow, m, nv);
+    hipLaunchKernelGGL((k_boundary_flux<T, D>), dim3(m.nbf), dim3(64), 0, st, B.f, B.gf, B.I, B.gI, B.xi_d, B.w_d,
+                       B.om_d, B.wo_d, B.rhow, B.bflux, B.bsurf, m, nv, no, p.d_r, p.d_v, p.sigma_R);
+}
+
+template <typename T, int D>
+void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_t no, const Phys &p, int init,
+                 hipStream_t st)
+{
+    hipLaunchKernelGGL((k_sync<T, D>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, sp, B.xi_d, nc, nv, no,
+                       p.d_r, p.d_v, init);
+}
+
+#define GSIS_INST_D(T, D, NFM)                                                                                    \
+    template void launch_kinetic<T, D, NFM>(KinBufs<T> &, const MeshDev &, const Phys &, const KinOpts &, int64_t, \
+                                            int64_t, hipStream_t, Prof *);                                        \
+    template void launch_boundary_state<T, D, NFM>(KinBufs<T> &, const MeshDev &, const Phys &, int, int64_t,     \
+                                                   int64_t, hipStream_t);
+#define GSIS_INST_T(T, D)                                                                                          \
+    template void launch_moments<T, D>(const KinBufs<T> &, const double *, double *, int64_t, int64_t, int64_t,   \
+                                       const Phys &, hipStream_t);                                                 \
+    template void launch_prologue<T, D>(const double *, T *, const double *, int64_t, const Phys &, double,       \
+                                        hipStream_t);                                                              \
+    template void launch_sync<T, D>(KinBufs<T> &, const double *, int64_t, int64_t, int64_t, const Phys &, int,   \
+                                    hipStream_t);
+
+GSIS_INST_D(float, 1, 2)
+GSIS_INST_D(double, 1, 2)
+GSIS_INST_D(float, 2, 3)
+GSIS_INST_D(double, 2, 3)
+GSIS_INST_D(float, 2, 4)
+GSIS_INST_D(double, 2, 4)
+GSIS_INST_D(float, 3, 4)
+GSIS_INST_D(double, 3, 4)
+GSIS_INST_D(float, 3, 6)
+GSIS_INST_D(double, 3, 6)
+GSIS_INST_T(float, 1)
+GSIS_INST_T(double, 1)
+GSIS_INST_T(float, 2)
+GSIS_INST_T(double, 2)
+GSIS_INST_T(float, 3)
+GSIS_INST_T(double, 3)
+
+}  // namespace gsis

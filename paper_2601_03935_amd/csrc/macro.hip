@@ -1,0 +1,850 @@
+// Synthetic-equation solver for gfx950 (Sec. 2.2 and Sec. 6 of the paper): FP64, one thread per cell.
+//
+// Per inner iteration: primitive state and gradient fields, residual R_i = -(1/V) sum F S + Q with the
+// Rusanov convective flux (its dissipation taken relative to the state the solve starts from), the NSF
+// viscous flux from face gradients plus the fixed face HoTs, boundary model fluxes plus frozen kinetic
+// corrections, the diagonal D_i with the diagonal source Jacobian (Appendix A), Jacobi sweeps of the
+// implicit operator, and the update.  The stopping test (relative residual drop) is evaluated on the
+// device; kernels of later iterations see the flag and return at once, so the host only polls it every
+// few iterations.
+#include "gsis_dev.h"
+#include "gsis_kernels.h"
+
+namespace gsis {
+
+struct Prim {
+    double rho, u[3], Tt, Tr, Tv, eR, mu, cs;
+};
+
+template <int D>
+__device__ __forceinline__ void prim_of(const double *W, const Phys &p, Prim &q)
+{
+    q.rho = W[0];
+    double ek = 0;
+    q.u[0] = q.u[1] = q.u[2] = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        q.u[a] = W[1 + a] / W[0];
+        ek += 0.5 * W[0] * q.u[a] * q.u[a];
+    }
+    q.Tt = 2.0 / (3.0 * W[0]) * (W[D + 1] - ek - W[D + 2] - W[D + 3] - W[D + 4]);
+    q.Tr = 2.0 * W[D + 2] / (p.d_r * W[0]);
+    q.Tv = 2.0 * W[D + 3] / (p.d_v * W[0]);
+    q.eR = W[D + 4];
+    q.mu = sqrt(2.0 / kPi) * p.Kn * pow(q.Tt, p.omega);
+    q.cs = sqrt(5.0 / 3.0 * q.Tt);
+}
+
+template <int D>
+__device__ __forceinline__ void euler_flux(const double *W, const double *n, const Phys &p, double *F)
+{
+    Prim q;
+    prim_of<D>(W, p, q);
+    double un = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) un += q.u[a] * n[a];
+    const double pt = q.rho * q.Tt;
+    F[0] = q.rho * un;
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[1 + a] = W[1 + a] * un + pt * n[a];
+    F[D + 1] = un * (W[D + 1] - W[D + 4] + pt);
+    F[D + 2] = un * W[D + 2];
+    F[D + 3] = un * W[D + 3];
+    F[D + 4] = 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ double rusanov(const double *WL, const double *WR, const double *n, const Phys &p,
+                                          double *F)
+{
+    constexpr int NW = D + 5;
+    double FL[NW], FR[NW];
+    euler_flux<D>(WL, n, p, FL);
+    euler_flux<D>(WR, n, p, FR);
+    Prim qL, qR;
+    prim_of<D>(WL, p, qL);
+    prim_of<D>(WR, p, qR);
+    double unL = 0, unR = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        unL += qL.u[a] * n[a];
+        unR += qR.u[a] * n[a];
+    }
+    const double lam = fmax(fabs(unL) + qL.cs, fabs(unR) + qR.cs);
+#pragma unroll
+    for (int i = 0; i < NW - 1; ++i) F[i] = 0.5 * (FL[i] + FR[i]) - 0.5 * lam * (WR[i] - WL[i]);
+    F[NW - 1] = 0.0;
+    return lam;
+}
+
+template <int D>
+__device__ __forceinline__ void W_of_state(double rho, const double *u, double T, const Phys &p, double *W)
+{
+    double ek = 0;
+    W[0] = rho;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        W[1 + a] = rho * u[a];
+        ek += 0.5 * rho * u[a] * u[a];
+    }
+    W[D + 2] = 0.5 * p.d_r * rho * T;
+    W[D + 3] = 0.5 * p.d_v * rho * T;
+    W[D + 4] = 4 * p.sigma_R * T * T * T * T;
+    W[D + 1] = ek + 1.5 * rho * T + W[D + 2] + W[D + 3] + W[D + 4];
+}
+
+// NSF stress and heat fluxes plus optional HoTs; g[i][a] gradients of (u[D], Tt, Tr, Tv, eR)
+template <int D>
+__device__ __forceinline__ void constitutive(double mu, const double g[][3], const double *hot, const Phys &p,
+                                             double sig[3][3], double q[4][3])
+{
+    const double kR = (p.keff > 0) ? 1.0 / (3 * p.keff) : 0.0;
+    double div = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) div += g[a][a];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            sig[a][b] = -mu * (g[b][a] + g[a][b] - (a == b ? 2.0 / 3.0 * div : 0.0));
+            if (hot) sig[a][b] += hot[a * 3 + b];
+        }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            double v = 0;
+#pragma unroll
+            for (int mm = 0; mm < 3; ++mm) v -= 0.5 * mu * p.K0[l][mm] * g[D + mm][a];
+            q[l][a] = v + (hot ? hot[9 + 3 * l + a] : 0.0);
+        }
+        q[3][a] = -kR * g[D + 3][a] + (hot ? hot[18 + a] : 0.0);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void viscous_flux(const double sig[3][3], const double q[4][3], const double *uf,
+                                             const double *n, double *F)
+{
+    double sn[3] = {0, 0, 0}, work = 0, qall = 0, qrn = 0, qvn = 0, qRn = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) sn[a] += sig[a][b] * n[b];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        work += sn[a] * uf[a];
+        qall += (q[0][a] + q[1][a] + q[2][a] + q[3][a]) * n[a];
+        qrn += q[1][a] * n[a];
+        qvn += q[2][a] * n[a];
+        qRn += q[3][a] * n[a];
+    }
+    F[0] = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[1 + a] = sn[a];
+    F[D + 1] = work + qall;
+    F[D + 2] = qrn;
+    F[D + 3] = qvn;
+    F[D + 4] = qRn;
+}
+
+// model flux of a boundary face for the cell state Wc (wall: impermeable NSF-type wall flux; far field:
+// Rusanov against the prescribed state; both with radiative diffusion towards B_R(T_b)); g1/g2 spectral radii
+template <int D>
+__device__ __forceinline__ void bmodel_flux(const MeshDev &m, int bfi, const double *Wc, const Phys &p, double *F,
+                                            double *g1, double *g2)
+{
+    constexpr int NW = D + 5;
+    const BcDev bc = m.bcs[m.bf_tag[bfi]];
+    Prim q;
+    prim_of<D>(Wc, p, q);
+    double n[D], delta = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        n[a] = m.bf_n[(int64_t)bfi * D + a];
+        delta += n[a] * m.bf_dxc[(int64_t)bfi * D + a];
+    }
+    delta = fabs(delta);
+    const double kR = (p.keff > 0) ? 1.0 / (3 * p.keff) : 0.0;
+    const double Tb = bc.T;
+    const double eRb = 4 * p.sigma_R * Tb * Tb * Tb * Tb;
+    const double qRn = -kR * (eRb - q.eR) / delta;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) F[i] = 0;
+    double un = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) un += q.u[a] * n[a];
+    *g1 = fabs(un) + q.cs + 2 * q.mu / (q.rho * delta);
+    *g2 = 2 * kR / delta;
+    if (bc.kind == 0) {
+        const double pt = q.rho * q.Tt;
+        double work = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double sn = -q.mu * (bc.u[a] - q.u[a]) / delta;
+            F[1 + a] = pt * n[a] + sn;
+            work += sn * bc.u[a];
+        }
+        const double dT[3] = {(Tb - q.Tt) / delta, (Tb - q.Tr) / delta, (Tb - q.Tv) / delta};
+        double qn[3];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            qn[l] = 0;
+#pragma unroll
+            for (int mm = 0; mm < 3; ++mm) qn[l] -= 0.5 * q.mu * p.K0[l][mm] * dT[mm];
+        }
+        F[D + 1] = work + qn[0] + qn[1] + qn[2] + qRn;
+        F[D + 2] = qn[1];
+        F[D + 3] = qn[2];
+        F[D + 4] = qRn;
+    } else {
+        double Wb[NW];
+        W_of_state<D>(bc.rho, bc.u, Tb, p, Wb);
+        rusanov<D>(Wc, Wb, n, p, F);
+        F[D + 1] += qRn;
+        F[D + 4] = qRn;
+    }
+}
+
+// point solve of the implicit operator in U = (rho, rho u, e_gas, e_r, e_v, e_R): diagonal except for the
+// gas-photon exchange, solved exactly per cell (with e' = d e_vR / d e_v):
+//   D_g dg = r_g - k e' dv + k dR,   D_v dv = r_v + k dR,   D_R dR = r_R + k e' dv
+template <int D>
+__device__ __forceinline__ void local_solve(const double *rhs, const double *Dg, const double rho, const double Tv,
+                                            const Phys &p, double *dU)
+{
+    constexpr int NW = D + 5, ig = D + 1, iv = D + 3, iR = D + 4;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) dU[i] = rhs[i] / Dg[i];
+    const double k = p.keff;
+    const double ep = 32.0 * p.sigma_R * Tv * Tv * Tv / (p.d_v * rho);
+    const double dv = (rhs[iv] + k * rhs[iR] / Dg[iR]) / (Dg[iv] - k * k * ep / Dg[iR]);
+    const double dR = (rhs[iR] + k * ep * dv) / Dg[iR];
+    dU[iv] = dv;
+    dU[iR] = dR;
+    dU[ig] = (rhs[ig] - k * ep * dv + k * dR) / Dg[ig];
+}
+
+// W += a dU with a = 2^-m the largest factor (m <= 20) keeping rho, T_t, e_r, e_v, e_R at least half
+template <int D>
+__device__ __forceinline__ void positive_update(double *W, const double *dU, const Phys &p)
+{
+    constexpr int NW = D + 5;
+    Prim p0;
+    prim_of<D>(W, p, p0);
+    double a = 1.0;
+    for (int m = 0; m <= 20; ++m, a *= 0.5) {
+        double Wn[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) Wn[i] = W[i] + a * dU[i];
+        Wn[D + 1] += a * dU[D + 4];
+        Prim p1;
+        prim_of<D>(Wn, p, p1);
+        if (Wn[0] >= 0.5 * W[0] && p1.Tt >= 0.5 * p0.Tt && Wn[D + 2] >= 0.5 * W[D + 2] &&
+            Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4]) {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) W[i] = Wn[i];
+            return;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ setup kernels
+template <int D>
+__global__ void k_W_from_mom(const double *__restrict__ mom, double *__restrict__ W, double *__restrict__ W0,
+                             const int64_t nc, const Phys p)
+{
+    constexpr MomLayout L{D};
+    constexpr int NW = D + 5;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double *M = mom + c * L.size();
+    const double rho = M[L.rho()];
+    double Wc[NW], ek = 0;
+    Wc[0] = rho;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        Wc[1 + a] = rho * M[L.u() + a];
+        ek += 0.5 * rho * M[L.u() + a] * M[L.u() + a];
+    }
+    const double er = 0.5 * p.d_r * rho * M[L.Tr()], ev = 0.5 * p.d_v * rho * M[L.Tv()];
+    Wc[D + 1] = ek + 1.5 * rho * M[L.Tt()] + er + ev + M[L.eR()];
+    Wc[D + 2] = er;
+    Wc[D + 3] = ev;
+    Wc[D + 4] = M[L.eR()];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        W[c * NW + i] = Wc[i];
+        W0[c * NW + i] = Wc[i];
+    }
+}
+
+// gradient fields (u[D], Tt, Tr, Tv, eR) from moments
+template <int D>
+__global__ void k_fld_from_mom(const double *__restrict__ mom, double *__restrict__ fld, double *__restrict__ P,
+                               const int64_t nc, const Phys p)
+{
+    constexpr MomLayout L{D};
+    constexpr int NF = D + 4;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double *M = mom + c * L.size();
+#pragma unroll
+    for (int a = 0; a < D; ++a) fld[c * NF + a] = M[L.u() + a];
+    fld[c * NF + D] = M[L.Tt()];
+    fld[c * NF + D + 1] = M[L.Tr()];
+    fld[c * NF + D + 2] = M[L.Tv()];
+    fld[c * NF + D + 3] = M[L.eR()];
+    P[c] = sqrt(2.0 / kPi) * p.Kn * pow(M[L.Tt()], p.omega);  // mu
+}
+
+// unlimited least-squares gradients of the NF fields (zero-gradient ghosts on boundary faces)
+template <int D, int NFM>
+__global__ void k_cell_grad(const double *__restrict__ fld, double *__restrict__ gfld, const MeshDev m,
+                            const int *__restrict__ flags)
+{
+    constexpr int NF = D + 4;
+    if (flags && flags[0]) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= m.nc) return;
+    const int nfc = m.nfc[c];
+    double g[NF][D];
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int a = 0; a < D; ++a) g[i][a] = 0;
+    for (int s = 0; s < nfc; ++s) {
+        const int j = m.nbr[c * NFM + s];
+        if (j < 0) continue;
+        const double *gs = m.geo + (c * NFM + s) * 4 * D + 3 * D;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const double df = fld[(int64_t)j * NF + i] - fld[c * NF + i];
+#pragma unroll
+            for (int a = 0; a < D; ++a) g[i][a] += gs[a] * df;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int a = 0; a < D; ++a) gfld[(c * NF + i) * D + a] = g[i][a];
+}
+
+// face gradient: mean of the cell gradients with the component along the centroid line replaced by the
+// centroid difference quotient
+template <int D>
+__device__ __forceinline__ void face_grad(const double *fld, const double *gfld, int64_t c, int64_t j,
+                                          const double *dvec, double g[][3])
+{
+    constexpr int NF = D + 4;
+    double dl = 0, dh[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) dl += dvec[a] * dvec[a];
+    dl = sqrt(dl);
+#pragma unroll
+    for (int a = 0; a < D; ++a) dh[a] = dvec[a] / dl;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        double avg[D], corr = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            avg[a] = 0.5 * (gfld[(c * NF + i) * D + a] + gfld[(j * NF + i) * D + a]);
+            corr += avg[a] * dh[a];
+        }
+        const double jump = (fld[j * NF + i] - fld[c * NF + i]) / dl;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[i][a] = (a < D) ? avg[a] + (jump - corr) * dh[a] : 0.0;
+    }
+}
+
+// face HoTs on interior faces: mean kinetic moments minus NSF with the face gradient (mu from the moments)
+template <int D>
+__global__ void k_face_hot(const double *__restrict__ mom, const double *__restrict__ fld,
+                           const double *__restrict__ gfld, const double *__restrict__ mu, double *__restrict__ hotf,
+                           const MeshDev m, const double *__restrict__ fdvec, const Phys p)
+{
+    constexpr MomLayout L{D};
+    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= m.nf) return;
+    double *h = hotf + f * kNHot;
+    for (int i = 0; i < kNHot; ++i) h[i] = 0;
+    const int64_t c = m.f_L[f], j = m.f_R[f];
+    if (j < 0) return;
+    double g[D + 4][3], sig[3][3], q[4][3];
+    face_grad<D>(fld, gfld, c, j, fdvec + f * D, g);
+    constitutive<D>(0.5 * (mu[c] + mu[j]), g, nullptr, p, sig, q);
+    const double *Mc = mom + c * L.size(), *Mj = mom + j * L.size();
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int b = 0; b < D; ++b)
+            h[a * 3 + b] = 0.5 * (Mc[L.sig() + a * D + b] + Mj[L.sig() + a * D + b]) - sig[a][b];
+        h[9 + a] = 0.5 * (Mc[L.qt() + a] + Mj[L.qt() + a]) - q[0][a];
+        h[12 + a] = 0.5 * (Mc[L.qr() + a] + Mj[L.qr() + a]) - q[1][a];
+        h[15 + a] = 0.5 * (Mc[L.qv() + a] + Mj[L.qv() + a]) - q[2][a];
+        h[18 + a] = 0.5 * (Mc[L.qR() + a] + Mj[L.qR() + a]) - q[3][a];
+    }
+}
+
+// frozen boundary corrections: kinetic boundary flux minus the model flux at W0
+template <int D>
+__global__ void k_bcorr(const double *__restrict__ W0, const double *__restrict__ bflux, double *__restrict__ bcorr,
+                        const MeshDev m, const Phys p)
+{
+    constexpr int NW = D + 5;
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= m.nbf) return;
+    double F[NW], g1, g2;
+    bmodel_flux<D>(m, (int)b, W0 + (int64_t)m.bf_cell[b] * NW, p, F, &g1, &g2);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) bcorr[b * NW + i] = bflux[b * NW + i] - F[i];
+}
+
+// reference dissipation 0.5 lam* (W0_R - W0_L) along the face normal (first-order face states)
+template <int D>
+__global__ void k_dref(const double *__restrict__ W0, double *__restrict__ dref, const MeshDev m, const Phys p)
+{
+    constexpr int NW = D + 5;
+    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= m.nf) return;
+    const int64_t c = m.f_L[f], j = m.f_R[f];
+    for (int i = 0; i < NW; ++i) dref[f * NW + i] = 0;
+    if (j < 0) return;
+    const double *WL = W0 + c * NW, *WR = W0 + j * NW;
+    double n[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) n[a] = m.f_n[f * D + a];
+    Prim qL, qR;
+    prim_of<D>(WL, p, qL);
+    prim_of<D>(WR, p, qR);
+    double unL = 0, unR = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        unL += qL.u[a] * n[a];
+        unR += qR.u[a] * n[a];
+    }
+    const double lam = fmax(fabs(unL) + qL.cs, fabs(unR) + qR.cs);
+    for (int i = 0; i < NW - 1; ++i) dref[f * NW + i] = 0.5 * lam * (WR[i] - WL[i]);
+}
+
+// ------------------------------------------------------------------ inner-iteration kernels
+template <int D>
+__global__ void k_mprim(const double *__restrict__ W, double *__restrict__ P, double *__restrict__ fld,
+                        const int64_t nc, const Phys p, const int *__restrict__ flags)
+{
+    constexpr int NW = D + 5, NF = D + 4, NP = D + 8;
+    if (flags[0]) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    Prim q;
+    prim_of<D>(W + c * NW, p, q);
+    double *pc = P + c * NP;
+    pc[0] = q.rho;
+#pragma unroll
+    for (int a = 0; a < D; ++a) pc[1 + a] = q.u[a];
+    pc[D + 1] = q.Tt;
+    pc[D + 2] = q.Tr;
+    pc[D + 3] = q.Tv;
+    pc[D + 4] = q.eR;
+    pc[D + 5] = q.mu;
+    pc[D + 6] = q.cs;
+    pc[D + 7] = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) fld[c * NF + a] = q.u[a];
+    fld[c * NF + D] = q.Tt;
+    fld[c * NF + D + 1] = q.Tr;
+    fld[c * NF + D + 2] = q.Tv;
+    fld[c * NF + D + 3] = q.eR;
+}
+
+// residual, its norm contribution, diagonal and first increment of the U unknowns
+template <int D, int NFM>
+__global__ void k_mres(const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ fld,
+                       const double *__restrict__ gfld, const double *__restrict__ hotf,
+                       const double *__restrict__ bcorr, const double *__restrict__ dref, double *__restrict__ R,
+                       double *__restrict__ Dg, double *__restrict__ dU, double *__restrict__ resc, const MeshDev m,
+                       const Phys p, const double cfl_macro, const int *__restrict__ flags)
+{
+    constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2;
+    if (flags[0]) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= m.nc) return;
+    const double kR = (p.keff > 0) ? 1.0 / (3 * p.keff) : 0.0;
+    const double *Pc = P + c * NP;
+    const int nfc = m.nfc[c];
+    double acc[NW], gs = 0, gsR = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) acc[i] = 0;
+    for (int s = 0; s < nfc; ++s) {
+        const int j = m.nbr[c * NFM + s];
+        const double *mg = m.mgeo + (c * NFM + s) * MG;
+        const double S = mg[D];
+        double Ff[NW];
+        if (j < 0) {
+            const int bfi = -j - 1;
+            double g1, g2;
+            bmodel_flux<D>(m, bfi, W + c * NW, p, Ff, &g1, &g2);
+#pragma unroll
+            for (int i = 0; i < NW; ++i) Ff[i] += bcorr[(int64_t)bfi * NW + i];
+            gs += g1 * S;
+            gsR += g2 * S;
+        } else {
+            const int64_t fid = (int64_t)mg[2 * D + 1];
+            const double sg = (m.f_L[fid] == c) ? 1.0 : -1.0;
+            const double *n = mg;
+            rusanov<D>(W + c * NW, W + (int64_t)j * NW, n, p, Ff);
+#pragma unroll
+            for (int i = 0; i < NW; ++i) Ff[i] += sg * dref[fid * NW + i];
+            double g[D + 4][3], sig[3][3], q[4][3], Fv[NW], uf[3] = {0, 0, 0};
+            face_grad<D>(fld, gfld, c, j, mg + D + 1, g);
+            const double *Pj = P + (int64_t)j * NP;
+#pragma unroll
+            for (int a = 0; a < D; ++a) uf[a] = 0.5 * (Pc[1 + a] + Pj[1 + a]);
+            constitutive<D>(0.5 * (Pc[D + 5] + Pj[D + 5]), g, hotf + fid * kNHot, p, sig, q);
+            viscous_flux<D>(sig, q, uf, n, Fv);
+#pragma unroll
+            for (int i = 0; i < NW; ++i) Ff[i] += Fv[i];
+            double ufn = 0, nd = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                ufn += uf[a] * n[a];
+                nd += n[a] * mg[D + 1 + a];
+            }
+            nd = fabs(nd);
+            const double G = fabs(ufn) + 0.5 * (Pc[D + 6] + Pj[D + 6]) +
+                             2 * 0.5 * (Pc[D + 5] + Pj[D + 5]) / (0.5 * (Pc[0] + Pj[0]) * nd);
+            gs += G * S;
+            gsR += 2 * kR / nd * S;
+        }
+#pragma unroll
+        for (int i = 0; i < NW; ++i) acc[i] += Ff[i] * S;
+    }
+    const double rho = Pc[0], Tt = Pc[D + 1], Tr = Pc[D + 2], Tv = Pc[D + 3];
+    const double tau = Pc[D + 5] / (rho * Tt);
+    const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = (3 * Tt + p.d_v * Tv) / (3 + p.d_v);
+    const double etr = 0.5 * p.d_r * rho * Ttr, etv = 0.5 * p.d_v * rho * Ttv;
+    const double evR = 4 * p.sigma_R * Tv * Tv * Tv * Tv;
+    const double er = W[c * NW + D + 2], ev = W[c * NW + D + 3], eR = W[c * NW + D + 4];
+    double Q[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) Q[i] = 0;
+    Q[D + 2] = (etr - er) / (p.Z_r * tau);
+    Q[D + 3] = (etv - ev) / (p.Z_v * tau) - p.keff * (evR - eR);
+    Q[D + 4] = p.keff * (evR - eR);
+    const double V = m.vol[c];
+    double Rc[NW], rs = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        Rc[i] = -acc[i] / V + Q[i];
+        rs += Rc[i] * Rc[i];
+    }
+    resc[c] = V * rs;
+    double un = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) un += Pc[1 + a] * Pc[1 + a];
+    const double dt = cfl_macro * m.h[c] / (sqrt(un) + Pc[D + 6]);
+    const double jr = -3.0 / ((3 + p.d_r) * p.Z_r * tau) + 2 * (p.omega - 1) * (Ttr - Tr) / (3 * p.Z_r * tau * Tt);
+    const double jv = -3.0 / ((3 + p.d_v) * p.Z_v * tau) + 2 * (p.omega - 1) * (Ttv - Tv) / (3 * p.Z_v * tau * Tt) -
+                      p.keff * 16 * p.sigma_R * Tv * Tv * Tv * 2.0 / (p.d_v * rho);
+    double Dc[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) Dc[i] = 1.0 / dt + gs / V;
+    Dc[D + 2] -= jr;
+    Dc[D + 3] -= jv;
+    Dc[D + 4] = 1.0 / dt + gsR / V + p.keff;
+    Rc[D + 1] -= Rc[D + 4];
+    double d0[NW];
+    local_solve<D>(Rc, Dc, rho, Tv, p, d0);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        R[c * NW + i] = Rc[i];
+        Dg[c * NW + i] = Dc[i];
+        dU[c * NW + i] = d0[i];
+    }
+}
+
+// single-block deterministic reduction of resc; decides convergence of inner iteration `it`
+__global__ __launch_bounds__(1024) void k_mcheck(const double *__restrict__ resc, const int64_t nc, const int it,
+                                                 const double tol, double *__restrict__ scal, int *__restrict__ flags)
+{
+    if (flags[0]) return;
+    __shared__ double sh[1024];
+    double s = 0;
+    for (int64_t i = threadIdx.x; i < nc; i += 1024) s += resc[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double res = sqrt(sh[0]);
+        if (it == 0) scal[0] = res;
+        scal[1] = res;
+        if (res <= tol * scal[0]) {
+            flags[0] = 1;
+            flags[1] = it;
+        }
+    }
+}
+
+template <int D, int NFM>
+__global__ void k_msweep(const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ R,
+                         const double *__restrict__ Dg, const double *__restrict__ dUin, double *__restrict__ dUout,
+                         const MeshDev m, const Phys p, const int *__restrict__ flags)
+{
+    constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2;
+    if (flags[0]) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= m.nc) return;
+    const double kR = (p.keff > 0) ? 1.0 / (3 * p.keff) : 0.0;
+    const double *Pc = P + c * NP;
+    const int nfc = m.nfc[c];
+    double acc[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) acc[i] = 0;
+    for (int s = 0; s < nfc; ++s) {
+        const int j = m.nbr[c * NFM + s];
+        if (j < 0) continue;
+        const double *mg = m.mgeo + (c * NFM + s) * MG;
+        const double *n = mg;
+        const double S = mg[D];
+        const double *Pj = P + (int64_t)j * NP;
+        double ufn = 0, nd = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            ufn += 0.5 * (Pc[1 + a] + Pj[1 + a]) * n[a];
+            nd += n[a] * mg[D + 1 + a];
+        }
+        nd = fabs(nd);
+        const double G = fabs(ufn) + 0.5 * (Pc[D + 6] + Pj[D + 6]) +
+                         2 * 0.5 * (Pc[D + 5] + Pj[D + 5]) / (0.5 * (Pc[0] + Pj[0]) * nd);
+        const double GR = 2 * kR / nd;
+        double Wn[NW], F1[NW], F0[NW];
+        const double *Wj = W + (int64_t)j * NW;
+        const double *dj = dUin + (int64_t)j * NW;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) Wn[i] = Wj[i] + dj[i];
+        Wn[D + 1] += dj[D + 4];
+        euler_flux<D>(Wn, n, p, F1);
+        euler_flux<D>(Wj, n, p, F0);
+#pragma unroll
+        for (int i = 0; i < NW - 1; ++i) acc[i] += (F1[i] - F0[i] - G * dj[i]) * S;
+        acc[NW - 1] += (-GR * dj[NW - 1]) * S;
+    }
+    const double V = m.vol[c];
+    double rhs[NW], Dc[NW], d1[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        rhs[i] = R[c * NW + i] - acc[i] / (2 * V);
+        Dc[i] = Dg[c * NW + i];
+    }
+    local_solve<D>(rhs, Dc, Pc[0], Pc[D + 3], p, d1);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) dUout[c * NW + i] = d1[i];
+}
+
+template <int D>
+__global__ void k_mupdate(double *__restrict__ W, const double *__restrict__ dU, const int64_t nc, const Phys p,
+                          const int *__restrict__ flags)
+{
+    constexpr int NW = D + 5;
+    if (flags[0]) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double Wc[NW], d[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        Wc[i] = W[c * NW + i];
+        d[i] = dU[c * NW + i];
+    }
+    positive_update<D>(Wc, d, p);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) W[c * NW + i] = Wc[i];
+}
+
+// out[c] = V_c * x[c * stride]
+__global__ void k_mass_terms(const double *__restrict__ x, const int stride, const double *__restrict__ vol,
+                             double *__restrict__ out, const int64_t nc)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    out[c] = vol[c] * x[c * stride];
+}
+
+template <int D>
+__global__ void k_mass_scale(double *__restrict__ W, const double *__restrict__ msum, const double *__restrict__ target,
+                             const int64_t nc)
+{
+    constexpr int NW = D + 5;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double sc = target[0] / msum[0];
+    for (int i = 0; i < NW - 1; ++i) W[c * NW + i] *= sc;
+    W[c * NW + D + 1] -= (sc - 1.0) * W[c * NW + D + 4];
+}
+
+__global__ __launch_bounds__(1024) void k_block_sum(const double *__restrict__ in, const int64_t n, const int k,
+                                                    double *__restrict__ out)
+{
+    __shared__ double sh[1024];
+    for (int comp = 0; comp < k; ++comp) {
+        double s = 0;
+        for (int64_t i = threadIdx.x; i < n; i += 1024) s += in[i * k + comp];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = 512; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[comp] = sh[0];
+        __syncthreads();
+    }
+}
+
+void launch_block_sum(const double *in, int64_t n, int k, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_block_sum, dim3(1), dim3(1024), 0, st, in, n, k, out);
+}
+
+// ------------------------------------------------------------------ driver of one macro solve
+template <int D, int NFM>
+int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &o, const double *mom,
+                const double *bflux, const double *mom_mass, hipStream_t st)
+{
+    const int64_t nc = m.nc;
+    const dim3 gc((nc + 255) / 256), gf((m.nf + 255) / 256), gb((m.nbf + 255) / 256), blk(256);
+    (void)hipMemsetAsync(B.flags, 0, 2 * sizeof(int), st);
+    hipLaunchKernelGGL(k_W_from_mom<D>, gc, blk, 0, st, mom, B.W, B.W0, nc, p);
+    // face HoTs from the kinetic moments (mu kept in P[0..nc))
+    hipLaunchKernelGGL(k_fld_from_mom<D>, gc, blk, 0, st, mom, B.fld, B.P, nc, p);
+    hipLaunchKernelGGL((k_cell_grad<D, NFM>), gc, blk, 0, st, B.fld, B.gfld, m, nullptr);
+    hipLaunchKernelGGL(k_face_hot<D>, gf, blk, 0, st, mom, B.fld, B.gfld, B.P, B.hotf, m, m.f_d, p);
+    if (m.nbf > 0) hipLaunchKernelGGL(k_bcorr<D>, gb, blk, 0, st, B.W0, bflux, B.bcorr, m, p);
+    hipLaunchKernelGGL(k_dref<D>, gf, blk, 0, st, B.W0, B.dref, m, p);
+    const int poll = 8;
+    int host_flags[2] = {0, 0};
+    int it = 0;
+    for (it = 0; it < o.max_inner; ++it) {
+        hipLaunchKernelGGL(k_mprim<D>, gc, blk, 0, st, B.W, B.P, B.fld, nc, p, B.flags);
+        hipLaunchKernelGGL((k_cell_grad<D, NFM>), gc, blk, 0, st, B.fld, B.gfld, m, B.flags);
+        hipLaunchKernelGGL((k_mres<D, NFM>), gc, blk, 0, st, B.W, B.P, B.fld, B.gfld, B.hotf, B.bcorr, B.dref, B.R,
+                           B.Dg, B.dU0, B.resc, m, p, o.cfl_macro, B.flags);
+        hipLaunchKernelGGL(k_mcheck, dim3(1), dim3(1024), 0, st, B.resc, nc, it, o.inner_tol, B.scal, B.flags);
+        double *din = B.dU0, *dout = B.dU1;
+        for (int s = 0; s < o.n_sweeps; ++s) {
+            hipLaunchKernelGGL((k_msweep<D, NFM>), gc, blk, 0, st, B.W, B.P, B.R, B.Dg, din, dout, m, p, B.flags);
+            std::swap(din, dout);
+        }
+        hipLaunchKernelGGL(k_mupdate<D>, gc, blk, 0, st, B.W, din, nc, p, B.flags);
+        if ((it + 1) % poll == 0) {
+            (void)hipMemcpyAsync(host_flags, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+            (void)hipStreamSynchronize(st);
+            if (host_flags[0]) break;
+        }
+    }
+    (void)hipMemcpyAsync(host_flags, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    const int count = host_flags[0] ? host_flags[1] : o.max_inner;
+    if (m.closed) {
+        // reading: closed domains keep the mass of mom_mass (the state the outer iteration started from)
+        constexpr MomLayout L{D};
+        hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, mom_mass, L.size(), m.vol, B.resc, nc);
+        launch_block_sum(B.resc, nc, 1, B.scal + 3, st);
+        hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, B.W, D + 5, m.vol, B.resc, nc);
+        launch_block_sum(B.resc, nc, 1, B.scal + 2, st);
+        hipLaunchKernelGGL(k_mass_scale<D>, gc, blk, 0, st, B.W, B.scal + 2, B.scal + 3, nc);
+    }
+    return count;
+}
+
+// ------------------------------------------------------------------ sync parameters and residual epsilon
+template <int D>
+__global__ void k_sync_params(const double *__restrict__ mom, const double *__restrict__ W, double *__restrict__ sp,
+                              const int64_t nc, const Phys p, const int from_W)
+{
+    constexpr MomLayout L{D};
+    constexpr int NS = D + 5, NW = D + 5;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double *M = mom + c * L.size();
+    double *s0 = sp + c * 2 * NS, *s1 = s0 + NS;
+    s0[0] = M[L.rho()];
+    for (int a = 0; a < D; ++a) s0[1 + a] = M[L.u() + a];
+    s0[D + 1] = M[L.Tt()];
+    s0[D + 2] = M[L.Tr()];
+    s0[D + 3] = M[L.Tv()];
+    s0[D + 4] = M[L.eR()];
+    if (from_W) {
+        Prim q;
+        prim_of<D>(W + c * NW, p, q);
+        s1[0] = q.rho;
+        for (int a = 0; a < D; ++a) s1[1 + a] = q.u[a];
+        s1[D + 1] = q.Tt;
+        s1[D + 2] = q.Tr;
+        s1[D + 3] = q.Tv;
+        s1[D + 4] = q.eR;
+    }
+}
+
+template <int D>
+void launch_sync_params(const double *mom, const double *W, double *sp, int64_t nc, const Phys &p, int from_W,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sync_params<D>, dim3((nc + 255) / 256), dim3(256), 0, st, mom, W, sp, nc, p, from_W);
+}
+
+template <int D>
+__global__ void k_resid_terms(const double *__restrict__ m1, const double *__restrict__ m0,
+                              const double *__restrict__ vol, double *__restrict__ out, const int64_t nc, const Phys p)
+{
+    constexpr MomLayout L{D};
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double *A = m1 + c * L.size(), *B = m0 + c * L.size();
+    const double V = vol[c];
+    double *o = out + c * 7;
+    o[0] = V * (A[L.rho()] - B[L.rho()]) * (A[L.rho()] - B[L.rho()]);
+    o[1] = V * B[L.rho()] * B[L.rho()];
+    double nu = 0, du = 0;
+    for (int a = 0; a < D; ++a) {
+        nu += (A[L.u() + a] - B[L.u() + a]) * (A[L.u() + a] - B[L.u() + a]);
+        du += B[L.u() + a] * B[L.u() + a];
+    }
+    o[2] = V * nu;
+    o[3] = V * du;
+    const double s = 3 + p.d_r + p.d_v;
+    const double Tn = (3 * A[L.Tt()] + p.d_r * A[L.Tr()] + p.d_v * A[L.Tv()]) / s;
+    const double To = (3 * B[L.Tt()] + p.d_r * B[L.Tr()] + p.d_v * B[L.Tv()]) / s;
+    o[4] = V * (Tn - To) * (Tn - To);
+    o[5] = V * To * To;
+    o[6] = V;
+}
+
+template <int D>
+void launch_residual(const double *mom1, const double *mom0, const double *vol, double *cellbuf, double *out7,
+                     int64_t nc, const Phys &p, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_resid_terms<D>, dim3((nc + 255) / 256), dim3(256), 0, st, mom1, mom0, vol, cellbuf, nc, p);
+    launch_block_sum(cellbuf, nc, 7, out7, st);
+}
+
+#define GSIS_INST_M(D, NFM)                                                                                      \
+    template int macro_solve<D, NFM>(MacroBufs &, const MeshDev &, const Phys &, const MacroOpts &, const double *, \
+                                     const double *, const double *, hipStream_t);
+GSIS_INST_M(1, 2)
+GSIS_INST_M(2, 3)
+GSIS_INST_M(2, 4)
+GSIS_INST_M(3, 4)
+GSIS_INST_M(3, 6)
+template void launch_sync_params<1>(const double *, const double *, double *, int64_t, const Phys &, int, hipStream_t);
+template void launch_sync_params<2>(const double *, const double *, double *, int64_t, const Phys &, int, hipStream_t);
+template void launch_sync_params<3>(const double *, const double *, double *, int64_t, const Phys &, int, hipStream_t);
+template void launch_residual<1>(const double *, const double *, const double *, double *, double *, int64_t,
+                                 const Phys &, hipStream_t);
+template void launch_residual<2>(const double *, const double *, const double *, double *, double *, int64_t,
+                                 const Phys &, hipStream_t);
+template void launch_residual<3>(const double *, const double *, const double *, double *, double *, int64_t,
+                                 const Phys &, hipStream_t);
+
+}  // namespace gsis

@@ -76,8 +76,8 @@ typedef struct {
 } gsis_flow;
 
 /* Iteration options.  Defaults (gsis_default_opts): GSIS, FP32, tol 1e-6, max_outer 1000,
- * n_precond 10, cfl_meso 1e5, cfl_v 5, kin_sweeps 4, kin_omega 1, limiter_K 1, second_order 1,
- * cfl_macro 1e3, inner_tol 1e-7, max_inner 500, n_sweeps 2. */
+ * n_precond 10, cfl_meso 1e5, cfl_v 5, kin_sweeps 8, kin_omega 1, limiter_K 5, second_order 1,
+ * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2. */
 typedef struct {
     int32_t scheme;       /* GSIS_CIS or GSIS_GSIS */
     int32_t precision;    /* GSIS_FP64 or GSIS_FP32: storage and arithmetic of f and I */

@@ -18,8 +18,8 @@ from .build import LIB, build
 _lib = None
 
 # option vector layout of orc_create
-DEFAULT_OPTS = dict(cfl_meso=1e5, cfl_macro=1e3, limiter_K=1.0, inner_tol=1e-7, max_inner=500, n_sweeps=2,
-                    second_order=1, cfl_v=5.0, kin_sweeps=4, kin_omega=1.0, diss_ref=1, macro_order2=0)
+DEFAULT_OPTS = dict(cfl_meso=1e5, cfl_macro=1e3, limiter_K=5.0, inner_tol=1e-7, max_inner=100, n_sweeps=2,
+                    second_order=1, cfl_v=5.0, kin_sweeps=8, kin_omega=1.0, diss_ref=1, macro_order2=0)
 
 
 def _load():

@@ -141,6 +141,7 @@ static void compute_phys(gsis_t *h)
 static void free_mesh(MeshDev &m)
 {
     dfree(m.nbr);
+    dfree(m.sfid);
     dfree(m.geo);
     dfree(m.mgeo);
     dfree(m.vol);
@@ -329,7 +330,10 @@ static int32_t build_mesh(gsis_t *h)
     m.nbcells = (int64_t)bcells.size();
     m.nbc = (int)hm.bcs.size();
     m.closed = closed;
-    bool ok = upload(m.nbr, nbr) && upload(m.geo, geo) && upload(m.mgeo, mgeo) && upload(m.vol, hm.vol) &&
+    std::vector<int> sfid(nc * NFM, 0);
+    for (int64_t k = 0; k < nc * NFM; ++k)
+        if (fid[k] >= 0) sfid[k] = (sgn[k] > 0) ? fid[k] : -(1 + fid[k]);
+    bool ok = upload(m.nbr, nbr) && upload(m.sfid, sfid) && upload(m.geo, geo) && upload(m.mgeo, mgeo) && upload(m.vol, hm.vol) &&
               upload(m.h, hh) && upload(m.eps2, eps2) && upload(m.nfc, nfc) && upload(m.bf_face, bf_face) &&
               upload(m.bf_cell, bf_cell) && upload(m.bf_tag, bf_tag) && upload(m.bf_n, bf_n) &&
               upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.f_L, fL) && upload(m.f_R, fR) &&
@@ -372,6 +376,12 @@ static void free_macro(MacroBufs &B)
     dfree(B.W0);
     dfree(B.P);
     dfree(B.fld);
+    dfree(B.W2);
+    dfree(B.P2);
+    dfree(B.fld2);
+    dfree(B.Ff);
+    dfree(B.Gf);
+    dfree(B.part);
     dfree(B.gfld);
     dfree(B.R);
     dfree(B.Dg);
@@ -440,6 +450,12 @@ static bool alloc_macro(gsis_t *h)
     B.W0 = dalloc<double>(nc * NW, ok);
     B.P = dalloc<double>(nc * (D + 8), ok);
     B.fld = dalloc<double>(nc * (D + 4), ok);
+    B.W2 = dalloc<double>(nc * NW, ok);
+    B.P2 = dalloc<double>(nc * (D + 8), ok);
+    B.fld2 = dalloc<double>(nc * (D + 4), ok);
+    B.Ff = dalloc<double>(nf * NW, ok);
+    B.Gf = dalloc<double>(nf * 2, ok);
+    B.part = dalloc<double>((nc + kMBlk - 1) / kMBlk + 1, ok);
     B.gfld = dalloc<double>(nc * (D + 4) * D, ok);
     B.R = dalloc<double>(nc * NW, ok);
     B.Dg = dalloc<double>(nc * NW, ok);
@@ -459,6 +475,7 @@ static bool alloc_macro(gsis_t *h)
     h->cellbuf = dalloc<double>(nc * 7, ok);
     h->red = dalloc<double>(16, ok);
     if (ok) {
+        (void)hipMemset(B.flags, 0, 4 * sizeof(int));
         (void)hipMemset(h->mom0, 0, nc * L.size() * sizeof(double));
         (void)hipMemset(h->mom1, 0, nc * L.size() * sizeof(double));
         (void)hipMemset(h->momh, 0, nc * L.size() * sizeof(double));
@@ -712,13 +729,13 @@ void gsis_default_opts(gsis_opts *o)
     o->n_precond = 10;
     o->cfl_meso = 1e5;
     o->cfl_v = 5.0;
-    o->kin_sweeps = 4;
+    o->kin_sweeps = 8;
     o->kin_omega = 1.0;
-    o->limiter_K = 1.0;
+    o->limiter_K = 5.0;
     o->second_order = 1;
     o->cfl_macro = 1e3;
     o->inner_tol = 1e-7;
-    o->max_inner = 500;
+    o->max_inner = 100;
     o->n_sweeps = 2;
 }
 

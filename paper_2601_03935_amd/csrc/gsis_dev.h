@@ -62,6 +62,7 @@ struct MeshDev {
     int D = 0, NFM = 0;
     int64_t nc = 0, nf = 0, nbf = 0;
     int *nbr = nullptr;
+    int *sfid = nullptr;  // per slot: face id if the cell is the face's left cell, -(1 + face id) otherwise
     double *geo = nullptr;
     double *mgeo = nullptr;
     double *vol = nullptr, *h = nullptr, *eps2 = nullptr;

@@ -20,10 +20,13 @@ struct KinBufs {
 // Device buffers of the synthetic-equation solver (FP64).
 struct MacroBufs {
     double *W = nullptr, *W0 = nullptr, *P = nullptr, *fld = nullptr, *gfld = nullptr;
+    double *W2 = nullptr, *P2 = nullptr, *fld2 = nullptr;  // second state of the inner-iteration ping-pong
     double *R = nullptr, *Dg = nullptr, *dU0 = nullptr, *dU1 = nullptr;
     double *hotf = nullptr, *bcorr = nullptr, *dref = nullptr;
+    double *Ff = nullptr, *Gf = nullptr;      // per interior face: flux (left to right), spectral radii
+    double *part = nullptr;                   // per-block partial sums of the residual norm
     double *resc = nullptr, *scal = nullptr;  // per-cell scratch, device scalars (res0, mass, ...)
-    int *flags = nullptr;                     // [0] done, [1] inner count
+    int *flags = nullptr;                     // [0] done, [1] inner count, [2] block arrival counter
 };
 
 // Optional per-kernel timing with HIP events on the launch stream.  Kinds (see gsis.h GSIS_K_*):
@@ -93,6 +96,8 @@ struct Prof {
         pool.clear();
     }
 };
+
+constexpr int kMBlk = 64;  // threads per block of the per-cell inner-iteration kernels (one wave)
 
 struct MacroOpts {
     double cfl_macro, inner_tol;

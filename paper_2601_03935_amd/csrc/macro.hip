@@ -16,8 +16,13 @@ struct Prim {
     double rho, u[3], Tt, Tr, Tv, eR, mu, cs;
 };
 
+// density, velocity and translational temperature of a conserved state
+struct PrimL {
+    double rho, u[3], Tt;
+};
+
 template <int D>
-__device__ __forceinline__ void prim_of(const double *W, const Phys &p, Prim &q)
+__device__ __forceinline__ void prim_lite(const double *W, PrimL &q)
 {
     q.rho = W[0];
     double ek = 0;
@@ -28,6 +33,18 @@ __device__ __forceinline__ void prim_of(const double *W, const Phys &p, Prim &q)
         ek += 0.5 * W[0] * q.u[a] * q.u[a];
     }
     q.Tt = 2.0 / (3.0 * W[0]) * (W[D + 1] - ek - W[D + 2] - W[D + 3] - W[D + 4]);
+}
+
+template <int D>
+__device__ __forceinline__ void prim_of(const double *W, const Phys &p, Prim &q)
+{
+    PrimL l;
+    prim_lite<D>(W, l);
+    q.rho = l.rho;
+    q.u[0] = l.u[0];
+    q.u[1] = l.u[1];
+    q.u[2] = l.u[2];
+    q.Tt = l.Tt;
     q.Tr = 2.0 * W[D + 2] / (p.d_r * W[0]);
     q.Tv = 2.0 * W[D + 3] / (p.d_v * W[0]);
     q.eR = W[D + 4];
@@ -35,11 +52,21 @@ __device__ __forceinline__ void prim_of(const double *W, const Phys &p, Prim &q)
     q.cs = sqrt(5.0 / 3.0 * q.Tt);
 }
 
+// primitive record of a cell: rho, u[D], Tt, Tr, Tv, eR, mu, cs, (pad)
 template <int D>
-__device__ __forceinline__ void euler_flux(const double *W, const double *n, const Phys &p, double *F)
+__device__ __forceinline__ void prim_load(const double *Pc, PrimL &q)
 {
-    Prim q;
-    prim_of<D>(W, p, q);
+    q.rho = Pc[0];
+    q.u[0] = q.u[1] = q.u[2] = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) q.u[a] = Pc[1 + a];
+    q.Tt = Pc[D + 1];
+}
+
+// Euler part of the synthetic-equation flux along n (the radiation energy is not convected)
+template <int D>
+__device__ __forceinline__ void euler_flux_q(const double *W, const PrimL &q, const double *n, double *F)
+{
     double un = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) un += q.u[a] * n[a];
@@ -54,27 +81,43 @@ __device__ __forceinline__ void euler_flux(const double *W, const double *n, con
 }
 
 template <int D>
-__device__ __forceinline__ double rusanov(const double *WL, const double *WR, const double *n, const Phys &p,
-                                          double *F)
+__device__ __forceinline__ void euler_flux(const double *W, const double *n, double *F)
+{
+    PrimL q;
+    prim_lite<D>(W, q);
+    euler_flux_q<D>(W, q, n, F);
+}
+
+// Rusanov flux from left/right conserved states, their primitives and sound speeds; exactly odd under
+// the exchange of the two sides together with n -> -n
+template <int D>
+__device__ __forceinline__ double rusanov_q(const double *WL, const PrimL &qL, double csL, const double *WR,
+                                            const PrimL &qR, double csR, const double *n, double *F)
 {
     constexpr int NW = D + 5;
     double FL[NW], FR[NW];
-    euler_flux<D>(WL, n, p, FL);
-    euler_flux<D>(WR, n, p, FR);
-    Prim qL, qR;
-    prim_of<D>(WL, p, qL);
-    prim_of<D>(WR, p, qR);
+    euler_flux_q<D>(WL, qL, n, FL);
+    euler_flux_q<D>(WR, qR, n, FR);
     double unL = 0, unR = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         unL += qL.u[a] * n[a];
         unR += qR.u[a] * n[a];
     }
-    const double lam = fmax(fabs(unL) + qL.cs, fabs(unR) + qR.cs);
+    const double lam = fmax(fabs(unL) + csL, fabs(unR) + csR);
 #pragma unroll
     for (int i = 0; i < NW - 1; ++i) F[i] = 0.5 * (FL[i] + FR[i]) - 0.5 * lam * (WR[i] - WL[i]);
     F[NW - 1] = 0.0;
     return lam;
+}
+
+template <int D>
+__device__ __forceinline__ double rusanov(const double *WL, const double *WR, const double *n, double *F)
+{
+    PrimL qL, qR;
+    prim_lite<D>(WL, qL);
+    prim_lite<D>(WR, qR);
+    return rusanov_q<D>(WL, qL, sqrt(5.0 / 3.0 * qL.Tt), WR, qR, sqrt(5.0 / 3.0 * qR.Tt), n, F);
 }
 
 template <int D>
@@ -200,7 +243,7 @@ __device__ __forceinline__ void bmodel_flux(const MeshDev &m, int bfi, const dou
     } else {
         double Wb[NW];
         W_of_state<D>(bc.rho, bc.u, Tb, p, Wb);
-        rusanov<D>(Wc, Wb, n, p, F);
+        rusanov<D>(Wc, Wb, n, F);
         F[D + 1] += qRn;
         F[D + 4] = qRn;
     }
@@ -227,19 +270,19 @@ __device__ __forceinline__ void local_solve(const double *rhs, const double *Dg,
 
 // W += a dU with a = 2^-m the largest factor (m <= 20) keeping rho, T_t, e_r, e_v, e_R at least half
 template <int D>
-__device__ __forceinline__ void positive_update(double *W, const double *dU, const Phys &p)
+__device__ __forceinline__ void positive_update(double *W, const double *dU)
 {
     constexpr int NW = D + 5;
-    Prim p0;
-    prim_of<D>(W, p, p0);
+    PrimL p0;
+    prim_lite<D>(W, p0);
     double a = 1.0;
     for (int m = 0; m <= 20; ++m, a *= 0.5) {
         double Wn[NW];
 #pragma unroll
         for (int i = 0; i < NW; ++i) Wn[i] = W[i] + a * dU[i];
         Wn[D + 1] += a * dU[D + 4];
-        Prim p1;
-        prim_of<D>(Wn, p, p1);
+        PrimL p1;
+        prim_lite<D>(Wn, p1);
         if (Wn[0] >= 0.5 * W[0] && p1.Tt >= 0.5 * p0.Tt && Wn[D + 2] >= 0.5 * W[D + 2] &&
             Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4]) {
 #pragma unroll
@@ -298,23 +341,20 @@ __global__ void k_fld_from_mom(const double *__restrict__ mom, double *__restric
     P[c] = sqrt(2.0 / kPi) * p.Kn * pow(M[L.Tt()], p.omega);  // mu
 }
 
-// unlimited least-squares gradients of the NF fields (zero-gradient ghosts on boundary faces)
+// unlimited least-squares gradient of the NF fields of cell c (zero-gradient ghosts on boundary faces)
 template <int D, int NFM>
-__global__ void k_cell_grad(const double *__restrict__ fld, double *__restrict__ gfld, const MeshDev m,
-                            const int *__restrict__ flags)
+__device__ __forceinline__ void cell_grad(const double *__restrict__ fld, const MeshDev &m, const int64_t c,
+                                          double g[][D])
 {
     constexpr int NF = D + 4;
-    if (flags && flags[0]) return;
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= m.nc) return;
-    const int nfc = m.nfc[c];
-    double g[NF][D];
 #pragma unroll
     for (int i = 0; i < NF; ++i)
 #pragma unroll
         for (int a = 0; a < D; ++a) g[i][a] = 0;
-    for (int s = 0; s < nfc; ++s) {
-        const int j = m.nbr[c * NFM + s];
+    const int nfc = m.nfc[c];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        const int j = (s < nfc) ? m.nbr[c * NFM + s] : -1;
         if (j < 0) continue;
         const double *gs = m.geo + (c * NFM + s) * 4 * D + 3 * D;
 #pragma unroll
@@ -324,17 +364,27 @@ __global__ void k_cell_grad(const double *__restrict__ fld, double *__restrict__
             for (int a = 0; a < D; ++a) g[i][a] += gs[a] * df;
         }
     }
+}
+
+template <int D, int NFM>
+__global__ void k_cell_grad(const double *__restrict__ fld, double *__restrict__ gfld, const MeshDev m)
+{
+    constexpr int NF = D + 4;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= m.nc) return;
+    double g[NF][D];
+    cell_grad<D, NFM>(fld, m, c, g);
 #pragma unroll
     for (int i = 0; i < NF; ++i)
 #pragma unroll
         for (int a = 0; a < D; ++a) gfld[(c * NF + i) * D + a] = g[i][a];
 }
 
-// face gradient: mean of the cell gradients with the component along the centroid line replaced by the
-// centroid difference quotient
+// face gradient: mean of the two cell gradients with the component along the centroid line replaced by
+// the centroid difference quotient (dvec = x_j - x_c)
 template <int D>
-__device__ __forceinline__ void face_grad(const double *fld, const double *gfld, int64_t c, int64_t j,
-                                          const double *dvec, double g[][3])
+__device__ __forceinline__ void face_grad_g(const double *fld, const double gc[][D], const double gj[][D],
+                                            int64_t c, int64_t j, const double *dvec, double g[][3])
 {
     constexpr int NF = D + 4;
     double dl = 0, dh[D];
@@ -348,13 +398,29 @@ __device__ __forceinline__ void face_grad(const double *fld, const double *gfld,
         double avg[D], corr = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            avg[a] = 0.5 * (gfld[(c * NF + i) * D + a] + gfld[(j * NF + i) * D + a]);
+            avg[a] = 0.5 * (gc[i][a] + gj[i][a]);
             corr += avg[a] * dh[a];
         }
         const double jump = (fld[j * NF + i] - fld[c * NF + i]) / dl;
 #pragma unroll
         for (int a = 0; a < 3; ++a) g[i][a] = (a < D) ? avg[a] + (jump - corr) * dh[a] : 0.0;
     }
+}
+
+template <int D>
+__device__ __forceinline__ void face_grad(const double *fld, const double *gfld, int64_t c, int64_t j,
+                                          const double *dvec, double g[][3])
+{
+    constexpr int NF = D + 4;
+    double gc[NF][D], gj[NF][D];
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            gc[i][a] = gfld[(c * NF + i) * D + a];
+            gj[i][a] = gfld[(j * NF + i) * D + a];
+        }
+    face_grad_g<D>(fld, gc, gj, c, j, dvec, g);
 }
 
 // face HoTs on interior faces: mean kinetic moments minus NSF with the face gradient (mu from the moments)
@@ -428,17 +494,13 @@ __global__ void k_dref(const double *__restrict__ W0, double *__restrict__ dref,
 }
 
 // ------------------------------------------------------------------ inner-iteration kernels
+
+// primitive record and gradient fields of W
 template <int D>
-__global__ void k_mprim(const double *__restrict__ W, double *__restrict__ P, double *__restrict__ fld,
-                        const int64_t nc, const Phys p, const int *__restrict__ flags)
+__device__ __forceinline__ void store_prim(const double *Wc, const Phys &p, double *pc, double *fc)
 {
-    constexpr int NW = D + 5, NF = D + 4, NP = D + 8;
-    if (flags[0]) return;
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= nc) return;
     Prim q;
-    prim_of<D>(W + c * NW, p, q);
-    double *pc = P + c * NP;
+    prim_of<D>(Wc, p, q);
     pc[0] = q.rho;
 #pragma unroll
     for (int a = 0; a < D; ++a) pc[1 + a] = q.u[a];
@@ -450,184 +512,254 @@ __global__ void k_mprim(const double *__restrict__ W, double *__restrict__ P, do
     pc[D + 6] = q.cs;
     pc[D + 7] = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) fld[c * NF + a] = q.u[a];
-    fld[c * NF + D] = q.Tt;
-    fld[c * NF + D + 1] = q.Tr;
-    fld[c * NF + D + 2] = q.Tv;
-    fld[c * NF + D + 3] = q.eR;
+    for (int a = 0; a < D; ++a) fc[a] = q.u[a];
+    fc[D] = q.Tt;
+    fc[D + 1] = q.Tr;
+    fc[D + 2] = q.Tv;
+    fc[D + 3] = q.eR;
 }
 
-// residual, its norm contribution, diagonal and first increment of the U unknowns
+template <int D>
+__global__ void k_mprim(const double *__restrict__ W, double *__restrict__ P, double *__restrict__ fld,
+                        const int64_t nc, const Phys p)
+{
+    constexpr int NW = D + 5, NF = D + 4, NP = D + 8;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    store_prim<D>(W + c * NW, p, P + c * NP, fld + c * NF);
+}
+
+// interior-face fluxes (orientation left -> right): Rusanov with the reference dissipation, NSF viscous
+// flux with the face gradient plus the frozen face HoTs; spectral radii of the convective-viscous and
+// radiative-diffusion operators for the diagonal.  Each face is evaluated once; the right cell uses the
+// negated flux (the discrete flux is exactly odd under the exchange of sides).
 template <int D, int NFM>
-__global__ void k_mres(const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ fld,
-                       const double *__restrict__ gfld, const double *__restrict__ hotf,
-                       const double *__restrict__ bcorr, const double *__restrict__ dref, double *__restrict__ R,
-                       double *__restrict__ Dg, double *__restrict__ dU, double *__restrict__ resc, const MeshDev m,
-                       const Phys p, const double cfl_macro, const int *__restrict__ flags)
+__global__ __launch_bounds__(kMBlk) void k_mface(const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ fld,
+                        const double *__restrict__ hotf, const double *__restrict__ dref, double *__restrict__ Ff,
+                        double *__restrict__ Gf, const MeshDev m, const Phys p, const int *__restrict__ flags)
+{
+    constexpr int NW = D + 5, NP = D + 8, NF = D + 4;
+    if (flags[0]) return;
+    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= m.nf) return;
+    const int64_t c = m.f_L[f], j = m.f_R[f];
+    if (j < 0) return;
+    const double kR = (p.keff > 0) ? 1.0 / (3 * p.keff) : 0.0;
+    double n[D], dvec[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        n[a] = m.f_n[f * D + a];
+        dvec[a] = m.f_d[f * D + a];
+    }
+    const double *Pc = P + c * NP, *Pj = P + j * NP;
+    PrimL qc, qj;
+    prim_load<D>(Pc, qc);
+    prim_load<D>(Pj, qj);
+    double Fc[NW];
+    rusanov_q<D>(W + c * NW, qc, Pc[D + 6], W + j * NW, qj, Pj[D + 6], n, Fc);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) Fc[i] += dref[f * NW + i];
+    double gc[NF][D], gj[NF][D], g[NF][3], sig[3][3], q[4][3], Fv[NW], uf[3] = {0, 0, 0};
+    cell_grad<D, NFM>(fld, m, c, gc);
+    cell_grad<D, NFM>(fld, m, j, gj);
+    face_grad_g<D>(fld, gc, gj, c, j, dvec, g);
+#pragma unroll
+    for (int a = 0; a < D; ++a) uf[a] = 0.5 * (Pc[1 + a] + Pj[1 + a]);
+    constitutive<D>(0.5 * (Pc[D + 5] + Pj[D + 5]), g, hotf + f * kNHot, p, sig, q);
+    viscous_flux<D>(sig, q, uf, n, Fv);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) Ff[f * NW + i] = Fc[i] + Fv[i];
+    double ufn = 0, nd = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        ufn += uf[a] * n[a];
+        nd += n[a] * dvec[a];
+    }
+    nd = fabs(nd);
+    Gf[f * 2] = fabs(ufn) + 0.5 * (Pc[D + 6] + Pj[D + 6]) +
+                2 * 0.5 * (Pc[D + 5] + Pj[D + 5]) / (0.5 * (Pc[0] + Pj[0]) * nd);
+    Gf[f * 2 + 1] = 2 * kR / nd;
+}
+
+// Per cell: residual R_i = -(1/V) sum_f F S + Q (face fluxes gathered in slot order, boundary model
+// fluxes plus the frozen kinetic corrections), the diagonal D_i and the first increment of the U
+// unknowns, and the per-block sums of the volume-weighted squared residual.
+template <int D, int NFM>
+__global__ __launch_bounds__(kMBlk) void k_mgather(
+    const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ bcorr,
+    const double *__restrict__ Ff, const double *__restrict__ Gf, double *__restrict__ R, double *__restrict__ Dg,
+    double *__restrict__ dU, double *__restrict__ part, const int *__restrict__ flags, const MeshDev m,
+    const Phys p, const double cfl_macro)
 {
     constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2;
     if (flags[0]) return;
+    __shared__ double sh[kMBlk];
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= m.nc) return;
-    const double kR = (p.keff > 0) ? 1.0 / (3 * p.keff) : 0.0;
-    const double *Pc = P + c * NP;
-    const int nfc = m.nfc[c];
-    double acc[NW], gs = 0, gsR = 0;
+    double contrib = 0;
+    if (c < m.nc) {
+        const double *Pc = P + c * NP;
+        const int nfc = m.nfc[c];
+        double acc[NW], gs = 0, gsR = 0;
 #pragma unroll
-    for (int i = 0; i < NW; ++i) acc[i] = 0;
-    for (int s = 0; s < nfc; ++s) {
-        const int j = m.nbr[c * NFM + s];
-        const double *mg = m.mgeo + (c * NFM + s) * MG;
-        const double S = mg[D];
-        double Ff[NW];
-        if (j < 0) {
-            const int bfi = -j - 1;
-            double g1, g2;
-            bmodel_flux<D>(m, bfi, W + c * NW, p, Ff, &g1, &g2);
+        for (int i = 0; i < NW; ++i) acc[i] = 0;
 #pragma unroll
-            for (int i = 0; i < NW; ++i) Ff[i] += bcorr[(int64_t)bfi * NW + i];
-            gs += g1 * S;
-            gsR += g2 * S;
-        } else {
-            const int64_t fid = (int64_t)mg[2 * D + 1];
-            const double sg = (m.f_L[fid] == c) ? 1.0 : -1.0;
-            const double *n = mg;
-            rusanov<D>(W + c * NW, W + (int64_t)j * NW, n, p, Ff);
+        for (int s = 0; s < NFM; ++s) {
+            if (s >= nfc) continue;
+            const int j = m.nbr[c * NFM + s];
+            const double S = m.mgeo[(c * NFM + s) * MG + D];
+            double Fs[NW];
+            if (j < 0) {
+                const int bfi = -j - 1;
+                double g1, g2;
+                bmodel_flux<D>(m, bfi, W + c * NW, p, Fs, &g1, &g2);
 #pragma unroll
-            for (int i = 0; i < NW; ++i) Ff[i] += sg * dref[fid * NW + i];
-            double g[D + 4][3], sig[3][3], q[4][3], Fv[NW], uf[3] = {0, 0, 0};
-            face_grad<D>(fld, gfld, c, j, mg + D + 1, g);
-            const double *Pj = P + (int64_t)j * NP;
+                for (int i = 0; i < NW; ++i) Fs[i] += bcorr[(int64_t)bfi * NW + i];
+                gs += g1 * S;
+                gsR += g2 * S;
+            } else {
+                const int sf = m.sfid[c * NFM + s];
+                const bool left = sf >= 0;
+                const int64_t fid = left ? sf : -(int64_t)sf - 1;
 #pragma unroll
-            for (int a = 0; a < D; ++a) uf[a] = 0.5 * (Pc[1 + a] + Pj[1 + a]);
-            constitutive<D>(0.5 * (Pc[D + 5] + Pj[D + 5]), g, hotf + fid * kNHot, p, sig, q);
-            viscous_flux<D>(sig, q, uf, n, Fv);
-#pragma unroll
-            for (int i = 0; i < NW; ++i) Ff[i] += Fv[i];
-            double ufn = 0, nd = 0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                ufn += uf[a] * n[a];
-                nd += n[a] * mg[D + 1 + a];
+                for (int i = 0; i < NW; ++i) {
+                    const double v = Ff[fid * NW + i];
+                    Fs[i] = left ? v : -v;
+                }
+                gs += Gf[fid * 2] * S;
+                gsR += Gf[fid * 2 + 1] * S;
             }
-            nd = fabs(nd);
-            const double G = fabs(ufn) + 0.5 * (Pc[D + 6] + Pj[D + 6]) +
-                             2 * 0.5 * (Pc[D + 5] + Pj[D + 5]) / (0.5 * (Pc[0] + Pj[0]) * nd);
-            gs += G * S;
-            gsR += 2 * kR / nd * S;
+#pragma unroll
+            for (int i = 0; i < NW; ++i) acc[i] += Fs[i] * S;
         }
+        const double rho = Pc[0], Tt = Pc[D + 1], Tr = Pc[D + 2], Tv = Pc[D + 3];
+        const double tau = Pc[D + 5] / (rho * Tt);
+        const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = (3 * Tt + p.d_v * Tv) / (3 + p.d_v);
+        const double etr = 0.5 * p.d_r * rho * Ttr, etv = 0.5 * p.d_v * rho * Ttv;
+        const double evR = 4 * p.sigma_R * Tv * Tv * Tv * Tv;
+        const double er = W[c * NW + D + 2], ev = W[c * NW + D + 3], eR = W[c * NW + D + 4];
+        double Q[NW];
 #pragma unroll
-        for (int i = 0; i < NW; ++i) acc[i] += Ff[i] * S;
+        for (int i = 0; i < NW; ++i) Q[i] = 0;
+        Q[D + 2] = (etr - er) / (p.Z_r * tau);
+        Q[D + 3] = (etv - ev) / (p.Z_v * tau) - p.keff * (evR - eR);
+        Q[D + 4] = p.keff * (evR - eR);
+        const double V = m.vol[c];
+        double Rc[NW], rs = 0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            Rc[i] = -acc[i] / V + Q[i];
+            rs += Rc[i] * Rc[i];
+        }
+        contrib = V * rs;
+        double un = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) un += Pc[1 + a] * Pc[1 + a];
+        const double dt = cfl_macro * m.h[c] / (sqrt(un) + Pc[D + 6]);
+        const double jr =
+            -3.0 / ((3 + p.d_r) * p.Z_r * tau) + 2 * (p.omega - 1) * (Ttr - Tr) / (3 * p.Z_r * tau * Tt);
+        const double jv = -3.0 / ((3 + p.d_v) * p.Z_v * tau) +
+                          2 * (p.omega - 1) * (Ttv - Tv) / (3 * p.Z_v * tau * Tt) -
+                          p.keff * 16 * p.sigma_R * Tv * Tv * Tv * 2.0 / (p.d_v * rho);
+        double Dc[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) Dc[i] = 1.0 / dt + gs / V;
+        Dc[D + 2] -= jr;
+        Dc[D + 3] -= jv;
+        Dc[D + 4] = 1.0 / dt + gsR / V + p.keff;
+        Rc[D + 1] -= Rc[D + 4];
+        double d0[NW];
+        local_solve<D>(Rc, Dc, rho, Tv, p, d0);
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            R[c * NW + i] = Rc[i];
+            Dg[c * NW + i] = Dc[i];
+            dU[c * NW + i] = d0[i];
+        }
     }
-    const double rho = Pc[0], Tt = Pc[D + 1], Tr = Pc[D + 2], Tv = Pc[D + 3];
-    const double tau = Pc[D + 5] / (rho * Tt);
-    const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = (3 * Tt + p.d_v * Tv) / (3 + p.d_v);
-    const double etr = 0.5 * p.d_r * rho * Ttr, etv = 0.5 * p.d_v * rho * Ttv;
-    const double evR = 4 * p.sigma_R * Tv * Tv * Tv * Tv;
-    const double er = W[c * NW + D + 2], ev = W[c * NW + D + 3], eR = W[c * NW + D + 4];
-    double Q[NW];
-#pragma unroll
-    for (int i = 0; i < NW; ++i) Q[i] = 0;
-    Q[D + 2] = (etr - er) / (p.Z_r * tau);
-    Q[D + 3] = (etv - ev) / (p.Z_v * tau) - p.keff * (evR - eR);
-    Q[D + 4] = p.keff * (evR - eR);
-    const double V = m.vol[c];
-    double Rc[NW], rs = 0;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        Rc[i] = -acc[i] / V + Q[i];
-        rs += Rc[i] * Rc[i];
-    }
-    resc[c] = V * rs;
-    double un = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) un += Pc[1 + a] * Pc[1 + a];
-    const double dt = cfl_macro * m.h[c] / (sqrt(un) + Pc[D + 6]);
-    const double jr = -3.0 / ((3 + p.d_r) * p.Z_r * tau) + 2 * (p.omega - 1) * (Ttr - Tr) / (3 * p.Z_r * tau * Tt);
-    const double jv = -3.0 / ((3 + p.d_v) * p.Z_v * tau) + 2 * (p.omega - 1) * (Ttv - Tv) / (3 * p.Z_v * tau * Tt) -
-                      p.keff * 16 * p.sigma_R * Tv * Tv * Tv * 2.0 / (p.d_v * rho);
-    double Dc[NW];
-#pragma unroll
-    for (int i = 0; i < NW; ++i) Dc[i] = 1.0 / dt + gs / V;
-    Dc[D + 2] -= jr;
-    Dc[D + 3] -= jv;
-    Dc[D + 4] = 1.0 / dt + gsR / V + p.keff;
-    Rc[D + 1] -= Rc[D + 4];
-    double d0[NW];
-    local_solve<D>(Rc, Dc, rho, Tv, p, d0);
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        R[c * NW + i] = Rc[i];
-        Dg[c * NW + i] = Dc[i];
-        dU[c * NW + i] = d0[i];
-    }
-}
-
-// single-block deterministic reduction of resc; decides convergence of inner iteration `it`
-__global__ __launch_bounds__(1024) void k_mcheck(const double *__restrict__ resc, const int64_t nc, const int it,
-                                                 const double tol, double *__restrict__ scal, int *__restrict__ flags)
-{
-    if (flags[0]) return;
-    __shared__ double sh[1024];
-    double s = 0;
-    for (int64_t i = threadIdx.x; i < nc; i += 1024) s += resc[i];
-    sh[threadIdx.x] = s;
+    const int t = threadIdx.x;
+    sh[t] = contrib;
     __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    for (int o = kMBlk / 2; o > 0; o >>= 1) {
+        if (t < o) sh[t] += sh[t + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double res = sqrt(sh[0]);
+    if (t == 0) part[blockIdx.x] = sh[0];
+}
+
+// Stopping test of inner iteration `it`, evaluated by every block of the kernel that follows the residual
+// (same fixed-order sum of the per-block partials in every block, so all blocks take the same decision);
+// block 0 records the norms and raises the flag that later kernels test.
+__device__ __forceinline__ bool inner_converged(const double *__restrict__ part, const int nb, const int it,
+                                                const double tol, double *__restrict__ scal, int *__restrict__ flags)
+{
+    __shared__ double sh[kMBlk];
+    const int t = threadIdx.x;
+    double v = 0;
+    for (int b = t; b < nb; b += kMBlk) v += part[b];
+    sh[t] = v;
+    __syncthreads();
+    for (int o = kMBlk / 2; o > 0; o >>= 1) {
+        if (t < o) sh[t] += sh[t + o];
+        __syncthreads();
+    }
+    const double res = sqrt(sh[0]);
+    const double res0 = (it == 0) ? res : scal[0];
+    const bool done = res <= tol * res0;
+    if (blockIdx.x == 0 && t == 0) {
         if (it == 0) scal[0] = res;
         scal[1] = res;
-        if (res <= tol * scal[0]) {
+        if (done) {
             flags[0] = 1;
             flags[1] = it;
         }
     }
+    return done;
 }
 
-template <int D, int NFM>
-__global__ void k_msweep(const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ R,
-                         const double *__restrict__ Dg, const double *__restrict__ dUin, double *__restrict__ dUout,
-                         const MeshDev m, const Phys p, const int *__restrict__ flags)
+// One Jacobi sweep of the implicit operator (off-diagonal flux increments of the neighbours' current
+// increments, halved).  The first sweep of an inner iteration takes its stopping decision first; the last
+// applies the safeguarded update and writes the next state and its primitives into the other buffer of
+// the ping-pong.
+template <int D, int NFM, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kMBlk) void k_msweep(
+    const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ R,
+    const double *__restrict__ Dg, const double *__restrict__ Gf, const double *__restrict__ dUin,
+    double *__restrict__ dUout, double *__restrict__ Wn_out, double *__restrict__ Pn_out, double *__restrict__ fn_out,
+    const MeshDev m, const Phys p, const double *__restrict__ part, const int it, const double tol,
+    double *__restrict__ scal, int *__restrict__ flags)
 {
-    constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2;
+    constexpr int NW = D + 5, NP = D + 8, NF = D + 4, MG = 2 * D + 2;
     if (flags[0]) return;
+    if constexpr (FIRST) {
+        if (inner_converged(part, gridDim.x, it, tol, scal, flags)) return;
+    }
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= m.nc) return;
-    const double kR = (p.keff > 0) ? 1.0 / (3 * p.keff) : 0.0;
     const double *Pc = P + c * NP;
     const int nfc = m.nfc[c];
     double acc[NW];
 #pragma unroll
     for (int i = 0; i < NW; ++i) acc[i] = 0;
-    for (int s = 0; s < nfc; ++s) {
-        const int j = m.nbr[c * NFM + s];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        const int j = (s < nfc) ? m.nbr[c * NFM + s] : -1;
         if (j < 0) continue;
         const double *mg = m.mgeo + (c * NFM + s) * MG;
         const double *n = mg;
         const double S = mg[D];
-        const double *Pj = P + (int64_t)j * NP;
-        double ufn = 0, nd = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            ufn += 0.5 * (Pc[1 + a] + Pj[1 + a]) * n[a];
-            nd += n[a] * mg[D + 1 + a];
-        }
-        nd = fabs(nd);
-        const double G = fabs(ufn) + 0.5 * (Pc[D + 6] + Pj[D + 6]) +
-                         2 * 0.5 * (Pc[D + 5] + Pj[D + 5]) / (0.5 * (Pc[0] + Pj[0]) * nd);
-        const double GR = 2 * kR / nd;
+        const int sf = m.sfid[c * NFM + s];
+        const int64_t fid = (sf >= 0) ? sf : -(int64_t)sf - 1;
+        const double G = Gf[fid * 2], GR = Gf[fid * 2 + 1];
         double Wn[NW], F1[NW], F0[NW];
         const double *Wj = W + (int64_t)j * NW;
         const double *dj = dUin + (int64_t)j * NW;
 #pragma unroll
         for (int i = 0; i < NW; ++i) Wn[i] = Wj[i] + dj[i];
         Wn[D + 1] += dj[D + 4];
-        euler_flux<D>(Wn, n, p, F1);
-        euler_flux<D>(Wj, n, p, F0);
+        PrimL qj;
+        prim_load<D>(P + (int64_t)j * NP, qj);
+        euler_flux<D>(Wn, n, F1);
+        euler_flux_q<D>(Wj, qj, n, F0);
 #pragma unroll
         for (int i = 0; i < NW - 1; ++i) acc[i] += (F1[i] - F0[i] - G * dj[i]) * S;
         acc[NW - 1] += (-GR * dj[NW - 1]) * S;
@@ -640,16 +772,31 @@ __global__ void k_msweep(const double *__restrict__ W, const double *__restrict_
         Dc[i] = Dg[c * NW + i];
     }
     local_solve<D>(rhs, Dc, Pc[0], Pc[D + 3], p, d1);
+    if constexpr (!LAST) {
 #pragma unroll
-    for (int i = 0; i < NW; ++i) dUout[c * NW + i] = d1[i];
+        for (int i = 0; i < NW; ++i) dUout[c * NW + i] = d1[i];
+    } else {
+        double Wc[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) Wc[i] = W[c * NW + i];
+        positive_update<D>(Wc, d1);
+#pragma unroll
+        for (int i = 0; i < NW; ++i) Wn_out[c * NW + i] = Wc[i];
+        store_prim<D>(Wc, p, Pn_out + c * NP, fn_out + c * NF);
+    }
 }
 
+// update without sweeps (in place: the kernel reads only its own cell) and the new primitives
 template <int D>
-__global__ void k_mupdate(double *__restrict__ W, const double *__restrict__ dU, const int64_t nc, const Phys p,
-                          const int *__restrict__ flags)
+__global__ __launch_bounds__(kMBlk) void k_mupdate(double *__restrict__ W, const double *__restrict__ dU,
+                                                   double *__restrict__ P, double *__restrict__ fld, const int64_t nc,
+                                                   const Phys p, const double *__restrict__ part, const int it,
+                                                   const double tol, double *__restrict__ scal,
+                                                   int *__restrict__ flags)
 {
-    constexpr int NW = D + 5;
+    constexpr int NW = D + 5, NP = D + 8, NF = D + 4;
     if (flags[0]) return;
+    if (inner_converged(part, gridDim.x, it, tol, scal, flags)) return;
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= nc) return;
     double Wc[NW], d[NW];
@@ -658,9 +805,10 @@ __global__ void k_mupdate(double *__restrict__ W, const double *__restrict__ dU,
         Wc[i] = W[c * NW + i];
         d[i] = dU[c * NW + i];
     }
-    positive_update<D>(Wc, d, p);
+    positive_update<D>(Wc, d);
 #pragma unroll
     for (int i = 0; i < NW; ++i) W[c * NW + i] = Wc[i];
+    store_prim<D>(Wc, p, P + c * NP, fld + c * NF);
 }
 
 // out[c] = V_c * x[c * stride]
@@ -718,25 +866,37 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     hipLaunchKernelGGL(k_W_from_mom<D>, gc, blk, 0, st, mom, B.W, B.W0, nc, p);
     // face HoTs from the kinetic moments (mu kept in P[0..nc))
     hipLaunchKernelGGL(k_fld_from_mom<D>, gc, blk, 0, st, mom, B.fld, B.P, nc, p);
-    hipLaunchKernelGGL((k_cell_grad<D, NFM>), gc, blk, 0, st, B.fld, B.gfld, m, nullptr);
+    hipLaunchKernelGGL((k_cell_grad<D, NFM>), gc, blk, 0, st, B.fld, B.gfld, m);
     hipLaunchKernelGGL(k_face_hot<D>, gf, blk, 0, st, mom, B.fld, B.gfld, B.P, B.hotf, m, m.f_d, p);
     if (m.nbf > 0) hipLaunchKernelGGL(k_bcorr<D>, gb, blk, 0, st, B.W0, bflux, B.bcorr, m, p);
     hipLaunchKernelGGL(k_dref<D>, gf, blk, 0, st, B.W0, B.dref, m, p);
+    const dim3 gci((nc + kMBlk - 1) / kMBlk), bi(kMBlk), gfi((m.nf + kMBlk - 1) / kMBlk);
+    hipLaunchKernelGGL(k_mprim<D>, gci, bi, 0, st, B.W, B.P, B.fld, nc, p);
+    // inner iteration `it` starts from the state in buffer `it % 2` when the sweeps ping-pong
+    double *Wb[2] = {B.W, B.W2}, *Pb[2] = {B.P, B.P2}, *Fb[2] = {B.fld, B.fld2};
+    const bool pingpong = o.n_sweeps > 0;
     const int poll = 8;
     int host_flags[2] = {0, 0};
-    int it = 0;
-    for (it = 0; it < o.max_inner; ++it) {
-        hipLaunchKernelGGL(k_mprim<D>, gc, blk, 0, st, B.W, B.P, B.fld, nc, p, B.flags);
-        hipLaunchKernelGGL((k_cell_grad<D, NFM>), gc, blk, 0, st, B.fld, B.gfld, m, B.flags);
-        hipLaunchKernelGGL((k_mres<D, NFM>), gc, blk, 0, st, B.W, B.P, B.fld, B.gfld, B.hotf, B.bcorr, B.dref, B.R,
-                           B.Dg, B.dU0, B.resc, m, p, o.cfl_macro, B.flags);
-        hipLaunchKernelGGL(k_mcheck, dim3(1), dim3(1024), 0, st, B.resc, nc, it, o.inner_tol, B.scal, B.flags);
+    for (int it = 0; it < o.max_inner; ++it) {
+        const int cur = pingpong ? (it & 1) : 0, nxt = cur ^ 1;
+        double *W = Wb[cur], *P = Pb[cur], *fld = Fb[cur];
+        hipLaunchKernelGGL((k_mface<D, NFM>), gfi, bi, 0, st, W, P, fld, B.hotf, B.dref, B.Ff, B.Gf, m, p, B.flags);
+        hipLaunchKernelGGL((k_mgather<D, NFM>), gci, bi, 0, st, W, P, B.bcorr, B.Ff, B.Gf, B.R, B.Dg, B.dU0, B.part,
+                           B.flags, m, p, o.cfl_macro);
         double *din = B.dU0, *dout = B.dU1;
-        for (int s = 0; s < o.n_sweeps; ++s) {
-            hipLaunchKernelGGL((k_msweep<D, NFM>), gc, blk, 0, st, B.W, B.P, B.R, B.Dg, din, dout, m, p, B.flags);
+        const int ns = o.n_sweeps;
+        for (int s = 0; s < ns; ++s) {
+            const bool first = (s == 0), last = (s + 1 == ns);
+            auto kern = first ? (last ? k_msweep<D, NFM, true, true> : k_msweep<D, NFM, true, false>)
+                              : (last ? k_msweep<D, NFM, false, true> : k_msweep<D, NFM, false, false>);
+            hipLaunchKernelGGL(kern, gci, bi, 0, st, W, P, B.R, B.Dg, B.Gf, din, last ? nullptr : dout,
+                               last ? Wb[nxt] : nullptr, last ? Pb[nxt] : nullptr, last ? Fb[nxt] : nullptr, m, p,
+                               B.part, it, o.inner_tol, B.scal, B.flags);
             std::swap(din, dout);
         }
-        hipLaunchKernelGGL(k_mupdate<D>, gc, blk, 0, st, B.W, din, nc, p, B.flags);
+        if (!pingpong)
+            hipLaunchKernelGGL(k_mupdate<D>, gci, bi, 0, st, W, B.dU0, P, fld, nc, p, B.part, it, o.inner_tol, B.scal,
+                               B.flags);
         if ((it + 1) % poll == 0) {
             (void)hipMemcpyAsync(host_flags, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
             (void)hipStreamSynchronize(st);
@@ -746,6 +906,11 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     (void)hipMemcpyAsync(host_flags, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
     (void)hipStreamSynchronize(st);
     const int count = host_flags[0] ? host_flags[1] : o.max_inner;
+    if (pingpong && (count & 1)) {
+        std::swap(B.W, B.W2);
+        std::swap(B.P, B.P2);
+        std::swap(B.fld, B.fld2);
+    }
     if (m.closed) {
         // reading: closed domains keep the mass of mom_mass (the state the outer iteration started from)
         constexpr MomLayout L{D};

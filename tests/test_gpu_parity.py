@@ -45,6 +45,13 @@ def _cases_small():
     ]
 
 
+# Inner iterations of the synthetic solve in the stage tests.  On the coarse supersonic cylinder the early
+# transient drives the inner iteration into its positivity safeguard (step halving), a discrete decision
+# that amplifies round-off differences; both sides agree to ~1e-14 for the first ten inner iterations and
+# the oracle alone is not converging there, so the cylinder stage tests stop at ten.
+_MAX_INNER = {"1d": 60, "cavity": 60, "cylinder": 10}
+
+
 def _warm(o, s, n=3):
     for _ in range(n):
         o.iterate(gsis=False)
@@ -72,7 +79,7 @@ def test_fields_and_kinetic_step_fp64(name, case):
 
 @pytest.mark.parametrize("name,case", _cases_small(), ids=[c[0] for c in _cases_small()])
 def test_macro_solve_and_sync_fp64(name, case):
-    s, o = _pair(case, precision="fp64", max_inner=60)
+    s, o = _pair(case, precision="fp64", max_inner=_MAX_INNER[name])
     _warm(o, s, n=4)
     Wo, ito = o.macro_solve()
     Wg, itg = s.macro_solve()
@@ -88,7 +95,7 @@ def test_macro_solve_and_sync_fp64(name, case):
 
 @pytest.mark.parametrize("name,case", _cases_small(), ids=[c[0] for c in _cases_small()])
 def test_gsis_iterations_fp64(name, case):
-    s, o = _pair(case, precision="fp64", max_inner=60)
+    s, o = _pair(case, precision="fp64", max_inner=_MAX_INNER[name])
     for k in range(6):
         g = k >= 2
         eo, io = o.iterate(gsis=g)
@@ -113,15 +120,16 @@ def test_kinetic_step_fp32_ragged_chunks():
     assert np.abs(Ig - Io).max() < 2e-6 * np.abs(Io).max()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-5)])
-def test_converged_gsis_fields(prec, tol):
+@pytest.mark.parametrize("prec,stol,tol", [("fp64", 1e-8, 1e-8), ("fp32", 1e-7, 1e-5)])
+def test_converged_gsis_fields(prec, stol, tol):
     """Converged GSIS on the 1D radiative Fourier flow (64 cells, 48 velocities, 16 ordinates):
-    every macroscopic field within the relative-L2 bound of the FP64 oracle."""
+    every macroscopic field within the relative-L2 bound of the FP64 oracle converged to 1e-8.  The FP32
+    run stops at 1e-7: its round-off floor on this case lies between 2e-8 and 4e-8."""
     case = case_fourier_1d()
-    s, o = _pair(case, precision=prec, tol=1e-8, max_outer=400, n_precond=10)
+    s, o = _pair(case, precision=prec, tol=stol, max_outer=400, n_precond=10)
     no, _ = o.solve(gsis=True, n_precond=10, tol=1e-8, max_outer=400)
     rc, rep, hist = s.solve()
-    assert rc == 0 and no > 0
+    assert rc == 0 and no > 0, (rc, rep.iters, hist[-5:])
     names = field_names(1)
     errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, names)
     assert max(errs.values()) < tol, errs

@@ -360,6 +360,7 @@ static void free_kin(KinBufs<T> &B)
     dfree(B.dI1);
     dfree(B.coef);
     dfree(B.xi);
+    dfree(B.xiT);
     dfree(B.om);
     dfree(B.rhow);
     dfree(B.xi_d);
@@ -418,6 +419,7 @@ static bool alloc_kin(gsis_t *h, KinBufs<T> &B)
     B.dI1 = dalloc<T>(nc * no, ok);
     B.coef = dalloc<T>(nc * coef_sz(D), ok);
     B.xi = dalloc<T>(nv * D, ok);
+    B.xiT = dalloc<T>(nv * D, ok);
     B.om = dalloc<T>(no * D, ok);
     B.rhow = dalloc<T>(nbf, ok);
     B.xi_d = dalloc<double>(nv * D, ok);
@@ -429,6 +431,10 @@ static bool alloc_kin(gsis_t *h, KinBufs<T> &B)
     if (!ok) return false;
     std::vector<T> xt(h->xi.begin(), h->xi.end()), ot(h->om.begin(), h->om.end());
     (void)hipMemcpy(B.xi, xt.data(), xt.size() * sizeof(T), hipMemcpyHostToDevice);
+    std::vector<T> xtT(nv * D);
+    for (size_t k = 0; k < nv; ++k)
+        for (int a = 0; a < D; ++a) xtT[a * nv + k] = xt[k * D + a];
+    (void)hipMemcpy(B.xiT, xtT.data(), xtT.size() * sizeof(T), hipMemcpyHostToDevice);
     (void)hipMemcpy(B.om, ot.data(), ot.size() * sizeof(T), hipMemcpyHostToDevice);
     (void)hipMemcpy(B.xi_d, h->xi.data(), h->xi.size() * sizeof(double), hipMemcpyHostToDevice);
     (void)hipMemcpy(B.w_d, h->w.data(), h->w.size() * sizeof(double), hipMemcpyHostToDevice);

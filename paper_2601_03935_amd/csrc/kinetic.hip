@@ -109,6 +109,96 @@ __global__ __launch_bounds__(256) void k_grad(const T *__restrict__ f, T *__rest
     }
 }
 
+// Vector form of k_grad for nv divisible by VW (each lane owns VW consecutive velocities); same
+// arithmetic per velocity, neighbour rows loaded with one 16-byte access per lane.
+template <typename T, int VW>
+using vec_t = T __attribute__((ext_vector_type(VW)));
+
+template <typename T, int D, int NFM, int VW>
+__global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__restrict__ gf, const MeshDev m,
+                                                const int64_t nv, const int second_order,
+                                                const int *__restrict__ cell_list, const int64_t ncl)
+{
+    using V = vec_t<T, VW>;
+    constexpr int ND = (D == 3) ? 3 : 4;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t idx = b * 4 + (threadIdx.x >> 6);
+    if (idx >= ncl) return;
+    const int c = uni_i(cell_list ? cell_list[idx] : (int)idx);
+    const int nfc = uni_i(m.nfc[c]);
+    int nb[NFM];
+    T lsq[NFM][D], dxc[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : -1;
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            dxc[s][a] = (s < nfc) ? (T)g[D + a] : T(0);
+            lsq[s][a] = (s < nfc) ? (T)g[3 * D + a] : T(0);
+        }
+    }
+    const T eps2 = (T)m.eps2[c];
+    for (int64_t k = (int64_t)lane * VW; k < nv; k += kWave * VW) {
+        V fcv[ND], fnv[NFM][ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) fcv[d] = *(const V *)(f + ((int64_t)c * ND + d) * nv + k);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s)
+            if (nb[s] >= 0) {
+#pragma unroll
+                for (int d = 0; d < ND; ++d) fnv[s][d] = *(const V *)(f + ((int64_t)nb[s] * ND + d) * nv + k);
+            }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            V go[D];
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                const T fc = fcv[d][e];
+                T g[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) g[a] = T(0);
+                T dmax = T(0), dmin = T(0);
+#pragma unroll
+                for (int s = 0; s < NFM; ++s) {
+                    if (nb[s] >= 0) {
+                        const T df = fnv[s][d][e] - fc;
+#pragma unroll
+                        for (int a = 0; a < D; ++a) g[a] += lsq[s][a] * df;
+                        dmax = df > dmax ? df : dmax;
+                        dmin = df < dmin ? df : dmin;
+                    }
+                }
+                T phi = T(0);
+                if (second_order) {
+                    phi = T(1);
+#pragma unroll
+                    for (int s = 0; s < NFM; ++s) {
+                        if (s < nfc) {
+                            T d2 = T(0);
+#pragma unroll
+                            for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
+                            if (d2 != T(0)) {
+                                const T d1 = d2 > T(0) ? dmax : dmin;
+                                T p = (d1 * d1 + eps2 + T(2) * d1 * d2) /
+                                      (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2);
+                                p = p > T(1) ? T(1) : p;
+                                phi = p < phi ? p : phi;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < D; ++a) go[a][e] = phi * g[a];
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                __builtin_nontemporal_store(go[a], (V *)(gf + (((int64_t)c * ND + d) * D + a) * nv + k));
+        }
+    }
+}
+
 // per-cell coefficient block (written by k_prologue) -------------------------------------------------
 //   [0..D) u, D invtau, D+1 inv_dt, D+2 radc = k_eff (e_vR - e_R)/rho, D+3 B = sigma_R Tv^4/pi,
 //   D+4 inv_dtR, D+5 radd = 4 k_eff e_vR / e_v (extra diagonal of f2), then for X in (t, r, v): inv2T, norm, a[D], gR, bR[D], gV, bV[D], hH
@@ -282,6 +372,148 @@ __global__ __launch_bounds__(256) void k_residual(const T *__restrict__ f, const
     }
 }
 
+// Vector form of k_residual for nv divisible by VW (each lane owns VW consecutive velocities); the
+// rows of interior neighbours are loaded for every lane and the upwind choice is made per velocity.
+template <typename T, int D, int NFM, int VW>
+__global__ __launch_bounds__(256) void k_residual_v(const T *__restrict__ f, const T *__restrict__ gf,
+                                                    const T *__restrict__ coef, const T *__restrict__ xiT,
+                                                    const T *__restrict__ rhow, T *__restrict__ r,
+                                                    T *__restrict__ dl, T *__restrict__ fout, const MeshDev m,
+                                                    const int64_t nv, const T cflv_fac, const T omega,
+                                                    const T wt, const T wr, const T wv, const T dr, const T dv)
+{
+    using V = vec_t<T, VW>;
+    constexpr int ND = (D == 3) ? 3 : 4;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t ci = b * 4 + (threadIdx.x >> 6);
+    if (ci >= m.nc) return;
+    const int c = uni_i((int)ci);
+    const int nfc = uni_i(m.nfc[c]);
+    int nb[NFM];
+    T nsv[NFM][D], dxc[NFM][D], dxj[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : INT32_MIN;
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            nsv[s][a] = (s < nfc) ? (T)g[a] : T(0);
+            dxc[s][a] = (s < nfc) ? (T)g[D + a] : T(0);
+            dxj[s][a] = (s < nfc) ? (T)g[2 * D + a] : T(0);
+        }
+    }
+    T cf[coef_size(3)];
+#pragma unroll
+    for (int i = 0; i < coef_size(D); ++i) cf[i] = coef[(int64_t)c * coef_size(D) + i];
+    for (int64_t k = (int64_t)lane * VW; k < nv; k += kWave * VW) {
+        V x[D], fc[ND], gc[ND][D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = *(const V *)(xiT + a * nv + k);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            fc[d] = *(const V *)(f + ((int64_t)c * ND + d) * nv + k);
+#pragma unroll
+            for (int a = 0; a < D; ++a) gc[d][a] = *(const V *)(gf + (((int64_t)c * ND + d) * D + a) * nv + k);
+        }
+        V flux[ND], dsum = T(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) flux[d] = T(0);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) {
+            if (nb[s] == INT32_MIN) continue;
+            V xn = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
+            if (nb[s] >= 0) {
+                const int64_t j = nb[s];
+                V fj[ND], gj[ND][D];
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    fj[d] = *(const V *)(f + (j * ND + d) * nv + k);
+#pragma unroll
+                    for (int a = 0; a < D; ++a) gj[d][a] = *(const V *)(gf + ((j * ND + d) * D + a) * nv + k);
+                }
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    T fv[4];
+                    if (xn[e] > T(0)) {
+#pragma unroll
+                        for (int d = 0; d < ND; ++d) {
+                            T v = fc[d][e];
+#pragma unroll
+                            for (int a = 0; a < D; ++a) v += gc[d][a][e] * dxc[s][a];
+                            fv[d] = v;
+                        }
+                        dsum[e] += xn[e];
+                    } else {
+#pragma unroll
+                        for (int d = 0; d < ND; ++d) {
+                            T v = fj[d][e];
+#pragma unroll
+                            for (int a = 0; a < D; ++a) v += gj[d][a][e] * dxj[s][a];
+                            fv[d] = v;
+                        }
+                    }
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) flux[d][e] += xn[e] * fv[d];
+                }
+            } else {
+                const int bfi = -nb[s] - 1;
+                const BcDev bc = m.bcs[m.bf_tag[bfi]];
+                const T rho = (bc.kind == 0) ? rhow[bfi] : (T)bc.rho;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    T fv[4];
+                    if (xn[e] > T(0)) {
+#pragma unroll
+                        for (int d = 0; d < ND; ++d) {
+                            T v = fc[d][e];
+#pragma unroll
+                            for (int a = 0; a < D; ++a) v += gc[d][a][e] * dxc[s][a];
+                            fv[d] = v;
+                        }
+                        dsum[e] += xn[e];
+                    } else {
+                        T xe[D];
+#pragma unroll
+                        for (int a = 0; a < D; ++a) xe[a] = x[a][e];
+                        boundary_values<T, D>(bc, rho, xe, dr, dv, fv);
+                    }
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) flux[d][e] += xn[e] * fv[d];
+                }
+            }
+        }
+        V rr[ND], dd[ND];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            T xe[D], fe[4], J[4];
+#pragma unroll
+            for (int a = 0; a < D; ++a) xe[a] = x[a][e];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) fe[d] = fc[d][e];
+            collision<T, D>(cf, xe, fe, J, ND, wt, wr, wv);
+            const T dcoef = cf[D + 1] + cf[D] + dsum[e] * cflv_fac;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                rr[d][e] = J[d] - flux[d][e];
+                dd[d][e] = (d == 2) ? dcoef + cf[D + 5] : dcoef;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const int64_t o = ((int64_t)c * ND + d) * nv + k;
+            if (fout) {
+                __builtin_nontemporal_store(fc[d] + omega * (rr[d] / dd[d]), (V *)(fout + o));
+            } else {
+                __builtin_nontemporal_store(rr[d], (V *)(r + o));
+                __builtin_nontemporal_store(rr[d] / dd[d], (V *)(dl + o));
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ Jacobi sweep of the implicit operator
 template <typename T, int D, int NFM>
 __global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ r, const T *__restrict__ dlin,
@@ -341,6 +573,90 @@ __global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ r, const T 
                 fout[o] = f[o] + omega * dn;
             else
                 dlout[o] = dn;
+        }
+    }
+}
+
+// Vector form of k_sweep for nv divisible by VW: each lane owns VW consecutive velocities (one 16-byte
+// load or store per row and lane); the rows of all upwind neighbours are loaded for every lane and the
+// upwind choice is a per-velocity select.  Same arithmetic as k_sweep except the division, done as a
+// multiplication by the reciprocal of the diagonal.
+template <typename T, int D, int NFM, int VW>
+__global__ __launch_bounds__(256) void k_sweep_v(const T *__restrict__ r, const T *__restrict__ dlin,
+                                                 T *__restrict__ dlout, const T *__restrict__ f,
+                                                 T *__restrict__ fout, const T *__restrict__ coef,
+                                                 const T *__restrict__ xiT, const MeshDev m, const int64_t nv,
+                                                 const T cflv_fac, const T omega)
+{
+    using V = vec_t<T, VW>;
+    constexpr int ND = (D == 3) ? 3 : 4;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int64_t ci = b * 4 + (threadIdx.x >> 6);
+    if (ci >= m.nc) return;
+    const int c = uni_i((int)ci);
+    const int nfc = uni_i(m.nfc[c]);
+    int nb[NFM];
+    T nsv[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : INT32_MIN;
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) nsv[s][a] = (s < nfc) ? (T)g[a] : T(0);
+    }
+    const T base = coef[(int64_t)c * coef_size(D) + D + 1] + coef[(int64_t)c * coef_size(D) + D];
+    const T radd = coef[(int64_t)c * coef_size(D) + D + 5];
+    for (int64_t k = (int64_t)lane * VW; k < nv; k += kWave * VW) {
+        V x[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = *(const V *)(xiT + a * nv + k);
+        V nbv[NFM][ND];
+#pragma unroll
+        for (int s = 0; s < NFM; ++s)
+            if (nb[s] >= 0) {
+#pragma unroll
+                for (int d = 0; d < ND; ++d) nbv[s][d] = *(const V *)(dlin + ((int64_t)nb[s] * ND + d) * nv + k);
+            }
+        V rv[ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) rv[d] = *(const V *)(r + ((int64_t)c * ND + d) * nv + k);
+        V acc[ND], dsum = T(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) acc[d] = T(0);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) {
+            if (nb[s] == INT32_MIN) continue;
+            V xn = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                if (xn[e] > T(0)) {
+                    dsum[e] += xn[e];
+                } else if (xn[e] < T(0) && nb[s] >= 0) {
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) acc[d][e] += xn[e] * nbv[s][d][e];
+                }
+            }
+        }
+        V inv0, inv2;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const T dc = base + dsum[e] * cflv_fac;
+            inv0[e] = T(1) / dc;
+            inv2[e] = T(1) / (dc + radd);
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const int64_t o = ((int64_t)c * ND + d) * nv + k;
+            const V dn = (rv[d] - acc[d]) * ((d == 2) ? inv2 : inv0);
+            if (fout) {
+                const V fo = *(const V *)(f + o) + omega * dn;
+                __builtin_nontemporal_store(fo, (V *)(fout + o));
+            } else {
+                __builtin_nontemporal_store(dn, (V *)(dlout + o));
+            }
         }
     }
 }
@@ -924,8 +1240,13 @@ void launch_grad(const T *f, T *gf, const MeshDev &m, int64_t nv, int so, const 
                  hipStream_t st)
 {
     if (ncl <= 0) return;
-    hipLaunchKernelGGL((k_grad<T, D, NFM>), dim3(wave_blocks(ncl)), dim3(256), 0, st, f, gf, m, (D == 3) ? 3 : 4,
-                       nv, so, cells, ncl);
+    constexpr int VW = 16 / sizeof(T);
+    if (nv % VW == 0)
+        hipLaunchKernelGGL((k_grad_v<T, D, NFM, VW>), dim3(wave_blocks(ncl)), dim3(256), 0, st, f, gf, m, nv, so,
+                           cells, ncl);
+    else
+        hipLaunchKernelGGL((k_grad<T, D, NFM>), dim3(wave_blocks(ncl)), dim3(256), 0, st, f, gf, m,
+                           (D == 3) ? 3 : 4, nv, so, cells, ncl);
 }
 
 template <typename T, int D, int NFM>
@@ -963,8 +1284,13 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
     P.end(ev);
     const int ks = o.kin_sweeps;
     ev = P.begin(1, ks == 0 ? cv * (2 + D) : cv * (3 + D));
-    hipLaunchKernelGGL((k_residual<T, D, NFM>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xi, B.rhow, B.r, B.dl0,
-                       ks == 0 ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
+    constexpr int VW = 16 / sizeof(T);
+    if (nv % VW == 0)
+        hipLaunchKernelGGL((k_residual_v<T, D, NFM, VW>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xiT, B.rhow, B.r,
+                           B.dl0, ks == 0 ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
+    else
+        hipLaunchKernelGGL((k_residual<T, D, NFM>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xi, B.rhow, B.r, B.dl0,
+                           ks == 0 ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
     P.end(ev);
     ev = P.begin(3, ks == 0 ? co * (2 + D) : co * (3 + D));
     hipLaunchKernelGGL((k_residual_I<T, D, NFM>), grid, blk, 0, st, B.I, B.gI, B.coef, B.om, B.rI, B.dI0,
@@ -974,8 +1300,12 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
     for (int s = 0; s < ks; ++s) {
         const bool last = (s == ks - 1);
         ev = P.begin(2, last ? 4 * cv : 3 * cv);
-        hipLaunchKernelGGL((k_sweep<T, D, NFM>), grid, blk, 0, st, B.r, din, dout, B.f, last ? B.f2 : nullptr,
-                           B.coef, B.xi, m, nv, fac, om);
+        if (nv % VW == 0)
+            hipLaunchKernelGGL((k_sweep_v<T, D, NFM, VW>), grid, blk, 0, st, B.r, din, dout, B.f,
+                               last ? B.f2 : nullptr, B.coef, B.xiT, m, nv, fac, om);
+        else
+            hipLaunchKernelGGL((k_sweep<T, D, NFM>), grid, blk, 0, st, B.r, din, dout, B.f, last ? B.f2 : nullptr,
+                               B.coef, B.xi, m, nv, fac, om);
         P.end(ev);
         ev = P.begin(3, last ? 4 * co : 3 * co);
         hipLaunchKernelGGL((k_sweep_I<T, D, NFM>), grid, blk, 0, st, B.rI, dIin, dIout, B.I,

@@ -120,6 +120,20 @@ def test_kinetic_step_fp32_ragged_chunks():
     assert np.abs(Ig - Io).max() < 2e-6 * np.abs(Io).max()
 
 
+def test_kinetic_step_fp32_vector_tail():
+    """FP32 storage with nv = 324 (18 x 18 velocities, a multiple of the 4-wide vector path but not of the
+    256 velocities one wave covers per pass) and 40 ordinates: one kinetic step against FP64."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=18, n_theta=2, n_phi=20, Kn=0.05)
+    s, o = _pair(case, precision="fp32")
+    _warm(o, s, n=2)
+    o.kinetic_step()
+    s.kinetic_step()
+    fo, Io = o.get_state()
+    fg, Ig = s.get_state()
+    assert np.abs(fg - fo).max() < 2e-6 * np.abs(fo).max()
+    assert np.abs(Ig - Io).max() < 2e-6 * np.abs(Io).max()
+
+
 @pytest.mark.parametrize("prec,stol,tol", [("fp64", 1e-8, 1e-8), ("fp32", 1e-7, 1e-5)])
 def test_converged_gsis_fields(prec, stol, tol):
     """Converged GSIS on the 1D radiative Fourier flow (64 cells, 48 velocities, 16 ordinates):

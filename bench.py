@@ -23,6 +23,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a copy)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_cavity20k_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2601_03935_amd", "csrc", "kinetic.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the sweep kernel from the committed counter summary, or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return t["bytes_per_launch"] if t.get("kernel_source_sha256") == sha else None
 
 
 def parse():
@@ -38,6 +54,8 @@ def parse():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-outer", type=int, default=600)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibration of the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -49,6 +67,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if a.copy_probe:
+        n = 1 << 28  # 1 GiB of float32
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": 4 * n, "copies": 3}), flush=True)
+        return
 
     from paper_2601_03935_amd.gsis import KERNEL_KINDS, Solver, oracle_opts
     from workloads import case_cavity
@@ -115,7 +143,9 @@ def main():
             "storage": a.precision + " distributions, fp64 moments and macro solve",
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if dom == "sweep" and a.precision == "fp32" else None,
+                     "algorithmic_bytes_per_launch": by / n},
         "kinetic_step": {"ms": kin_ms, "ideal_bytes": kin_bytes_ideal,
                          "ideal_gbs": kin_bytes_ideal / (kin_ms * 1e-3) / 1e9},
         "kernels": kernels,

@@ -28,14 +28,23 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_cavity20k_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2601_03935_amd", "csrc", "kinetic.hip")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the sweep kernel from the committed counter summary, or None when the kernel
-    source has changed since the counters were taken."""
+def kernel_source_sha256(path=KERNEL_SOURCE, name="k_sweep_v"):
+    """Hash of one kernel's definition text (from its template line to the closing brace at column 0)."""
     import hashlib
 
+    src = open(path).read()
+    i = src.index(f"void {name}(")
+    i = src.rindex("template <", 0, i)
+    j = src.index("\n}\n", i) + 3
+    return hashlib.sha256(src[i:j].encode()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the sweep kernel from the committed counter summary, or None when the kernel
+    definition has changed since the counters were taken."""
     try:
         t = json.load(open(TRAFFIC_FILE))
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        sha = kernel_source_sha256()
     except (OSError, ValueError):
         return None
     return t["bytes_per_launch"] if t.get("kernel_source_sha256") == sha else None
@@ -54,9 +63,60 @@ def parse():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-outer", type=int, default=600)
+    ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--ws-cases", type=int, default=24, help="training cases of the warm-start network")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibration of the HBM byte counters)")
     return ap.parse_args()
+
+
+def warmstart_leg(a, case, stream, plain_fields):
+    """Learned warm start: converged solutions of seeded coarse cavities (Kn, optical thickness and lid speed
+    drawn around the benchmark case) train the network on the GPU; the benchmark case then starts from its
+    prediction.  Reported: time and iterations to tolerance (inference included), data and training cost,
+    and the prediction error against the converged plain solve of the same case."""
+    import numpy as np
+    import torch
+
+    from paper_2601_03935_amd import warmstart as WS
+    from paper_2601_03935_amd.gsis import Solver
+    from workloads import case_cavity, mesh_cavity, warmstart_cavity_params
+
+    st = stream.cuda_stream
+    coarse = mesh_cavity(h=0.025)
+    P = warmstart_cavity_params(a.ws_cases, seed=2)
+    cases = [case_cavity(Kn=k, tau_opt=t, u_lid=u, mesh=coarse, nvx=16) for k, t, u in P]
+    t0 = time.perf_counter()
+    X, Y = WS.training_set(cases, stream=st, precision="fp32", tol=1e-5, max_outer=a.max_outer)
+    t_data = time.perf_counter() - t0
+    ws = WS.WarmStart(width=256, bf16=True, seed=0, stream=st)
+    t0 = time.perf_counter()
+    loss = ws.fit(X, Y, epochs=60, batch=4096, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    s = Solver(case, device=0, stream=st, precision=a.precision, tol=a.tol, max_outer=a.max_outer)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = ws.init_solver(s, case)
+    rc, rep, _ = s.solve()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    F = s.fields()
+    s.close()
+    err = {}
+    if plain_fields is not None:
+        w = case.mesh.vol
+        for name, pv, i in (("rho", pred["rho"], 0), ("Tt", pred["Tt"], 3), ("TR", pred["TR"], 6)):
+            ref = plain_fields[:, i]
+            err[name] = float(np.sqrt((w * (pv - ref) ** 2).sum() / (w * ref ** 2).sum()))
+        uref = plain_fields[:, 1:3]
+        err["u"] = float(np.sqrt((w[:, None] * (pred["u"] - uref) ** 2).sum() / (w[:, None] * uref ** 2).sum()))
+        err["converged_vs_plain_T"] = float(np.sqrt((w * (F[:, 7] - plain_fields[:, 7]) ** 2).sum() /
+                                                    (w * plain_fields[:, 7] ** 2).sum()))
+    return {"tol": a.tol, "seconds": sec, "iterations": int(rep.iters), "converged": bool(rc == 0),
+            "eps_final": float(rep.eps_final), "t_kinetic_s": rep.t_kinetic_s, "t_macro_s": rep.t_macro_s,
+            "prediction_rel_l2_vs_plain": err, "train_cases": len(cases), "train_rows": int(X.shape[0]),
+            "train_data_s": t_data, "train_s": t_train, "train_loss": loss,
+            "network": "4-layer MLP 7-256-256-256-7, tanh, BF16 weights, FP32 accumulation, Adam"}
 
 
 def main():
@@ -153,9 +213,10 @@ def main():
         "eps_last": eps[-1],
     }
     if not a.no_time_to_tol:
-        # wall time to the residual tolerance from the equilibrium start (10 conventional iterations first),
+        # wall time to the residual tolerance from the uniform start (10 conventional iterations first),
         # the configured precision and plain FP64 GSIS on the same GPU
         out["time_to_tol"] = {}
+        plain_fields = None
         for prec in dict.fromkeys((a.precision, "fp64")):
             s2 = Solver(case, device=0, stream=stream.cuda_stream, precision=prec, tol=a.tol, max_outer=a.max_outer)
             torch.cuda.synchronize()
@@ -165,7 +226,11 @@ def main():
             out["time_to_tol"][prec] = {"tol": a.tol, "seconds": time.perf_counter() - t0, "iterations": int(rep.iters),
                                         "converged": bool(rc == 0), "eps_final": float(rep.eps_final),
                                         "t_kinetic_s": rep.t_kinetic_s, "t_macro_s": rep.t_macro_s}
+            if prec == a.precision:
+                plain_fields = s2.fields()
             s2.close()
+        if not a.no_warmstart:
+            out["time_to_tol"][a.precision + "+warmstart"] = warmstart_leg(a, case, stream, plain_fields)
     if not a.no_cpu_baseline:
         from oracle import Oracle
 

@@ -143,6 +143,12 @@ int32_t gsis_set_opts(gsis_t *h, const gsis_opts *opts);
 /* Equilibrium initial state from fields: rho[nc], u[nc*dim], T[nc] (all modes and T_R equal T). */
 int32_t gsis_init_equilibrium(gsis_t *h, const double *rho, const double *u, const double *T);
 
+/* Multi-temperature equilibrium initial state (the f^eq of the synchronisation step, Sec. 3):
+ * rho[nc], u[nc*dim], T_t[nc], T_r[nc], T_v[nc], T_R[nc] (radiation intensity sigma_R T_R^4 / pi on
+ * every ordinate).  Used to start from predicted fields (learned warm start). */
+int32_t gsis_init_fields(gsis_t *h, const double *rho, const double *u, const double *Tt, const double *Tr,
+                         const double *Tv, const double *TR);
+
 /* Full state in and out (double host arrays; f [nc][ND][nv], I [nc][no]). */
 int32_t gsis_set_state(gsis_t *h, const double *f, const double *I);
 int32_t gsis_get_state(gsis_t *h, double *f, double *I);

@@ -1238,6 +1238,33 @@ static void positive_update(const orc_t *o, double *W, const double *dU)
     }
 }
 
+/* 1 when every boundary face is a wall */
+static int domain_closed(const orc_t *o)
+{
+    for (int64_t f = 0; f < o->nf; ++f) {
+        int64_t R = o->fc[2 * f + 1];
+        if (R < 0 && o->bck[-R - 1] != BC_WALL) return 0;
+    }
+    return 1;
+}
+
+/* reading: in a domain closed by walls the total mass is not fixed by the steady equations (kinetic or
+ * synthetic), and neither the point-implicit macro update nor the point relaxation of the kinetic step
+ * conserves it, so an unconstrained iteration would pick the mass of its converged state along the way.
+ * The macro states W are rescaled to a target mass with u and the temperatures unchanged (every
+ * component except e_R scales with the density; e contains e_R). */
+static void rescale_mass(const orc_t *o, double *W, double mass_target)
+{
+    int D = o->D, NW = NWof(D);
+    double m1 = 0;
+    for (int64_t c = 0; c < o->nc; ++c) m1 += o->vol[c] * W[c * NW];
+    double sc = mass_target / m1;
+    for (int64_t c = 0; c < o->nc; ++c) {
+        for (int i = 0; i < NW - 1; ++i) W[c * NW + i] *= sc;
+        W[c * NW + D + 1] -= (sc - 1.0) * W[c * NW + D + 4];
+    }
+}
+
 /* Solve the synthetic equations (Eq. macroscopic_equation; FV and implicit incremental forms of Sec. 6)
  * with the HoTs fixed, starting from W (in/out [nc*NW]) = W(M^{k+1/2}); m = M^{k+1/2}. */
 static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
@@ -1351,24 +1378,9 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
         }
         for (int64_t c = 0; c < nc; ++c) positive_update(o, W + c * NW, dW + c * NW);
     }
-    /* reading: in a domain closed by walls the total mass is not fixed by the steady synthetic equations,
-     * and neither the point-implicit macro update nor the point relaxation of the kinetic step conserves
-     * it; the solution is rescaled to the mass the outer iteration started from (mass_target; u and T
-     * unchanged), so that the GSIS iteration conserves mass. */
-    int closed = 1;
-    for (int64_t f = 0; f < o->nf; ++f) {
-        int64_t R = o->fc[2 * f + 1];
-        if (R < 0 && o->bck[-R - 1] != BC_WALL) closed = 0;
-    }
-    if (closed) {
-        double m1 = 0;
-        for (int64_t c = 0; c < nc; ++c) m1 += o->vol[c] * W[c * NW];
-        double sc = mass_target / m1;
-        for (int64_t c = 0; c < nc; ++c)
-            for (int i = 0; i < NW - 1; ++i) W[c * NW + i] *= sc;
-        /* e contains e_R, which is not scaled */
-        for (int64_t c = 0; c < nc; ++c) W[c * NW + D + 1] -= (sc - 1.0) * W[c * NW + D + 4];
-    }
+    /* reading: in a domain closed by walls the solution is rescaled to the mass the outer iteration
+     * started from (see rescale_mass) */
+    if (domain_closed(o)) rescale_mass(o, W, mass_target);
     o->last_inner = it;
     free(R);
     free(Dg);
@@ -1721,6 +1733,20 @@ double orc_iterate(orc_t *o, int gsis, int *inner)
     all_moments(o, o->f, o->I, m0);
     orc_kinetic_step(o, NULL);
     if (inner) *inner = 0;
+    if (!gsis && domain_closed(o)) {
+        /* reading (closed domains, conventional iteration): the kinetic step does not conserve mass (point
+         * relaxation); f^{k+1/2} is scaled uniformly by mass(f^k) / mass(f^{k+1/2}) (the radiation is not) */
+        mom_t *mh = (mom_t *)malloc(nc * sizeof(mom_t));
+        all_moments(o, o->f, o->I, mh);
+        double mt = 0, mk = 0;
+        for (int64_t c = 0; c < nc; ++c) {
+            mt += o->vol[c] * m0[c].rho;
+            mk += o->vol[c] * mh[c].rho;
+        }
+        const double sc = mt / mk;
+        for (int64_t i = 0; i < nc * o->ND * o->nv; ++i) o->f[i] *= sc;
+        free(mh);
+    }
     if (gsis) {
         mom_t *mh = (mom_t *)malloc(nc * sizeof(mom_t));
         all_moments(o, o->f, o->I, mh);

@@ -681,6 +681,15 @@ static double iterate_T(gsis_t *h, KinBufs<T> &B, bool gsis, int *inner, double 
     h->cnt_updates += (double)h->hm.nc * h->nv;
     h->cnt_bytes += kinetic_alg_bytes(h);
     if (inner) *inner = 0;
+    if (!gsis && h->m.closed) {
+        // reading (closed domains, conventional iteration): the point relaxation does not conserve mass;
+        // f^{k+1/2} is scaled uniformly by mass(f^k) / mass(f^{k+1/2}) (the radiation is not)
+        moments_T(h, B, h->mom0, h->momh);
+        dispatch_dn(h->hm.D, h->m.NFM, [&](auto Dc, auto) {
+            launch_mass_ratio<decltype(Dc)::value>(h->Mb, h->m, h->mom0, h->momh, h->stream);
+        });
+        launch_scale<T>(B.f, (int64_t)h->hm.nc * ndist(h->hm.D) * h->nv, h->Mb.scal + 3, h->Mb.scal + 2, h->stream);
+    }
     if (gsis) {
         auto t2 = std::chrono::steady_clock::now();
         moments_T(h, B, h->mom0, h->momh);
@@ -897,20 +906,24 @@ int32_t gsis_set_opts(gsis_t *h, const gsis_opts *o)
     return GSIS_OK;
 }
 
-int32_t gsis_init_equilibrium(gsis_t *h, const double *rho, const double *u, const double *T)
+int32_t gsis_init_fields(gsis_t *h, const double *rho, const double *u, const double *Tt, const double *Tr,
+                         const double *Tv, const double *TR)
 {
-    if (!h || !rho || !u || !T) return GSIS_E_ARG;
-    if (!h->have_state) return fail(h, GSIS_E_STATE, "gsis_init_equilibrium: call gsis_set_opts first");
+    if (!h || !rho || !u || !Tt || !Tr || !Tv || !TR) return GSIS_E_ARG;
+    if (!h->have_state) return fail(h, GSIS_E_STATE, "gsis_init_fields: call gsis_set_opts first");
     const int D = h->hm.D;
     const int64_t nc = h->hm.nc;
     std::vector<double> sp(nc * 2 * (D + 5), 0.0);
     for (int64_t c = 0; c < nc; ++c) {
-        if (!(rho[c] > 0 && T[c] > 0)) return fail(h, GSIS_E_ARG, "gsis_init_equilibrium: non-positive rho or T");
+        if (!(rho[c] > 0 && Tt[c] > 0 && Tr[c] > 0 && Tv[c] > 0 && TR[c] > 0))
+            return fail(h, GSIS_E_ARG, "gsis_init_fields: non-positive density or temperature");
         double *s1 = &sp[c * 2 * (D + 5) + (D + 5)];
         s1[0] = rho[c];
         for (int a = 0; a < D; ++a) s1[1 + a] = u[c * D + a];
-        s1[D + 1] = s1[D + 2] = s1[D + 3] = T[c];
-        s1[D + 4] = 4 * h->gas.sigma_R * std::pow(T[c], 4);
+        s1[D + 1] = Tt[c];
+        s1[D + 2] = Tr[c];
+        s1[D + 3] = Tv[c];
+        s1[D + 4] = 4 * h->gas.sigma_R * std::pow(TR[c], 4);
     }
     (void)hipSetDevice(h->device);
     HIPCHECK(h, hipMemcpy(h->sp, sp.data(), sp.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -919,6 +932,11 @@ int32_t gsis_init_equilibrium(gsis_t *h, const double *rho, const double *u, con
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     h->mom0_valid = false;
     return GSIS_OK;
+}
+
+int32_t gsis_init_equilibrium(gsis_t *h, const double *rho, const double *u, const double *T)
+{
+    return gsis_init_fields(h, rho, u, T, T, T, T);
 }
 
 int32_t gsis_set_state(gsis_t *h, const double *f, const double *I)

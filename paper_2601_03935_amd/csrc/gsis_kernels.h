@@ -127,6 +127,12 @@ void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_
 template <int D, int NFM>
 int macro_solve(MacroBufs &Mb, const MeshDev &m, const Phys &p, const MacroOpts &o, const double *mom,
                 const double *bflux, const double *mom_mass, hipStream_t st);
+// total masses of two moment arrays: B.scal[3] = sum V rho(mom_num), B.scal[2] = sum V rho(mom_den)
+template <int D>
+void launch_mass_ratio(MacroBufs &B, const MeshDev &m, const double *mom_num, const double *mom_den, hipStream_t st);
+// f[i] *= num[0] / den[0] for n values (device scalars)
+template <typename T>
+void launch_scale(T *f, int64_t n, const double *num, const double *den, hipStream_t st);
 // per-cell sync parameters [rho, u[D], Tt, Tr, Tv, eR] of the moments (slot 0) and of W (slot 1)
 template <int D>
 void launch_sync_params(const double *mom, const double *W, double *sp, int64_t nc, const Phys &p, int from_W,

@@ -1258,6 +1258,24 @@ void launch_grad_I(const T *I, T *gI, const MeshDev &m, int64_t no, int so, cons
                        ncl);
 }
 
+template <typename T>
+__global__ void k_scale(T *__restrict__ f, const int64_t n, const double *__restrict__ num,
+                        const double *__restrict__ den)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double sc = num[0] / den[0];
+    f[i] = (T)((double)f[i] * sc);
+}
+
+template <typename T>
+void launch_scale(T *f, int64_t n, const double *num, const double *den, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scale<T>, dim3((n + 255) / 256), dim3(256), 0, st, f, n, num, den);
+}
+template void launch_scale<float>(float *, int64_t, const double *, const double *, hipStream_t);
+template void launch_scale<double>(double *, int64_t, const double *, const double *, hipStream_t);
+
 template <typename T, int D, int NFM>
 void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpts &o, int64_t nv, int64_t no,
                     hipStream_t st, Prof *pf)

@@ -855,6 +855,20 @@ void launch_block_sum(const double *in, int64_t n, int k, double *out, hipStream
     hipLaunchKernelGGL(k_block_sum, dim3(1), dim3(1024), 0, st, in, n, k, out);
 }
 
+// B.W scaled to the total mass of the moments mom_mass (u and temperatures unchanged; e_R not scaled)
+template <int D>
+void rescale_mass(MacroBufs &B, const MeshDev &m, const double *mom_mass, hipStream_t st)
+{
+    constexpr MomLayout L{D};
+    const int64_t nc = m.nc;
+    const dim3 gc((nc + 255) / 256), blk(256);
+    hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, mom_mass, L.size(), m.vol, B.resc, nc);
+    launch_block_sum(B.resc, nc, 1, B.scal + 3, st);
+    hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, B.W, D + 5, m.vol, B.resc, nc);
+    launch_block_sum(B.resc, nc, 1, B.scal + 2, st);
+    hipLaunchKernelGGL(k_mass_scale<D>, gc, blk, 0, st, B.W, B.scal + 2, B.scal + 3, nc);
+}
+
 // ------------------------------------------------------------------ driver of one macro solve
 template <int D, int NFM>
 int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &o, const double *mom,
@@ -911,16 +925,21 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
         std::swap(B.P, B.P2);
         std::swap(B.fld, B.fld2);
     }
-    if (m.closed) {
-        // reading: closed domains keep the mass of mom_mass (the state the outer iteration started from)
-        constexpr MomLayout L{D};
-        hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, mom_mass, L.size(), m.vol, B.resc, nc);
-        launch_block_sum(B.resc, nc, 1, B.scal + 3, st);
-        hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, B.W, D + 5, m.vol, B.resc, nc);
-        launch_block_sum(B.resc, nc, 1, B.scal + 2, st);
-        hipLaunchKernelGGL(k_mass_scale<D>, gc, blk, 0, st, B.W, B.scal + 2, B.scal + 3, nc);
-    }
+    // reading: closed domains keep the mass of mom_mass (the state the outer iteration started from)
+    if (m.closed) rescale_mass<D>(B, m, mom_mass, st);
     return count;
+}
+
+template <int D>
+void launch_mass_ratio(MacroBufs &B, const MeshDev &m, const double *mom_num, const double *mom_den, hipStream_t st)
+{
+    constexpr MomLayout L{D};
+    const int64_t nc = m.nc;
+    const dim3 gc((nc + 255) / 256), blk(256);
+    hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, mom_num, L.size(), m.vol, B.resc, nc);
+    launch_block_sum(B.resc, nc, 1, B.scal + 3, st);
+    hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, mom_den, L.size(), m.vol, B.resc, nc);
+    launch_block_sum(B.resc, nc, 1, B.scal + 2, st);
 }
 
 // ------------------------------------------------------------------ sync parameters and residual epsilon
@@ -1002,6 +1021,9 @@ GSIS_INST_M(2, 3)
 GSIS_INST_M(2, 4)
 GSIS_INST_M(3, 4)
 GSIS_INST_M(3, 6)
+template void launch_mass_ratio<1>(MacroBufs &, const MeshDev &, const double *, const double *, hipStream_t);
+template void launch_mass_ratio<2>(MacroBufs &, const MeshDev &, const double *, const double *, hipStream_t);
+template void launch_mass_ratio<3>(MacroBufs &, const MeshDev &, const double *, const double *, hipStream_t);
 template void launch_sync_params<1>(const double *, const double *, double *, int64_t, const Phys &, int, hipStream_t);
 template void launch_sync_params<2>(const double *, const double *, double *, int64_t, const Phys &, int, hipStream_t);
 template void launch_sync_params<3>(const double *, const double *, double *, int64_t, const Phys &, int, hipStream_t);

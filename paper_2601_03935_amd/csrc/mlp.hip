@@ -1,0 +1,613 @@
+// Warm-start network on gfx950 (declarations and documentation in include/gsis_warmstart.h): a 4-layer
+// perceptron with BF16 weights and FP32 accumulation; forward, mean-squared-error backward and Adam, all in
+// HIP kernels.  Products are LDS-tiled (64 x 64 outputs per 256-thread workgroup, 16-deep k slices, 4 x 4
+// outputs per thread, k summed in ascending order); column sums and the loss use two-pass fixed-order
+// reductions, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gsis.h"
+#include "../../include/gsis_warmstart.h"
+
+namespace {
+
+constexpr int kLayers = 4;
+constexpr int TBM = 64, TBN = 64, TBK = 16;
+
+__host__ __device__ inline uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float ld(const float *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ld(const uint16_t *p, int64_t i)
+{
+    return __builtin_bit_cast(float, (uint32_t)p[i] << 16);
+}
+
+enum { EPI_BIAS_TANH = 0, EPI_BIAS = 1, EPI_DTANH = 2, EPI_STORE = 3 };
+
+// C[m][n] = epilogue(sum_k A(m,k) B(k,n)) with A(m,k) = TA ? A[k lda + m] : A[m lda + k] and
+// B(k,n) = TB ? B[n ldb + k] : B[k ldb + n].
+template <bool TA, bool TB, typename BT, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(const int M, const int N, const int K, const float *__restrict__ A,
+                                              const int lda, const BT *__restrict__ B, const int ldb,
+                                              float *__restrict__ C, const int ldc, const float *__restrict__ bias,
+                                              const float *__restrict__ aux)
+{
+    __shared__ float As[TBK][TBM + 4];
+    __shared__ float Bs[TBK][TBN + 4];
+    const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
+    const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    for (int k0 = 0; k0 < K; k0 += TBK) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = t + 256 * e;
+            int mm, kk;
+            if (TA) {
+                mm = idx % TBM;
+                kk = idx / TBM;
+            } else {
+                kk = idx % TBK;
+                mm = idx / TBK;
+            }
+            const int m = m0 + mm, k = k0 + kk;
+            float v = 0.f;
+            if (m < M && k < K) v = TA ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k];
+            As[kk][mm] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = t + 256 * e;
+            int nn, kk;
+            if (TB) {
+                kk = idx % TBK;
+                nn = idx / TBK;
+            } else {
+                nn = idx % TBN;
+                kk = idx / TBN;
+            }
+            const int n = n0 + nn, k = k0 + kk;
+            float v = 0.f;
+            if (n < N && k < K) v = TB ? ld(B, (int64_t)n * ldb + k) : ld(B, (int64_t)k * ldb + n);
+            Bs[kk][nn] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TBK; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + ty * 4 + i;
+        if (m >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + tx * 4 + j;
+            if (n >= N) continue;
+            const int64_t o = (int64_t)m * ldc + n;
+            float v = acc[i][j];
+            if (EPI == EPI_BIAS_TANH) {
+                v = tanhf(v + bias[n]);
+            } else if (EPI == EPI_BIAS) {
+                v = v + bias[n];
+            } else if (EPI == EPI_DTANH) {
+                const float a = aux[o];
+                v = v * (1.f - a * a);
+            }
+            C[o] = v;
+        }
+    }
+}
+
+// column sums of X [M][N] in two fixed-order passes: partial sums over 256-row chunks, then over chunks
+constexpr int kColRows = 256;
+__global__ void k_colsum_part(const int M, const int N, const float *__restrict__ X, float *__restrict__ part)
+{
+    const int n = blockIdx.y * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int r0 = blockIdx.x * kColRows, r1 = min(M, r0 + kColRows);
+    float s = 0.f;
+    for (int r = r0; r < r1; ++r) s += X[(int64_t)r * N + n];
+    part[(int64_t)blockIdx.x * N + n] = s;
+}
+
+__global__ void k_colsum_final(const int nchunk, const int N, const float *__restrict__ part, float *__restrict__ out)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * N + n];
+    out[n] = s;
+}
+
+// dY = 2 (y - t) / (n n_out); per-block sums of (y - t)^2 in FP64
+__global__ __launch_bounds__(256) void k_mse(const int64_t cnt, const float *__restrict__ y,
+                                             const float *__restrict__ t, const float scale, float *__restrict__ dy,
+                                             double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double e2 = 0;
+    if (i < cnt) {
+        const float d = y[i] - t[i];
+        dy[i] = scale * d;
+        e2 = (double)d * (double)d;
+    }
+    sh[threadIdx.x] = e2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const int nb, const double *__restrict__ part, const double scale,
+                                                   double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    double s = 0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[b];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0] * scale;
+}
+
+__global__ void k_adam(const int64_t np, float *__restrict__ P, const float *__restrict__ G, float *__restrict__ Mm,
+                       float *__restrict__ Vv, uint16_t *__restrict__ Ph, const float lr, const float b1,
+                       const float b2, const float eps, const float bc1, const float bc2)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float g = G[i];
+    const float m = b1 * Mm[i] + (1.f - b1) * g;
+    const float v = b2 * Vv[i] + (1.f - b2) * g * g;
+    Mm[i] = m;
+    Vv[i] = v;
+    const float p = P[i] - lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+    P[i] = p;
+    Ph[i] = f32_to_bf16(p);
+}
+
+__global__ void k_to_bf16(const int64_t np, const float *__restrict__ P, uint16_t *__restrict__ Ph)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < np) Ph[i] = f32_to_bf16(P[i]);
+}
+
+__global__ void k_gather_rows(const int64_t nb, const int *__restrict__ idx, const int w,
+                              const float *__restrict__ src, float *__restrict__ dst)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nb * w) return;
+    const int64_t r = i / w, c = i % w;
+    dst[i] = src[(int64_t)idx[r] * w + c];
+}
+
+uint64_t splitmix64(uint64_t &s)
+{
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t &s) { return (double)(splitmix64(s) >> 11) * 0x1.0p-53; }
+
+}  // namespace
+
+struct gsis_mlp_s {
+    int device = 0;
+    hipStream_t st = nullptr;
+    int n_in = 0, width = 0, n_out = 0;
+    bool bf16 = true;
+    int in_[kLayers] = {0}, out_[kLayers] = {0};
+    int64_t offW[kLayers] = {0}, offb[kLayers] = {0}, np = 0;
+    float *P = nullptr, *G = nullptr, *Mm = nullptr, *Vv = nullptr;
+    uint16_t *Ph = nullptr;
+    int64_t cap = 0;
+    float *X = nullptr, *T = nullptr, *Y = nullptr, *dY = nullptr, *A[3] = {nullptr, nullptr, nullptr};
+    float *dZ[2] = {nullptr, nullptr}, *cpart = nullptr;
+    double *lpart = nullptr, *loss = nullptr;
+    int64_t adam_t = 0;
+    std::string err;
+};
+
+namespace {
+
+int32_t fail(gsis_mlp_t *m, int32_t code, const std::string &msg)
+{
+    m->err = msg;
+    return code;
+}
+
+#define MCHECK(m, expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail(m, GSIS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+bool dalloc(T *&p, int64_t n)
+{
+    p = nullptr;
+    return hipMalloc((void **)&p, std::max<int64_t>(n, 1) * sizeof(T)) == hipSuccess;
+}
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_batch(gsis_mlp_t *m)
+{
+    dfree(m->X);
+    dfree(m->T);
+    dfree(m->Y);
+    dfree(m->dY);
+    for (auto &a : m->A) dfree(a);
+    for (auto &d : m->dZ) dfree(d);
+    dfree(m->cpart);
+    dfree(m->lpart);
+    m->cap = 0;
+}
+
+bool ensure_batch(gsis_mlp_t *m, int64_t n)
+{
+    if (n <= m->cap) return true;
+    free_batch(m);
+    const int64_t w = m->width;
+    bool ok = dalloc(m->X, n * m->n_in) && dalloc(m->T, n * m->n_out) && dalloc(m->Y, n * m->n_out) &&
+              dalloc(m->dY, n * m->n_out) && dalloc(m->A[0], n * w) && dalloc(m->A[1], n * w) &&
+              dalloc(m->A[2], n * w) && dalloc(m->dZ[0], n * w) && dalloc(m->dZ[1], n * w) &&
+              dalloc(m->cpart, ((n + kColRows - 1) / kColRows) * std::max<int64_t>({w, m->n_in, m->n_out})) &&
+              dalloc(m->lpart, (n * m->n_out + 255) / 256);
+    if (!ok) {
+        free_batch(m);
+        return false;
+    }
+    m->cap = n;
+    return true;
+}
+
+template <bool TA, bool TB, typename BT, int EPI>
+void gemm(gsis_mlp_t *m, int M, int N, int K, const float *A, int lda, const BT *B, int ldb, float *C, int ldc,
+          const float *bias, const float *aux)
+{
+    const dim3 grid((N + TBN - 1) / TBN, (M + TBM - 1) / TBM);
+    hipLaunchKernelGGL((k_gemm<TA, TB, BT, EPI>), grid, dim3(256), 0, m->st, M, N, K, A, lda, B, ldb, C, ldc, bias,
+                       aux);
+}
+
+// weights of layer l as the product kernels read them
+template <typename BT>
+const BT *wptr(gsis_mlp_t *m, int l);
+template <>
+const float *wptr<float>(gsis_mlp_t *m, int l)
+{
+    return m->P + m->offW[l];
+}
+template <>
+const uint16_t *wptr<uint16_t>(gsis_mlp_t *m, int l)
+{
+    return m->Ph + m->offW[l];
+}
+
+template <typename BT>
+void forward_T(gsis_mlp_t *m, int n)
+{
+    const int w = m->width;
+    gemm<false, true, BT, EPI_BIAS_TANH>(m, n, w, m->n_in, m->X, m->n_in, wptr<BT>(m, 0), m->n_in, m->A[0], w,
+                                         m->P + m->offb[0], nullptr);
+    gemm<false, true, BT, EPI_BIAS_TANH>(m, n, w, w, m->A[0], w, wptr<BT>(m, 1), w, m->A[1], w, m->P + m->offb[1],
+                                         nullptr);
+    gemm<false, true, BT, EPI_BIAS_TANH>(m, n, w, w, m->A[1], w, wptr<BT>(m, 2), w, m->A[2], w, m->P + m->offb[2],
+                                         nullptr);
+    gemm<false, true, BT, EPI_BIAS>(m, n, m->n_out, w, m->A[2], w, wptr<BT>(m, 3), w, m->Y, m->n_out,
+                                    m->P + m->offb[3], nullptr);
+}
+
+void forward(gsis_mlp_t *m, int n)
+{
+    if (m->bf16) forward_T<uint16_t>(m, n);
+    else forward_T<float>(m, n);
+}
+
+void colsum(gsis_mlp_t *m, int M, int N, const float *X, float *out)
+{
+    const int nchunk = (M + kColRows - 1) / kColRows;
+    hipLaunchKernelGGL(k_colsum_part, dim3(nchunk, (N + 255) / 256), dim3(256), 0, m->st, M, N, X, m->cpart);
+    hipLaunchKernelGGL(k_colsum_final, dim3((N + 255) / 256), dim3(256), 0, m->st, nchunk, N, m->cpart, out);
+}
+
+// loss into m->loss (device) and gradient into m->G, for the n rows in X, T
+template <typename BT>
+void backward_T(gsis_mlp_t *m, int n)
+{
+    const int w = m->width, no = m->n_out;
+    const int64_t cnt = (int64_t)n * no;
+    const int nb = (int)((cnt + 255) / 256);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, m->st, cnt, m->Y, m->T, (float)(2.0 / (double)cnt), m->dY,
+                       m->lpart);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, m->st, nb, m->lpart, 1.0 / (double)cnt, m->loss);
+    float *G = m->G;
+    // layer 4
+    gemm<true, false, float, EPI_STORE>(m, no, w, n, m->dY, no, m->A[2], w, G + m->offW[3], w, nullptr, nullptr);
+    colsum(m, n, no, m->dY, G + m->offb[3]);
+    gemm<false, false, BT, EPI_DTANH>(m, n, w, no, m->dY, no, wptr<BT>(m, 3), w, m->dZ[0], w, nullptr, m->A[2]);
+    // layer 3
+    gemm<true, false, float, EPI_STORE>(m, w, w, n, m->dZ[0], w, m->A[1], w, G + m->offW[2], w, nullptr, nullptr);
+    colsum(m, n, w, m->dZ[0], G + m->offb[2]);
+    gemm<false, false, BT, EPI_DTANH>(m, n, w, w, m->dZ[0], w, wptr<BT>(m, 2), w, m->dZ[1], w, nullptr, m->A[1]);
+    // layer 2
+    gemm<true, false, float, EPI_STORE>(m, w, w, n, m->dZ[1], w, m->A[0], w, G + m->offW[1], w, nullptr, nullptr);
+    colsum(m, n, w, m->dZ[1], G + m->offb[1]);
+    gemm<false, false, BT, EPI_DTANH>(m, n, w, w, m->dZ[1], w, wptr<BT>(m, 1), w, m->dZ[0], w, nullptr, m->A[0]);
+    // layer 1
+    gemm<true, false, float, EPI_STORE>(m, w, m->n_in, n, m->dZ[0], w, m->X, m->n_in, G + m->offW[0], m->n_in,
+                                        nullptr, nullptr);
+    colsum(m, n, w, m->dZ[0], G + m->offb[0]);
+}
+
+void backward(gsis_mlp_t *m, int n)
+{
+    if (m->bf16) backward_T<uint16_t>(m, n);
+    else backward_T<float>(m, n);
+}
+
+void adam(gsis_mlp_t *m, const gsis_mlp_train_opts *o)
+{
+    m->adam_t += 1;
+    const double bc1 = 1.0 - std::pow(o->beta1, (double)m->adam_t), bc2 = 1.0 - std::pow(o->beta2, (double)m->adam_t);
+    hipLaunchKernelGGL(k_adam, dim3((m->np + 255) / 256), dim3(256), 0, m->st, m->np, m->P, m->G, m->Mm, m->Vv, m->Ph,
+                       (float)o->lr, (float)o->beta1, (float)o->beta2, (float)o->eps, (float)bc1, (float)bc2);
+}
+
+int32_t check_rows(gsis_mlp_t *m, int64_t n, const void *x)
+{
+    if (!x || n <= 0) return fail(m, GSIS_E_ARG, "row count must be positive and arrays non-null");
+    if (n > (int64_t)INT32_MAX / 1024) return fail(m, GSIS_E_ARG, "too many rows in one call");
+    return GSIS_OK;
+}
+
+int32_t upload_rows(gsis_mlp_t *m, int64_t n, const float *x, const float *t)
+{
+    if (!ensure_batch(m, n)) return fail(m, GSIS_E_OOM, "batch buffers: device allocation failed");
+    MCHECK(m, hipMemcpyAsync(m->X, x, n * m->n_in * sizeof(float), hipMemcpyHostToDevice, m->st));
+    if (t) MCHECK(m, hipMemcpyAsync(m->T, t, n * m->n_out * sizeof(float), hipMemcpyHostToDevice, m->st));
+    return GSIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gsis_mlp_create(int32_t device, int32_t n_in, int32_t width, int32_t n_out, int32_t bf16_weights,
+                        uint64_t seed, gsis_mlp_t **out)
+{
+    if (!out) return GSIS_E_ARG;
+    *out = nullptr;
+    if (n_in < 1 || n_in > 64 || n_out < 1 || n_out > 64 || width < 1 || width > 1024) return GSIS_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GSIS_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return GSIS_E_DEVICE;
+    auto *m = new gsis_mlp_t();
+    m->device = device;
+    m->n_in = n_in;
+    m->width = width;
+    m->n_out = n_out;
+    m->bf16 = bf16_weights != 0;
+    const int ins[kLayers] = {n_in, width, width, width}, outs[kLayers] = {width, width, width, n_out};
+    int64_t off = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        m->in_[l] = ins[l];
+        m->out_[l] = outs[l];
+        m->offW[l] = off;
+        off += (int64_t)ins[l] * outs[l];
+        m->offb[l] = off;
+        off += outs[l];
+    }
+    m->np = off;
+    std::vector<float> p(off, 0.f);
+    uint64_t s = seed;
+    for (int l = 0; l < kLayers; ++l) {
+        const double a = std::sqrt(6.0 / (double)(ins[l] + outs[l]));
+        for (int64_t i = 0; i < (int64_t)ins[l] * outs[l]; ++i) p[m->offW[l] + i] = (float)((2 * uniform01(s) - 1) * a);
+    }
+    bool ok = dalloc(m->P, off) && dalloc(m->G, off) && dalloc(m->Mm, off) && dalloc(m->Vv, off) &&
+              dalloc(m->Ph, off) && dalloc(m->loss, 1);
+    if (!ok) {
+        gsis_mlp_destroy(m);
+        return GSIS_E_OOM;
+    }
+    *out = m;
+    return gsis_mlp_set_params(m, p.data());
+}
+
+void gsis_mlp_destroy(gsis_mlp_t *m)
+{
+    if (!m) return;
+    (void)hipSetDevice(m->device);
+    if (m->st) (void)hipStreamSynchronize(m->st);
+    else (void)hipDeviceSynchronize();
+    free_batch(m);
+    dfree(m->P);
+    dfree(m->G);
+    dfree(m->Mm);
+    dfree(m->Vv);
+    dfree(m->Ph);
+    dfree(m->loss);
+    delete m;
+}
+
+const char *gsis_mlp_last_error(gsis_mlp_t *m) { return m ? m->err.c_str() : "null handle"; }
+
+int32_t gsis_mlp_set_stream(gsis_mlp_t *m, void *hip_stream)
+{
+    if (!m) return GSIS_E_ARG;
+    m->st = (hipStream_t)hip_stream;
+    return GSIS_OK;
+}
+
+int64_t gsis_mlp_num_params(gsis_mlp_t *m) { return m ? m->np : (int64_t)GSIS_E_ARG; }
+
+int32_t gsis_mlp_get_params(gsis_mlp_t *m, float *params)
+{
+    if (!m || !params) return GSIS_E_ARG;
+    (void)hipSetDevice(m->device);
+    MCHECK(m, hipStreamSynchronize(m->st));
+    MCHECK(m, hipMemcpy(params, m->P, m->np * sizeof(float), hipMemcpyDeviceToHost));
+    return GSIS_OK;
+}
+
+int32_t gsis_mlp_set_params(gsis_mlp_t *m, const float *params)
+{
+    if (!m || !params) return GSIS_E_ARG;
+    (void)hipSetDevice(m->device);
+    MCHECK(m, hipStreamSynchronize(m->st));
+    MCHECK(m, hipMemcpy(m->P, params, m->np * sizeof(float), hipMemcpyHostToDevice));
+    MCHECK(m, hipMemset(m->Mm, 0, m->np * sizeof(float)));
+    MCHECK(m, hipMemset(m->Vv, 0, m->np * sizeof(float)));
+    hipLaunchKernelGGL(k_to_bf16, dim3((m->np + 255) / 256), dim3(256), 0, m->st, m->np, m->P, m->Ph);
+    MCHECK(m, hipStreamSynchronize(m->st));
+    m->adam_t = 0;
+    return GSIS_OK;
+}
+
+int32_t gsis_mlp_forward(gsis_mlp_t *m, int64_t n, const float *x, float *y)
+{
+    if (!m || !y) return GSIS_E_ARG;
+    int32_t rc = check_rows(m, n, x);
+    if (rc != GSIS_OK) return rc;
+    (void)hipSetDevice(m->device);
+    if ((rc = upload_rows(m, n, x, nullptr)) != GSIS_OK) return rc;
+    forward(m, (int)n);
+    MCHECK(m, hipMemcpyAsync(y, m->Y, n * m->n_out * sizeof(float), hipMemcpyDeviceToHost, m->st));
+    MCHECK(m, hipStreamSynchronize(m->st));
+    return GSIS_OK;
+}
+
+int32_t gsis_mlp_loss_grad(gsis_mlp_t *m, int64_t n, const float *x, const float *t, double *loss, float *grad)
+{
+    if (!m || !t) return GSIS_E_ARG;
+    int32_t rc = check_rows(m, n, x);
+    if (rc != GSIS_OK) return rc;
+    (void)hipSetDevice(m->device);
+    if ((rc = upload_rows(m, n, x, t)) != GSIS_OK) return rc;
+    forward(m, (int)n);
+    backward(m, (int)n);
+    if (loss) MCHECK(m, hipMemcpyAsync(loss, m->loss, sizeof(double), hipMemcpyDeviceToHost, m->st));
+    if (grad) MCHECK(m, hipMemcpyAsync(grad, m->G, m->np * sizeof(float), hipMemcpyDeviceToHost, m->st));
+    MCHECK(m, hipStreamSynchronize(m->st));
+    return GSIS_OK;
+}
+
+int32_t gsis_mlp_adam_step(gsis_mlp_t *m, const gsis_mlp_train_opts *o, int64_t n, const float *x, const float *t,
+                           double *loss)
+{
+    if (!m || !o || !t) return GSIS_E_ARG;
+    int32_t rc = check_rows(m, n, x);
+    if (rc != GSIS_OK) return rc;
+    (void)hipSetDevice(m->device);
+    if ((rc = upload_rows(m, n, x, t)) != GSIS_OK) return rc;
+    forward(m, (int)n);
+    backward(m, (int)n);
+    adam(m, o);
+    if (loss) MCHECK(m, hipMemcpyAsync(loss, m->loss, sizeof(double), hipMemcpyDeviceToHost, m->st));
+    MCHECK(m, hipStreamSynchronize(m->st));
+    return GSIS_OK;
+}
+
+int32_t gsis_mlp_train(gsis_mlp_t *m, int64_t n, const float *x, const float *t, const gsis_mlp_train_opts *o,
+                       double *final_loss)
+{
+    if (!m || !o || !t) return GSIS_E_ARG;
+    int32_t rc = check_rows(m, n, x);
+    if (rc != GSIS_OK) return rc;
+    if (o->epochs < 0 || o->batch < 1 || !(o->lr > 0)) return fail(m, GSIS_E_ARG, "gsis_mlp_train: invalid options");
+    (void)hipSetDevice(m->device);
+    const int64_t bs = std::min<int64_t>(o->batch, n);
+    const int64_t nbat = (n + bs - 1) / bs;
+    if (!ensure_batch(m, bs)) return fail(m, GSIS_E_OOM, "gsis_mlp_train: device allocation failed");
+    float *Xall = nullptr, *Tall = nullptr;
+    int *idx = nullptr;
+    double *lossv = nullptr;
+    struct Guard {
+        float *&a, *&b;
+        int *&c;
+        double *&d;
+        ~Guard()
+        {
+            dfree(a);
+            dfree(b);
+            dfree(c);
+            dfree(d);
+        }
+    } guard{Xall, Tall, idx, lossv};
+    if (!(dalloc(Xall, n * m->n_in) && dalloc(Tall, n * m->n_out) && dalloc(idx, n) && dalloc(lossv, nbat)))
+        return fail(m, GSIS_E_OOM, "gsis_mlp_train: device allocation failed");
+    MCHECK(m, hipMemcpyAsync(Xall, x, n * m->n_in * sizeof(float), hipMemcpyHostToDevice, m->st));
+    MCHECK(m, hipMemcpyAsync(Tall, t, n * m->n_out * sizeof(float), hipMemcpyHostToDevice, m->st));
+    std::vector<int> perm(n);
+    uint64_t s = o->seed;
+    for (int ep = 0; ep < o->epochs; ++ep) {
+        for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
+        for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[(int64_t)(uniform01(s) * (double)(i + 1))]);
+        MCHECK(m, hipMemcpyAsync(idx, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, m->st));
+        for (int64_t b = 0; b < nbat; ++b) {
+            const int64_t r0 = b * bs, nr = std::min(bs, n - r0);
+            hipLaunchKernelGGL(k_gather_rows, dim3((nr * m->n_in + 255) / 256), dim3(256), 0, m->st, nr, idx + r0,
+                               m->n_in, Xall, m->X);
+            hipLaunchKernelGGL(k_gather_rows, dim3((nr * m->n_out + 255) / 256), dim3(256), 0, m->st, nr, idx + r0,
+                               m->n_out, Tall, m->T);
+            forward(m, (int)nr);
+            backward(m, (int)nr);
+            adam(m, o);
+            MCHECK(m, hipMemcpyAsync(lossv + b, m->loss, sizeof(double), hipMemcpyDeviceToDevice, m->st));
+        }
+        // the permutation buffer is rewritten next epoch: wait for this epoch's gathers
+        MCHECK(m, hipStreamSynchronize(m->st));
+    }
+    if (final_loss) {
+        std::vector<double> lv(nbat);
+        MCHECK(m, hipMemcpy(lv.data(), lossv, nbat * sizeof(double), hipMemcpyDeviceToHost));
+        double sum = 0;
+        for (double v : lv) sum += v;
+        *final_loss = o->epochs > 0 ? sum / (double)nbat : 0.0;
+    }
+    return GSIS_OK;
+}
+
+}  // extern "C"

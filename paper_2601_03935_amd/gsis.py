@@ -26,7 +26,7 @@ GSIS_FP64, GSIS_FP32 = 0, 1
 EXPORTS = [
     "gsis_create", "gsis_destroy", "gsis_last_error", "gsis_default_opts", "gsis_set_stream", "gsis_set_mesh",
     "gsis_set_velocity_grid", "gsis_set_ordinates", "gsis_set_gas", "gsis_set_flow", "gsis_set_opts",
-    "gsis_init_equilibrium", "gsis_set_state", "gsis_get_state", "gsis_iterate", "gsis_solve",
+    "gsis_init_equilibrium", "gsis_init_fields", "gsis_set_state", "gsis_get_state", "gsis_iterate", "gsis_solve",
     "gsis_kinetic_step", "gsis_macro_solve", "gsis_sync", "gsis_nfields", "gsis_get_fields",
     "gsis_get_residual_history", "gsis_get_surface_flux", "gsis_get_counters", "gsis_set_profiling",
     "gsis_get_kernel_stats",
@@ -92,6 +92,7 @@ def lib():
         "gsis_kinetic_step": ([P], I32),
         "gsis_macro_solve": ([P, P, C.POINTER(I32)], I32),
         "gsis_sync": ([P, P], I32),
+        "gsis_init_fields": ([P, P, P, P, P, P, P], I32),
         "gsis_nfields": ([P], I32),
         "gsis_get_fields": ([P, P], I32),
         "gsis_get_residual_history": ([P, P, I64, C.POINTER(I64)], I32),
@@ -172,6 +173,18 @@ class Solver:
         self._check(self.L.gsis_set_opts(self.h, C.byref(self.opts)), "gsis_set_opts")
         self.init_equilibrium(case.init_rho, case.init_u, case.init_T)
 
+    def set_opts(self, **kw):
+        """Change options between iterations; the state is kept unless the precision or the limiter
+        constant changes (those reallocate and need a new initial state)."""
+        o = self.opts
+        for k, v in kw.items():
+            if k == "precision" and isinstance(v, str):
+                v = {"fp32": GSIS_FP32, "fp64": GSIS_FP64}[v]
+            if k == "scheme" and isinstance(v, str):
+                v = {"cis": GSIS_CIS, "gsis": GSIS_GSIS}[v]
+            setattr(o, k, v)
+        self._check(self.L.gsis_set_opts(self.h, C.byref(o)), "gsis_set_opts")
+
     def _check(self, rc, what, handle="self"):
         if rc < 0:
             msg = ""
@@ -195,6 +208,11 @@ class Solver:
     def init_equilibrium(self, rho, u, T):
         self._check(self.L.gsis_init_equilibrium(self.h, _p(_f64(rho)), _p(_f64(u)), _p(_f64(T))),
                     "gsis_init_equilibrium")
+
+    def init_fields(self, rho, u, Tt, Tr, Tv, TR):
+        """Multi-temperature equilibrium start from fields (e.g. a learned warm start)."""
+        a = [_f64(v) for v in (rho, u, Tt, Tr, Tv, TR)]
+        self._check(self.L.gsis_init_fields(self.h, *[_p(v) for v in a]), "gsis_init_fields")
 
     def set_state(self, f, I):
         f, I = _f64(f), _f64(I)

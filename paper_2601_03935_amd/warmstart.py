@@ -1,0 +1,247 @@
+"""Learned warm start (ctypes binding of include/gsis_warmstart.h plus feature plumbing).
+
+A 4-layer perceptron maps case parameters and cell geometry to initial macroscopic fields; it is trained
+on the GPU, by the library's own forward/backward/Adam kernels, on converged solutions the solver itself
+produced.  The solver then starts from the multi-temperature equilibrium of the predicted fields
+(``gsis_init_fields``) instead of the uniform start; the converged answer is unchanged (same fixed
+point), only the number of iterations to reach it.
+
+Features here are for the lid-driven cavity family (unit square with the concentric square obstacle):
+log10 Kn, log10 optical thickness, lid speed, x, y, distance to the nearest wall, distance to the lid.
+Targets: log rho, u_x, u_y, log T_t, log T_r, log T_v, log T_R.  Inputs and targets are standardised
+with the training-set mean and spread, stored with the weights.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import time
+
+import numpy as np
+
+from .gsis import GsisError, Solver, lib
+
+EXPORTS = [
+    "gsis_mlp_create", "gsis_mlp_destroy", "gsis_mlp_last_error", "gsis_mlp_set_stream", "gsis_mlp_num_params",
+    "gsis_mlp_get_params", "gsis_mlp_set_params", "gsis_mlp_forward", "gsis_mlp_loss_grad", "gsis_mlp_adam_step",
+    "gsis_mlp_train",
+]
+
+N_IN, N_OUT = 7, 7
+HOLE = (0.35, 0.65)
+
+
+class gsis_mlp_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
+
+
+_registered = False
+
+
+def _lib():
+    global _registered
+    L = lib()
+    if not _registered:
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "gsis_mlp_create": ([I32, I32, I32, I32, I32, C.c_uint64, C.POINTER(C.c_void_p)], I32),
+            "gsis_mlp_destroy": ([P], None),
+            "gsis_mlp_last_error": ([P], C.c_char_p),
+            "gsis_mlp_set_stream": ([P, P], I32),
+            "gsis_mlp_num_params": ([P], I64),
+            "gsis_mlp_get_params": ([P, P], I32),
+            "gsis_mlp_set_params": ([P, P], I32),
+            "gsis_mlp_forward": ([P, I64, P, P], I32),
+            "gsis_mlp_loss_grad": ([P, I64, P, P, C.POINTER(C.c_double), P], I32),
+            "gsis_mlp_adam_step": ([P, C.POINTER(gsis_mlp_train_opts), I64, P, P, C.POINTER(C.c_double)], I32),
+            "gsis_mlp_train": ([P, I64, P, P, C.POINTER(gsis_mlp_train_opts), C.POINTER(C.c_double)], I32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _registered = True
+    return L
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def train_opts(epochs=10, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+    return gsis_mlp_train_opts(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps),
+                               int(seed))
+
+
+class MLP:
+    """Handle on one network in the library (weights, Adam state and work buffers live on the GPU)."""
+
+    def __init__(self, n_in=N_IN, width=256, n_out=N_OUT, bf16=True, seed=0, device=0, stream=None):
+        self.L = _lib()
+        h = C.c_void_p()
+        rc = self.L.gsis_mlp_create(device, n_in, width, n_out, 1 if bf16 else 0, seed, C.byref(h))
+        if rc < 0:
+            raise GsisError(f"gsis_mlp_create failed with code {rc}")
+        self.h = h
+        self.n_in, self.width, self.n_out, self.bf16 = n_in, width, n_out, bf16
+        if stream is not None:
+            self._check(self.L.gsis_mlp_set_stream(self.h, C.c_void_p(stream)), "gsis_mlp_set_stream")
+        self.np = int(self.L.gsis_mlp_num_params(self.h))
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise GsisError(f"{what} failed with code {rc}: {self.L.gsis_mlp_last_error(self.h).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gsis_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shapes(self):
+        """(W, b) shapes per layer in parameter-vector order."""
+        ins = [self.n_in, self.width, self.width, self.width]
+        outs = [self.width, self.width, self.width, self.n_out]
+        return [((o, i), (o,)) for i, o in zip(ins, outs)]
+
+    def get_params(self):
+        p = np.empty(self.np, dtype=np.float32)
+        self._check(self.L.gsis_mlp_get_params(self.h, _ptr(p)), "gsis_mlp_get_params")
+        return p
+
+    def set_params(self, p):
+        p = _f32(p)
+        assert p.size == self.np
+        self._check(self.L.gsis_mlp_set_params(self.h, _ptr(p)), "gsis_mlp_set_params")
+
+    def forward(self, x):
+        x = _f32(x)
+        y = np.empty((x.shape[0], self.n_out), dtype=np.float32)
+        self._check(self.L.gsis_mlp_forward(self.h, x.shape[0], _ptr(x), _ptr(y)), "gsis_mlp_forward")
+        return y
+
+    def loss_grad(self, x, t):
+        x, t = _f32(x), _f32(t)
+        g = np.empty(self.np, dtype=np.float32)
+        loss = C.c_double(0)
+        self._check(self.L.gsis_mlp_loss_grad(self.h, x.shape[0], _ptr(x), _ptr(t), C.byref(loss), _ptr(g)),
+                    "gsis_mlp_loss_grad")
+        return loss.value, g
+
+    def adam_step(self, x, t, **kw):
+        x, t = _f32(x), _f32(t)
+        o = train_opts(**kw)
+        loss = C.c_double(0)
+        self._check(self.L.gsis_mlp_adam_step(self.h, C.byref(o), x.shape[0], _ptr(x), _ptr(t), C.byref(loss)),
+                    "gsis_mlp_adam_step")
+        return loss.value
+
+    def train(self, x, t, **kw):
+        x, t = _f32(x), _f32(t)
+        o = train_opts(**kw)
+        loss = C.c_double(0)
+        self._check(self.L.gsis_mlp_train(self.h, x.shape[0], _ptr(x), _ptr(t), C.byref(o), C.byref(loss)),
+                    "gsis_mlp_train")
+        return loss.value
+
+
+# ---------------------------------------------------------------------------------------------------------
+# features and targets (cavity family)
+
+
+def cavity_features(case) -> np.ndarray:
+    """Per-cell features [log10 Kn, log10 tau_opt, u_lid, x, y, wall distance, lid distance]."""
+    ctr = case.mesh.ctr
+    x, y = ctr[:, 0], ctr[:, 1]
+    lo, hi = HOLE
+    d_outer = np.minimum(np.minimum(x, 1 - x), np.minimum(y, 1 - y))
+    dx = np.maximum(np.maximum(lo - x, x - hi), 0.0)
+    dy = np.maximum(np.maximum(lo - y, y - hi), 0.0)
+    d_hole = np.hypot(dx, dy)
+    ulid = [b for b in case.bcs if abs(b.get("u", (0, 0, 0))[0]) > 0]
+    u_lid = ulid[0]["u"][0] if ulid else 0.0
+    n = case.mesh.nc
+    return np.stack([np.full(n, np.log10(case.flow.Kn_gas)), np.full(n, np.log10(case.flow.k_eff)),
+                     np.full(n, u_lid), x, y, np.minimum(d_outer, d_hole), 1 - y], axis=1)
+
+
+def field_targets(F: np.ndarray) -> np.ndarray:
+    """[log rho, u_x, u_y, log T_t, log T_r, log T_v, log T_R] from the library's 2D field array."""
+    return np.stack([np.log(F[:, 0]), F[:, 1], F[:, 2], np.log(F[:, 3]), np.log(F[:, 4]), np.log(F[:, 5]),
+                     np.log(F[:, 6])], axis=1)
+
+
+def targets_to_fields(Y: np.ndarray) -> dict:
+    return dict(rho=np.exp(Y[:, 0]), u=np.ascontiguousarray(Y[:, 1:3]), Tt=np.exp(Y[:, 3]), Tr=np.exp(Y[:, 4]),
+                Tv=np.exp(Y[:, 5]), TR=np.exp(Y[:, 6]))
+
+
+class WarmStart:
+    """Standardisation + network; fit on (features, targets) of converged cases, predict initial fields."""
+
+    def __init__(self, width=256, bf16=True, seed=0, device=0, stream=None):
+        self.net = MLP(N_IN, width, N_OUT, bf16=bf16, seed=seed, device=device, stream=stream)
+        self.xm = self.xs = self.ym = self.ys = None
+
+    def fit(self, X, Y, epochs=40, batch=4096, lr=2e-3, seed=0):
+        X, Y = np.asarray(X, dtype=np.float64), np.asarray(Y, dtype=np.float64)
+        self.xm, self.xs = X.mean(0), X.std(0) + 1e-12
+        self.ym, self.ys = Y.mean(0), Y.std(0) + 1e-12
+        return self.net.train((X - self.xm) / self.xs, (Y - self.ym) / self.ys, epochs=epochs, batch=batch, lr=lr,
+                              seed=seed)
+
+    def predict(self, X):
+        Yn = self.net.forward((np.asarray(X, dtype=np.float64) - self.xm) / self.xs)
+        return Yn.astype(np.float64) * self.ys + self.ym
+
+    def init_solver(self, solver: Solver, case):
+        """Start `solver` from the predicted fields.  In a domain closed by walls the total mass is an input
+        (the iteration conserves it), so the predicted density is rescaled to the mass of the case's own
+        initial state."""
+        f = targets_to_fields(self.predict(cavity_features(case)))
+        if all(b["kind"] == 0 for b in case.bcs):
+            V = case.mesh.vol
+            f["rho"] = f["rho"] * (np.dot(V, case.init_rho) / np.dot(V, f["rho"]))
+        solver.init_fields(f["rho"], f["u"], f["Tt"], f["Tr"], f["Tv"], f["TR"])
+        return f
+
+    def save(self, path):
+        np.savez(path, params=self.net.get_params(), xm=self.xm, xs=self.xs, ym=self.ym, ys=self.ys,
+                 width=self.net.width, bf16=self.net.bf16)
+
+    def load(self, path):
+        d = np.load(path)  # plain arrays only (no pickled objects)
+        self.net.set_params(d["params"])
+        self.xm, self.xs, self.ym, self.ys = d["xm"], d["xs"], d["ym"], d["ys"]
+
+
+def converged_fields(case, device=0, stream=None, **opts):
+    """Solve a case from its uniform start; returns (fields, iterations, seconds, converged)."""
+    s = Solver(case, device=device, stream=stream, **opts)
+    t0 = time.perf_counter()
+    rc, rep, _ = s.solve()
+    dt = time.perf_counter() - t0
+    F = s.fields()
+    s.close()
+    return F, int(rep.iters), dt, rc == 0
+
+
+def training_set(cases, device=0, stream=None, **opts):
+    """Features and targets stacked over converged cases."""
+    X, Y = [], []
+    for c in cases:
+        F, _, _, ok = converged_fields(c, device=device, stream=stream, **opts)
+        X.append(cavity_features(c))
+        Y.append(field_targets(F))
+    return np.concatenate(X), np.concatenate(Y)

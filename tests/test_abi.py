@@ -6,18 +6,22 @@ import re
 import pytest
 
 from paper_2601_03935_amd import gsis as G
+from paper_2601_03935_amd import warmstart as WS
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "gsis.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gsis_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in ("gsis.h", "gsis_warmstart.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(gsis_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_matches_binding_list():
-    assert _declared() == sorted(G.EXPORTS)
+    assert _declared() == sorted(G.EXPORTS + WS.EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
@@ -32,6 +36,17 @@ def test_default_opts():
     assert o.kin_sweeps == 8 and o.max_inner == 100 and o.n_precond == 10 and o.limiter_K == 5.0
     o2 = G.default_opts(precision="fp64", scheme="cis", tol=1e-8)
     assert o2.precision == G.GSIS_FP64 and o2.scheme == G.GSIS_CIS and o2.tol == 1e-8
+
+
+def test_mlp_argument_errors():
+    L = WS._lib()
+    import ctypes as C
+
+    h = C.c_void_p()
+    assert L.gsis_mlp_create(0, 0, 8, 2, 1, 0, C.byref(h)) == G.GSIS_E_ARG
+    assert L.gsis_mlp_create(0, 3, 8, 65, 1, 0, C.byref(h)) == G.GSIS_E_ARG
+    assert L.gsis_mlp_forward(None, 1, None, None) == G.GSIS_E_ARG
+    assert L.gsis_mlp_num_params(None) == G.GSIS_E_ARG
 
 
 def test_null_handle_errors():

@@ -170,3 +170,15 @@ def test_surface_flux_matches_oracle():
     np.testing.assert_allclose(qc[b], bs[b, 0], rtol=1e-10, atol=1e-14)
     np.testing.assert_allclose(qr[b], bs[b, 1], rtol=1e-10, atol=1e-14)
     np.testing.assert_allclose(pw[b], bs[b, 2], rtol=1e-10, atol=1e-14)
+
+
+def test_conventional_iterations_keep_mass_closed_domain():
+    """Closed cavity, FP32: the conventional iterations keep the initial mass (uniform rescaling of f after
+    the point relaxation), as the oracle does."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1, u_lid=0.3)
+    s = Solver(case, precision="fp32")
+    V = case.mesh.vol
+    m0 = (V * s.fields()[:, 0]).sum()
+    for _ in range(5):
+        s.iterate(gsis=False)
+        assert abs((V * s.fields()[:, 0]).sum() - m0) < 2e-6 * m0

@@ -27,4 +27,5 @@ from .cases import (  # noqa: F401
     case_cylinder,
     case_capsule,
     warmstart_case_params,
+    warmstart_cavity_params,
 )

@@ -139,3 +139,14 @@ def warmstart_case_params(n: int = 256, seed: int = 2):
     Kn = 10 ** rng.uniform(-3.0, 0.0, n)
     tau = 10 ** rng.uniform(-2.0, 2.0, n)
     return np.stack([Ma, Kn, tau], axis=1)
+
+
+def warmstart_cavity_params(n: int = 32, seed: int = 2):
+    """Seeded (Kn, optical thickness, lid speed) draws for warm-start training sets on the cavity family:
+    Kn log-uniform in [0.03, 0.3], optical thickness log-uniform in [0.3, 3], lid speed uniform in
+    [0.1, 0.3]."""
+    rng = np.random.default_rng(seed)
+    Kn = 10 ** rng.uniform(np.log10(0.03), np.log10(0.3), n)
+    tau = 10 ** rng.uniform(np.log10(0.3), np.log10(3.0), n)
+    ulid = rng.uniform(0.1, 0.3, n)
+    return np.stack([Kn, tau, ulid], axis=1)

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import Oracle, field_names
 from paper_2601_03935_amd.gsis import Solver, oracle_opts
-from workloads import case_cavity, case_cylinder, case_fourier_1d, mesh_annulus, mesh_cavity
+from workloads import case_capsule, case_cavity, case_cylinder, case_fourier_1d, mesh_annulus, mesh_cavity
 
 pytestmark = pytest.mark.gpu
 
@@ -42,14 +42,17 @@ def _cases_small():
         ("cavity", case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1)),
         ("cylinder", case_cylinder(mesh=mesh_annulus(n_theta=24, n_r=8), nvx=24, xmax=10.0, n_theta=2, n_phi=4,
                                    Kn=0.1, Ma=2.0)),
+        # 3D: 1,040 tetrahedra around the capsule, 8^3 velocities (three distributions), 8 ordinates
+        ("capsule", case_capsule(Kn=0.1, Ma=2.0, nvx=8, xmax=8.0, n_theta=2, n_phi=4,
+                                 mesh_kw=dict(n_s=6, n_phi=8, n_r=4))),
     ]
 
 
 # Inner iterations of the synthetic solve in the stage tests.  On the coarse supersonic cylinder the early
 # transient drives the inner iteration into its positivity safeguard (step halving), a discrete decision
 # that amplifies round-off differences; both sides agree to ~1e-14 for the first ten inner iterations and
-# the oracle alone is not converging there, so the cylinder stage tests stop at ten.
-_MAX_INNER = {"1d": 60, "cavity": 60, "cylinder": 10}
+# the oracle alone is not converging there, so the cylinder and capsule stage tests stop at ten.
+_MAX_INNER = {"1d": 60, "cavity": 60, "cylinder": 10, "capsule": 10}
 
 
 def _warm(o, s, n=3):

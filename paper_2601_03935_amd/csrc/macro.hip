@@ -495,6 +495,16 @@ __global__ void k_dref(const double *__restrict__ W0, double *__restrict__ dref,
 
 // ------------------------------------------------------------------ inner-iteration kernels
 
+// sum over the 64 lanes of the (single-wave) block in a fixed butterfly order; every lane gets lane 0's
+// result (the lanes' own butterfly results may differ in the last bit)
+__device__ __forceinline__ double wave_sum64(double v)
+{
+    static_assert(kMBlk == 64, "inner-iteration blocks are one wave");
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return __shfl(v, 0, 64);
+}
+
 // primitive record and gradient fields of W
 template <int D>
 __device__ __forceinline__ void store_prim(const double *Wc, const Phys &p, double *pc, double *fc)
@@ -593,7 +603,6 @@ __global__ __launch_bounds__(kMBlk) void k_mgather(
 {
     constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2;
     if (flags[0]) return;
-    __shared__ double sh[kMBlk];
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double contrib = 0;
     if (c < m.nc) {
@@ -676,14 +685,8 @@ __global__ __launch_bounds__(kMBlk) void k_mgather(
             dU[c * NW + i] = d0[i];
         }
     }
-    const int t = threadIdx.x;
-    sh[t] = contrib;
-    __syncthreads();
-    for (int o = kMBlk / 2; o > 0; o >>= 1) {
-        if (t < o) sh[t] += sh[t + o];
-        __syncthreads();
-    }
-    if (t == 0) part[blockIdx.x] = sh[0];
+    const double tot = wave_sum64(contrib);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 // Stopping test of inner iteration `it`, evaluated by every block of the kernel that follows the residual
@@ -692,17 +695,10 @@ __global__ __launch_bounds__(kMBlk) void k_mgather(
 __device__ __forceinline__ bool inner_converged(const double *__restrict__ part, const int nb, const int it,
                                                 const double tol, double *__restrict__ scal, int *__restrict__ flags)
 {
-    __shared__ double sh[kMBlk];
     const int t = threadIdx.x;
     double v = 0;
     for (int b = t; b < nb; b += kMBlk) v += part[b];
-    sh[t] = v;
-    __syncthreads();
-    for (int o = kMBlk / 2; o > 0; o >>= 1) {
-        if (t < o) sh[t] += sh[t + o];
-        __syncthreads();
-    }
-    const double res = sqrt(sh[0]);
+    const double res = sqrt(wave_sum64(v));
     const double res0 = (it == 0) ? res : scal[0];
     const bool done = res <= tol * res0;
     if (blockIdx.x == 0 && t == 0) {
@@ -889,7 +885,7 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     // inner iteration `it` starts from the state in buffer `it % 2` when the sweeps ping-pong
     double *Wb[2] = {B.W, B.W2}, *Pb[2] = {B.P, B.P2}, *Fb[2] = {B.fld, B.fld2};
     const bool pingpong = o.n_sweeps > 0;
-    const int poll = 8;
+    const int poll = 32;
     int host_flags[2] = {0, 0};
     for (int it = 0; it < o.max_inner; ++it) {
         const int cur = pingpong ? (it & 1) : 0, nxt = cur ^ 1;

@@ -315,3 +315,65 @@ def test_fourier_cis_conserved_modes():
     C = FA.cis_matrix(1e-6, 1.0, 1.0, 0.01)
     ev = np.sort(np.abs(np.linalg.eigvals(C)))[::-1]
     assert np.all(ev[:5] > 1 - 1e-5)
+
+
+def test_mirror_symmetry_cavity():
+    """P12: a cavity mesh that is exactly mirror-symmetric about x = 1/2, a resting lid, symmetric velocity
+    and ordinate sets: every iterate (conventional and GSIS, macro solve included) is mirror-symmetric --
+    rho, u_y, T, q_y, sigma_xx, sigma_yy even, u_x, q_x, sigma_xy odd.  A direction-dependent mistake
+    (a component index, a face orientation, a sign in one flux term) breaks it."""
+    from scipy.spatial import cKDTree
+
+    from workloads import mesh_cavity_mirror
+
+    m = mesh_cavity_mirror(h=0.1)
+    c = case_cavity(mesh=m, nvx=8, n_theta=2, n_phi=4, u_lid=0.0, T_lid=3.0, Kn=0.1)
+    o = Oracle(c, max_inner=30)
+    names = field_names(2)
+    mc = m.ctr.copy()
+    mc[:, 0] = 1 - mc[:, 0]
+    d, j = cKDTree(m.ctr).query(mc)
+    assert d.max() < 1e-12
+    odd = {"ux", "qtx", "qrx", "qvx", "qRx", "sigxy"}
+    sign = np.array([-1.0 if n in odd else 1.0 for n in names])
+    for k in range(6):
+        o.iterate(gsis=k >= 3)
+        F = o.fields()
+        err = np.abs(F - sign * F[j]).max(0) / np.maximum(np.abs(F).max(0), 1e-30)
+        assert err.max() < 1e-11, (k, dict(zip(names, err)))
+
+
+def test_conventional_steady_state_energy_balance():
+    """P10: at the steady state of the conventional iteration (kinetic residual zero) in the closed 1D
+    radiative slab, the gas and radiative energy fluxes into the two walls cancel and no mass crosses a
+    wall: the discrete transport, the boundary fluxes and the gas-photon exchange conserve energy."""
+    c = case_fourier_1d(n=32, nv=24, no=8, Kn=0.3)
+    o = Oracle(c)
+    n, hist = o.solve(gsis=False, tol=1e-12, max_outer=3000)
+    assert hist[n - 1] < 1e-12
+    bf, bs = o.boundary()
+    b = c.mesh.boundary_faces()
+    q = bs[b, 0] + bs[b, 1]
+    assert np.abs(q).min() > 0.5  # a real heat flux crosses the slab
+    assert abs(q.sum()) < 1e-10 * np.abs(q).max()
+    assert np.abs(bf[b, 0]).max() < 1e-14
+
+
+def test_heat_flux_hots_scale_with_kn_squared():
+    """P9: near the continuum limit the gas heat-flux HoTs away from the Knudsen layers (0.2 < x < 0.8)
+    vanish like Kn^2 (Sec. 5): log-log slope 2 +- 0.3 over Kn = 0.008, 0.004, 0.002 on a fixed mesh.
+    (The radiative HoT stays O(1) here because the photon Knudsen number is held at 1.)"""
+    vals = []
+    Kns = [0.008, 0.004, 0.002]
+    for Kn in Kns:
+        c = case_fourier_1d(n=64, nv=48, no=16, Kn=Kn)
+        o = Oracle(c)
+        n, hist = o.solve(gsis=True, n_precond=10, tol=1e-10, max_outer=800)
+        assert hist[n - 1] < 1e-10
+        H = o.face_hot()
+        inner = c.mesh.face_cells[:, 1] >= 0
+        x = c.mesh.face_ctr[inner, 0]
+        core = (x > 0.2) & (x < 0.8)
+        vals.append(np.sqrt((H[inner][core][:, 9:18] ** 2).sum()))
+    slope = np.polyfit(np.log(Kns), np.log(vals), 1)[0]
+    assert abs(slope - 2.0) < 0.3, (vals, slope)

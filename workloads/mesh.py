@@ -115,8 +115,10 @@ def mesh_1d(n: int, x0: float = 0.0, x1: float = 1.0, bc_left: int = 0, bc_right
 def _tri_mesh_from_points(pts: np.ndarray, keep_tri, classify_edge, name: str) -> Mesh:
     from scipy.spatial import Delaunay
 
-    tri = Delaunay(pts)
-    simp = tri.simplices
+    return _tri_mesh_from_simplices(pts, Delaunay(pts).simplices, keep_tri, classify_edge, name)
+
+
+def _tri_mesh_from_simplices(pts: np.ndarray, simp: np.ndarray, keep_tri, classify_edge, name: str) -> Mesh:
     cen = pts[simp].mean(axis=1)
     keep = keep_tri(cen)
     simp = simp[keep]
@@ -196,6 +198,60 @@ def mesh_cavity(h: float = 0.0095, jitter: float = 0.3, seed: int = 0, hole=(0.3
         return np.where(np.abs(fc[:, 1] - 1.0) < 1e-9, 1, 0)
 
     return _tri_mesh_from_points(pts, keep, classify, f"cavity_h{h}")
+
+
+def mesh_cavity_mirror(h: float = 0.05, jitter: float = 0.3, seed: int = 0, hole=(0.35, 0.65)) -> Mesh:
+    """Cavity mesh that is exactly mirror-symmetric about x = 1/2: the left half (jittered points plus
+    points on the mid-line) is triangulated and its triangles are mirrored.  Same boundary tags as
+    mesh_cavity."""
+    from scipy.spatial import Delaunay
+
+    rng = np.random.default_rng(seed)
+    lo, hi = hole
+    n = int(round(1.0 / h))
+    assert n % 2 == 0, "an even number of intervals puts grid lines on the mid-line"
+    g = np.arange(1, n) / n
+    X, Y = np.meshgrid(g[g < 0.5 - 1e-12], g, indexing="ij")
+    P = np.stack([X.ravel(), Y.ravel()], axis=1)
+    P = P + (rng.random(P.shape) - 0.5) * 2 * jitter * h
+    margin = 0.5 * h
+    inside = (P[:, 0] > margin) & (P[:, 0] < 0.5 - margin) & (P[:, 1] > margin) & (P[:, 1] < 1 - margin)
+    near_hole = (P > lo - margin).all(axis=1) & (P[:, 1] < hi + margin)
+    P = P[inside & ~near_hole]
+    B = []
+    for s_ in np.linspace(0, 1, n + 1):
+        B += [(0.0, s_)]
+        if s_ <= 0.5 + 1e-12:
+            B += [(s_, 0.0), (s_, 1.0)]
+        if s_ <= lo + 1e-12 or s_ >= hi - 1e-12:
+            B += [(0.5, s_)]
+    nh = max(2, int(round((hi - lo) / h)))
+    for s_ in np.linspace(lo, hi, nh + 1):
+        B += [(lo, s_)]
+        if s_ <= 0.5 + 1e-12:
+            B += [(s_, lo), (s_, hi)]
+    B += [(0.5, lo), (0.5, hi)]
+    B = np.unique(np.round(np.array(B), 12), axis=0)
+    left = np.concatenate([P, B], axis=0)
+    simp = Delaunay(left).simplices
+    mid = np.abs(left[:, 0] - 0.5) < 1e-12
+    # mirrored copies of the points off the mid-line
+    idx_m = np.full(left.shape[0], -1)
+    off = np.nonzero(~mid)[0]
+    idx_m[off] = left.shape[0] + np.arange(off.size)
+    idx_m[mid] = np.nonzero(mid)[0]
+    right = left[off].copy()
+    right[:, 0] = 1.0 - right[:, 0]
+    pts = np.concatenate([left, right], axis=0)
+    simp = np.concatenate([simp, idx_m[simp][:, ::-1]], axis=0)
+
+    def keep(cen):
+        return ~((cen > lo).all(axis=1) & (cen < hi).all(axis=1))
+
+    def classify(fc):
+        return np.where(np.abs(fc[:, 1] - 1.0) < 1e-9, 1, 0)
+
+    return _tri_mesh_from_simplices(pts, simp, keep, classify, f"cavity_mirror_h{h}")
 
 
 def mesh_annulus(r0: float = 1.0, r1: float = 6.0, n_theta: int = 256, n_r: int = 80, stretch: float = 1.045,

@@ -14,6 +14,15 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kWave = 64;
 constexpr int kNHot = 21;  // HoT_sigma (3x3), HoT_qt, HoT_qr, HoT_qv, HoT_qR (3 each)
 
+// Workgroup b of nb is dispatched to XCD b % 8; remap so that XCD x walks the contiguous block range
+// [x nb/8, (x+1) nb/8) (cells and faces are in locality order, so neighbours share that XCD's L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    const int64_t q = nb / 8, r = nb % 8;
+    const int64_t x = b % 8, i = b / 8;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // Moment vector per cell (FP64), index helpers for dimension D:
 //   rho, u[D], Tt, Tr, Tv, eR, er, ev, sig[D*D] (full), qt[D], qr[D], qv[D], qR[D]
 struct MomLayout {

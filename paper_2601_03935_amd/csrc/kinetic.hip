@@ -12,13 +12,6 @@
 
 namespace gsis {
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
-{
-    const int64_t q = nb / 8, r = nb % 8;
-    const int64_t x = b % 8, i = b / 8;
-    return x * q + (x < r ? x : r) + i;
-}
-
 __device__ __forceinline__ int uni_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <typename T>

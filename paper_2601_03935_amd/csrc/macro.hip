@@ -534,7 +534,7 @@ __global__ void k_mprim(const double *__restrict__ W, double *__restrict__ P, do
                         const int64_t nc, const Phys p)
 {
     constexpr int NW = D + 5, NF = D + 4, NP = D + 8;
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     store_prim<D>(W + c * NW, p, P + c * NP, fld + c * NF);
 }
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kMBlk) void k_mface(const double *__restrict__ W, c
 {
     constexpr int NW = D + 5, NP = D + 8, NF = D + 4;
     if (flags[0]) return;
-    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t f = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= m.nf) return;
     const int64_t c = m.f_L[f], j = m.f_R[f];
     if (j < 0) return;
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(kMBlk) void k_mgather(
 {
     constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2;
     if (flags[0]) return;
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     double contrib = 0;
     if (c < m.nc) {
         const double *Pc = P + c * NP;
@@ -729,7 +729,7 @@ __global__ __launch_bounds__(kMBlk) void k_msweep(
     if constexpr (FIRST) {
         if (inner_converged(part, gridDim.x, it, tol, scal, flags)) return;
     }
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= m.nc) return;
     const double *Pc = P + c * NP;
     const int nfc = m.nfc[c];
@@ -793,7 +793,7 @@ __global__ __launch_bounds__(kMBlk) void k_mupdate(double *__restrict__ W, const
     constexpr int NW = D + 5, NP = D + 8, NF = D + 4;
     if (flags[0]) return;
     if (inner_converged(part, gridDim.x, it, tol, scal, flags)) return;
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     double Wc[NW], d[NW];
 #pragma unroll

@@ -3,9 +3,10 @@
 Plain definitions, no blocking or fusion: a 4-layer perceptron x -> tanh(W1 x + b1) -> tanh(W2 . + b2)
 -> tanh(W3 . + b3) -> W4 . + b4, the mean squared error over all rows and outputs, its gradient by the
 chain rule written out layer by layer, and one bias-corrected Adam step (Kingma & Ba, 2015).  The
-parameter vector is laid out as W_l (row-major [out][in]) then b_l for l = 1..4.  When ``bf16`` is set the
-products use the weights rounded to bfloat16 (round to nearest even), as the GPU path does; the
-arithmetic stays FP64.  The learned warm start is not part of the paper.
+parameter vector is laid out as W_l (row-major [out][in]) then b_l for l = 1..4.  When ``bf16`` is set
+both operands of every matrix product (weights, layer inputs, back-propagated gradients) are rounded to
+bfloat16 (round to nearest even, from their FP32 values), as the GPU path does; the arithmetic stays FP64
+and the bias gradients use the unrounded values.  The learned warm start is not part of the paper.
 """
 
 from __future__ import annotations
@@ -41,6 +42,11 @@ def round_bf16(a: np.ndarray) -> np.ndarray:
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def _op(a, bf16):
+    """Operand of a matrix product as the GPU path feeds it."""
+    return round_bf16(a) if bf16 else a
+
+
 def forward(p, shp, x, bf16=False):
     """Returns the list of layer outputs [a1, a2, a3, y] (a_l = tanh of the pre-activation)."""
     Ws, bs = unpack(np.asarray(p, dtype=np.float64), shp)
@@ -49,7 +55,7 @@ def forward(p, shp, x, bf16=False):
     a = np.asarray(x, dtype=np.float64)
     outs = []
     for l in range(4):
-        z = a @ Ws[l].T + bs[l]
+        z = _op(a, bf16) @ Ws[l].T + bs[l]
         a = np.tanh(z) if l < 3 else z
         outs.append(a)
     return outs
@@ -74,10 +80,10 @@ def loss_grad(p, shp, x, t, bf16=False):
     d = 2.0 * (y - t) / n  # dL/dy
     gW, gb = [None] * 4, [None] * 4
     for l in range(3, -1, -1):
-        gW[l] = d.T @ acts[l]
+        gW[l] = _op(d, bf16).T @ _op(acts[l], bf16)
         gb[l] = d.sum(axis=0)
         if l > 0:
-            d = (d @ Ws[l]) * (1.0 - acts[l] ** 2)  # through tanh of layer l
+            d = (_op(d, bf16) @ Ws[l]) * (1.0 - acts[l] ** 2)  # through tanh of layer l
     return L, pack(gW, gb)
 
 

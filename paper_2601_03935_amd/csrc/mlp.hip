@@ -1,7 +1,8 @@
 // Warm-start network on gfx950 (declarations and documentation in include/gsis_warmstart.h): a 4-layer
 // perceptron with BF16 weights and FP32 accumulation; forward, mean-squared-error backward and Adam, all in
-// HIP kernels.  Products are LDS-tiled (64 x 64 outputs per 256-thread workgroup, 16-deep k slices, 4 x 4
-// outputs per thread, k summed in ascending order); column sums and the loss use two-pass fixed-order
+// HIP kernels.  With BF16 weights every product runs on the matrix cores (both operands rounded to BF16 in
+// LDS, FP32 accumulation); with FP32 weights on the vector ALUs (64 x 64 outputs per 256-thread workgroup,
+// 4 x 4 per thread).  k is summed in a fixed order; column sums and the loss use two-pass fixed-order
 // reductions, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
@@ -122,6 +123,97 @@ __global__ __launch_bounds__(256) void k_gemm(const int M, const int N, const in
             }
             C[o] = v;
         }
+    }
+}
+
+// BF16 matrix-core form of the same product (used when the weights are BF16): both operands are rounded to
+// BF16 (round to nearest even) while they are staged in LDS, products accumulate in FP32 with
+// v_mfma_f32_32x32x8bf16.  Workgroup: 4 waves, 64 x 64 outputs, each wave a 32 x 32 block; k advances by
+// 32 per LDS stage (four 8-deep MFMA steps), so every output sums its k terms in a fixed order.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+constexpr int MBK = 32, MPAD = 8;
+
+__device__ __forceinline__ float ldf(const float *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ldf(const uint16_t *p, int64_t i)
+{
+    return __builtin_bit_cast(float, (uint32_t)p[i] << 16);
+}
+
+template <bool TA, bool TB, typename BT, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_mfma(const int M, const int N, const int K,
+                                                   const float *__restrict__ A, const int lda,
+                                                   const BT *__restrict__ B, const int ldb, float *__restrict__ C,
+                                                   const int ldc, const float *__restrict__ bias,
+                                                   const float *__restrict__ aux)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[TBM][MBK + MPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[TBN][MBK + MPAD];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+    f32x16_t acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+    for (int k0 = 0; k0 < K; k0 += MBK) {
+        // stage A (64 x 32) and B (32 x 64): 8 consecutive elements of the contiguous index per thread
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int mm, kk;
+            if (TA) {
+                kk = t >> 3;
+                mm = ((t & 7) << 3) + e;
+            } else {
+                mm = t >> 2;
+                kk = ((t & 3) << 3) + e;
+            }
+            const int m = m0 + mm, k = k0 + kk;
+            float v = 0.f;
+            if (m < M && k < K) v = TA ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k];
+            As[mm][kk] = f32_to_bf16(v);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int nn, kk;
+            if (TB) {
+                nn = t >> 2;
+                kk = ((t & 3) << 3) + e;
+            } else {
+                kk = t >> 3;
+                nn = ((t & 7) << 3) + e;
+            }
+            const int n = n0 + nn, k = k0 + kk;
+            float v = 0.f;
+            if (n < N && k < K) v = TB ? ldf(B, (int64_t)n * ldb + k) : ldf(B, (int64_t)k * ldb + n);
+            Bs[nn][kk] = f32_to_bf16(v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < MBK; kk += 8) {
+            const int kc = kk + 4 * (lane >> 5);
+            const bf16x4_t a = *(const bf16x4_t *)&As[wm * 32 + (lane & 31)][kc];
+            const bf16x4_t b = *(const bf16x4_t *)&Bs[wn * 32 + (lane & 31)][kc];
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int n = n0 + wn * 32 + (lane & 31);
+    if (n >= N) return;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int m = m0 + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (m >= M) continue;
+        const int64_t o = (int64_t)m * ldc + n;
+        float x = acc[v];
+        if (EPI == EPI_BIAS_TANH) {
+            x = tanhf(x + bias[n]);
+        } else if (EPI == EPI_BIAS) {
+            x = x + bias[n];
+        } else if (EPI == EPI_DTANH) {
+            const float a = aux[o];
+            x = x * (1.f - a * a);
+        }
+        C[o] = x;
     }
 }
 
@@ -302,13 +394,18 @@ bool ensure_batch(gsis_mlp_t *m, int64_t n)
     return true;
 }
 
+// products: BF16 matrix cores when the network runs with BF16 weights, FP32 vector ALUs otherwise
 template <bool TA, bool TB, typename BT, int EPI>
 void gemm(gsis_mlp_t *m, int M, int N, int K, const float *A, int lda, const BT *B, int ldb, float *C, int ldc,
           const float *bias, const float *aux)
 {
     const dim3 grid((N + TBN - 1) / TBN, (M + TBM - 1) / TBM);
-    hipLaunchKernelGGL((k_gemm<TA, TB, BT, EPI>), grid, dim3(256), 0, m->st, M, N, K, A, lda, B, ldb, C, ldc, bias,
-                       aux);
+    if (m->bf16)
+        hipLaunchKernelGGL((k_gemm_mfma<TA, TB, BT, EPI>), grid, dim3(256), 0, m->st, M, N, K, A, lda, B, ldb, C, ldc,
+                           bias, aux);
+    else
+        hipLaunchKernelGGL((k_gemm<TA, TB, BT, EPI>), grid, dim3(256), 0, m->st, M, N, K, A, lda, B, ldb, C, ldc,
+                           bias, aux);
 }
 
 // weights of layer l as the product kernels read them

@@ -19,24 +19,27 @@ def _data(n, n_in, n_out, seed):
     return x, t
 
 
-@pytest.mark.parametrize("bf16", [True, False], ids=["bf16", "fp32"])
-def test_forward_and_gradient_match_reference(bf16):
-    """300 rows (ragged against the 64-row tiles), width 96 (ragged against 64-column tiles)."""
+@pytest.mark.parametrize("bf16,tol", [(True, 1e-3), (False, 1e-4)], ids=["bf16", "fp32"])
+def test_forward_and_gradient_match_reference(bf16, tol):
+    """300 rows (ragged against the 64-row tiles), width 96 (ragged against 64-column tiles and the 32-deep
+    matrix-core k slices).  BF16: the reference rounds the same operands to bfloat16; the GPU rounds its FP32
+    values, which sit within FP32 accumulation error of the reference's, so an operand near a rounding
+    midpoint can land on the neighbouring bfloat16 value (a 2^-8 change of one term): tolerance 1e-3."""
     net = WS.MLP(7, 96, 7, bf16=bf16, seed=5)
     shp = M.shapes(7, 96, 7)
     x, t = _data(300, 7, 7, 0)
     p = net.get_params().astype(np.float64)
     y = net.forward(x)
     y_ref = M.forward(p, shp, x, bf16=bf16)[-1]
-    assert np.abs(y - y_ref).max() <= 2e-5 * np.abs(y_ref).max()
+    assert np.abs(y - y_ref).max() <= 0.2 * tol * np.abs(y_ref).max()
     L, g = net.loss_grad(x, t)
     L_ref, g_ref = M.loss_grad(p, shp, x, t, bf16=bf16)
-    assert abs(L - L_ref) <= 1e-5 * L_ref
+    assert abs(L - L_ref) <= 0.1 * tol * L_ref
     Ws, bs = M.unpack(g.astype(np.float64), shp)
     Wr, br = M.unpack(g_ref, shp)
     for l in range(4):
-        assert np.linalg.norm(Ws[l] - Wr[l]) <= 1e-4 * np.linalg.norm(Wr[l]), l
-        assert np.linalg.norm(bs[l] - br[l]) <= 1e-4 * np.linalg.norm(br[l]), l
+        assert np.linalg.norm(Ws[l] - Wr[l]) <= tol * np.linalg.norm(Wr[l]), l
+        assert np.linalg.norm(bs[l] - br[l]) <= tol * np.linalg.norm(br[l]), l
     net.close()
 
 

@@ -63,11 +63,66 @@ def parse():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-outer", type=int, default=600)
+    ap.add_argument("--workload", default="cavity", choices=["cavity", "capsule-shard"],
+                    help="cavity: GSIS iterations of the 2D radiative cavity (default); capsule-shard: kinetic steps "
+                         "of the 3D capsule on one eighth of its velocity space (one GPU's share)")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--ws-cases", type=int, default=24, help="training cases of the warm-start network")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibration of the HBM byte counters)")
     return ap.parse_args()
+
+
+def bench_capsule_shard(a):
+    """Kinetic steps (moments, prologue, gradients, wall densities, residual with the relaxation source,
+    Jacobi sweeps, radiation) of the 3D capsule on ~213k tetrahedra with 12^3 velocities -- one eighth of the
+    24^3 grid, i.e. one GPU's share when velocity space is split over eight -- and 96 ordinates, FP32."""
+    import torch
+
+    from paper_2601_03935_amd.gsis import KERNEL_KINDS, Solver
+    from workloads import case_capsule
+
+    case = case_capsule(Kn=0.01, tau_opt=1.0, Ma=10.0, nvx=12, xmax=20.0, n_theta=8, n_phi=12, sigma_R=0.045,
+                        mesh_kw=dict(n_s=46, n_phi=28, n_r=28))
+    nc, nv, no = case.mesh.nc, case.vgrid.nv, case.ords.no
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    s = Solver(case, device=0, stream=stream.cuda_stream, precision=a.precision)
+    for _ in range(a.warmup):
+        s.kinetic_step()
+    torch.cuda.synchronize()
+    s.set_profiling(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(a.steps):
+        s.kinetic_step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    stats = s.kernel_stats()
+    s.set_profiling(False)
+    s.close()
+    kernels = {}
+    for k in KERNEL_KINDS:
+        tms, n, by = stats[k]
+        if n:
+            kernels[k] = dict(ms_per_step=tms / a.steps, launches_per_step=n / a.steps,
+                              gbs=(by / (tms * 1e-3) / 1e9) if by > 0 and tms > 0 else None)
+    tms, n, by = stats["sweep"]
+    achieved = by / n / (tms / n * 1e-3) / 1e9
+    return {
+        "metric": "DVM cell-velocity updates/s of the kinetic step (3D capsule, one velocity-space shard)",
+        "value": nc * nv * a.steps / (ms * 1e-3), "unit": "cell-velocity updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if a.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D blunt capsule (spherical cap + 33 deg cone), kinetic step on 1/8 of velocity space",
+                   "cells": nc, "velocities": nv, "velocities_full_grid": 24 ** 3, "distributions_per_velocity": 3,
+                   "ordinates": no, "Kn_gas": 0.01, "Mach": 10.0, "optical_thickness": 1.0},
+        "roofline": {"bound": "hbm", "kernel": "sweep", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": by / n},
+        "kernels": kernels,
+    }
 
 
 def warmstart_leg(a, case, stream, plain_fields):
@@ -128,6 +183,9 @@ def main():
     import numpy as np
     import torch
 
+    if a.workload == "capsule-shard":
+        print(json.dumps(bench_capsule_shard(a)), flush=True)
+        return
     if a.copy_probe:
         n = 1 << 28  # 1 GiB of float32
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")

@@ -187,13 +187,23 @@ def main():
         print(json.dumps(bench_capsule_shard(a)), flush=True)
         return
     if a.copy_probe:
+        # plain device copies: the calibration kernel of the HBM byte counters, and the bandwidth a
+        # streaming copy reaches on this GPU (context for the roofline fractions)
         n = 1 << 28  # 1 GiB of float32
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each": 4 * n, "copies": 3}), flush=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps({"copy_bytes_each": 4 * n, "copies": 13, "copy_ms": ms,
+                          "copy_gbs_read_plus_write": 2 * 4 * n / (ms * 1e-3) / 1e9}), flush=True)
         return
 
     from paper_2601_03935_amd.gsis import KERNEL_KINDS, Solver, oracle_opts

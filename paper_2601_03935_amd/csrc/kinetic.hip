@@ -107,6 +107,31 @@ __global__ __launch_bounds__(256) void k_grad(const T *__restrict__ f, T *__rest
 template <typename T, int VW>
 using vec_t = T __attribute__((ext_vector_type(VW)));
 
+// VW consecutive values at p (16-byte aligned when VW > 1)
+template <typename T, int VW>
+__device__ __forceinline__ void load_vw(const T *p, T *v)
+{
+    if constexpr (VW == 1) {
+        v[0] = p[0];
+    } else {
+        const vec_t<T, VW> x = *(const vec_t<T, VW> *)p;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[e] = x[e];
+    }
+}
+template <typename T, int VW>
+__device__ __forceinline__ void store_vw(T *p, const T *v)
+{
+    if constexpr (VW == 1) {
+        p[0] = v[0];
+    } else {
+        vec_t<T, VW> x;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) x[e] = v[e];
+        *(vec_t<T, VW> *)p = x;
+    }
+}
+
 template <typename T, int D, int NFM, int VW>
 __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__restrict__ gf, const MeshDev m,
                                                 const int64_t nv, const int second_order,
@@ -844,7 +869,7 @@ __global__ __launch_bounds__(256) void k_sweep_I(const T *__restrict__ r, const 
 // ------------------------------------------------------------------ moments (Eq. getmoment, reduced form)
 // Raw FP64 moments about a reference velocity u_ref (the cell's previous velocity) reduced across the
 // wave, then shifted to central moments.  mom layout: see MomLayout.
-template <typename T, int D>
+template <typename T, int D, int VW>
 __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const T *__restrict__ I,
                                                  const double *__restrict__ xi, const double *__restrict__ w,
                                                  const double *__restrict__ om, const double *__restrict__ wo,
@@ -870,9 +895,16 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
 #pragma unroll
         for (int bb = 0; bb < D; ++bb) m2[a][bb] = 0;
     }
-    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
-        const int64_t k = k0 + lane;
-        if (k >= nv) break;
+    for (int64_t kb = (int64_t)lane * VW; kb < nv; kb += kWave * VW) {
+      T fG[VW], fR[VW], fV[VW], fH[VW];
+      load_vw<T, VW>(f + ((int64_t)c * ND + 0) * nv + kb, fG);
+      load_vw<T, VW>(f + ((int64_t)c * ND + 1) * nv + kb, fR);
+      load_vw<T, VW>(f + ((int64_t)c * ND + 2) * nv + kb, fV);
+      if (ND == 4) load_vw<T, VW>(f + ((int64_t)c * ND + (ND == 4 ? 3 : 0)) * nv + kb, fH);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int64_t k = kb + e;
+        if (VW == 1 && k >= nv) break;
         const double wk = w[k];
         double cc[D], c2 = 0;
 #pragma unroll
@@ -880,10 +912,10 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
             cc[a] = xi[k * D + a] - ur[a];
             c2 += cc[a] * cc[a];
         }
-        const double G = wk * (double)f[((int64_t)c * ND + 0) * nv + k];
-        const double R = wk * (double)f[((int64_t)c * ND + 1) * nv + k];
-        const double V = wk * (double)f[((int64_t)c * ND + 2) * nv + k];
-        const double H = (ND == 4) ? wk * (double)f[((int64_t)c * ND + (ND == 4 ? 3 : 0)) * nv + k] : 0.0;
+        const double G = wk * (double)fG[e];
+        const double R = wk * (double)fR[e];
+        const double V = wk * (double)fV[e];
+        const double H = (ND == 4) ? wk * (double)fH[e] : 0.0;
         m0 += G;
         h0 += H;
         r0 += R;
@@ -898,6 +930,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
 #pragma unroll
             for (int bb = 0; bb < D; ++bb) m2[a][bb] += cc[a] * cc[bb] * G;
         }
+      }
     }
     m0 = wave_sum(m0);
     h0 = wave_sum(h0);
@@ -1175,7 +1208,7 @@ __global__ __launch_bounds__(64) void k_boundary_flux(const T *__restrict__ f, c
 // ------------------------------------------------------------------ synchronisation and initialisation
 // f += f^eq(M1) - f^eq(M0) with f^eq the multi-temperature equilibrium; I += (eR1 - eR0)/(4 pi).
 // sp per cell: [rho, u[D], Tt, Tr, Tv, eR] for M0 then M1.
-template <typename T, int D>
+template <typename T, int D, int VW>
 __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__ I, const double *__restrict__ sp,
                                               const double *__restrict__ xi, const int64_t nc, const int64_t nv,
                                               const int64_t no, const double dr, const double dv, const int init)
@@ -1189,9 +1222,15 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
     const int c = uni_i((int)ci);
     const double *s0 = sp + (int64_t)c * 2 * NS, *s1 = s0 + NS;
     const double n0 = s0[0] * pow(2 * kPi * s0[D + 1], -0.5 * D), n1 = s1[0] * pow(2 * kPi * s1[D + 1], -0.5 * D);
-    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
-        const int64_t k = k0 + lane;
-        if (k >= nv) break;
+    for (int64_t kb = (int64_t)lane * VW; kb < nv; kb += kWave * VW) {
+      T fv[4][VW];
+      if (!init) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) load_vw<T, VW>(f + ((int64_t)c * ND + d) * nv + kb, fv[d]);
+      }
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int64_t k = kb + e;
         double c20 = 0, c21 = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -1205,13 +1244,10 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
                               0.5 * dv * (s1[D + 3] * G1 - s0[D + 3] * G0),
                               (3 - D) * (s1[D + 1] * G1 - s0[D + 1] * G0)};
 #pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            const int64_t o = ((int64_t)c * ND + d) * nv + k;
-            if (init)
-                f[o] = (T)dG[d];
-            else
-                f[o] = (T)((double)f[o] + dG[d]);
-        }
+        for (int d = 0; d < ND; ++d) fv[d][e] = init ? (T)dG[d] : (T)((double)fv[d][e] + dG[d]);
+      }
+#pragma unroll
+      for (int d = 0; d < ND; ++d) store_vw<T, VW>(f + ((int64_t)c * ND + d) * nv + kb, fv[d]);
     }
     const double dI = init ? s1[D + 4] / (4 * kPi) : (s1[D + 4] - s0[D + 4]) / (4 * kPi);
     for (int64_t q0 = 0; q0 < no; q0 += kWave) {
@@ -1333,8 +1369,13 @@ template <typename T, int D>
 void launch_moments(const KinBufs<T> &B, const double *uref, double *mom, int64_t nc, int64_t nv, int64_t no,
                     const Phys &p, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_moments<T, D>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d,
-                       B.om_d, B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
+    constexpr int VW = 16 / sizeof(T);
+    if (nv % VW == 0)
+        hipLaunchKernelGGL((k_moments<T, D, VW>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d,
+                           B.om_d, B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
+    else
+        hipLaunchKernelGGL((k_moments<T, D, 1>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d,
+                           B.om_d, B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
 }
 
 template <typename T, int D>
@@ -1361,8 +1402,13 @@ template <typename T, int D>
 void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_t no, const Phys &p, int init,
                  hipStream_t st)
 {
-    hipLaunchKernelGGL((k_sync<T, D>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, sp, B.xi_d, nc, nv, no,
-                       p.d_r, p.d_v, init);
+    constexpr int VW = 16 / sizeof(T);
+    if (nv % VW == 0)
+        hipLaunchKernelGGL((k_sync<T, D, VW>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, sp, B.xi_d, nc, nv,
+                           no, p.d_r, p.d_v, init);
+    else
+        hipLaunchKernelGGL((k_sync<T, D, 1>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, sp, B.xi_d, nc, nv,
+                           no, p.d_r, p.d_v, init);
 }
 
 #define GSIS_INST_D(T, D, NFM)                                                                                    \

@@ -77,7 +77,7 @@ typedef struct {
 
 /* Iteration options.  Defaults (gsis_default_opts): GSIS, FP32, tol 1e-6, max_outer 1000,
  * n_precond 10, cfl_meso 1e5, cfl_v 5, kin_sweeps 8, kin_omega 1, limiter_K 5, second_order 1,
- * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2. */
+ * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2, first_order_iters 0. */
 typedef struct {
     int32_t scheme;       /* GSIS_CIS or GSIS_GSIS */
     int32_t precision;    /* GSIS_FP64 or GSIS_FP32: storage and arithmetic of f and I */
@@ -94,6 +94,8 @@ typedef struct {
     double inner_tol;     /* relative drop of the macro residual that ends the inner solve */
     int32_t max_inner;    /* inner iteration limit */
     int32_t n_sweeps;     /* Jacobi sweeps of the macro implicit operator */
+    int32_t first_order_iters; /* gsis_solve: the first this many outer iterations use first-order
+                                  reconstruction (start-up of strongly non-equilibrium flows); 0 = none */
 } gsis_opts;
 
 typedef struct {

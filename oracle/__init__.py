@@ -54,6 +54,7 @@ def _load():
         lib.orc_iterate.restype = C.c_double
         lib.orc_solve.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_int, P]
         lib.orc_solve.restype = C.c_int
+        lib.orc_set_second_order.argtypes = [P, C.c_int]
         _lib = lib
     return _lib
 
@@ -183,10 +184,29 @@ class Oracle:
         e = self.lib.orc_iterate(self.h, int(bool(gsis)), C.byref(inner))
         return e, inner.value
 
-    def solve(self, gsis=True, n_precond=10, tol=1e-6, max_outer=1000):
-        hist = np.zeros(max_outer)
-        n = self.lib.orc_solve(self.h, int(bool(gsis)), int(n_precond), float(tol), int(max_outer), _p(hist))
-        return n, hist[: abs(n)]
+    def set_second_order(self, so: int):
+        """Switch the face reconstruction order between iterations (start-up protocols)."""
+        self.lib.orc_set_second_order(self.h, int(so))
+
+    def solve(self, gsis=True, n_precond=10, tol=1e-6, max_outer=1000, first_order_iters=0):
+        """n_precond conventional iterations then GSIS, the first `first_order_iters` iterations with first-order
+        reconstruction.  Returns (iterations, eps history); negative iterations flag a NaN residual."""
+        if first_order_iters <= 0:
+            hist = np.zeros(max_outer)
+            n = self.lib.orc_solve(self.h, int(bool(gsis)), int(n_precond), float(tol), int(max_outer), _p(hist))
+            return n, hist[: abs(n)]
+        so = int(self.opts["second_order"])
+        hist = []
+        for k in range(max_outer):
+            self.set_second_order(0 if k < first_order_iters else so)
+            e, _ = self.iterate(gsis=gsis and k >= n_precond)
+            hist.append(e)
+            if e != e:
+                return -(k + 1), np.array(hist)
+            if e < tol:
+                return k + 1, np.array(hist)
+        self.set_second_order(so)
+        return max_outer, np.array(hist)
 
 
 def field_names(D: int):

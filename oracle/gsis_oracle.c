@@ -1216,13 +1216,18 @@ static void local_solve(const orc_t *o, const prim_t *p, const double *rhs, cons
 }
 
 /* W += alpha dU (the increment of e is dU_egas + dU_eR), alpha = 2^-m the largest factor (m <= 20) keeping
- * rho, T_t, e_r, e_v and e_R at least half their current values (reading: a positivity safeguard of the
- * pseudo-time update; it never acts once the solve is near its steady state). */
-static void positive_update(const orc_t *o, double *W, const double *dU)
+ * rho, T_t, e_r, e_v and e_R at least half their current values and within a factor two of their values Ws
+ * at the start of the solve (the kinetic moments); no update when no such factor exists.
+ * reading: a positivity and trust-region safeguard of the pseudo-time update.  The paper states none; it
+ * never acts once the outer iteration is near its fixed point (the macro state then stays close to the
+ * kinetic moments), but it keeps hypersonic start-ups (Ma 5 cylinder) from driving the synthetic solve to
+ * vanishing temperatures in the expansion or to overflow. */
+static void positive_update(const orc_t *o, double *W, const double *dU, const double *Ws)
 {
     int D = o->D, NW = NWof(D);
-    prim_t p0;
+    prim_t p0, ps;
     prim_of(o, W, &p0);
+    prim_of(o, Ws, &ps);
     double a = 1.0;
     for (int m = 0; m <= 20; ++m, a *= 0.5) {
         double Wn[8];
@@ -1231,7 +1236,10 @@ static void positive_update(const orc_t *o, double *W, const double *dU)
         prim_t p1;
         prim_of(o, Wn, &p1);
         if (Wn[0] >= 0.5 * W[0] && p1.Tt >= 0.5 * p0.Tt && Wn[D + 2] >= 0.5 * W[D + 2] &&
-            Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4]) {
+            Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4] && Wn[0] >= 0.5 * Ws[0] &&
+            p1.Tt >= 0.5 * ps.Tt && Wn[D + 2] >= 0.5 * Ws[D + 2] && Wn[D + 3] >= 0.5 * Ws[D + 3] &&
+            Wn[D + 4] >= 0.5 * Ws[D + 4] && Wn[0] <= 2 * Ws[0] && p1.Tt <= 2 * ps.Tt &&
+            Wn[D + 2] <= 2 * Ws[D + 2] && Wn[D + 3] <= 2 * Ws[D + 3] && Wn[D + 4] <= 2 * Ws[D + 4]) {
             for (int i = 0; i < NW; ++i) W[i] = Wn[i];
             return;
         }
@@ -1279,6 +1287,8 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
     double *bcorr = (double *)malloc((size_t)o->nf * NW * sizeof(double));
     prim_t *P = (prim_t *)malloc(nc * sizeof(prim_t));
     double *dref = o->diss_ref ? (double *)malloc((size_t)o->nf * NW * sizeof(double)) : NULL;
+    double *W0 = (double *)malloc(nc * NW * sizeof(double));
+    memcpy(W0, W, nc * NW * sizeof(double));
     face_hot(o, m, hotf);
     boundary_corr(o, W, bcorr);
     if (dref) dissipation_ref(o, W, dref);
@@ -1376,12 +1386,13 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
             dW = dW2;
             dW2 = t;
         }
-        for (int64_t c = 0; c < nc; ++c) positive_update(o, W + c * NW, dW + c * NW);
+        for (int64_t c = 0; c < nc; ++c) positive_update(o, W + c * NW, dW + c * NW, W0 + c * NW);
     }
     /* reading: in a domain closed by walls the solution is rescaled to the mass the outer iteration
      * started from (see rescale_mass) */
     if (domain_closed(o)) rescale_mass(o, W, mass_target);
     o->last_inner = it;
+    free(W0);
     free(R);
     free(Dg);
     free(dW);
@@ -1768,6 +1779,9 @@ double orc_iterate(orc_t *o, int gsis, int *inner)
     free(m1);
     return e;
 }
+
+/* Switch the face reconstruction between first (0) and second (1) order between iterations. */
+void orc_set_second_order(orc_t *o, int so) { o->second_order = so; }
 
 /* Solve: n_precond CIS iterations, then GSIS (or CIS only when gsis = 0) until eps < tol or max_outer.
  * hist receives eps per iteration (capacity max_outer). Returns the iteration count. */

@@ -751,6 +751,7 @@ void gsis_default_opts(gsis_opts *o)
     o->cfl_macro = 1e3;
     o->inner_tol = 1e-7;
     o->max_inner = 100;
+    o->first_order_iters = 0;
     o->n_sweeps = 2;
 }
 
@@ -884,7 +885,8 @@ int32_t gsis_set_opts(gsis_t *h, const gsis_opts *o)
     if (!(h->have_mesh && h->have_vel && h->have_ord && h->have_gas && h->have_flow))
         return fail(h, GSIS_E_STATE, "gsis_set_opts: mesh, grids, gas and flow must be set first");
     if ((o->precision != GSIS_FP32 && o->precision != GSIS_FP64) || o->kin_sweeps < 0 || o->max_inner < 0 ||
-        o->n_sweeps < 0 || !(o->cfl_v > 0) || !(o->cfl_meso > 0) || !(o->cfl_macro > 0))
+        o->n_sweeps < 0 || o->first_order_iters < 0 || !(o->cfl_v > 0) || !(o->cfl_meso > 0) ||
+        !(o->cfl_macro > 0))
         return fail(h, GSIS_E_ARG, "gsis_set_opts: invalid options");
     (void)hipSetDevice(h->device);
     const bool realloc = !h->have_state || o->precision != h->prec || o->limiter_K != h->opts.limiter_K;
@@ -995,8 +997,10 @@ int32_t gsis_solve(gsis_t *h, gsis_report *rep)
     int k = 0;
     int32_t status = GSIS_W_NOT_CONVERGED;
     auto t0 = std::chrono::steady_clock::now();
+    const int32_t so_user = h->opts.second_order;
     for (k = 0; k < h->opts.max_outer; ++k) {
         const bool g = (h->opts.scheme == GSIS_GSIS) && k >= h->opts.n_precond;
+        h->opts.second_order = (k < h->opts.first_order_iters) ? 0 : so_user;
         int in = 0;
         e = (h->prec == GSIS_FP32) ? iterate_T(h, h->Bf, g, &in, &tk, &tm) : iterate_T(h, h->Bd, g, &in, &tk, &tm);
         inner_total += in;
@@ -1012,6 +1016,7 @@ int32_t gsis_solve(gsis_t *h, gsis_report *rep)
             break;
         }
     }
+    h->opts.second_order = so_user;
     const double tt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     hipError_t herr = hipGetLastError();
     if (herr != hipSuccess) return fail(h, GSIS_E_DEVICE, std::string("gsis_solve: ") + hipGetErrorString(herr));

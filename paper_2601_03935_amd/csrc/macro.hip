@@ -268,13 +268,15 @@ __device__ __forceinline__ void local_solve(const double *rhs, const double *Dg,
     dU[ig] = (rhs[ig] - k * ep * dv + k * dR) / Dg[ig];
 }
 
-// W += a dU with a = 2^-m the largest factor (m <= 20) keeping rho, T_t, e_r, e_v, e_R at least half
+// W += a dU with a = 2^-m the largest factor (m <= 20) keeping rho, T_t, e_r, e_v, e_R at least half their
+// current values and within a factor two of their values Ws at the start of the solve; no update if none
 template <int D>
-__device__ __forceinline__ void positive_update(double *W, const double *dU)
+__device__ __forceinline__ void positive_update(double *W, const double *dU, const double *Ws)
 {
     constexpr int NW = D + 5;
-    PrimL p0;
+    PrimL p0, ps;
     prim_lite<D>(W, p0);
+    prim_lite<D>(Ws, ps);
     double a = 1.0;
     for (int m = 0; m <= 20; ++m, a *= 0.5) {
         double Wn[NW];
@@ -284,7 +286,10 @@ __device__ __forceinline__ void positive_update(double *W, const double *dU)
         PrimL p1;
         prim_lite<D>(Wn, p1);
         if (Wn[0] >= 0.5 * W[0] && p1.Tt >= 0.5 * p0.Tt && Wn[D + 2] >= 0.5 * W[D + 2] &&
-            Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4]) {
+            Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4] && Wn[0] >= 0.5 * Ws[0] &&
+            p1.Tt >= 0.5 * ps.Tt && Wn[D + 2] >= 0.5 * Ws[D + 2] && Wn[D + 3] >= 0.5 * Ws[D + 3] &&
+            Wn[D + 4] >= 0.5 * Ws[D + 4] && Wn[0] <= 2 * Ws[0] && p1.Tt <= 2 * ps.Tt &&
+            Wn[D + 2] <= 2 * Ws[D + 2] && Wn[D + 3] <= 2 * Ws[D + 3] && Wn[D + 4] <= 2 * Ws[D + 4]) {
 #pragma unroll
             for (int i = 0; i < NW; ++i) W[i] = Wn[i];
             return;
@@ -721,8 +726,8 @@ __global__ __launch_bounds__(kMBlk) void k_msweep(
     const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ R,
     const double *__restrict__ Dg, const double *__restrict__ Gf, const double *__restrict__ dUin,
     double *__restrict__ dUout, double *__restrict__ Wn_out, double *__restrict__ Pn_out, double *__restrict__ fn_out,
-    const MeshDev m, const Phys p, const double *__restrict__ part, const int it, const double tol,
-    double *__restrict__ scal, int *__restrict__ flags)
+    const double *__restrict__ W0, const MeshDev m, const Phys p, const double *__restrict__ part, const int it,
+    const double tol, double *__restrict__ scal, int *__restrict__ flags)
 {
     constexpr int NW = D + 5, NP = D + 8, NF = D + 4, MG = 2 * D + 2;
     if (flags[0]) return;
@@ -775,7 +780,7 @@ __global__ __launch_bounds__(kMBlk) void k_msweep(
         double Wc[NW];
 #pragma unroll
         for (int i = 0; i < NW; ++i) Wc[i] = W[c * NW + i];
-        positive_update<D>(Wc, d1);
+        positive_update<D>(Wc, d1, W0 + c * NW);
 #pragma unroll
         for (int i = 0; i < NW; ++i) Wn_out[c * NW + i] = Wc[i];
         store_prim<D>(Wc, p, Pn_out + c * NP, fn_out + c * NF);
@@ -785,7 +790,8 @@ __global__ __launch_bounds__(kMBlk) void k_msweep(
 // update without sweeps (in place: the kernel reads only its own cell) and the new primitives
 template <int D>
 __global__ __launch_bounds__(kMBlk) void k_mupdate(double *__restrict__ W, const double *__restrict__ dU,
-                                                   double *__restrict__ P, double *__restrict__ fld, const int64_t nc,
+                                                   double *__restrict__ P, double *__restrict__ fld,
+                                                   const double *__restrict__ W0, const int64_t nc,
                                                    const Phys p, const double *__restrict__ part, const int it,
                                                    const double tol, double *__restrict__ scal,
                                                    int *__restrict__ flags)
@@ -801,7 +807,7 @@ __global__ __launch_bounds__(kMBlk) void k_mupdate(double *__restrict__ W, const
         Wc[i] = W[c * NW + i];
         d[i] = dU[c * NW + i];
     }
-    positive_update<D>(Wc, d);
+    positive_update<D>(Wc, d, W0 + c * NW);
 #pragma unroll
     for (int i = 0; i < NW; ++i) W[c * NW + i] = Wc[i];
     store_prim<D>(Wc, p, P + c * NP, fld + c * NF);
@@ -900,13 +906,13 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
             auto kern = first ? (last ? k_msweep<D, NFM, true, true> : k_msweep<D, NFM, true, false>)
                               : (last ? k_msweep<D, NFM, false, true> : k_msweep<D, NFM, false, false>);
             hipLaunchKernelGGL(kern, gci, bi, 0, st, W, P, B.R, B.Dg, B.Gf, din, last ? nullptr : dout,
-                               last ? Wb[nxt] : nullptr, last ? Pb[nxt] : nullptr, last ? Fb[nxt] : nullptr, m, p,
-                               B.part, it, o.inner_tol, B.scal, B.flags);
+                               last ? Wb[nxt] : nullptr, last ? Pb[nxt] : nullptr, last ? Fb[nxt] : nullptr, B.W0, m,
+                               p, B.part, it, o.inner_tol, B.scal, B.flags);
             std::swap(din, dout);
         }
         if (!pingpong)
-            hipLaunchKernelGGL(k_mupdate<D>, gci, bi, 0, st, W, B.dU0, P, fld, nc, p, B.part, it, o.inner_tol, B.scal,
-                               B.flags);
+            hipLaunchKernelGGL(k_mupdate<D>, gci, bi, 0, st, W, B.dU0, P, fld, B.W0, nc, p, B.part, it, o.inner_tol,
+                               B.scal, B.flags);
         if ((it + 1) % poll == 0) {
             (void)hipMemcpyAsync(host_flags, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
             (void)hipStreamSynchronize(st);

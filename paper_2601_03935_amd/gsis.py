@@ -51,7 +51,7 @@ class gsis_opts(C.Structure):
                 ("n_precond", C.c_int32), ("cfl_meso", C.c_double), ("cfl_v", C.c_double),
                 ("kin_sweeps", C.c_int32), ("kin_omega", C.c_double), ("limiter_K", C.c_double),
                 ("second_order", C.c_int32), ("cfl_macro", C.c_double), ("inner_tol", C.c_double),
-                ("max_inner", C.c_int32), ("n_sweeps", C.c_int32)]
+                ("max_inner", C.c_int32), ("n_sweeps", C.c_int32), ("first_order_iters", C.c_int32)]
 
 
 class gsis_report(C.Structure):

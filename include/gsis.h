@@ -128,6 +128,11 @@ int32_t gsis_set_mesh(gsis_t *h, int32_t dim, int64_t nc, int64_t nf, const doub
                       const int64_t *face_cells, const double *face_n, const double *face_area,
                       const double *face_ctr, int32_t nbc, const gsis_bc *bcs);
 
+/* Replace the state of boundary tag `tag` (0 <= tag < nbc of gsis_set_mesh) between iterations, e.g. to
+ * raise a free-stream Mach number step by step from a converged state (continuation).  The kind must
+ * stay the same (GSIS_E_ARG otherwise); the distributions are kept. */
+int32_t gsis_set_boundary(gsis_t *h, int32_t tag, const gsis_bc *bc);
+
 /* Discrete velocities xi[nv*dim] with quadrature weights w[nv] (int g dxi ~ sum w_k g(xi_k)). */
 int32_t gsis_set_velocity_grid(gsis_t *h, int64_t nv, const double *xi, const double *w);
 

@@ -827,6 +827,27 @@ int32_t gsis_set_mesh(gsis_t *h, int32_t dim, int64_t nc, int64_t nf, const doub
     return rc;
 }
 
+int32_t gsis_set_boundary(gsis_t *h, int32_t tag, const gsis_bc *bc)
+{
+    if (!h || !bc) return GSIS_E_ARG;
+    if (!h->have_mesh) return fail(h, GSIS_E_STATE, "gsis_set_boundary: call gsis_set_mesh first");
+    if (tag < 0 || tag >= (int32_t)h->hm.bcs.size() || bc->kind != h->hm.bcs[tag].kind || !(bc->T > 0) ||
+        !(bc->rho > 0))
+        return fail(h, GSIS_E_ARG, "gsis_set_boundary: bad tag, kind change or non-positive state");
+    h->hm.bcs[tag] = *bc;
+    if (h->m.bcs) {
+        BcDev d;
+        d.kind = bc->kind;
+        d.rho = bc->rho;
+        d.T = bc->T;
+        for (int a = 0; a < 3; ++a) d.u[a] = bc->u[a];
+        (void)hipSetDevice(h->device);
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        HIPCHECK(h, hipMemcpy(h->m.bcs + tag, &d, sizeof(BcDev), hipMemcpyHostToDevice));
+    }
+    return GSIS_OK;
+}
+
 int32_t gsis_set_velocity_grid(gsis_t *h, int64_t nv, const double *xi, const double *w)
 {
     if (!h) return GSIS_E_ARG;

@@ -25,7 +25,7 @@ GSIS_FP64, GSIS_FP32 = 0, 1
 # every entry point declared in include/gsis.h
 EXPORTS = [
     "gsis_create", "gsis_destroy", "gsis_last_error", "gsis_default_opts", "gsis_set_stream", "gsis_set_mesh",
-    "gsis_set_velocity_grid", "gsis_set_ordinates", "gsis_set_gas", "gsis_set_flow", "gsis_set_opts",
+    "gsis_set_velocity_grid", "gsis_set_boundary", "gsis_set_ordinates", "gsis_set_gas", "gsis_set_flow", "gsis_set_opts",
     "gsis_init_equilibrium", "gsis_init_fields", "gsis_set_state", "gsis_get_state", "gsis_iterate", "gsis_solve",
     "gsis_kinetic_step", "gsis_macro_solve", "gsis_sync", "gsis_nfields", "gsis_get_fields",
     "gsis_get_residual_history", "gsis_get_surface_flux", "gsis_get_counters", "gsis_set_profiling",
@@ -93,6 +93,7 @@ def lib():
         "gsis_macro_solve": ([P, P, C.POINTER(I32)], I32),
         "gsis_sync": ([P, P], I32),
         "gsis_init_fields": ([P, P, P, P, P, P, P], I32),
+        "gsis_set_boundary": ([P, I32, C.POINTER(gsis_bc)], I32),
         "gsis_nfields": ([P], I32),
         "gsis_get_fields": ([P, P], I32),
         "gsis_get_residual_history": ([P, P, I64, C.POINTER(I64)], I32),
@@ -172,6 +173,43 @@ class Solver:
         self.opts = default_opts(**opts)
         self._check(self.L.gsis_set_opts(self.h, C.byref(self.opts)), "gsis_set_opts")
         self.init_equilibrium(case.init_rho, case.init_u, case.init_T)
+
+    def set_boundary(self, tag, kind, rho, T, u):
+        """New state for a boundary tag (same kind), e.g. a Mach-number continuation step."""
+        b = gsis_bc()
+        b.kind, b.rho, b.T = int(kind), float(rho), float(T)
+        for a in range(3):
+            b.u[a] = float(u[a]) if a < len(u) else 0.0
+        self._check(self.L.gsis_set_boundary(self.h, int(tag), C.byref(b)), "gsis_set_boundary")
+
+    def solve_continuation(self, tag, states, stage_tol=1e-4, tol=1e-6, max_stage=400, n_precond=40,
+                           first_order_iters=60, first_order_jump=10):
+        """Continuation in the boundary state of `tag` (e.g. free-stream Mach 2, 3, 4, 5): each (rho, T, u)
+        in `states` is imposed in turn and GSIS iterated until epsilon < stage_tol (tol for the last one)
+        or max_stage iterations.  The first stage starts with n_precond conventional iterations and uses
+        first-order reconstruction for its first `first_order_iters` iterations; later stages for their
+        first `first_order_jump`.  Returns (iterations per stage, epsilon history, converged)."""
+        so = int(self.opts.second_order)
+        kind = self.case.bcs[tag]["kind"]
+        its, hist = [], []
+        ok = False
+        for i, (rho, T, u) in enumerate(states):
+            self.set_boundary(tag, kind, rho, T, u)
+            last = i == len(states) - 1
+            thr = tol if last else stage_tol
+            k = 0
+            while k < max_stage:
+                nfo = first_order_iters if i == 0 else first_order_jump
+                self.set_opts(second_order=0 if k < nfo else so)
+                e, _ = self.iterate(gsis=(i > 0 or k >= n_precond))
+                hist.append(e)
+                k += 1
+                if e < thr and k > nfo:
+                    break
+            its.append(k)
+            ok = bool(hist[-1] < thr)
+        self.set_opts(second_order=so)
+        return its, np.asarray(hist), ok
 
     def set_opts(self, **kw):
         """Change options between iterations; the state is kept unless the precision or the limiter

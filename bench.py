@@ -68,6 +68,7 @@ def parse():
                          "of the 3D capsule on one eighth of its velocity space (one GPU's share); cylinder: the "
                          "Ma 5 cylinder solved from the free stream to the tolerance")
     ap.add_argument("--cyl-Kn", type=float, default=0.01, help="Kn of the cylinder workload")
+    ap.add_argument("--max-stage", type=int, default=400, help="iteration limit per Mach stage (cylinder)")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--ws-cases", type=int, default=24, help="training cases of the warm-start network")
     ap.add_argument("--copy-probe", action="store_true",
@@ -149,7 +150,7 @@ def bench_cylinder(a):
     states = [(1.0, 1.0, (Ma * np.sqrt(gam), 0.0, 0.0)) for Ma in (2.0, 3.0, 4.0, 5.0)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    its, hist, ok = s.solve_continuation(1, states, stage_tol=1e-4, tol=a.tol)
+    its, hist, ok = s.solve_continuation(1, states, stage_tol=1e-4, tol=a.tol, max_stage=a.max_stage)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     s.set_profiling(True)

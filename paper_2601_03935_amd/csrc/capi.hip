@@ -774,7 +774,8 @@ void gsis_destroy(gsis_t *h)
 {
     if (!h) return;
     (void)hipSetDevice(h->device);
-    if (h->stream) hipStreamSynchronize(h->stream);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    h->prof.destroy();
     free_state(h);
     free_mesh(h->m);
     delete h;

@@ -29,6 +29,7 @@ EXPORTS = [
 
 N_IN, N_OUT = 7, 7
 HOLE = (0.35, 0.65)
+FEATURES = {}
 
 
 class gsis_mlp_train_opts(C.Structure):
@@ -176,6 +177,20 @@ def cavity_features(case) -> np.ndarray:
                      np.full(n, u_lid), x, y, np.minimum(d_outer, d_hole), 1 - y], axis=1)
 
 
+def cylinder_features(case) -> np.ndarray:
+    """Per-cell features [log10 Kn, Mach, log10 tau_opt, x, y, wall distance, cos, sin of the polar angle]
+    for flows past the unit cylinder."""
+    ctr = case.mesh.ctr
+    x, y = ctr[:, 0], ctr[:, 1]
+    r = np.hypot(x, y)
+    n = case.mesh.nc
+    return np.stack([np.full(n, np.log10(case.flow.Kn_gas)), np.full(n, case.meta.get("Ma", 0.0)),
+                     np.full(n, np.log10(case.flow.k_eff)), x, y, r - 1.0, x / r, y / r], axis=1)
+
+
+FEATURES.update(cavity=(cavity_features, 7), cylinder=(cylinder_features, 8))
+
+
 def field_targets(F: np.ndarray) -> np.ndarray:
     """[log rho, u_x, u_y, log T_t, log T_r, log T_v, log T_R] from the library's 2D field array."""
     return np.stack([np.log(F[:, 0]), F[:, 1], F[:, 2], np.log(F[:, 3]), np.log(F[:, 4]), np.log(F[:, 5]),
@@ -188,10 +203,13 @@ def targets_to_fields(Y: np.ndarray) -> dict:
 
 
 class WarmStart:
-    """Standardisation + network; fit on (features, targets) of converged cases, predict initial fields."""
+    """Standardisation + network; fit on (features, targets) of converged cases, predict initial fields.
+    `family` selects the feature set ("cavity" or "cylinder")."""
 
-    def __init__(self, width=256, bf16=True, seed=0, device=0, stream=None):
-        self.net = MLP(N_IN, width, N_OUT, bf16=bf16, seed=seed, device=device, stream=stream)
+    def __init__(self, width=256, bf16=True, seed=0, device=0, stream=None, family="cavity"):
+        self.family = family
+        self.features, n_in = FEATURES[family]
+        self.net = MLP(n_in, width, N_OUT, bf16=bf16, seed=seed, device=device, stream=stream)
         self.xm = self.xs = self.ym = self.ys = None
 
     def fit(self, X, Y, epochs=40, batch=4096, lr=2e-3, seed=0):
@@ -209,7 +227,7 @@ class WarmStart:
         """Start `solver` from the predicted fields.  In a domain closed by walls the total mass is an input
         (the iteration conserves it), so the predicted density is rescaled to the mass of the case's own
         initial state."""
-        f = targets_to_fields(self.predict(cavity_features(case)))
+        f = targets_to_fields(self.predict(self.features(case)))
         if all(b["kind"] == 0 for b in case.bcs):
             V = case.mesh.vol
             f["rho"] = f["rho"] * (np.dot(V, case.init_rho) / np.dot(V, f["rho"]))
@@ -237,11 +255,59 @@ def converged_fields(case, device=0, stream=None, **opts):
     return F, int(rep.iters), dt, rc == 0
 
 
-def training_set(cases, device=0, stream=None, **opts):
-    """Features and targets stacked over converged cases."""
+def training_set(cases, device=0, stream=None, family="cavity", **opts):
+    """Features and targets stacked over converged cases (solved from their uniform start)."""
+    feat = FEATURES[family][0]
     X, Y = [], []
     for c in cases:
         F, _, _, ok = converged_fields(c, device=device, stream=stream, **opts)
-        X.append(cavity_features(c))
+        X.append(feat(c))
         Y.append(field_targets(F))
     return np.concatenate(X), np.concatenate(Y)
+
+
+def continuation_fields(case, tag, mach_steps, device=0, stream=None, stage_tol=1e-4, tol=1e-6, **opts):
+    """Solve a free-stream case by Mach continuation up to case.meta["Ma"]; returns (fields, total
+    iterations, seconds, converged)."""
+    g = case.gas.gamma
+    s = Solver(case, device=device, stream=stream, **opts)
+    Ma = case.meta["Ma"]
+    states = [(1.0, 1.0, (m * np.sqrt(g), 0.0, 0.0)) for m in list(mach_steps) + [Ma]]
+    n, D = case.mesh.nc, case.mesh.dim
+    u0 = np.zeros((n, D))
+    u0[:, 0] = states[0][2][0]
+    s.init_equilibrium(np.ones(n), u0, np.ones(n))  # uniform free stream of the first stage
+    t0 = time.perf_counter()
+    its, hist, ok = s.solve_continuation(tag, states, stage_tol=stage_tol, tol=tol)
+    dt = time.perf_counter() - t0
+    F = s.fields()
+    s.close()
+    return F, int(sum(its)), dt, ok
+
+
+def mach_steps(Ma):
+    """Intermediate free-stream Mach numbers of the continuation towards Ma (2, 3, 4 below Ma)."""
+    return [x for x in (2.0, 3.0, 4.0) if x < Ma - 0.25]
+
+
+def cylinder_training_set(cases, device=0, stream=None, tol=1e-6, **opts):
+    """Features and targets of cylinder cases solved from the free stream by Mach continuation; cases whose
+    solve fails or does not converge are skipped.  Returns (X, Y, per-case records)."""
+    X, Y, info = [], [], []
+    for c in cases:
+        rec = dict(Ma=c.meta["Ma"], Kn=c.flow.Kn_gas, tau=c.flow.k_eff)
+        try:
+            F, it, dt, ok = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), device=device, stream=stream,
+                                                tol=tol, **opts)
+        except GsisError as ex:
+            rec.update(ok=False, error=str(ex))
+            info.append(rec)
+            continue
+        rec.update(ok=ok, iterations=it, seconds=dt)
+        info.append(rec)
+        if ok:
+            X.append(cylinder_features(c))
+            Y.append(field_targets(F))
+    if not X:
+        raise GsisError("no training case converged")
+    return np.concatenate(X), np.concatenate(Y), info

@@ -110,3 +110,35 @@ def test_warm_start_saves_iterations():
             assert np.linalg.norm(F1[:, i] - F0[:, i]) <= 1e-4 * np.linalg.norm(F0[:, i])
     print("plain", plain_it, "warm", warm_it)
     assert np.mean(warm_it) < np.mean(plain_it)
+
+
+def test_warm_start_replaces_mach_continuation():
+    """Hypersonic cylinders (Mach 3-5, Kn 0.01-0.1, optical thickness 0.3-3, 6,144 triangles, 32 x 32
+    velocities): solved from the free stream they need a Mach continuation; started from the network's
+    prediction they converge directly at their Mach number, in fewer iterations, to the same fields."""
+    from paper_2601_03935_amd.warmstart import continuation_fields, cylinder_training_set, mach_steps
+    from workloads import case_cylinder, mesh_annulus, warmstart_cylinder_params
+
+    mesh = mesh_annulus(n_theta=96, n_r=32)
+    kw = dict(nvx=32, xmax=12.0, sigma_R=0.1, n_theta=2, n_phi=4)
+    P = warmstart_cylinder_params(12, seed=3)
+    train = [case_cylinder(mesh=mesh, Ma=m, Kn=k, tau_opt=t, **kw) for m, k, t in P]
+    X, Y, info = cylinder_training_set(train, limiter_K=1.0)
+    assert sum(r["ok"] for r in info) >= 6, info
+    ws = WS.WarmStart(width=256, seed=0, family="cylinder")
+    ws.fit(X, Y, epochs=200, batch=2048, lr=2e-3)
+    tests = [case_cylinder(mesh=mesh, Ma=4.17, Kn=0.062, tau_opt=1.72, **kw),
+             case_cylinder(mesh=mesh, Ma=4.48, Kn=0.037, tau_opt=2.27, **kw)]
+    for c in tests:
+        F0, it0, _, ok0 = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), limiter_K=1.0, tol=1e-6)
+        s = Solver(c, limiter_K=1.0, tol=1e-6, max_outer=800, n_precond=10, first_order_iters=20)
+        pred = ws.init_solver(s, c)
+        rc, rep, _ = s.solve()
+        F1 = s.fields()
+        s.close()
+        print("Ma %.2f: continuation %d iterations, warm start %d" % (c.meta["Ma"], it0, rep.iters))
+        assert ok0 and rc == 0
+        assert rep.iters < it0
+        assert np.linalg.norm(pred["Tt"] - F0[:, 3]) < 0.1 * np.linalg.norm(F0[:, 3])
+        for i in (0, 3, 7):
+            assert np.linalg.norm(F1[:, i] - F0[:, i]) <= 1e-4 * np.linalg.norm(F0[:, i])

@@ -28,4 +28,5 @@ from .cases import (  # noqa: F401
     case_capsule,
     warmstart_case_params,
     warmstart_cavity_params,
+    warmstart_cylinder_params,
 )

@@ -150,3 +150,13 @@ def warmstart_cavity_params(n: int = 32, seed: int = 2):
     tau = 10 ** rng.uniform(np.log10(0.3), np.log10(3.0), n)
     ulid = rng.uniform(0.1, 0.3, n)
     return np.stack([Kn, tau, ulid], axis=1)
+
+
+def warmstart_cylinder_params(n: int = 16, seed: int = 3):
+    """Seeded (Mach, Kn, optical thickness) draws for warm-start training sets on the cylinder family:
+    Mach uniform in [3, 5], Kn log-uniform in [0.01, 0.1], optical thickness log-uniform in [0.3, 3]."""
+    rng = np.random.default_rng(seed)
+    Ma = rng.uniform(3.0, 5.0, n)
+    Kn = 10 ** rng.uniform(np.log10(0.01), np.log10(0.1), n)
+    tau = 10 ** rng.uniform(np.log10(0.3), np.log10(3.0), n)
+    return np.stack([Ma, Kn, tau], axis=1)

@@ -2,11 +2,14 @@
 // source, Jacobi sweeps of the first-order implicit operator, moments, wall re-emission, boundary flux
 // moments, synchronisation and equilibrium initialisation.
 //
-// Mapping: one wavefront (64 lanes) per cell; lanes run over the discrete velocities (or ordinates) of
-// that cell in chunks of 64, so every row f[cell][slot][0..nv) is read and written with unit stride.
-// Per-cell geometry and coefficients are wave-uniform and live in scalar registers.  Four cells per
-// 256-thread workgroup; workgroups are remapped so that each of the 8 XCDs walks a contiguous range of
-// (Morton-ordered) cells and finds neighbour rows in its own L2.
+// Mapping: lanes run over the discrete velocities (or ordinates) of one cell, so every row
+// f[cell][slot][0..nv) is read and written with unit stride.  The vector kernels over velocities
+// (gradients, residual, sweeps, synchronisation) give each wavefront one chunk of 64 x VW velocities of one
+// cell (VW values of 16 bytes per lane) and end it there: many short waves, no loop-carried waits.  The
+// moment reduction gives each cell a 4-wave workgroup; the scalar fallbacks and the ordinate kernels use
+// one wavefront per cell looping over chunks of 64.  Per-cell geometry and coefficients are wave-uniform
+// and live in scalar registers.  Workgroups are remapped so that each of the 8 XCDs walks a contiguous
+// range of (Morton-ordered) cells and finds neighbour rows in its own L2.
 #include "gsis_dev.h"
 #include "gsis_kernels.h"
 
@@ -134,31 +137,31 @@ __device__ __forceinline__ void store_vw(T *p, const T *v)
 
 template <typename T, int D, int NFM, int VW>
 __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__restrict__ gf, const MeshDev m,
-                                                const int64_t nv, const int second_order,
+                                                const int64_t nv, const int nchunk, const int second_order,
                                                 const int *__restrict__ cell_list, const int64_t ncl)
 {
     using V = vec_t<T, VW>;
     constexpr int ND = (D == 3) ? 3 : 4;
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x & 63;
-    const int64_t idx = b * 4 + (threadIdx.x >> 6);
+    const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
+    const int idx = w / nchunk;
     if (idx >= ncl) return;
-    const int c = uni_i(cell_list ? cell_list[idx] : (int)idx);
-    const int nfc = uni_i(m.nfc[c]);
+    const int64_t k = ((int64_t)(w - idx * nchunk) * kWave + (threadIdx.x & 63)) * VW;
+    const int c = uni_i(cell_list ? cell_list[idx] : idx);
+    // padded slots: nbr = INT32_MIN, zero geometry (no gradient term, no limiter test)
     int nb[NFM];
     T lsq[NFM][D], dxc[NFM][D];
 #pragma unroll
     for (int s = 0; s < NFM; ++s) {
-        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : -1;
+        nb[s] = m.nbr[(int64_t)c * NFM + s];
         const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            dxc[s][a] = (s < nfc) ? (T)g[D + a] : T(0);
-            lsq[s][a] = (s < nfc) ? (T)g[3 * D + a] : T(0);
+            dxc[s][a] = (T)g[D + a];
+            lsq[s][a] = (T)g[3 * D + a];
         }
     }
     const T eps2 = (T)m.eps2[c];
-    for (int64_t k = (int64_t)lane * VW; k < nv; k += kWave * VW) {
+    if (k < nv) {
         V fcv[ND], fnv[NFM][ND];
 #pragma unroll
         for (int d = 0; d < ND; ++d) fcv[d] = *(const V *)(f + ((int64_t)c * ND + d) * nv + k);
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__re
                     phi = T(1);
 #pragma unroll
                     for (int s = 0; s < NFM; ++s) {
-                        if (s < nfc) {
+                        if (nb[s] != INT32_MIN) {
                             T d2 = T(0);
 #pragma unroll
                             for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
@@ -397,34 +400,34 @@ __global__ __launch_bounds__(256) void k_residual_v(const T *__restrict__ f, con
                                                     const T *__restrict__ coef, const T *__restrict__ xiT,
                                                     const T *__restrict__ rhow, T *__restrict__ r,
                                                     T *__restrict__ dl, T *__restrict__ fout, const MeshDev m,
-                                                    const int64_t nv, const T cflv_fac, const T omega,
-                                                    const T wt, const T wr, const T wv, const T dr, const T dv)
+                                                    const int64_t nv, const int nchunk, const T cflv_fac,
+                                                    const T omega, const T wt, const T wr, const T wv, const T dr,
+                                                    const T dv)
 {
     using V = vec_t<T, VW>;
     constexpr int ND = (D == 3) ? 3 : 4;
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x & 63;
-    const int64_t ci = b * 4 + (threadIdx.x >> 6);
-    if (ci >= m.nc) return;
-    const int c = uni_i((int)ci);
-    const int nfc = uni_i(m.nfc[c]);
+    const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
+    const int c = w / nchunk;
+    if (c >= m.nc) return;
+    const int64_t k = ((int64_t)(w - c * nchunk) * kWave + (threadIdx.x & 63)) * VW;
+    // padded slots: nbr = INT32_MIN, zero geometry
     int nb[NFM];
     T nsv[NFM][D], dxc[NFM][D], dxj[NFM][D];
 #pragma unroll
     for (int s = 0; s < NFM; ++s) {
-        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : INT32_MIN;
+        nb[s] = m.nbr[(int64_t)c * NFM + s];
         const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            nsv[s][a] = (s < nfc) ? (T)g[a] : T(0);
-            dxc[s][a] = (s < nfc) ? (T)g[D + a] : T(0);
-            dxj[s][a] = (s < nfc) ? (T)g[2 * D + a] : T(0);
+            nsv[s][a] = (T)g[a];
+            dxc[s][a] = (T)g[D + a];
+            dxj[s][a] = (T)g[2 * D + a];
         }
     }
     T cf[coef_size(3)];
 #pragma unroll
     for (int i = 0; i < coef_size(D); ++i) cf[i] = coef[(int64_t)c * coef_size(D) + i];
-    for (int64_t k = (int64_t)lane * VW; k < nv; k += kWave * VW) {
+    if (k < nv) {
         V x[D], fc[ND], gc[ND][D];
 #pragma unroll
         for (int a = 0; a < D; ++a) x[a] = *(const V *)(xiT + a * nv + k);
@@ -595,86 +598,86 @@ __global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ r, const T 
     }
 }
 
-// Vector form of k_sweep for nv divisible by VW: each lane owns VW consecutive velocities (one 16-byte
-// load or store per row and lane); the rows of all upwind neighbours are loaded for every lane and the
-// upwind choice is a per-velocity select.  Same arithmetic as k_sweep except the division, done as a
-// multiplication by the reciprocal of the diagonal.
+// Vector form of k_sweep for nv divisible by VW.  One wave per (cell, chunk of 64 VW velocities): each
+// lane owns VW consecutive velocities (one 16-byte load or store per row and lane) and the wave ends after
+// its chunk, so many short waves keep the memory system busy without loop-carried waits.  The rows of all
+// upwind neighbours are loaded for every lane and the upwind choice is a per-velocity select.  Same
+// arithmetic as k_sweep except the division, done as a multiplication by the reciprocal of the diagonal.
+// Padded cell slots hold nbr = INT32_MIN and zero geometry, so the per-cell tables are read without
+// waiting for the face count.
 template <typename T, int D, int NFM, int VW>
 __global__ __launch_bounds__(256) void k_sweep_v(const T *__restrict__ r, const T *__restrict__ dlin,
                                                  T *__restrict__ dlout, const T *__restrict__ f,
                                                  T *__restrict__ fout, const T *__restrict__ coef,
                                                  const T *__restrict__ xiT, const MeshDev m, const int64_t nv,
-                                                 const T cflv_fac, const T omega)
+                                                 const int nchunk, const T cflv_fac, const T omega)
 {
     using V = vec_t<T, VW>;
     constexpr int ND = (D == 3) ? 3 : 4;
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x & 63;
-    const int64_t ci = b * 4 + (threadIdx.x >> 6);
-    if (ci >= m.nc) return;
-    const int c = uni_i((int)ci);
-    const int nfc = uni_i(m.nfc[c]);
+    const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
+    const int c = w / nchunk;
+    if (c >= m.nc) return;
+    const int64_t k = ((int64_t)(w - c * nchunk) * kWave + (threadIdx.x & 63)) * VW;
     int nb[NFM];
     T nsv[NFM][D];
 #pragma unroll
     for (int s = 0; s < NFM; ++s) {
-        nb[s] = (s < nfc) ? m.nbr[(int64_t)c * NFM + s] : INT32_MIN;
+        nb[s] = m.nbr[(int64_t)c * NFM + s];
         const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
 #pragma unroll
-        for (int a = 0; a < D; ++a) nsv[s][a] = (s < nfc) ? (T)g[a] : T(0);
+        for (int a = 0; a < D; ++a) nsv[s][a] = (T)g[a];
     }
     const T base = coef[(int64_t)c * coef_size(D) + D + 1] + coef[(int64_t)c * coef_size(D) + D];
     const T radd = coef[(int64_t)c * coef_size(D) + D + 5];
-    for (int64_t k = (int64_t)lane * VW; k < nv; k += kWave * VW) {
-        V x[D];
+    if (k >= nv) return;
+    V x[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) x[a] = *(const V *)(xiT + a * nv + k);
-        V nbv[NFM][ND];
+    for (int a = 0; a < D; ++a) x[a] = *(const V *)(xiT + a * nv + k);
+    V nbv[NFM][ND];
 #pragma unroll
-        for (int s = 0; s < NFM; ++s)
-            if (nb[s] >= 0) {
+    for (int s = 0; s < NFM; ++s)
+        if (nb[s] >= 0) {
 #pragma unroll
-                for (int d = 0; d < ND; ++d) nbv[s][d] = *(const V *)(dlin + ((int64_t)nb[s] * ND + d) * nv + k);
-            }
-        V rv[ND];
-#pragma unroll
-        for (int d = 0; d < ND; ++d) rv[d] = *(const V *)(r + ((int64_t)c * ND + d) * nv + k);
-        V acc[ND], dsum = T(0);
-#pragma unroll
-        for (int d = 0; d < ND; ++d) acc[d] = T(0);
-#pragma unroll
-        for (int s = 0; s < NFM; ++s) {
-            if (nb[s] == INT32_MIN) continue;
-            V xn = T(0);
-#pragma unroll
-            for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
-#pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                if (xn[e] > T(0)) {
-                    dsum[e] += xn[e];
-                } else if (xn[e] < T(0) && nb[s] >= 0) {
-#pragma unroll
-                    for (int d = 0; d < ND; ++d) acc[d][e] += xn[e] * nbv[s][d][e];
-                }
-            }
+            for (int d = 0; d < ND; ++d) nbv[s][d] = *(const V *)(dlin + ((int64_t)nb[s] * ND + d) * nv + k);
         }
-        V inv0, inv2;
+    V rv[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) rv[d] = *(const V *)(r + ((int64_t)c * ND + d) * nv + k);
+    V acc[ND], dsum = T(0);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[d] = T(0);
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        if (nb[s] == INT32_MIN) continue;
+        V xn = T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
-            const T dc = base + dsum[e] * cflv_fac;
-            inv0[e] = T(1) / dc;
-            inv2[e] = T(1) / (dc + radd);
-        }
+            if (xn[e] > T(0)) {
+                dsum[e] += xn[e];
+            } else if (xn[e] < T(0) && nb[s] >= 0) {
 #pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            const int64_t o = ((int64_t)c * ND + d) * nv + k;
-            const V dn = (rv[d] - acc[d]) * ((d == 2) ? inv2 : inv0);
-            if (fout) {
-                const V fo = *(const V *)(f + o) + omega * dn;
-                __builtin_nontemporal_store(fo, (V *)(fout + o));
-            } else {
-                __builtin_nontemporal_store(dn, (V *)(dlout + o));
+                for (int d = 0; d < ND; ++d) acc[d][e] += xn[e] * nbv[s][d][e];
             }
+        }
+    }
+    V inv0, inv2;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+        const T dc = base + dsum[e] * cflv_fac;
+        inv0[e] = T(1) / dc;
+        inv2[e] = T(1) / (dc + radd);
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int64_t o = ((int64_t)c * ND + d) * nv + k;
+        const V dn = (rv[d] - acc[d]) * ((d == 2) ? inv2 : inv0);
+        if (fout) {
+            const V fo = *(const V *)(f + o) + omega * dn;
+            __builtin_nontemporal_store(fo, (V *)(fout + o));
+        } else {
+            __builtin_nontemporal_store(dn, (V *)(dlout + o));
         }
     }
 }
@@ -895,6 +898,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
 #pragma unroll
         for (int bb = 0; bb < D; ++bb) m2[a][bb] = 0;
     }
+#pragma unroll 4
     for (int64_t kb = (int64_t)lane * VW; kb < nv; kb += kWave * VW) {
       T fG[VW], fR[VW], fV[VW], fH[VW];
       load_vw<T, VW>(f + ((int64_t)c * ND + 0) * nv + kb, fG);
@@ -1206,23 +1210,36 @@ __global__ __launch_bounds__(64) void k_boundary_flux(const T *__restrict__ f, c
 }
 
 // ------------------------------------------------------------------ synchronisation and initialisation
+// rho (2 pi T)^(-D/2), the normalisation of a D-dimensional Maxwellian, with a division and a square root
+template <int D>
+__device__ __forceinline__ double gauss_norm(const double rho, const double T)
+{
+    const double x = 2 * kPi * T;
+    if constexpr (D == 1) return rho / sqrt(x);
+    else if constexpr (D == 2) return rho / x;
+    else return rho / (x * sqrt(x));
+}
+
 // f += f^eq(M1) - f^eq(M0) with f^eq the multi-temperature equilibrium; I += (eR1 - eR0)/(4 pi).
 // sp per cell: [rho, u[D], Tt, Tr, Tv, eR] for M0 then M1.
 template <typename T, int D, int VW>
 __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__ I, const double *__restrict__ sp,
                                               const double *__restrict__ xi, const int64_t nc, const int64_t nv,
-                                              const int64_t no, const double dr, const double dv, const int init)
+                                              const int nchunk, const int64_t no, const double dr, const double dv,
+                                              const int init)
 {
     constexpr int ND = (D == 3) ? 3 : 4;
     constexpr int NS = D + 5;
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    // one wave per (cell, chunk of kWave * VW velocities); chunk 0 also updates the cell's ordinates
     const int lane = threadIdx.x & 63;
-    const int64_t ci = b * 4 + (threadIdx.x >> 6);
-    if (ci >= nc) return;
-    const int c = uni_i((int)ci);
+    const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
+    const int c = w / nchunk;
+    if (c >= nc) return;
+    const int ch = w - c * nchunk;
     const double *s0 = sp + (int64_t)c * 2 * NS, *s1 = s0 + NS;
-    const double n0 = s0[0] * pow(2 * kPi * s0[D + 1], -0.5 * D), n1 = s1[0] * pow(2 * kPi * s1[D + 1], -0.5 * D);
-    for (int64_t kb = (int64_t)lane * VW; kb < nv; kb += kWave * VW) {
+    const double n0 = gauss_norm<D>(s0[0], s0[D + 1]), n1 = gauss_norm<D>(s1[0], s1[D + 1]);
+    const int64_t kb = ((int64_t)ch * kWave + lane) * VW;
+    if (kb < nv) {
       T fv[4][VW];
       if (!init) {
 #pragma unroll
@@ -1249,6 +1266,7 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
 #pragma unroll
       for (int d = 0; d < ND; ++d) store_vw<T, VW>(f + ((int64_t)c * ND + d) * nv + kb, fv[d]);
     }
+    if (ch != 0) return;
     const double dI = init ? s1[D + 4] / (4 * kPi) : (s1[D + 4] - s0[D + 4]) / (4 * kPi);
     for (int64_t q0 = 0; q0 < no; q0 += kWave) {
         const int64_t q = q0 + lane;
@@ -1270,9 +1288,11 @@ void launch_grad(const T *f, T *gf, const MeshDev &m, int64_t nv, int so, const 
 {
     if (ncl <= 0) return;
     constexpr int VW = 16 / sizeof(T);
-    if (nv % VW == 0)
-        hipLaunchKernelGGL((k_grad_v<T, D, NFM, VW>), dim3(wave_blocks(ncl)), dim3(256), 0, st, f, gf, m, nv, so,
-                           cells, ncl);
+    if (nv % VW == 0) {
+        const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
+        hipLaunchKernelGGL((k_grad_v<T, D, NFM, VW>), dim3(wave_blocks(ncl * nchunk)), dim3(256), 0, st, f, gf, m,
+                           nv, nchunk, so, cells, ncl);
+    }
     else
         hipLaunchKernelGGL((k_grad<T, D, NFM>), dim3(wave_blocks(ncl)), dim3(256), 0, st, f, gf, m,
                            (D == 3) ? 3 : 4, nv, so, cells, ncl);
@@ -1332,9 +1352,13 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
     const int ks = o.kin_sweeps;
     ev = P.begin(1, ks == 0 ? cv * (2 + D) : cv * (3 + D));
     constexpr int VW = 16 / sizeof(T);
+    // vector kernels with one wave per (cell, chunk of kWave * VW velocities)
+    const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
+    const dim3 chunk_grid((unsigned)((m.nc * nchunk + 3) / 4));
     if (nv % VW == 0)
-        hipLaunchKernelGGL((k_residual_v<T, D, NFM, VW>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xiT, B.rhow, B.r,
-                           B.dl0, ks == 0 ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
+        hipLaunchKernelGGL((k_residual_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.f, B.gf, B.coef, B.xiT, B.rhow,
+                           B.r, B.dl0, ks == 0 ? B.f2 : nullptr, m, nv, nchunk, fac, om, wt, wr, wv, (T)p.d_r,
+                           (T)p.d_v);
     else
         hipLaunchKernelGGL((k_residual<T, D, NFM>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xi, B.rhow, B.r, B.dl0,
                            ks == 0 ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
@@ -1348,8 +1372,8 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
         const bool last = (s == ks - 1);
         ev = P.begin(2, last ? 4 * cv : 3 * cv);
         if (nv % VW == 0)
-            hipLaunchKernelGGL((k_sweep_v<T, D, NFM, VW>), grid, blk, 0, st, B.r, din, dout, B.f,
-                               last ? B.f2 : nullptr, B.coef, B.xiT, m, nv, fac, om);
+            hipLaunchKernelGGL((k_sweep_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.r, din, dout, B.f,
+                               last ? B.f2 : nullptr, B.coef, B.xiT, m, nv, nchunk, fac, om);
         else
             hipLaunchKernelGGL((k_sweep<T, D, NFM>), grid, blk, 0, st, B.r, din, dout, B.f, last ? B.f2 : nullptr,
                                B.coef, B.xi, m, nv, fac, om);
@@ -1403,12 +1427,15 @@ void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_
                  hipStream_t st)
 {
     constexpr int VW = 16 / sizeof(T);
-    if (nv % VW == 0)
-        hipLaunchKernelGGL((k_sync<T, D, VW>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, sp, B.xi_d, nc, nv,
-                           no, p.d_r, p.d_v, init);
-    else
-        hipLaunchKernelGGL((k_sync<T, D, 1>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, sp, B.xi_d, nc, nv,
-                           no, p.d_r, p.d_v, init);
+    if (nv % VW == 0) {
+        const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
+        hipLaunchKernelGGL((k_sync<T, D, VW>), dim3(wave_blocks(nc * nchunk)), dim3(256), 0, st, B.f, B.I, sp,
+                           B.xi_d, nc, nv, nchunk, no, p.d_r, p.d_v, init);
+    } else {
+        const int nchunk = (int)((nv + kWave - 1) / kWave);
+        hipLaunchKernelGGL((k_sync<T, D, 1>), dim3(wave_blocks(nc * nchunk)), dim3(256), 0, st, B.f, B.I, sp,
+                           B.xi_d, nc, nv, nchunk, no, p.d_r, p.d_v, init);
+    }
 }
 
 #define GSIS_INST_D(T, D, NFM)                                                                                    \

@@ -141,6 +141,7 @@ static void compute_phys(gsis_t *h)
 static void free_mesh(MeshDev &m)
 {
     dfree(m.nbr);
+    dfree(m.nb2);
     dfree(m.sfid);
     dfree(m.geo);
     dfree(m.mgeo);
@@ -333,7 +334,12 @@ static int32_t build_mesh(gsis_t *h)
     std::vector<int> sfid(nc * NFM, 0);
     for (int64_t k = 0; k < nc * NFM; ++k)
         if (fid[k] >= 0) sfid[k] = (sgn[k] > 0) ? fid[k] : -(1 + fid[k]);
-    bool ok = upload(m.nbr, nbr) && upload(m.sfid, sfid) && upload(m.geo, geo) && upload(m.mgeo, mgeo) && upload(m.vol, hm.vol) &&
+    // per slot (c, s) with an interior neighbour j: the slots of j (neighbour lists two cells away)
+    std::vector<int> nb2(nc * NFM * NFM, INT32_MIN);
+    for (int64_t k = 0; k < nc * NFM; ++k)
+        if (nbr[k] >= 0)
+            for (int t = 0; t < NFM; ++t) nb2[k * NFM + t] = nbr[(int64_t)nbr[k] * NFM + t];
+    bool ok = upload(m.nbr, nbr) && upload(m.nb2, nb2) && upload(m.sfid, sfid) && upload(m.geo, geo) && upload(m.mgeo, mgeo) && upload(m.vol, hm.vol) &&
               upload(m.h, hh) && upload(m.eps2, eps2) && upload(m.nfc, nfc) && upload(m.bf_face, bf_face) &&
               upload(m.bf_cell, bf_cell) && upload(m.bf_tag, bf_tag) && upload(m.bf_n, bf_n) &&
               upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.f_L, fL) && upload(m.f_R, fR) &&
@@ -380,8 +386,7 @@ static void free_macro(MacroBufs &B)
     dfree(B.W2);
     dfree(B.P2);
     dfree(B.fld2);
-    dfree(B.Ff);
-    dfree(B.Gf);
+    dfree(B.Gs);
     dfree(B.part);
     dfree(B.gfld);
     dfree(B.R);
@@ -459,9 +464,8 @@ static bool alloc_macro(gsis_t *h)
     B.W2 = dalloc<double>(nc * NW, ok);
     B.P2 = dalloc<double>(nc * (D + 8), ok);
     B.fld2 = dalloc<double>(nc * (D + 4), ok);
-    B.Ff = dalloc<double>(nf * NW, ok);
-    B.Gf = dalloc<double>(nf * 2, ok);
-    B.part = dalloc<double>((nc + kMBlk - 1) / kMBlk + 1, ok);
+    B.Gs = dalloc<double>(nc * h->m.NFM * 2, ok);
+    B.part = dalloc<double>(macro_nparts(nc, h->m.NFM) + 1, ok);
     B.gfld = dalloc<double>(nc * (D + 4) * D, ok);
     B.R = dalloc<double>(nc * NW, ok);
     B.Dg = dalloc<double>(nc * NW, ok);

@@ -71,6 +71,7 @@ struct MeshDev {
     int D = 0, NFM = 0;
     int64_t nc = 0, nf = 0, nbf = 0;
     int *nbr = nullptr;
+    int *nb2 = nullptr;   // per slot (c, s): the NFM slots of neighbour j = nbr(c, s) (INT32_MIN if none)
     int *sfid = nullptr;  // per slot: face id if the cell is the face's left cell, -(1 + face id) otherwise
     double *geo = nullptr;
     double *mgeo = nullptr;

@@ -24,7 +24,7 @@ struct MacroBufs {
     double *W2 = nullptr, *P2 = nullptr, *fld2 = nullptr;  // second state of the inner-iteration ping-pong
     double *R = nullptr, *Dg = nullptr, *dU0 = nullptr, *dU1 = nullptr;
     double *hotf = nullptr, *bcorr = nullptr, *dref = nullptr;
-    double *Ff = nullptr, *Gf = nullptr;      // per interior face: flux (left to right), spectral radii
+    double *Gs = nullptr;                     // per cell slot (interior faces): spectral radii G, G_R
     double *part = nullptr;                   // per-block partial sums of the residual norm
     double *resc = nullptr, *scal = nullptr;  // per-cell scratch, device scalars (res0, mass, ...)
     int *flags = nullptr;                     // [0] done, [1] inner count, [2] block arrival counter
@@ -98,7 +98,12 @@ struct Prof {
     }
 };
 
-constexpr int kMBlk = 64;  // threads per block of the per-cell inner-iteration kernels (one wave)
+constexpr int kMBlk = 64;   // threads per block of the per-cell macro kernels (one wave)
+constexpr int kSBlk = 256;  // threads per block of the slot-parallel inner-iteration kernels
+// lanes per cell in the slot-parallel kernels (a power of two >= the number of face slots)
+__host__ __device__ constexpr int slot_lanes(int nfm) { return nfm <= 2 ? 2 : (nfm <= 4 ? 4 : 8); }
+// blocks of the slot-parallel kernels = number of per-block partial sums of the inner residual norm
+inline int64_t macro_nparts(int64_t nc, int nfm) { return (nc * slot_lanes(nfm) + kSBlk - 1) / kSBlk; }
 
 struct MacroOpts {
     double cfl_macro, inner_tol;

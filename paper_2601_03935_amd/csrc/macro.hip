@@ -1,4 +1,5 @@
-// Synthetic-equation solver for gfx950 (Sec. 2.2 and Sec. 6 of the paper): FP64, one thread per cell.
+// Synthetic-equation solver for gfx950 (Sec. 2.2 and Sec. 6 of the paper): FP64; set-up kernels run one
+// thread per cell or face, the inner iteration one lane per (cell, face slot).
 //
 // Per inner iteration: primitive state and gradient fields, residual R_i = -(1/V) sum F S + Q with the
 // Rusanov convective flux (its dissipation taken relative to the state the solve starts from), the NSF
@@ -371,6 +372,30 @@ __device__ __forceinline__ void cell_grad(const double *__restrict__ fld, const 
     }
 }
 
+// the same gradient with the neighbour list of c given (nb[s] < 0: boundary or padded slot)
+template <int D, int NFM>
+__device__ __forceinline__ void cell_grad_l(const double *__restrict__ fld, const MeshDev &m, const int64_t c,
+                                            const int *nb, double g[][D])
+{
+    constexpr int NF = D + 4;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int a = 0; a < D; ++a) g[i][a] = 0;
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        const int j = nb[s];
+        if (j < 0) continue;
+        const double *gs = m.geo + (c * NFM + s) * 4 * D + 3 * D;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const double df = fld[(int64_t)j * NF + i] - fld[c * NF + i];
+#pragma unroll
+            for (int a = 0; a < D; ++a) g[i][a] += gs[a] * df;
+        }
+    }
+}
+
 template <int D, int NFM>
 __global__ void k_cell_grad(const double *__restrict__ fld, double *__restrict__ gfld, const MeshDev m)
 {
@@ -544,46 +569,48 @@ __global__ void k_mprim(const double *__restrict__ W, double *__restrict__ P, do
     store_prim<D>(W + c * NW, p, P + c * NP, fld + c * NF);
 }
 
-// interior-face fluxes (orientation left -> right): Rusanov with the reference dissipation, NSF viscous
-// flux with the face gradient plus the frozen face HoTs; spectral radii of the convective-viscous and
-// radiative-diffusion operators for the diagonal.  Each face is evaluated once; the right cell uses the
-// negated flux (the discrete flux is exactly odd under the exchange of sides).
+// ---- slot-parallel inner-iteration kernels: kSBlk threads per block, slot_lanes(NFM) consecutive lanes per
+// cell, lane s of a cell's group handling its face slot s (padded slots hold nbr = INT32_MIN).  The per-face
+// work runs on separate lanes; the cell's sums are gathered from its lanes in slot order with shuffles and
+// the per-cell point solve runs on the group's first lane.
+
+// Interior face fid in its own orientation (left cell cL -> right cell cR): Rusanov with the reference
+// dissipation, NSF viscous flux with the face gradient plus the frozen face HoTs; spectral radii of the
+// convective-viscous and radiative-diffusion operators for the diagonal.  Both sides of a face evaluate
+// this same expression and the right side negates it, so the discrete flux is exactly odd.
 template <int D, int NFM>
-__global__ __launch_bounds__(kMBlk) void k_mface(const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ fld,
-                        const double *__restrict__ hotf, const double *__restrict__ dref, double *__restrict__ Ff,
-                        double *__restrict__ Gf, const MeshDev m, const Phys p, const int *__restrict__ flags)
+__device__ __forceinline__ void face_flux(const double *__restrict__ W, const double *__restrict__ P,
+                                          const double *__restrict__ fld, const double *__restrict__ hotf,
+                                          const double *__restrict__ dref, const MeshDev &m, const Phys &p,
+                                          const int64_t fid, const int64_t cL, const int64_t cR,
+                                          const int *nbL, const int *nbR, double *F, double *G, double *GR)
 {
     constexpr int NW = D + 5, NP = D + 8, NF = D + 4;
-    if (flags[0]) return;
-    const int64_t f = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (f >= m.nf) return;
-    const int64_t c = m.f_L[f], j = m.f_R[f];
-    if (j < 0) return;
     const double kR = (p.keff > 0) ? 1.0 / (3 * p.keff) : 0.0;
     double n[D], dvec[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        n[a] = m.f_n[f * D + a];
-        dvec[a] = m.f_d[f * D + a];
+        n[a] = m.f_n[fid * D + a];
+        dvec[a] = m.f_d[fid * D + a];
     }
-    const double *Pc = P + c * NP, *Pj = P + j * NP;
+    const double *Pc = P + cL * NP, *Pj = P + cR * NP;
     PrimL qc, qj;
     prim_load<D>(Pc, qc);
     prim_load<D>(Pj, qj);
     double Fc[NW];
-    rusanov_q<D>(W + c * NW, qc, Pc[D + 6], W + j * NW, qj, Pj[D + 6], n, Fc);
+    rusanov_q<D>(W + cL * NW, qc, Pc[D + 6], W + cR * NW, qj, Pj[D + 6], n, Fc);
 #pragma unroll
-    for (int i = 0; i < NW; ++i) Fc[i] += dref[f * NW + i];
+    for (int i = 0; i < NW; ++i) Fc[i] += dref[fid * NW + i];
     double gc[NF][D], gj[NF][D], g[NF][3], sig[3][3], q[4][3], Fv[NW], uf[3] = {0, 0, 0};
-    cell_grad<D, NFM>(fld, m, c, gc);
-    cell_grad<D, NFM>(fld, m, j, gj);
-    face_grad_g<D>(fld, gc, gj, c, j, dvec, g);
+    cell_grad_l<D, NFM>(fld, m, cL, nbL, gc);
+    cell_grad_l<D, NFM>(fld, m, cR, nbR, gj);
+    face_grad_g<D>(fld, gc, gj, cL, cR, dvec, g);
 #pragma unroll
     for (int a = 0; a < D; ++a) uf[a] = 0.5 * (Pc[1 + a] + Pj[1 + a]);
-    constitutive<D>(0.5 * (Pc[D + 5] + Pj[D + 5]), g, hotf + f * kNHot, p, sig, q);
+    constitutive<D>(0.5 * (Pc[D + 5] + Pj[D + 5]), g, hotf + fid * kNHot, p, sig, q);
     viscous_flux<D>(sig, q, uf, n, Fv);
 #pragma unroll
-    for (int i = 0; i < NW; ++i) Ff[f * NW + i] = Fc[i] + Fv[i];
+    for (int i = 0; i < NW; ++i) F[i] = Fc[i] + Fv[i];
     double ufn = 0, nd = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -591,73 +618,146 @@ __global__ __launch_bounds__(kMBlk) void k_mface(const double *__restrict__ W, c
         nd += n[a] * dvec[a];
     }
     nd = fabs(nd);
-    Gf[f * 2] = fabs(ufn) + 0.5 * (Pc[D + 6] + Pj[D + 6]) +
-                2 * 0.5 * (Pc[D + 5] + Pj[D + 5]) / (0.5 * (Pc[0] + Pj[0]) * nd);
-    Gf[f * 2 + 1] = 2 * kR / nd;
+    *G = fabs(ufn) + 0.5 * (Pc[D + 6] + Pj[D + 6]) + 2 * 0.5 * (Pc[D + 5] + Pj[D + 5]) / (0.5 * (Pc[0] + Pj[0]) * nd);
+    *GR = 2 * kR / nd;
 }
 
-// Per cell: residual R_i = -(1/V) sum_f F S + Q (face fluxes gathered in slot order, boundary model
-// fluxes plus the frozen kinetic corrections), the diagonal D_i and the first increment of the U
-// unknowns, and the per-block sums of the volume-weighted squared residual.
-template <int D, int NFM>
-__global__ __launch_bounds__(kMBlk) void k_mgather(
-    const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ bcorr,
-    const double *__restrict__ Ff, const double *__restrict__ Gf, double *__restrict__ R, double *__restrict__ Dg,
-    double *__restrict__ dU, double *__restrict__ part, const int *__restrict__ flags, const MeshDev m,
-    const Phys p, const double cfl_macro)
+// Sum over the 64 partial sums per lane stride of the per-block residual sums, in a fixed order (every
+// wave of every block forms the same value).  The loads are issued by the caller before its own work.
+constexpr int kPartRegs = 8;
+__device__ __forceinline__ void part_load(const double *__restrict__ part, const int nb, double pr[kPartRegs],
+                                          double *rest)
 {
-    constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2;
-    if (flags[0]) return;
-    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    double contrib = 0;
-    if (c < m.nc) {
-        const double *Pc = P + c * NP;
-        const int nfc = m.nfc[c];
-        double acc[NW], gs = 0, gsR = 0;
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-        for (int i = 0; i < NW; ++i) acc[i] = 0;
+    for (int u = 0; u < kPartRegs; ++u) {
+        const int b = lane + 64 * u;
+        pr[u] = (b < nb) ? part[b] : 0.0;
+    }
+    double v = 0;
+    for (int b = lane + 64 * kPartRegs; b < nb; b += 64) v += part[b];
+    *rest = v;
+}
+
+// Stopping test of inner iteration `it` from the loaded partial sums; block 0 records the norms and raises
+// the flag that later kernels test.
+__device__ __forceinline__ bool inner_converged(const double pr[kPartRegs], const double rest, const int it,
+                                                const double tol, double *__restrict__ scal, int *__restrict__ flags)
+{
+    double v = 0;
 #pragma unroll
-        for (int s = 0; s < NFM; ++s) {
-            if (s >= nfc) continue;
-            const int j = m.nbr[c * NFM + s];
-            const double S = m.mgeo[(c * NFM + s) * MG + D];
-            double Fs[NW];
-            if (j < 0) {
-                const int bfi = -j - 1;
-                double g1, g2;
-                bmodel_flux<D>(m, bfi, W + c * NW, p, Fs, &g1, &g2);
-#pragma unroll
-                for (int i = 0; i < NW; ++i) Fs[i] += bcorr[(int64_t)bfi * NW + i];
-                gs += g1 * S;
-                gsR += g2 * S;
-            } else {
-                const int sf = m.sfid[c * NFM + s];
-                const bool left = sf >= 0;
-                const int64_t fid = left ? sf : -(int64_t)sf - 1;
-#pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    const double v = Ff[fid * NW + i];
-                    Fs[i] = left ? v : -v;
-                }
-                gs += Gf[fid * 2] * S;
-                gsR += Gf[fid * 2 + 1] * S;
-            }
-#pragma unroll
-            for (int i = 0; i < NW; ++i) acc[i] += Fs[i] * S;
+    for (int u = 0; u < kPartRegs; ++u) v += pr[u];
+    v += rest;
+    const double res = sqrt(wave_sum64(v));
+    const double res0 = (it == 0) ? res : scal[0];
+    const bool done = res <= tol * res0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (it == 0) scal[0] = res;
+        scal[1] = res;
+        if (done) {
+            flags[0] = 1;
+            flags[1] = it;
         }
+    }
+    return done;
+}
+
+// Residual of every cell: R_i = -(1/V) sum_f F S + Q (face fluxes of the cell's slots gathered in slot
+// order, boundary model fluxes plus the frozen kinetic corrections), the diagonal D_i and the first
+// increment of the U unknowns; per-slot spectral radii for the sweeps; per-block sums of the
+// volume-weighted squared residual.
+template <int D, int NFM>
+__global__ __launch_bounds__(kSBlk) void k_mres(
+    const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ fld,
+    const double *__restrict__ hotf, const double *__restrict__ dref, const double *__restrict__ bcorr,
+    double *__restrict__ Gs, double *__restrict__ R, double *__restrict__ Dg, double *__restrict__ dU,
+    double *__restrict__ part, const int *__restrict__ flags, const MeshDev m, const Phys p, const double cfl_macro)
+{
+    constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2, LS = slot_lanes(NFM);
+    __shared__ double sh[kSBlk / 64];
+    const int done = flags[0];
+    const int t = threadIdx.x, lane = t & 63, base = lane & ~(LS - 1);
+    const int64_t gi = xcd_remap(blockIdx.x, gridDim.x) * kSBlk + t;
+    const int64_t c = gi / LS;
+    const int s = (int)(gi % LS);
+    const bool cell = c < m.nc;
+    const bool slot = cell && s < NFM;
+    // every index this lane needs is read here (one level of dependent loads): the slot, the cell's own
+    // neighbour list and the neighbour's (for the two cell gradients), and the cell's point-solve data
+    const int j = slot ? m.nbr[c * NFM + s] : INT32_MIN;
+    const int sf = slot ? m.sfid[c * NFM + s] : 0;
+    const double Sl = slot ? m.mgeo[(c * NFM + s) * MG + D] : 0.0;
+    int nbc[NFM], nbj[NFM];
+#pragma unroll
+    for (int q = 0; q < NFM; ++q) {
+        nbc[q] = cell ? m.nbr[c * NFM + q] : INT32_MIN;
+        nbj[q] = slot ? m.nb2[(c * NFM + s) * NFM + q] : INT32_MIN;
+    }
+    double Wc[NW], Pc[D + 7], V = 1, hc = 1;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) Wc[i] = cell ? W[c * NW + i] : 1.0;
+#pragma unroll
+    for (int i = 0; i < D + 7; ++i) Pc[i] = cell ? P[c * NP + i] : 1.0;
+    if (cell) {
+        V = m.vol[c];
+        hc = m.h[c];
+    }
+    if (done) return;
+    double Fs[NW], S = 0, gS = 0, gRS = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) Fs[i] = 0;
+    if (j != INT32_MIN) {
+        S = Sl;
+        if (j < 0) {
+            const int bfi = -j - 1;
+            double g1, g2;
+            bmodel_flux<D>(m, bfi, Wc, p, Fs, &g1, &g2);
+#pragma unroll
+            for (int i = 0; i < NW; ++i) Fs[i] += bcorr[(int64_t)bfi * NW + i];
+            gS = g1 * S;
+            gRS = g2 * S;
+        } else {
+            const bool left = sf >= 0;
+            const int64_t fid = left ? sf : -(int64_t)sf - 1;
+            double G, GR;
+            face_flux<D, NFM>(W, P, fld, hotf, dref, m, p, fid, left ? c : j, left ? j : c, left ? nbc : nbj,
+                              left ? nbj : nbc, Fs, &G, &GR);
+            if (!left) {
+#pragma unroll
+                for (int i = 0; i < NW; ++i) Fs[i] = -Fs[i];
+            }
+            Gs[(c * NFM + s) * 2] = G;
+            Gs[(c * NFM + s) * 2 + 1] = GR;
+            gS = G * S;
+            gRS = GR * S;
+        }
+    }
+    // the cell's sums, slot by slot (every lane takes part in the shuffles)
+    double acc[NW], gs = 0, gsR = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) acc[i] = 0;
+#pragma unroll
+    for (int q = 0; q < NFM; ++q) {
+        const double Sq = __shfl(S, base + q, 64);
+#pragma unroll
+        for (int i = 0; i < NW; ++i) acc[i] += __shfl(Fs[i], base + q, 64) * Sq;
+        gs += __shfl(gS, base + q, 64);
+        gsR += __shfl(gRS, base + q, 64);
+    }
+    double contrib = 0;
+    if (cell && s == 0) {
         const double rho = Pc[0], Tt = Pc[D + 1], Tr = Pc[D + 2], Tv = Pc[D + 3];
         const double tau = Pc[D + 5] / (rho * Tt);
         const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = (3 * Tt + p.d_v * Tv) / (3 + p.d_v);
         const double etr = 0.5 * p.d_r * rho * Ttr, etv = 0.5 * p.d_v * rho * Ttv;
         const double evR = 4 * p.sigma_R * Tv * Tv * Tv * Tv;
-        const double er = W[c * NW + D + 2], ev = W[c * NW + D + 3], eR = W[c * NW + D + 4];
+        const double er = Wc[D + 2], ev = Wc[D + 3], eR = Wc[D + 4];
         double Q[NW];
 #pragma unroll
         for (int i = 0; i < NW; ++i) Q[i] = 0;
         Q[D + 2] = (etr - er) / (p.Z_r * tau);
         Q[D + 3] = (etv - ev) / (p.Z_v * tau) - p.keff * (evR - eR);
         Q[D + 4] = p.keff * (evR - eR);
-        const double V = m.vol[c];
         double Rc[NW], rs = 0;
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
@@ -668,7 +768,7 @@ __global__ __launch_bounds__(kMBlk) void k_mgather(
         double un = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) un += Pc[1 + a] * Pc[1 + a];
-        const double dt = cfl_macro * m.h[c] / (sqrt(un) + Pc[D + 6]);
+        const double dt = cfl_macro * hc / (sqrt(un) + Pc[D + 6]);
         const double jr =
             -3.0 / ((3 + p.d_r) * p.Z_r * tau) + 2 * (p.omega - 1) * (Ttr - Tr) / (3 * p.Z_r * tau * Tt);
         const double jv = -3.0 / ((3 + p.d_v) * p.Z_v * tau) +
@@ -690,67 +790,49 @@ __global__ __launch_bounds__(kMBlk) void k_mgather(
             dU[c * NW + i] = d0[i];
         }
     }
-    const double tot = wave_sum64(contrib);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-// Stopping test of inner iteration `it`, evaluated by every block of the kernel that follows the residual
-// (same fixed-order sum of the per-block partials in every block, so all blocks take the same decision);
-// block 0 records the norms and raises the flag that later kernels test.
-__device__ __forceinline__ bool inner_converged(const double *__restrict__ part, const int nb, const int it,
-                                                const double tol, double *__restrict__ scal, int *__restrict__ flags)
-{
-    const int t = threadIdx.x;
-    double v = 0;
-    for (int b = t; b < nb; b += kMBlk) v += part[b];
-    const double res = sqrt(wave_sum64(v));
-    const double res0 = (it == 0) ? res : scal[0];
-    const bool done = res <= tol * res0;
-    if (blockIdx.x == 0 && t == 0) {
-        if (it == 0) scal[0] = res;
-        scal[1] = res;
-        if (done) {
-            flags[0] = 1;
-            flags[1] = it;
-        }
+    const double ws = wave_sum64(contrib);
+    if (lane == 0) sh[t >> 6] = ws;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0;
+#pragma unroll
+        for (int w = 0; w < kSBlk / 64; ++w) tot += sh[w];
+        part[blockIdx.x] = tot;
     }
-    return done;
 }
 
 // One Jacobi sweep of the implicit operator (off-diagonal flux increments of the neighbours' current
-// increments, halved).  The first sweep of an inner iteration takes its stopping decision first; the last
-// applies the safeguarded update and writes the next state and its primitives into the other buffer of
-// the ping-pong.
+// increments, halved; each slot lane forms its neighbour's term).  The first sweep of an inner iteration
+// takes the stopping decision before it stores anything; the last applies the safeguarded update and
+// writes the next state and its primitives into the other buffer of the ping-pong.
 template <int D, int NFM, bool FIRST, bool LAST>
-__global__ __launch_bounds__(kMBlk) void k_msweep(
+__global__ __launch_bounds__(kSBlk) void k_msweep(
     const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ R,
-    const double *__restrict__ Dg, const double *__restrict__ Gf, const double *__restrict__ dUin,
+    const double *__restrict__ Dg, const double *__restrict__ Gs, const double *__restrict__ dUin,
     double *__restrict__ dUout, double *__restrict__ Wn_out, double *__restrict__ Pn_out, double *__restrict__ fn_out,
-    const double *__restrict__ W0, const MeshDev m, const Phys p, const double *__restrict__ part, const int it,
-    const double tol, double *__restrict__ scal, int *__restrict__ flags)
+    const double *__restrict__ W0, const MeshDev m, const Phys p, const double *__restrict__ part, const int npart,
+    const int it, const double tol, double *__restrict__ scal, int *__restrict__ flags)
 {
-    constexpr int NW = D + 5, NP = D + 8, NF = D + 4, MG = 2 * D + 2;
-    if (flags[0]) return;
-    if constexpr (FIRST) {
-        if (inner_converged(part, gridDim.x, it, tol, scal, flags)) return;
-    }
-    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (c >= m.nc) return;
-    const double *Pc = P + c * NP;
-    const int nfc = m.nfc[c];
-    double acc[NW];
+    constexpr int NW = D + 5, NP = D + 8, NF = D + 4, MG = 2 * D + 2, LS = slot_lanes(NFM);
+    const int done = flags[0];
+    double pr[kPartRegs], rest = 0;
+    if constexpr (FIRST) part_load(part, npart, pr, &rest);
+    const int t = threadIdx.x, lane = t & 63, base = lane & ~(LS - 1);
+    const int64_t gi = xcd_remap(blockIdx.x, gridDim.x) * kSBlk + t;
+    const int64_t c = gi / LS;
+    const int s = (int)(gi % LS);
+    const bool cell = c < m.nc;
+    const bool slot = cell && s < NFM;
+    const int j = slot ? m.nbr[c * NFM + s] : INT32_MIN;
+    if (done) return;
+    double x[NW], S = 0;
 #pragma unroll
-    for (int i = 0; i < NW; ++i) acc[i] = 0;
-#pragma unroll
-    for (int s = 0; s < NFM; ++s) {
-        const int j = (s < nfc) ? m.nbr[c * NFM + s] : -1;
-        if (j < 0) continue;
+    for (int i = 0; i < NW; ++i) x[i] = 0;
+    if (j >= 0) {
         const double *mg = m.mgeo + (c * NFM + s) * MG;
         const double *n = mg;
-        const double S = mg[D];
-        const int sf = m.sfid[c * NFM + s];
-        const int64_t fid = (sf >= 0) ? sf : -(int64_t)sf - 1;
-        const double G = Gf[fid * 2], GR = Gf[fid * 2 + 1];
+        S = mg[D];
+        const double G = Gs[(c * NFM + s) * 2], GR = Gs[(c * NFM + s) * 2 + 1];
         double Wn[NW], F1[NW], F0[NW];
         const double *Wj = W + (int64_t)j * NW;
         const double *dj = dUin + (int64_t)j * NW;
@@ -762,9 +844,23 @@ __global__ __launch_bounds__(kMBlk) void k_msweep(
         euler_flux<D>(Wn, n, F1);
         euler_flux_q<D>(Wj, qj, n, F0);
 #pragma unroll
-        for (int i = 0; i < NW - 1; ++i) acc[i] += (F1[i] - F0[i] - G * dj[i]) * S;
-        acc[NW - 1] += (-GR * dj[NW - 1]) * S;
+        for (int i = 0; i < NW - 1; ++i) x[i] = F1[i] - F0[i] - G * dj[i];
+        x[NW - 1] = -GR * dj[NW - 1];
     }
+    double acc[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) acc[i] = 0;
+#pragma unroll
+    for (int q = 0; q < NFM; ++q) {
+        const double Sq = __shfl(S, base + q, 64);
+#pragma unroll
+        for (int i = 0; i < NW; ++i) acc[i] += __shfl(x[i], base + q, 64) * Sq;
+    }
+    if constexpr (FIRST) {
+        if (inner_converged(pr, rest, it, tol, scal, flags)) return;
+    }
+    if (!cell || s != 0) return;
+    const double *Pc = P + c * NP;
     const double V = m.vol[c];
     double rhs[NW], Dc[NW], d1[NW];
 #pragma unroll
@@ -792,13 +888,15 @@ template <int D>
 __global__ __launch_bounds__(kMBlk) void k_mupdate(double *__restrict__ W, const double *__restrict__ dU,
                                                    double *__restrict__ P, double *__restrict__ fld,
                                                    const double *__restrict__ W0, const int64_t nc,
-                                                   const Phys p, const double *__restrict__ part, const int it,
-                                                   const double tol, double *__restrict__ scal,
+                                                   const Phys p, const double *__restrict__ part, const int npart,
+                                                   const int it, const double tol, double *__restrict__ scal,
                                                    int *__restrict__ flags)
 {
     constexpr int NW = D + 5, NP = D + 8, NF = D + 4;
     if (flags[0]) return;
-    if (inner_converged(part, gridDim.x, it, tol, scal, flags)) return;
+    double pr[kPartRegs], rest;
+    part_load(part, npart, pr, &rest);
+    if (inner_converged(pr, rest, it, tol, scal, flags)) return;
     const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     double Wc[NW], d[NW];
@@ -886,7 +984,9 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     hipLaunchKernelGGL(k_face_hot<D>, gf, blk, 0, st, mom, B.fld, B.gfld, B.P, B.hotf, m, m.f_d, p);
     if (m.nbf > 0) hipLaunchKernelGGL(k_bcorr<D>, gb, blk, 0, st, B.W0, bflux, B.bcorr, m, p);
     hipLaunchKernelGGL(k_dref<D>, gf, blk, 0, st, B.W0, B.dref, m, p);
-    const dim3 gci((nc + kMBlk - 1) / kMBlk), bi(kMBlk), gfi((m.nf + kMBlk - 1) / kMBlk);
+    const dim3 gci((nc + kMBlk - 1) / kMBlk), bi(kMBlk);
+    const int npart = (int)macro_nparts(nc, NFM);
+    const dim3 gsl(npart), bsl(kSBlk);
     hipLaunchKernelGGL(k_mprim<D>, gci, bi, 0, st, B.W, B.P, B.fld, nc, p);
     // inner iteration `it` starts from the state in buffer `it % 2` when the sweeps ping-pong
     double *Wb[2] = {B.W, B.W2}, *Pb[2] = {B.P, B.P2}, *Fb[2] = {B.fld, B.fld2};
@@ -896,23 +996,22 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     for (int it = 0; it < o.max_inner; ++it) {
         const int cur = pingpong ? (it & 1) : 0, nxt = cur ^ 1;
         double *W = Wb[cur], *P = Pb[cur], *fld = Fb[cur];
-        hipLaunchKernelGGL((k_mface<D, NFM>), gfi, bi, 0, st, W, P, fld, B.hotf, B.dref, B.Ff, B.Gf, m, p, B.flags);
-        hipLaunchKernelGGL((k_mgather<D, NFM>), gci, bi, 0, st, W, P, B.bcorr, B.Ff, B.Gf, B.R, B.Dg, B.dU0, B.part,
-                           B.flags, m, p, o.cfl_macro);
+        hipLaunchKernelGGL((k_mres<D, NFM>), gsl, bsl, 0, st, W, P, fld, B.hotf, B.dref, B.bcorr, B.Gs, B.R, B.Dg,
+                           B.dU0, B.part, B.flags, m, p, o.cfl_macro);
         double *din = B.dU0, *dout = B.dU1;
         const int ns = o.n_sweeps;
         for (int s = 0; s < ns; ++s) {
             const bool first = (s == 0), last = (s + 1 == ns);
             auto kern = first ? (last ? k_msweep<D, NFM, true, true> : k_msweep<D, NFM, true, false>)
                               : (last ? k_msweep<D, NFM, false, true> : k_msweep<D, NFM, false, false>);
-            hipLaunchKernelGGL(kern, gci, bi, 0, st, W, P, B.R, B.Dg, B.Gf, din, last ? nullptr : dout,
+            hipLaunchKernelGGL(kern, gsl, bsl, 0, st, W, P, B.R, B.Dg, B.Gs, din, last ? nullptr : dout,
                                last ? Wb[nxt] : nullptr, last ? Pb[nxt] : nullptr, last ? Fb[nxt] : nullptr, B.W0, m,
-                               p, B.part, it, o.inner_tol, B.scal, B.flags);
+                               p, B.part, npart, it, o.inner_tol, B.scal, B.flags);
             std::swap(din, dout);
         }
         if (!pingpong)
-            hipLaunchKernelGGL(k_mupdate<D>, gci, bi, 0, st, W, B.dU0, P, fld, B.W0, nc, p, B.part, it, o.inner_tol,
-                               B.scal, B.flags);
+            hipLaunchKernelGGL(k_mupdate<D>, gci, bi, 0, st, W, B.dU0, P, fld, B.W0, nc, p, B.part, npart, it,
+                               o.inner_tol, B.scal, B.flags);
         if ((it + 1) % poll == 0) {
             (void)hipMemcpyAsync(host_flags, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
             (void)hipStreamSynchronize(st);

@@ -1200,7 +1200,10 @@ static void boundary_corr(const orc_t *o, const double *W0, double *bcorr)
  * except for the gas-photon exchange k_eff (e_vR(T_v) - e_R), which couples e_gas, e_v and e_R and is
  * solved exactly per cell (reading: the printed diagonal Jacobian leaves this coupling lagged, which lets
  * e_gas and e_v respond inconsistently to strong emission).  With e' = d e_vR / d e_v:
- *   D_g dg = r_g - k e' dv + k dR,   D_v dv = r_v + k dR,   D_R dR = r_R + k e' dv. */
+ *   D_g dg = r_g - k e' dv + k dR,   D_v dv = r_v + k dR,   D_R dR = r_R + k e' dv.
+ * Reading: with k_eff = 0 (absorption and emission off) the e_R row has neither a diffusion term nor a
+ * source and is singular; e_R is then not a synthetic unknown (dR = 0), keeps its kinetic value, and the
+ * synchronisation leaves I unchanged. */
 static void local_solve(const orc_t *o, const prim_t *p, const double *rhs, const double *Dg, double *dU)
 {
     int D = o->D, NW = NWof(D);
@@ -1211,7 +1214,7 @@ static void local_solve(const orc_t *o, const prim_t *p, const double *rhs, cons
     const double dv = (rhs[iv] + k * rhs[iR] / Dg[iR]) / (Dg[iv] - k * k * ep / Dg[iR]);
     const double dR = (rhs[iR] + k * ep * dv) / Dg[iR];
     dU[iv] = dv;
-    dU[iR] = dR;
+    dU[iR] = (k > 0) ? dR : 0.0;
     dU[ig] = (rhs[ig] - k * ep * dv + k * dR) / Dg[ig];
 }
 

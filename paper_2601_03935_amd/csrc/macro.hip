@@ -253,6 +253,8 @@ __device__ __forceinline__ void bmodel_flux(const MeshDev &m, int bfi, const dou
 // point solve of the implicit operator in U = (rho, rho u, e_gas, e_r, e_v, e_R): diagonal except for the
 // gas-photon exchange, solved exactly per cell (with e' = d e_vR / d e_v):
 //   D_g dg = r_g - k e' dv + k dR,   D_v dv = r_v + k dR,   D_R dR = r_R + k e' dv
+// With k = 0 (absorption and emission off) the e_R row is singular (no diffusion, no source): e_R is not
+// a synthetic unknown there (dR = 0), so it keeps its kinetic value and the synchronisation leaves I alone.
 template <int D>
 __device__ __forceinline__ void local_solve(const double *rhs, const double *Dg, const double rho, const double Tv,
                                             const Phys &p, double *dU)
@@ -265,7 +267,7 @@ __device__ __forceinline__ void local_solve(const double *rhs, const double *Dg,
     const double dv = (rhs[iv] + k * rhs[iR] / Dg[iR]) / (Dg[iv] - k * k * ep / Dg[iR]);
     const double dR = (rhs[iR] + k * ep * dv) / Dg[iR];
     dU[iv] = dv;
-    dU[iR] = dR;
+    dU[iR] = (k > 0) ? dR : 0.0;
     dU[ig] = (rhs[ig] - k * ep * dv + k * dR) / Dg[ig];
 }
 

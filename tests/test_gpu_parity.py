@@ -108,6 +108,27 @@ def test_gsis_iterations_fp64(name, case):
     assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-8
 
 
+def test_decoupled_radiation_macro_solve_and_iterations():
+    """Optical thickness 0 (absorption and emission off): the synthetic solve keeps e_R at its kinetic
+    value on both sides, W agrees with the oracle, and GSIS iterations stay finite and agree."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1, tau_opt=0.0)
+    s, o = _pair(case, precision="fp64", max_inner=60)
+    _warm(o, s, n=3)
+    o.kinetic_step()
+    s.kinetic_step()
+    Wo, ito = o.macro_solve()
+    Wg, itg = s.macro_solve()
+    assert ito == itg
+    assert _relerr(Wg, Wo) < 1e-9
+    s2, o2 = _pair(case, precision="fp64", max_inner=60)
+    for k in range(8):
+        eo, _ = o2.iterate(gsis=k >= 2)
+        eg, _ = s2.iterate(gsis=k >= 2)
+        assert np.isfinite(eg) and abs(eg - eo) <= 1e-8 * abs(eo) + 1e-14
+    s.close()
+    s2.close()
+
+
 def test_kinetic_step_fp32_ragged_chunks():
     """FP32 storage: one kinetic step against FP64, with nv = 81 (two velocity chunks, ragged tail) and
     no = 72 ordinates (two chunks)."""

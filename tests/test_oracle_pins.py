@@ -285,6 +285,29 @@ def test_sync_restores_macro_state():
     np.testing.assert_allclose(W3, W2, rtol=1e-10, atol=1e-13)
 
 
+def test_decoupled_radiation_is_not_a_synthetic_unknown():
+    """With absorption and emission off (optical thickness 0) the e_R row of the synthetic equations has
+    neither a diffusion term nor a source.  The synthetic solve must leave e_R at its kinetic value and the
+    synchronisation must leave I unchanged; the gas part still converges (a drifting e_R drove I negative
+    and the iteration to NaN)."""
+    c = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1, tau_opt=0.0)
+    o = Oracle(c, max_inner=60)
+    for _ in range(2):
+        o.iterate(gsis=False)
+    o.kinetic_step()
+    Wh = o.macro_state()
+    _, I0 = o.get_state()
+    W, it = o.macro_solve()
+    assert it > 0
+    np.testing.assert_array_equal(W[:, -1], Wh[:, -1])
+    assert np.abs(W[:, 0] - Wh[:, 0]).max() > 1e-6  # the gas part did move
+    o.sync(W)
+    _, I1 = o.get_state()
+    np.testing.assert_array_equal(I1, I0)
+    eps = [o.iterate(gsis=True)[0] for _ in range(12)]
+    assert np.all(np.isfinite(eps)) and eps[-1] < 0.2 * eps[0]
+
+
 def test_fourier_cis_thresholds():
     """CIS Fourier analysis (Sec. 4.2): e_max -> 1 as Kn theta -> 0 (case A), divergence for the
     coupling product 0.05 (cases B and C), and a divergence threshold near 0.03."""

@@ -869,6 +869,223 @@ __global__ __launch_bounds__(256) void k_sweep_I(const T *__restrict__ r, const 
     }
 }
 
+// Packed vector forms of the ordinate kernels for N_o divisible by VW: a cell's ordinates are spread over
+// 2^lsh consecutive lanes (the smallest power of two covering N_o / VW, at most 64), so one wave serves
+// 64 >> lsh cells; each lane owns VW consecutive ordinates (one 16-byte access per row).  Per-cell
+// tables are loaded per lane (the lanes of a cell read the same addresses).  Same arithmetic as the
+// scalar kernels.
+template <typename T, int D, int NFM, int VW>
+__global__ __launch_bounds__(256) void k_grad_Iv(const T *__restrict__ I, T *__restrict__ gI, const MeshDev m,
+                                                 const int64_t no, const int lsh, const int second_order,
+                                                 const int *__restrict__ cell_list, const int64_t ncl)
+{
+    using V = vec_t<T, VW>;
+    const int64_t gi = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int64_t idx = gi >> lsh;
+    if (idx >= ncl) return;
+    const int lg = (int)(gi & ((1 << lsh) - 1));
+    const int64_t c = cell_list ? cell_list[idx] : idx;
+    int nb[NFM];
+    T lsq[NFM][D], dxc[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = m.nbr[c * NFM + s];
+        const double *g = m.geo + (c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            dxc[s][a] = (T)g[D + a];
+            lsq[s][a] = (T)g[3 * D + a];
+        }
+    }
+    const T eps2 = (T)m.eps2[c];
+    for (int64_t q = (int64_t)lg * VW; q < no; q += (int64_t)VW << lsh) {
+        const V Ic = *(const V *)(I + c * no + q);
+        V nbv[NFM];
+#pragma unroll
+        for (int s = 0; s < NFM; ++s)
+            if (nb[s] >= 0) nbv[s] = *(const V *)(I + (int64_t)nb[s] * no + q);
+        V go[D];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            T g[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) g[a] = T(0);
+            T dmax = T(0), dmin = T(0);
+#pragma unroll
+            for (int s = 0; s < NFM; ++s) {
+                if (nb[s] >= 0) {
+                    const T df = nbv[s][e] - Ic[e];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) g[a] += lsq[s][a] * df;
+                    dmax = df > dmax ? df : dmax;
+                    dmin = df < dmin ? df : dmin;
+                }
+            }
+            T phi = T(0);
+            if (second_order) {
+                phi = T(1);
+#pragma unroll
+                for (int s = 0; s < NFM; ++s) {
+                    if (nb[s] != INT32_MIN) {
+                        T d2 = T(0);
+#pragma unroll
+                        for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
+                        if (d2 != T(0)) {
+                            const T d1 = d2 > T(0) ? dmax : dmin;
+                            T p = (d1 * d1 + eps2 + T(2) * d1 * d2) / (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2);
+                            p = p > T(1) ? T(1) : p;
+                            phi = p < phi ? p : phi;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) go[a][e] = phi * g[a];
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) *(V *)(gI + (c * D + a) * no + q) = go[a];
+    }
+}
+
+template <typename T, int D, int NFM, int VW>
+__global__ __launch_bounds__(256) void k_residual_Iv(const T *__restrict__ I, const T *__restrict__ gI,
+                                                     const T *__restrict__ coef, const T *__restrict__ om,
+                                                     T *__restrict__ r, T *__restrict__ dl, T *__restrict__ Iout,
+                                                     const MeshDev m, const int64_t no, const int lsh,
+                                                     const T cflv_fac, const T omega, const T keff, const T sigR)
+{
+    using V = vec_t<T, VW>;
+    const int64_t gi = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int64_t c = gi >> lsh;
+    if (c >= m.nc) return;
+    const int lg = (int)(gi & ((1 << lsh) - 1));
+    int nb[NFM];
+    T nsv[NFM][D], dxc[NFM][D], dxj[NFM][D], Tb4[NFM];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = m.nbr[c * NFM + s];
+        const double *g = m.geo + (c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            nsv[s][a] = (T)g[a];
+            dxc[s][a] = (T)g[D + a];
+            dxj[s][a] = (T)g[2 * D + a];
+        }
+        Tb4[s] = T(0);
+        if (nb[s] < 0 && nb[s] != INT32_MIN) {
+            const T Tb = (T)m.bcs[m.bf_tag[-nb[s] - 1]].T;
+            Tb4[s] = sigR * Tb * Tb * Tb * Tb / T(kPi);
+        }
+    }
+    const T B = coef[c * coef_size(D) + D + 3];
+    const T inv_dtR = coef[c * coef_size(D) + D + 4];
+    for (int64_t q = (int64_t)lg * VW; q < no; q += (int64_t)VW << lsh) {
+        const V Ic = *(const V *)(I + c * no + q);
+        V gc[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) gc[a] = *(const V *)(gI + (c * D + a) * no + q);
+        V nI[NFM], ng[NFM][D];
+#pragma unroll
+        for (int s = 0; s < NFM; ++s)
+            if (nb[s] >= 0) {
+                nI[s] = *(const V *)(I + (int64_t)nb[s] * no + q);
+#pragma unroll
+                for (int a = 0; a < D; ++a) ng[s][a] = *(const V *)(gI + ((int64_t)nb[s] * D + a) * no + q);
+            }
+        V rr, dd;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            T o[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) o[a] = om[(q + e) * D + a];
+            T flux = T(0), dsum = T(0);
+#pragma unroll
+            for (int s = 0; s < NFM; ++s) {
+                if (nb[s] == INT32_MIN) continue;
+                T on = T(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) on += o[a] * nsv[s][a];
+                T Iv;
+                if (on > T(0)) {
+                    Iv = Ic[e];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) Iv += gc[a][e] * dxc[s][a];
+                    dsum += on;
+                } else if (nb[s] >= 0) {
+                    Iv = nI[s][e];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) Iv += ng[s][a][e] * dxj[s][a];
+                } else {
+                    Iv = Tb4[s];
+                }
+                flux += on * Iv;
+            }
+            rr[e] = keff * (B - Ic[e]) - flux;
+            dd[e] = inv_dtR + keff + dsum * cflv_fac;
+        }
+        const int64_t idx = c * no + q;
+        if (Iout) {
+            *(V *)(Iout + idx) = Ic + omega * (rr / dd);
+        } else {
+            *(V *)(r + idx) = rr;
+            *(V *)(dl + idx) = rr / dd;
+        }
+    }
+}
+
+template <typename T, int D, int NFM, int VW>
+__global__ __launch_bounds__(256) void k_sweep_Iv(const T *__restrict__ r, const T *__restrict__ dlin,
+                                                  T *__restrict__ dlout, const T *__restrict__ I,
+                                                  T *__restrict__ Iout, const T *__restrict__ coef,
+                                                  const T *__restrict__ om, const MeshDev m, const int64_t no,
+                                                  const int lsh, const T cflv_fac, const T omega, const T keff)
+{
+    using V = vec_t<T, VW>;
+    const int64_t gi = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int64_t c = gi >> lsh;
+    if (c >= m.nc) return;
+    const int lg = (int)(gi & ((1 << lsh) - 1));
+    int nb[NFM];
+    T nsv[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = m.nbr[c * NFM + s];
+        const double *g = m.geo + (c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) nsv[s][a] = (T)g[a];
+    }
+    const T base = coef[c * coef_size(D) + D + 4] + keff;
+    for (int64_t q = (int64_t)lg * VW; q < no; q += (int64_t)VW << lsh) {
+        V nd[NFM];
+#pragma unroll
+        for (int s = 0; s < NFM; ++s)
+            if (nb[s] >= 0) nd[s] = *(const V *)(dlin + (int64_t)nb[s] * no + q);
+        const int64_t idx = c * no + q;
+        const V rv = *(const V *)(r + idx);
+        V dn;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            T acc = T(0), dsum = T(0);
+#pragma unroll
+            for (int s = 0; s < NFM; ++s) {
+                if (nb[s] == INT32_MIN) continue;
+                T on = T(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) on += om[(q + e) * D + a] * nsv[s][a];
+                if (on > T(0))
+                    dsum += on;
+                else if (on < T(0) && nb[s] >= 0)
+                    acc += on * nd[s][e];
+            }
+            dn[e] = (rv[e] - acc) / (base + dsum * cflv_fac);
+        }
+        if (Iout)
+            *(V *)(Iout + idx) = *(const V *)(I + idx) + omega * dn;
+        else
+            *(V *)(dlout + idx) = dn;
+    }
+}
+
 // ------------------------------------------------------------------ moments (Eq. getmoment, reduced form)
 // Raw FP64 moments about a reference velocity u_ref (the cell's previous velocity) reduced across the
 // wave, then shifted to central moments.  mom layout: see MomLayout.
@@ -1298,13 +1515,29 @@ void launch_grad(const T *f, T *gf, const MeshDev &m, int64_t nv, int so, const 
                            (D == 3) ? 3 : 4, nv, so, cells, ncl);
 }
 
+// lanes per cell of the packed ordinate kernels: 2^ord_lsh(no) covers no / VW ordinates (at most 64)
+static inline int ord_lsh(int64_t no, int vw)
+{
+    int l = 0;
+    while (l < 6 && ((int64_t)vw << l) < no) ++l;
+    return l;
+}
+static inline int64_t packed_blocks(int64_t ncells, int lsh) { return ((ncells << lsh) + 255) / 256; }
+
 template <typename T, int D, int NFM>
 void launch_grad_I(const T *I, T *gI, const MeshDev &m, int64_t no, int so, const int *cells, int64_t ncl,
                    hipStream_t st)
 {
-    if (ncl <= 0) return;
-    hipLaunchKernelGGL((k_grad_I<T, D, NFM>), dim3(wave_blocks(ncl)), dim3(256), 0, st, I, gI, m, no, so, cells,
-                       ncl);
+    if (ncl <= 0 || no <= 0) return;
+    constexpr int VW = 16 / sizeof(T);
+    if (no % VW == 0) {
+        const int lsh = ord_lsh(no, VW);
+        hipLaunchKernelGGL((k_grad_Iv<T, D, NFM, VW>), dim3(packed_blocks(ncl, lsh)), dim3(256), 0, st, I, gI, m,
+                           no, lsh, so, cells, ncl);
+    } else {
+        hipLaunchKernelGGL((k_grad_I<T, D, NFM>), dim3(wave_blocks(ncl)), dim3(256), 0, st, I, gI, m, no, so,
+                           cells, ncl);
+    }
 }
 
 template <typename T>
@@ -1364,8 +1597,15 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
                            ks == 0 ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
     P.end(ev);
     ev = P.begin(3, ks == 0 ? co * (2 + D) : co * (3 + D));
-    hipLaunchKernelGGL((k_residual_I<T, D, NFM>), grid, blk, 0, st, B.I, B.gI, B.coef, B.om, B.rI, B.dI0,
-                       ks == 0 ? B.I2 : nullptr, m, no, fac, om, (T)p.keff, (T)p.sigma_R);
+    const bool ovec = (no % VW == 0);
+    const int olsh = ord_lsh(no, VW);
+    const dim3 ogrid((unsigned)packed_blocks(m.nc, olsh));
+    if (ovec)
+        hipLaunchKernelGGL((k_residual_Iv<T, D, NFM, VW>), ogrid, blk, 0, st, B.I, B.gI, B.coef, B.om, B.rI, B.dI0,
+                           ks == 0 ? B.I2 : nullptr, m, no, olsh, fac, om, (T)p.keff, (T)p.sigma_R);
+    else
+        hipLaunchKernelGGL((k_residual_I<T, D, NFM>), grid, blk, 0, st, B.I, B.gI, B.coef, B.om, B.rI, B.dI0,
+                           ks == 0 ? B.I2 : nullptr, m, no, fac, om, (T)p.keff, (T)p.sigma_R);
     P.end(ev);
     T *din = B.dl0, *dout = B.dl1, *dIin = B.dI0, *dIout = B.dI1;
     for (int s = 0; s < ks; ++s) {
@@ -1379,8 +1619,12 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
                                B.coef, B.xi, m, nv, fac, om);
         P.end(ev);
         ev = P.begin(3, last ? 4 * co : 3 * co);
-        hipLaunchKernelGGL((k_sweep_I<T, D, NFM>), grid, blk, 0, st, B.rI, dIin, dIout, B.I,
-                           last ? B.I2 : nullptr, B.coef, B.om, m, no, fac, om, (T)p.keff);
+        if (ovec)
+            hipLaunchKernelGGL((k_sweep_Iv<T, D, NFM, VW>), ogrid, blk, 0, st, B.rI, dIin, dIout, B.I,
+                               last ? B.I2 : nullptr, B.coef, B.om, m, no, olsh, fac, om, (T)p.keff);
+        else
+            hipLaunchKernelGGL((k_sweep_I<T, D, NFM>), grid, blk, 0, st, B.rI, dIin, dIout, B.I,
+                               last ? B.I2 : nullptr, B.coef, B.om, m, no, fac, om, (T)p.keff);
         P.end(ev);
         std::swap(din, dout);
         std::swap(dIin, dIout);

@@ -130,9 +130,9 @@ def test_decoupled_radiation_macro_solve_and_iterations():
 
 
 def test_kinetic_step_fp32_ragged_chunks():
-    """FP32 storage: one kinetic step against FP64, with nv = 81 (two velocity chunks, ragged tail) and
-    no = 72 ordinates (two chunks)."""
-    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=9, n_theta=3, n_phi=24, Kn=0.05)
+    """FP32 storage: one kinetic step against FP64, with nv = 81 (two velocity chunks, ragged tail, the
+    scalar velocity kernels) and no = 69 ordinates (two chunks of the scalar ordinate kernels)."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=9, n_theta=3, n_phi=23, Kn=0.05)
     s, o = _pair(case, precision="fp32")
     f, I = _warm(o, s, n=2)
     o.kinetic_step()
@@ -146,7 +146,8 @@ def test_kinetic_step_fp32_ragged_chunks():
 
 def test_kinetic_step_fp32_vector_tail():
     """FP32 storage with nv = 324 (18 x 18 velocities, a multiple of the 4-wide vector path but not of the
-    256 velocities one wave covers per pass) and 40 ordinates: one kinetic step against FP64."""
+    256 velocities one wave covers) and 40 ordinates (packed ordinate kernels: a cell's 40 ordinates on
+    10 of 16 lanes, four cells per wave): one kinetic step against FP64."""
     case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=18, n_theta=2, n_phi=20, Kn=0.05)
     s, o = _pair(case, precision="fp32")
     _warm(o, s, n=2)

@@ -339,7 +339,8 @@ static int32_t build_mesh(gsis_t *h)
     for (int64_t k = 0; k < nc * NFM; ++k)
         if (nbr[k] >= 0)
             for (int t = 0; t < NFM; ++t) nb2[k * NFM + t] = nbr[(int64_t)nbr[k] * NFM + t];
-    bool ok = upload(m.nbr, nbr) && upload(m.nb2, nb2) && upload(m.sfid, sfid) && upload(m.geo, geo) && upload(m.mgeo, mgeo) && upload(m.vol, hm.vol) &&
+    bool ok = upload(m.nbr, nbr) && upload(m.nb2, nb2) && upload(m.sfid, sfid) && upload(m.geo, geo) &&
+              upload(m.mgeo, mgeo) && upload(m.vol, hm.vol) &&
               upload(m.h, hh) && upload(m.eps2, eps2) && upload(m.nfc, nfc) && upload(m.bf_face, bf_face) &&
               upload(m.bf_cell, bf_cell) && upload(m.bf_tag, bf_tag) && upload(m.bf_n, bf_n) &&
               upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.f_L, fL) && upload(m.f_R, fR) &&

@@ -10,6 +10,8 @@
 // one wavefront per cell looping over chunks of 64.  Per-cell geometry and coefficients are wave-uniform
 // and live in scalar registers.  Workgroups are remapped so that each of the 8 XCDs walks a contiguous
 // range of (Morton-ordered) cells and finds neighbour rows in its own L2.
+#include <algorithm>
+
 #include "gsis_dev.h"
 #include "gsis_kernels.h"
 
@@ -35,6 +37,30 @@ __device__ __forceinline__ double wave_sum(double v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Wave w of a (cell, velocity chunk) grid: cells are taken in groups of G consecutive cells and each group
+// is traversed chunk-major (chunk 0 of its cells, then chunk 1, ...), so the rows a wave's neighbours
+// touch in the same chunk were read shortly before.  G = 1 is cell-major, G >= ncell fully chunk-major.
+// Returns false past the end of the grid.
+__device__ __forceinline__ bool wave_cell_chunk(const int w, const int ncell, const int nchunk, const int G,
+                                                int &c, int &ch)
+{
+    const int nfull = ncell / G;
+    const int wfull = nfull * G * nchunk;
+    if (w < wfull) {
+        const int cb = w / (G * nchunk);
+        const int rem = w - cb * G * nchunk;
+        ch = rem / G;
+        c = cb * G + (rem - ch * G);
+        return true;
+    }
+    const int tg = ncell - nfull * G;
+    if (tg <= 0) return false;
+    const int wt = w - wfull;
+    ch = wt / tg;
+    c = nfull * G + (wt - ch * tg);
+    return ch < nchunk;
 }
 
 // ------------------------------------------------------------------ limited gradients of f
@@ -137,15 +163,16 @@ __device__ __forceinline__ void store_vw(T *p, const T *v)
 
 template <typename T, int D, int NFM, int VW>
 __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__restrict__ gf, const MeshDev m,
-                                                const int64_t nv, const int nchunk, const int second_order,
+                                                const int64_t nv, const int nchunk, const int cgroup,
+                                                const int second_order,
                                                 const int *__restrict__ cell_list, const int64_t ncl)
 {
     using V = vec_t<T, VW>;
     constexpr int ND = (D == 3) ? 3 : 4;
     const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
-    const int idx = w / nchunk;
-    if (idx >= ncl) return;
-    const int64_t k = ((int64_t)(w - idx * nchunk) * kWave + (threadIdx.x & 63)) * VW;
+    int idx, ch;
+    if (!wave_cell_chunk(w, (int)ncl, nchunk, cgroup, idx, ch)) return;
+    const int64_t k = ((int64_t)ch * kWave + (threadIdx.x & 63)) * VW;
     const int c = uni_i(cell_list ? cell_list[idx] : idx);
     // padded slots: nbr = INT32_MIN, zero geometry (no gradient term, no limiter test)
     int nb[NFM];
@@ -222,7 +249,8 @@ __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__re
 
 // per-cell coefficient block (written by k_prologue) -------------------------------------------------
 //   [0..D) u, D invtau, D+1 inv_dt, D+2 radc = k_eff (e_vR - e_R)/rho, D+3 B = sigma_R Tv^4/pi,
-//   D+4 inv_dtR, D+5 radd = 4 k_eff e_vR / e_v (extra diagonal of f2), then for X in (t, r, v): inv2T, norm, a[D], gR, bR[D], gV, bV[D], hH
+//   D+4 inv_dtR, D+5 radd = 4 k_eff e_vR / e_v (extra diagonal of f2),
+//   then for X in (t, r, v): inv2T, norm, a[D], gR, bR[D], gV, bV[D], hH
 __host__ __device__ constexpr int coef_x(int D) { return 5 + 3 * D; }
 __host__ __device__ constexpr int coef_size(int D) { return D + 6 + 3 * coef_x(D); }
 
@@ -400,16 +428,17 @@ __global__ __launch_bounds__(256) void k_residual_v(const T *__restrict__ f, con
                                                     const T *__restrict__ coef, const T *__restrict__ xiT,
                                                     const T *__restrict__ rhow, T *__restrict__ r,
                                                     T *__restrict__ dl, T *__restrict__ fout, const MeshDev m,
-                                                    const int64_t nv, const int nchunk, const T cflv_fac,
+                                                    const int64_t nv, const int nchunk, const int cgroup,
+                                                    const T cflv_fac,
                                                     const T omega, const T wt, const T wr, const T wv, const T dr,
                                                     const T dv)
 {
     using V = vec_t<T, VW>;
     constexpr int ND = (D == 3) ? 3 : 4;
     const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
-    const int c = w / nchunk;
-    if (c >= m.nc) return;
-    const int64_t k = ((int64_t)(w - c * nchunk) * kWave + (threadIdx.x & 63)) * VW;
+    int c, ch;
+    if (!wave_cell_chunk(w, (int)m.nc, nchunk, cgroup, c, ch)) return;
+    const int64_t k = ((int64_t)ch * kWave + (threadIdx.x & 63)) * VW;
     // padded slots: nbr = INT32_MIN, zero geometry
     int nb[NFM];
     T nsv[NFM][D], dxc[NFM][D], dxj[NFM][D];
@@ -610,14 +639,15 @@ __global__ __launch_bounds__(256) void k_sweep_v(const T *__restrict__ r, const 
                                                  T *__restrict__ dlout, const T *__restrict__ f,
                                                  T *__restrict__ fout, const T *__restrict__ coef,
                                                  const T *__restrict__ xiT, const MeshDev m, const int64_t nv,
-                                                 const int nchunk, const T cflv_fac, const T omega)
+                                                 const int nchunk, const int cgroup, const T cflv_fac,
+                                                 const T omega)
 {
     using V = vec_t<T, VW>;
     constexpr int ND = (D == 3) ? 3 : 4;
     const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
-    const int c = w / nchunk;
-    if (c >= m.nc) return;
-    const int64_t k = ((int64_t)(w - c * nchunk) * kWave + (threadIdx.x & 63)) * VW;
+    int c, ch;
+    if (!wave_cell_chunk(w, (int)m.nc, nchunk, cgroup, c, ch)) return;
+    const int64_t k = ((int64_t)ch * kWave + (threadIdx.x & 63)) * VW;
     int nb[NFM];
     T nsv[NFM][D];
 #pragma unroll
@@ -1442,7 +1472,8 @@ __device__ __forceinline__ double gauss_norm(const double rho, const double T)
 template <typename T, int D, int VW>
 __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__ I, const double *__restrict__ sp,
                                               const double *__restrict__ xi, const int64_t nc, const int64_t nv,
-                                              const int nchunk, const int64_t no, const double dr, const double dv,
+                                              const int nchunk, const int cgroup, const int64_t no,
+                                              const double dr, const double dv,
                                               const int init)
 {
     constexpr int ND = (D == 3) ? 3 : 4;
@@ -1450,9 +1481,8 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
     // one wave per (cell, chunk of kWave * VW velocities); chunk 0 also updates the cell's ordinates
     const int lane = threadIdx.x & 63;
     const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
-    const int c = w / nchunk;
-    if (c >= nc) return;
-    const int ch = w - c * nchunk;
+    int c, ch;
+    if (!wave_cell_chunk(w, (int)nc, nchunk, cgroup, c, ch)) return;
     const double *s0 = sp + (int64_t)c * 2 * NS, *s1 = s0 + NS;
     const double n0 = gauss_norm<D>(s0[0], s0[D + 1]), n1 = gauss_norm<D>(s1[0], s1[D + 1]);
     const int64_t kb = ((int64_t)ch * kWave + lane) * VW;
@@ -1499,6 +1529,23 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
 // ------------------------------------------------------------------ launchers
 static inline int64_t wave_blocks(int64_t n) { return (n + 3) / 4; }
 
+// Cells per chunk-major group of the (cell, velocity chunk) kernels, measured (MI355X; 20k-triangle cavity,
+// 1,024 velocities, 4 chunks; 214k-tetrahedron capsule shard, 1,728 velocities, 7 chunks): the residual
+// is fastest fully chunk-major in 2D and 3D (3D: 3.32 against 3.13 TB/s cell-major); the sweep and the
+// gradients fully chunk-major in 2D (sweep 5.82 against 5.53 TB/s) but cell-major in 3D (sweep 4.79
+// against 4.55); the synchronisation with groups of 1,024 cells.
+enum class CG { grad, residual, sweep, sync };
+static int chunk_group(CG k, int D, int64_t ncell)
+{
+    const int all = (int)ncell;
+    switch (k) {
+    case CG::residual: return all;
+    case CG::sweep:
+    case CG::grad: return D == 3 ? 1 : all;
+    default: return (int)std::min<int64_t>(ncell, 1024);
+    }
+}
+
 template <typename T, int D, int NFM>
 void launch_grad(const T *f, T *gf, const MeshDev &m, int64_t nv, int so, const int *cells, int64_t ncl,
                  hipStream_t st)
@@ -1508,7 +1555,7 @@ void launch_grad(const T *f, T *gf, const MeshDev &m, int64_t nv, int so, const 
     if (nv % VW == 0) {
         const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
         hipLaunchKernelGGL((k_grad_v<T, D, NFM, VW>), dim3(wave_blocks(ncl * nchunk)), dim3(256), 0, st, f, gf, m,
-                           nv, nchunk, so, cells, ncl);
+                           nv, nchunk, chunk_group(CG::grad, D, ncl), so, cells, ncl);
     }
     else
         hipLaunchKernelGGL((k_grad<T, D, NFM>), dim3(wave_blocks(ncl)), dim3(256), 0, st, f, gf, m,
@@ -1590,8 +1637,8 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
     const dim3 chunk_grid((unsigned)((m.nc * nchunk + 3) / 4));
     if (nv % VW == 0)
         hipLaunchKernelGGL((k_residual_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.f, B.gf, B.coef, B.xiT, B.rhow,
-                           B.r, B.dl0, ks == 0 ? B.f2 : nullptr, m, nv, nchunk, fac, om, wt, wr, wv, (T)p.d_r,
-                           (T)p.d_v);
+                           B.r, B.dl0, ks == 0 ? B.f2 : nullptr, m, nv, nchunk, chunk_group(CG::residual, D, m.nc),
+                           fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
     else
         hipLaunchKernelGGL((k_residual<T, D, NFM>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xi, B.rhow, B.r, B.dl0,
                            ks == 0 ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
@@ -1613,7 +1660,8 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
         ev = P.begin(2, last ? 4 * cv : 3 * cv);
         if (nv % VW == 0)
             hipLaunchKernelGGL((k_sweep_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.r, din, dout, B.f,
-                               last ? B.f2 : nullptr, B.coef, B.xiT, m, nv, nchunk, fac, om);
+                               last ? B.f2 : nullptr, B.coef, B.xiT, m, nv, nchunk,
+                               chunk_group(CG::sweep, D, m.nc), fac, om);
         else
             hipLaunchKernelGGL((k_sweep<T, D, NFM>), grid, blk, 0, st, B.r, din, dout, B.f, last ? B.f2 : nullptr,
                                B.coef, B.xi, m, nv, fac, om);
@@ -1674,11 +1722,11 @@ void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_
     if (nv % VW == 0) {
         const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
         hipLaunchKernelGGL((k_sync<T, D, VW>), dim3(wave_blocks(nc * nchunk)), dim3(256), 0, st, B.f, B.I, sp,
-                           B.xi_d, nc, nv, nchunk, no, p.d_r, p.d_v, init);
+                           B.xi_d, nc, nv, nchunk, chunk_group(CG::sync, D, nc), no, p.d_r, p.d_v, init);
     } else {
         const int nchunk = (int)((nv + kWave - 1) / kWave);
         hipLaunchKernelGGL((k_sync<T, D, 1>), dim3(wave_blocks(nc * nchunk)), dim3(256), 0, st, B.f, B.I, sp,
-                           B.xi_d, nc, nv, nchunk, no, p.d_r, p.d_v, init);
+                           B.xi_d, nc, nv, nchunk, chunk_group(CG::sync, D, nc), no, p.d_r, p.d_v, init);
     }
 }
 

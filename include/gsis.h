@@ -144,7 +144,10 @@ int32_t gsis_set_gas(gsis_t *h, const gsis_gas *gas);
 int32_t gsis_set_flow(gsis_t *h, const gsis_flow *flow);
 
 /* Options; allocates the device state for the chosen precision (mesh, grids, gas and flow must be
- * set first).  Changing the precision discards the state (re-initialise afterwards). */
+ * set first, else GSIS_E_STATE).  Changing the precision discards the state (re-initialise afterwards).
+ * GSIS_E_ARG for an unknown scheme or precision, negative counts (sweeps, iteration limits,
+ * n_precond, first_order_iters), second_order outside {0, 1}, negative tolerances, or a non-positive
+ * limiter constant, relaxation factor or CFL number. */
 int32_t gsis_set_opts(gsis_t *h, const gsis_opts *opts);
 
 /* Equilibrium initial state from fields: rho[nc], u[nc*dim], T[nc] (all modes and T_R equal T). */

@@ -911,9 +911,11 @@ int32_t gsis_set_opts(gsis_t *h, const gsis_opts *o)
     if (!h || !o) return GSIS_E_ARG;
     if (!(h->have_mesh && h->have_vel && h->have_ord && h->have_gas && h->have_flow))
         return fail(h, GSIS_E_STATE, "gsis_set_opts: mesh, grids, gas and flow must be set first");
-    if ((o->precision != GSIS_FP32 && o->precision != GSIS_FP64) || o->kin_sweeps < 0 || o->max_inner < 0 ||
-        o->n_sweeps < 0 || o->first_order_iters < 0 || !(o->cfl_v > 0) || !(o->cfl_meso > 0) ||
-        !(o->cfl_macro > 0))
+    if ((o->precision != GSIS_FP32 && o->precision != GSIS_FP64) || (o->scheme != GSIS_CIS && o->scheme != GSIS_GSIS) ||
+        o->kin_sweeps < 0 || o->max_inner < 0 || o->max_outer < 0 || o->n_precond < 0 || o->n_sweeps < 0 ||
+        o->first_order_iters < 0 || (o->second_order != 0 && o->second_order != 1) || !(o->tol >= 0) ||
+        !(o->inner_tol >= 0) || !(o->limiter_K > 0) || !(o->kin_omega > 0) || !(o->cfl_v > 0) ||
+        !(o->cfl_meso > 0) || !(o->cfl_macro > 0))
         return fail(h, GSIS_E_ARG, "gsis_set_opts: invalid options");
     (void)hipSetDevice(h->device);
     const bool realloc = !h->have_state || o->precision != h->prec || o->limiter_K != h->opts.limiter_K;

@@ -1,0 +1,110 @@
+"""Argument and call-order errors of the C ABI (host-side validation; a device is needed for a handle).
+
+Every call below must fail with its documented status before touching the GPU state, and the handle
+must stay usable: a valid set-up afterwards still solves."""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2601_03935_amd import gsis as G
+from workloads import case_cavity, mesh_cavity
+
+pytestmark = pytest.mark.gpu
+
+
+def _mesh_args(m, **over):
+    a = dict(vol=G._f64(m.vol), ctr=G._f64(m.ctr), fc=np.ascontiguousarray(m.face_cells, dtype=np.int64),
+             fn=G._f64(m.face_n), fa=G._f64(m.face_area), fctr=G._f64(m.face_ctr), nc=m.nc, nf=m.nf, dim=m.dim)
+    a.update(over)
+    return a
+
+
+def _set_mesh(L, h, a, bcs, nbc):
+    return L.gsis_set_mesh(h, a["dim"], a["nc"], a["nf"], G._p(a["vol"]), G._p(a["ctr"]), G._p(a["fc"]),
+                           G._p(a["fn"]), G._p(a["fa"]), G._p(a["fctr"]), nbc, C.cast(bcs, C.c_void_p))
+
+
+def test_argument_and_order_errors():
+    L = G.lib()
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=8, n_theta=2, n_phi=4, Kn=0.1)
+    m, g, q = case.mesh, case.vgrid, case.ords
+    kind, rho, T, u = case.bc_arrays()
+    bcs = (G.gsis_bc * len(kind))()
+    for i in range(len(kind)):
+        bcs[i].kind, bcs[i].rho, bcs[i].T = int(kind[i]), float(rho[i]), float(T[i])
+    h = C.c_void_p()
+    assert L.gsis_create(0, C.byref(h)) == G.GSIS_OK
+    try:
+        rep = G.gsis_report()
+        # call order: nothing set up yet
+        assert L.gsis_solve(h, C.byref(rep)) == G.GSIS_E_STATE
+        assert L.gsis_kinetic_step(h) == G.GSIS_E_STATE
+        # mesh validation
+        a = _mesh_args(m)
+        assert _set_mesh(L, h, _mesh_args(m, nc=0), bcs, len(kind)) == G.GSIS_E_ARG  # empty mesh
+        assert _set_mesh(L, h, _mesh_args(m, dim=4), bcs, len(kind)) == G.GSIS_E_ARG
+        bad = a["fc"].copy()
+        bad[0, 1] = m.nc  # right cell out of range
+        assert _set_mesh(L, h, _mesh_args(m, fc=bad), bcs, len(kind)) == G.GSIS_E_ARG
+        bnd = np.where(a["fc"][:, 1] < 0)[0][0]
+        bad = a["fc"].copy()
+        bad[bnd, 1] = -(1 + len(kind))  # unknown boundary tag
+        assert _set_mesh(L, h, _mesh_args(m, fc=bad), bcs, len(kind)) == G.GSIS_E_ARG
+        fa = a["fa"].copy()
+        fa[3] = 0.0
+        assert _set_mesh(L, h, _mesh_args(m, fa=fa), bcs, len(kind)) == G.GSIS_E_ARG
+        vol = a["vol"].copy()
+        vol[5] = -1.0
+        assert _set_mesh(L, h, _mesh_args(m, vol=vol), bcs, len(kind)) == G.GSIS_E_ARG
+        # a triangle with too many faces: point four interior faces at cell 0
+        bad = a["fc"].copy()
+        inner = np.where(bad[:, 1] >= 0)[0][:4]
+        bad[inner, 0] = 0
+        bad[inner, 1] = 1
+        assert _set_mesh(L, h, _mesh_args(m, fc=bad), bcs, len(kind)) == G.GSIS_E_ARG
+        bk = (G.gsis_bc * len(kind))()
+        for i in range(len(kind)):
+            bk[i].kind, bk[i].rho, bk[i].T = 7, 1.0, 1.0  # unknown boundary kind
+        assert _set_mesh(L, h, a, bk, len(kind)) == G.GSIS_E_ARG
+        assert b"gsis_set_mesh" in L.gsis_last_error(h)
+        # a valid mesh; then grids, gas, flow and options validation
+        assert _set_mesh(L, h, a, bcs, len(kind)) == G.GSIS_OK
+        xi, w = G._f64(g.xi), G._f64(g.w)
+        assert L.gsis_set_velocity_grid(h, 0, G._p(xi), G._p(w)) == G.GSIS_E_ARG
+        assert L.gsis_set_velocity_grid(h, g.nv, G._p(xi), G._p(w)) == G.GSIS_OK
+        om, wo = G._f64(q.omega), G._f64(q.w)
+        assert L.gsis_set_ordinates(h, 0, G._p(om), G._p(wo)) == G.GSIS_E_ARG
+        assert L.gsis_set_ordinates(h, q.no, G._p(om), G._p(wo)) == G.GSIS_OK
+        gs = case.gas
+        assert L.gsis_set_gas(h, C.byref(G.gsis_gas(gs.d_r, gs.d_v, gs.Z_r, gs.Z_v, gs.omega, gs.Sc,
+                                                    gs.sigma_R))) == G.GSIS_OK
+        assert L.gsis_set_flow(h, C.byref(G.gsis_flow(0.0, 1.0))) == G.GSIS_E_ARG
+        assert L.gsis_set_flow(h, C.byref(G.gsis_flow(0.1, -1.0))) == G.GSIS_E_ARG
+        assert L.gsis_set_flow(h, C.byref(G.gsis_flow(0.1, 1.0))) == G.GSIS_OK
+        for bad_opts in (dict(tol=-1.0), dict(max_inner=-1), dict(kin_sweeps=-1), dict(first_order_iters=-1),
+                         dict(limiter_K=0.0), dict(second_order=2), dict(scheme=7), dict(n_precond=-1)):
+            o = G.default_opts(**bad_opts)
+            assert L.gsis_set_opts(h, C.byref(o)) == G.GSIS_E_ARG, bad_opts
+        o = G.default_opts(max_outer=5, precision="fp64")
+        assert L.gsis_set_opts(h, C.byref(o)) == G.GSIS_OK
+        # fields and boundary states
+        n = m.nc
+        one, zero = np.ones(n), np.zeros(n)
+        uu = np.zeros(n * 2)
+        assert L.gsis_init_fields(h, G._p(one), G._p(uu), G._p(zero), G._p(one), G._p(one),
+                                  G._p(one)) == G.GSIS_E_ARG
+        assert L.gsis_init_fields(h, G._p(one), G._p(uu), G._p(one), G._p(one), G._p(one),
+                                  G._p(one)) == G.GSIS_OK
+        b = G.gsis_bc()
+        b.kind, b.rho, b.T = int(kind[0]), 1.0, 1.0
+        assert L.gsis_set_boundary(h, len(kind), C.byref(b)) == G.GSIS_E_ARG  # no such tag
+        b.kind = 1 - int(kind[0])
+        assert L.gsis_set_boundary(h, 0, C.byref(b)) == G.GSIS_E_ARG  # kind change
+        assert L.gsis_iterate(h, G.GSIS_GSIS, -1, None, None) == G.GSIS_E_ARG
+        # the handle is still usable: five outer iterations run (and do not converge)
+        rc = L.gsis_solve(h, C.byref(rep))
+        assert rc in (G.GSIS_OK, G.GSIS_W_NOT_CONVERGED) and rep.iters == 5 and np.isfinite(rep.eps_final)
+    finally:
+        L.gsis_destroy(h)

@@ -233,6 +233,7 @@ def cylinder_warmstart_leg(a, case, stream, plain_fields):
     return {"tol": a.tol, "seconds": sec, "iterations": int(rep.iters), "converged": bool(rc == 0),
             "eps_final": float(rep.eps_final), "prediction_rel_l2_vs_plain": err,
             "train_cases": len(cases), "train_cases_converged": int(sum(r["ok"] for r in info)),
+            "train_cases_first_order": int(sum(r["ok"] and r.get("order") == 1 for r in info)),
             "train_rows": int(X.shape[0]), "train_data_s": t_data, "train_s": t_train, "train_loss": loss,
             "network": "4-layer MLP 8-256-256-256-7, tanh, BF16 operands on MFMA, FP32 accumulation, Adam"}
 

@@ -266,9 +266,9 @@ def training_set(cases, device=0, stream=None, family="cavity", **opts):
     return np.concatenate(X), np.concatenate(Y)
 
 
-def continuation_fields(case, tag, mach_steps, device=0, stream=None, stage_tol=1e-4, tol=1e-6, **opts):
-    """Solve a free-stream case by Mach continuation up to case.meta["Ma"]; returns (fields, total
-    iterations, seconds, converged)."""
+def continuation_fields(case, tag, mach_steps, device=0, stream=None, stage_tol=1e-4, tol=1e-6, cont=None, **opts):
+    """Solve a free-stream case by Mach continuation up to case.meta["Ma"]; `cont` holds extra arguments of
+    Solver.solve_continuation.  Returns (fields, total iterations, seconds, converged)."""
     g = case.gas.gamma
     s = Solver(case, device=device, stream=stream, **opts)
     Ma = case.meta["Ma"]
@@ -278,7 +278,7 @@ def continuation_fields(case, tag, mach_steps, device=0, stream=None, stage_tol=
     u0[:, 0] = states[0][2][0]
     s.init_equilibrium(np.ones(n), u0, np.ones(n))  # uniform free stream of the first stage
     t0 = time.perf_counter()
-    its, hist, ok = s.solve_continuation(tag, states, stage_tol=stage_tol, tol=tol)
+    its, hist, ok = s.solve_continuation(tag, states, stage_tol=stage_tol, tol=tol, **(cont or {}))
     dt = time.perf_counter() - t0
     F = s.fields()
     s.close()
@@ -290,24 +290,32 @@ def mach_steps(Ma):
     return [x for x in (2.0, 3.0, 4.0) if x < Ma - 0.25]
 
 
-def cylinder_training_set(cases, device=0, stream=None, tol=1e-6, **opts):
-    """Features and targets of cylinder cases solved from the free stream by Mach continuation; cases whose
-    solve fails or does not converge are skipped.  Returns (X, Y, per-case records)."""
+def cylinder_training_set(cases, device=0, stream=None, tol=1e-6, first_order_fallback=True, **opts):
+    """Features and targets of cylinder cases solved from the free stream by Mach continuation.  A case
+    whose second-order continuation fails (a NaN residual or no convergence: on coarse training meshes at
+    Kn ~ 0.01-0.02 the limited second-order shock does not settle) is solved again with first-order
+    reconstruction throughout, and that solution is used; cases that still fail are skipped.  Returns
+    (X, Y, per-case records with the order used)."""
     X, Y, info = [], [], []
     for c in cases:
         rec = dict(Ma=c.meta["Ma"], Kn=c.flow.Kn_gas, tau=c.flow.k_eff)
-        try:
-            F, it, dt, ok = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), device=device, stream=stream,
-                                                tol=tol, **opts)
-        except GsisError as ex:
-            rec.update(ok=False, error=str(ex))
-            info.append(rec)
-            continue
-        rec.update(ok=ok, iterations=it, seconds=dt)
+        tries = [(2, opts, None)]
+        if first_order_fallback:
+            tries.append((1, dict(opts, second_order=0), dict(first_order_iters=0, first_order_jump=0)))
+        for order, o, cont in tries:
+            try:
+                F, it, dt, ok = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), device=device, stream=stream,
+                                                    tol=tol, cont=cont, **o)
+            except GsisError as ex:
+                rec.update(ok=False, order=order, error=str(ex))
+                continue
+            rec.update(ok=ok, order=order, iterations=it, seconds=dt)
+            rec.pop("error", None)
+            if ok:
+                X.append(cylinder_features(c))
+                Y.append(field_targets(F))
+                break
         info.append(rec)
-        if ok:
-            X.append(cylinder_features(c))
-            Y.append(field_targets(F))
     if not X:
         raise GsisError("no training case converged")
     return np.concatenate(X), np.concatenate(Y), info

@@ -124,7 +124,8 @@ def test_warm_start_replaces_mach_continuation():
     P = warmstart_cylinder_params(12, seed=3)
     train = [case_cylinder(mesh=mesh, Ma=m, Kn=k, tau_opt=t, **kw) for m, k, t in P]
     X, Y, info = cylinder_training_set(train, limiter_K=1.0)
-    assert sum(r["ok"] for r in info) >= 6, info
+    # every case converges: second order, or first order where the coarse-mesh shock does not settle
+    assert sum(r["ok"] for r in info) == len(train), info
     ws = WS.WarmStart(width=256, seed=0, family="cylinder")
     ws.fit(X, Y, epochs=200, batch=2048, lr=2e-3)
     tests = [case_cylinder(mesh=mesh, Ma=4.17, Kn=0.062, tau_opt=1.72, **kw),

@@ -70,7 +70,8 @@ typedef struct {
 } gsis_gas;
 
 /* Flow parameters: Kn_gas enters tau = sqrt(2/pi) T_t^(omega-1) Kn_gas / rho; k_eff = 1/Kn_photon
- * (optical thickness per reference length; 0 switches absorption and emission off). */
+ * (optical thickness per reference length; 0 switches absorption and emission off, and the radiation
+ * energy then keeps its kinetic value in the synthetic solve, whose e_R row would be singular). */
 typedef struct {
     double Kn_gas, k_eff;
 } gsis_flow;

@@ -917,6 +917,9 @@ int32_t gsis_set_opts(gsis_t *h, const gsis_opts *o)
         !(o->inner_tol >= 0) || !(o->limiter_K > 0) || !(o->kin_omega > 0) || !(o->cfl_v > 0) ||
         !(o->cfl_meso > 0) || !(o->cfl_macro > 0))
         return fail(h, GSIS_E_ARG, "gsis_set_opts: invalid options");
+    // the kinetic kernels index waves over (cell, 64-velocity chunk) pairs with 32-bit integers
+    if (h->hm.nc * ((h->nv + 63) / 64 + 1) > (int64_t)(INT32_MAX / 8))
+        return fail(h, GSIS_E_ARG, "gsis_set_opts: mesh x velocity grid too large for one device");
     (void)hipSetDevice(h->device);
     const bool realloc = !h->have_state || o->precision != h->prec || o->limiter_K != h->opts.limiter_K;
     h->opts = *o;

@@ -108,10 +108,12 @@ def test_gsis_iterations_fp64(name, case):
     assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-8
 
 
-def test_decoupled_radiation_macro_solve_and_iterations():
-    """Optical thickness 0 (absorption and emission off): the synthetic solve keeps e_R at its kinetic
-    value on both sides, W agrees with the oracle, and GSIS iterations stay finite and agree."""
-    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1, tau_opt=0.0)
+@pytest.mark.parametrize("kw", [dict(tau_opt=0.0), dict(sigma_R=0.0)], ids=["optically_thin_limit", "no_radiation"])
+def test_decoupled_radiation_macro_solve_and_iterations(kw):
+    """Degenerate radiation: optical thickness 0 (absorption and emission off; the synthetic solve keeps
+    e_R at its kinetic value) and sigma_R = 0 (no radiation energy at all): the synthetic solve agrees with
+    the oracle and GSIS iterations stay finite and agree."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1, **kw)
     s, o = _pair(case, precision="fp64", max_inner=60)
     _warm(o, s, n=3)
     o.kinetic_step()
@@ -125,6 +127,9 @@ def test_decoupled_radiation_macro_solve_and_iterations():
         eo, _ = o2.iterate(gsis=k >= 2)
         eg, _ = s2.iterate(gsis=k >= 2)
         assert np.isfinite(eg) and abs(eg - eo) <= 1e-8 * abs(eo) + 1e-14
+    names = field_names(2)
+    Fg = s2.fields()
+    assert np.isfinite(np.delete(Fg, names.index("TR"), axis=1)).all()
     s.close()
     s2.close()
 

@@ -389,6 +389,7 @@ static void free_macro(MacroBufs &B)
     dfree(B.fld2);
     dfree(B.Gs);
     dfree(B.part);
+    dfree(B.bpart);
     dfree(B.gfld);
     dfree(B.R);
     dfree(B.Dg);
@@ -477,6 +478,7 @@ static bool alloc_macro(gsis_t *h)
     B.dref = dalloc<double>(nf * NW, ok);
     B.resc = dalloc<double>(nc * 7, ok);
     B.scal = dalloc<double>(16, ok);
+    B.bpart = dalloc<double>(8 * kSumBlocks, ok);
     B.flags = dalloc<int>(4, ok);
     const MomLayout L{D};
     h->mom0 = dalloc<double>(nc * L.size(), ok);
@@ -640,9 +642,10 @@ static int macro_T(gsis_t *h, const double *mom, const double *bflux, const doub
 static double epsilon_of(gsis_t *h, const double *m1, const double *m0)
 {
     const int D = h->hm.D;
-    if (D == 1) launch_residual<1>(m1, m0, h->m.vol, h->cellbuf, h->red, h->hm.nc, h->phys, h->stream);
-    else if (D == 2) launch_residual<2>(m1, m0, h->m.vol, h->cellbuf, h->red, h->hm.nc, h->phys, h->stream);
-    else launch_residual<3>(m1, m0, h->m.vol, h->cellbuf, h->red, h->hm.nc, h->phys, h->stream);
+    if (D == 1) launch_residual<1>(m1, m0, h->m.vol, h->cellbuf, h->red, h->Mb.bpart, h->hm.nc, h->phys, h->stream);
+    else if (D == 2) launch_residual<2>(m1, m0, h->m.vol, h->cellbuf, h->red, h->Mb.bpart, h->hm.nc,
+                                         h->phys, h->stream);
+    else launch_residual<3>(m1, m0, h->m.vol, h->cellbuf, h->red, h->Mb.bpart, h->hm.nc, h->phys, h->stream);
     double s[7];
     (void)hipMemcpyAsync(s, h->red, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     (void)hipStreamSynchronize(h->stream);

@@ -27,6 +27,7 @@ struct MacroBufs {
     double *Gs = nullptr;                     // per cell slot (interior faces): spectral radii G, G_R
     double *part = nullptr;                   // per-block partial sums of the residual norm
     double *resc = nullptr, *scal = nullptr;  // per-cell scratch, device scalars (res0, mass, ...)
+    double *bpart = nullptr;                  // partial sums of launch_block_sum (8 * kSumBlocks)
     int *flags = nullptr;                     // [0] done, [1] inner count, [2] block arrival counter
 };
 
@@ -146,8 +147,9 @@ void launch_sync_params(const double *mom, const double *W, double *sp, int64_t 
 // num T, den T, V) and their deterministic sum
 template <int D>
 void launch_residual(const double *mom1, const double *mom0, const double *vol, double *cellbuf, double *out7,
-                     int64_t nc, const Phys &p, hipStream_t st);
-// deterministic single-block sum of n values with stride k (k sums)
-void launch_block_sum(const double *in, int64_t n, int k, double *out, hipStream_t st);
+                     double *part, int64_t nc, const Phys &p, hipStream_t st);
+// deterministic sums of n rows of k interleaved values (k sums); part: k * kSumBlocks doubles of scratch
+constexpr int kSumBlocks = 128;
+void launch_block_sum(const double *in, int64_t n, int k, double *out, double *part, hipStream_t st);
 
 }  // namespace gsis

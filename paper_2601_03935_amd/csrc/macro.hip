@@ -934,27 +934,43 @@ __global__ void k_mass_scale(double *__restrict__ W, const double *__restrict__ 
     W[c * NW + D + 1] -= (sc - 1.0) * W[c * NW + D + 4];
 }
 
-__global__ __launch_bounds__(1024) void k_block_sum(const double *__restrict__ in, const int64_t n, const int k,
-                                                    double *__restrict__ out)
+// Deterministic sums of k interleaved components over n rows (in[i * k + comp]): kSumBlocks blocks each
+// reduce a contiguous row range in a fixed tree order into part[comp * kSumBlocks + block]; a single
+// wave then adds the partials of each component in block order.
+__global__ __launch_bounds__(256) void k_block_sum1(const double *__restrict__ in, const int64_t n, const int k,
+                                                    double *__restrict__ part)
 {
-    __shared__ double sh[1024];
+    __shared__ double sh[256];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
     for (int comp = 0; comp < k; ++comp) {
-        double s = 0;
-        for (int64_t i = threadIdx.x; i < n; i += 1024) s += in[i * k + comp];
-        sh[threadIdx.x] = s;
+        double v = 0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) v += in[i * k + comp];
+        sh[threadIdx.x] = v;
         __syncthreads();
-        for (int o = 512; o > 0; o >>= 1) {
+        for (int o = 128; o > 0; o >>= 1) {
             if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
             __syncthreads();
         }
-        if (threadIdx.x == 0) out[comp] = sh[0];
+        if (threadIdx.x == 0) part[comp * gridDim.x + blockIdx.x] = sh[0];
         __syncthreads();
     }
 }
 
-void launch_block_sum(const double *in, int64_t n, int k, double *out, hipStream_t st)
+__global__ __launch_bounds__(64) void k_block_sum2(const double *__restrict__ part, const int nb, const int k,
+                                                   double *__restrict__ out)
 {
-    hipLaunchKernelGGL(k_block_sum, dim3(1), dim3(1024), 0, st, in, n, k, out);
+    const int comp = threadIdx.x;
+    if (comp >= k) return;
+    double v = 0;
+    for (int b = 0; b < nb; ++b) v += part[comp * nb + b];
+    out[comp] = v;
+}
+
+void launch_block_sum(const double *in, int64_t n, int k, double *out, double *part, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_block_sum1, dim3(kSumBlocks), dim3(256), 0, st, in, n, k, part);
+    hipLaunchKernelGGL(k_block_sum2, dim3(1), dim3(64), 0, st, part, kSumBlocks, k, out);
 }
 
 // B.W scaled to the total mass of the moments mom_mass (u and temperatures unchanged; e_R not scaled)
@@ -965,9 +981,9 @@ void rescale_mass(MacroBufs &B, const MeshDev &m, const double *mom_mass, hipStr
     const int64_t nc = m.nc;
     const dim3 gc((nc + 255) / 256), blk(256);
     hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, mom_mass, L.size(), m.vol, B.resc, nc);
-    launch_block_sum(B.resc, nc, 1, B.scal + 3, st);
+    launch_block_sum(B.resc, nc, 1, B.scal + 3, B.bpart, st);
     hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, B.W, D + 5, m.vol, B.resc, nc);
-    launch_block_sum(B.resc, nc, 1, B.scal + 2, st);
+    launch_block_sum(B.resc, nc, 1, B.scal + 2, B.bpart, st);
     hipLaunchKernelGGL(k_mass_scale<D>, gc, blk, 0, st, B.W, B.scal + 2, B.scal + 3, nc);
 }
 
@@ -1040,9 +1056,9 @@ void launch_mass_ratio(MacroBufs &B, const MeshDev &m, const double *mom_num, co
     const int64_t nc = m.nc;
     const dim3 gc((nc + 255) / 256), blk(256);
     hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, mom_num, L.size(), m.vol, B.resc, nc);
-    launch_block_sum(B.resc, nc, 1, B.scal + 3, st);
+    launch_block_sum(B.resc, nc, 1, B.scal + 3, B.bpart, st);
     hipLaunchKernelGGL(k_mass_terms, gc, blk, 0, st, mom_den, L.size(), m.vol, B.resc, nc);
-    launch_block_sum(B.resc, nc, 1, B.scal + 2, st);
+    launch_block_sum(B.resc, nc, 1, B.scal + 2, B.bpart, st);
 }
 
 // ------------------------------------------------------------------ sync parameters and residual epsilon
@@ -1110,10 +1126,10 @@ __global__ void k_resid_terms(const double *__restrict__ m1, const double *__res
 
 template <int D>
 void launch_residual(const double *mom1, const double *mom0, const double *vol, double *cellbuf, double *out7,
-                     int64_t nc, const Phys &p, hipStream_t st)
+                     double *part, int64_t nc, const Phys &p, hipStream_t st)
 {
     hipLaunchKernelGGL(k_resid_terms<D>, dim3((nc + 255) / 256), dim3(256), 0, st, mom1, mom0, vol, cellbuf, nc, p);
-    launch_block_sum(cellbuf, nc, 7, out7, st);
+    launch_block_sum(cellbuf, nc, 7, out7, part, st);
 }
 
 #define GSIS_INST_M(D, NFM)                                                                                      \
@@ -1130,11 +1146,11 @@ template void launch_mass_ratio<3>(MacroBufs &, const MeshDev &, const double *,
 template void launch_sync_params<1>(const double *, const double *, double *, int64_t, const Phys &, int, hipStream_t);
 template void launch_sync_params<2>(const double *, const double *, double *, int64_t, const Phys &, int, hipStream_t);
 template void launch_sync_params<3>(const double *, const double *, double *, int64_t, const Phys &, int, hipStream_t);
-template void launch_residual<1>(const double *, const double *, const double *, double *, double *, int64_t,
-                                 const Phys &, hipStream_t);
-template void launch_residual<2>(const double *, const double *, const double *, double *, double *, int64_t,
-                                 const Phys &, hipStream_t);
-template void launch_residual<3>(const double *, const double *, const double *, double *, double *, int64_t,
-                                 const Phys &, hipStream_t);
+template void launch_residual<1>(const double *, const double *, const double *, double *, double *, double *,
+                                 int64_t, const Phys &, hipStream_t);
+template void launch_residual<2>(const double *, const double *, const double *, double *, double *, double *,
+                                 int64_t, const Phys &, hipStream_t);
+template void launch_residual<3>(const double *, const double *, const double *, double *, double *, double *,
+                                 int64_t, const Phys &, hipStream_t);
 
 }  // namespace gsis

@@ -374,30 +374,6 @@ __device__ __forceinline__ void cell_grad(const double *__restrict__ fld, const 
     }
 }
 
-// the same gradient with the neighbour list of c given (nb[s] < 0: boundary or padded slot)
-template <int D, int NFM>
-__device__ __forceinline__ void cell_grad_l(const double *__restrict__ fld, const MeshDev &m, const int64_t c,
-                                            const int *nb, double g[][D])
-{
-    constexpr int NF = D + 4;
-#pragma unroll
-    for (int i = 0; i < NF; ++i)
-#pragma unroll
-        for (int a = 0; a < D; ++a) g[i][a] = 0;
-#pragma unroll
-    for (int s = 0; s < NFM; ++s) {
-        const int j = nb[s];
-        if (j < 0) continue;
-        const double *gs = m.geo + (c * NFM + s) * 4 * D + 3 * D;
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-            const double df = fld[(int64_t)j * NF + i] - fld[c * NF + i];
-#pragma unroll
-            for (int a = 0; a < D; ++a) g[i][a] += gs[a] * df;
-        }
-    }
-}
-
 template <int D, int NFM>
 __global__ void k_cell_grad(const double *__restrict__ fld, double *__restrict__ gfld, const MeshDev m)
 {
@@ -412,11 +388,32 @@ __global__ void k_cell_grad(const double *__restrict__ fld, double *__restrict__
         for (int a = 0; a < D; ++a) gfld[(c * NF + i) * D + a] = g[i][a];
 }
 
-// face gradient: mean of the two cell gradients with the component along the centroid line replaced by
-// the centroid difference quotient (dvec = x_j - x_c)
+// adds the least-squares gradient of cell c (as cell_grad) to g, with the neighbour list of c given
+// (nb[s] < 0: boundary or padded slot)
+template <int D, int NFM>
+__device__ __forceinline__ void cell_grad_add(const double *__restrict__ fld, const MeshDev &m, const int64_t c,
+                                              const int *nb, double g[][D])
+{
+    constexpr int NF = D + 4;
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        const int j = nb[s];
+        if (j < 0) continue;
+        const double *gs = m.geo + (c * NFM + s) * 4 * D + 3 * D;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const double df = fld[(int64_t)j * NF + i] - fld[c * NF + i];
+#pragma unroll
+            for (int a = 0; a < D; ++a) g[i][a] += gs[a] * df;
+        }
+    }
+}
+
+// face gradient from the sum gs of the two cell gradients: their mean with the component along the
+// centroid line replaced by the centroid difference quotient (dvec = x_j - x_c)
 template <int D>
-__device__ __forceinline__ void face_grad_g(const double *fld, const double gc[][D], const double gj[][D],
-                                            int64_t c, int64_t j, const double *dvec, double g[][3])
+__device__ __forceinline__ void face_grad_sum(const double *fld, const double gs[][D], int64_t c, int64_t j,
+                                              const double *dvec, double g[][3])
 {
     constexpr int NF = D + 4;
     double dl = 0, dh[D];
@@ -430,7 +427,7 @@ __device__ __forceinline__ void face_grad_g(const double *fld, const double gc[]
         double avg[D], corr = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            avg[a] = 0.5 * (gc[i][a] + gj[i][a]);
+            avg[a] = 0.5 * gs[i][a];
             corr += avg[a] * dh[a];
         }
         const double jump = (fld[j * NF + i] - fld[c * NF + i]) / dl;
@@ -444,20 +441,17 @@ __device__ __forceinline__ void face_grad(const double *fld, const double *gfld,
                                           const double *dvec, double g[][3])
 {
     constexpr int NF = D + 4;
-    double gc[NF][D], gj[NF][D];
+    double gs[NF][D];
 #pragma unroll
     for (int i = 0; i < NF; ++i)
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            gc[i][a] = gfld[(c * NF + i) * D + a];
-            gj[i][a] = gfld[(j * NF + i) * D + a];
-        }
-    face_grad_g<D>(fld, gc, gj, c, j, dvec, g);
+        for (int a = 0; a < D; ++a) gs[i][a] = gfld[(c * NF + i) * D + a] + gfld[(j * NF + i) * D + a];
+    face_grad_sum<D>(fld, gs, c, j, dvec, g);
 }
 
 // face HoTs on interior faces: mean kinetic moments minus NSF with the face gradient (mu from the moments)
 template <int D>
-__global__ void k_face_hot(const double *__restrict__ mom, const double *__restrict__ fld,
+__global__ __launch_bounds__(256) void k_face_hot(const double *__restrict__ mom, const double *__restrict__ fld,
                            const double *__restrict__ gfld, const double *__restrict__ mu, double *__restrict__ hotf,
                            const MeshDev m, const double *__restrict__ fdvec, const Phys p)
 {
@@ -603,10 +597,14 @@ __device__ __forceinline__ void face_flux(const double *__restrict__ W, const do
     rusanov_q<D>(W + cL * NW, qc, Pc[D + 6], W + cR * NW, qj, Pj[D + 6], n, Fc);
 #pragma unroll
     for (int i = 0; i < NW; ++i) Fc[i] += dref[fid * NW + i];
-    double gc[NF][D], gj[NF][D], g[NF][3], sig[3][3], q[4][3], Fv[NW], uf[3] = {0, 0, 0};
-    cell_grad_l<D, NFM>(fld, m, cL, nbL, gc);
-    cell_grad_l<D, NFM>(fld, m, cR, nbR, gj);
-    face_grad_g<D>(fld, gc, gj, cL, cR, dvec, g);
+    double gsum[NF][D], g[NF][3], sig[3][3], q[4][3], Fv[NW], uf[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int a = 0; a < D; ++a) gsum[i][a] = 0;
+    cell_grad_add<D, NFM>(fld, m, cL, nbL, gsum);
+    cell_grad_add<D, NFM>(fld, m, cR, nbR, gsum);
+    face_grad_sum<D>(fld, gsum, cL, cR, dvec, g);
 #pragma unroll
     for (int a = 0; a < D; ++a) uf[a] = 0.5 * (Pc[1 + a] + Pj[1 + a]);
     constitutive<D>(0.5 * (Pc[D + 5] + Pj[D + 5]), g, hotf + fid * kNHot, p, sig, q);
@@ -668,7 +666,10 @@ __device__ __forceinline__ bool inner_converged(const double pr[kPartRegs], cons
 // order, boundary model fluxes plus the frozen kinetic corrections), the diagonal D_i and the first
 // increment of the U unknowns; per-slot spectral radii for the sweeps; per-block sums of the
 // volume-weighted squared residual.
-template <int D, int NFM>
+// PRE: the cell's point-solve data is loaded up front with the slot tables (one dependent-load level
+// less; 22 more VGPRs, two waves per SIMD), else in the per-cell tail (three waves per SIMD, for grids
+// that would not fit the GPU in one round at two).
+template <int D, int NFM, bool PRE>
 __global__ __launch_bounds__(kSBlk) void k_mres(
     const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ fld,
     const double *__restrict__ hotf, const double *__restrict__ dref, const double *__restrict__ bcorr,
@@ -696,13 +697,15 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
         nbj[q] = slot ? m.nb2[(c * NFM + s) * NFM + q] : INT32_MIN;
     }
     double Wc[NW], Pc[D + 7], V = 1, hc = 1;
+    if constexpr (PRE) {
 #pragma unroll
-    for (int i = 0; i < NW; ++i) Wc[i] = cell ? W[c * NW + i] : 1.0;
+        for (int i = 0; i < NW; ++i) Wc[i] = cell ? W[c * NW + i] : 1.0;
 #pragma unroll
-    for (int i = 0; i < D + 7; ++i) Pc[i] = cell ? P[c * NP + i] : 1.0;
-    if (cell) {
-        V = m.vol[c];
-        hc = m.h[c];
+        for (int i = 0; i < D + 7; ++i) Pc[i] = cell ? P[c * NP + i] : 1.0;
+        if (cell) {
+            V = m.vol[c];
+            hc = m.h[c];
+        }
     }
     if (done) return;
     double Fs[NW], S = 0, gS = 0, gRS = 0;
@@ -713,7 +716,7 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
         if (j < 0) {
             const int bfi = -j - 1;
             double g1, g2;
-            bmodel_flux<D>(m, bfi, Wc, p, Fs, &g1, &g2);
+            bmodel_flux<D>(m, bfi, PRE ? Wc : W + c * NW, p, Fs, &g1, &g2);
 #pragma unroll
             for (int i = 0; i < NW; ++i) Fs[i] += bcorr[(int64_t)bfi * NW + i];
             gS = g1 * S;
@@ -748,6 +751,14 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
     }
     double contrib = 0;
     if (cell && s == 0) {
+        if constexpr (!PRE) {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) Wc[i] = W[c * NW + i];
+#pragma unroll
+            for (int i = 0; i < D + 7; ++i) Pc[i] = P[c * NP + i];
+            V = m.vol[c];
+            hc = m.h[c];
+        }
         const double rho = Pc[0], Tt = Pc[D + 1], Tr = Pc[D + 2], Tv = Pc[D + 3];
         const double tau = Pc[D + 5] / (rho * Tt);
         const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = (3 * Tt + p.d_v * Tv) / (3 + p.d_v);
@@ -1005,6 +1016,11 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     const dim3 gci((nc + kMBlk - 1) / kMBlk), bi(kMBlk);
     const int npart = (int)macro_nparts(nc, NFM);
     const dim3 gsl(npart), bsl(kSBlk);
+    // the preloading residual kernel runs two waves per SIMD: use it while its blocks fit the GPU at once
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const bool one_round = (int64_t)npart * (kSBlk / kWave) <= (int64_t)ncu * 4 * 2;
     hipLaunchKernelGGL(k_mprim<D>, gci, bi, 0, st, B.W, B.P, B.fld, nc, p);
     // inner iteration `it` starts from the state in buffer `it % 2` when the sweeps ping-pong
     double *Wb[2] = {B.W, B.W2}, *Pb[2] = {B.P, B.P2}, *Fb[2] = {B.fld, B.fld2};
@@ -1014,8 +1030,12 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     for (int it = 0; it < o.max_inner; ++it) {
         const int cur = pingpong ? (it & 1) : 0, nxt = cur ^ 1;
         double *W = Wb[cur], *P = Pb[cur], *fld = Fb[cur];
-        hipLaunchKernelGGL((k_mres<D, NFM>), gsl, bsl, 0, st, W, P, fld, B.hotf, B.dref, B.bcorr, B.Gs, B.R, B.Dg,
-                           B.dU0, B.part, B.flags, m, p, o.cfl_macro);
+        if (one_round)
+            hipLaunchKernelGGL((k_mres<D, NFM, true>), gsl, bsl, 0, st, W, P, fld, B.hotf, B.dref, B.bcorr, B.Gs, B.R,
+                               B.Dg, B.dU0, B.part, B.flags, m, p, o.cfl_macro);
+        else
+            hipLaunchKernelGGL((k_mres<D, NFM, false>), gsl, bsl, 0, st, W, P, fld, B.hotf, B.dref, B.bcorr, B.Gs,
+                               B.R, B.Dg, B.dU0, B.part, B.flags, m, p, o.cfl_macro);
         double *din = B.dU0, *dout = B.dU1;
         const int ns = o.n_sweeps;
         for (int s = 0; s < ns; ++s) {

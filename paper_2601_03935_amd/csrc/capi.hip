@@ -145,6 +145,7 @@ static void free_mesh(MeshDev &m)
     dfree(m.sfid);
     dfree(m.geo);
     dfree(m.mgeo);
+    dfree(m.lsq);
     dfree(m.vol);
     dfree(m.h);
     dfree(m.eps2);
@@ -339,8 +340,11 @@ static int32_t build_mesh(gsis_t *h)
     for (int64_t k = 0; k < nc * NFM; ++k)
         if (nbr[k] >= 0)
             for (int t = 0; t < NFM; ++t) nb2[k * NFM + t] = nbr[(int64_t)nbr[k] * NFM + t];
+    std::vector<double> lsq(nc * NFM * D);
+    for (int64_t k = 0; k < nc * NFM; ++k)
+        for (int a = 0; a < D; ++a) lsq[k * D + a] = geo[k * 4 * D + 3 * D + a];
     bool ok = upload(m.nbr, nbr) && upload(m.nb2, nb2) && upload(m.sfid, sfid) && upload(m.geo, geo) &&
-              upload(m.mgeo, mgeo) && upload(m.vol, hm.vol) &&
+              upload(m.mgeo, mgeo) && upload(m.lsq, lsq) && upload(m.vol, hm.vol) &&
               upload(m.h, hh) && upload(m.eps2, eps2) && upload(m.nfc, nfc) && upload(m.bf_face, bf_face) &&
               upload(m.bf_cell, bf_cell) && upload(m.bf_tag, bf_tag) && upload(m.bf_n, bf_n) &&
               upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.f_L, fL) && upload(m.f_R, fR) &&
@@ -395,9 +399,8 @@ static void free_macro(MacroBufs &B)
     dfree(B.Dg);
     dfree(B.dU0);
     dfree(B.dU1);
-    dfree(B.hotf);
+    dfree(B.fcon);
     dfree(B.bcorr);
-    dfree(B.dref);
     dfree(B.resc);
     dfree(B.scal);
     dfree(B.flags);
@@ -473,9 +476,8 @@ static bool alloc_macro(gsis_t *h)
     B.Dg = dalloc<double>(nc * NW, ok);
     B.dU0 = dalloc<double>(nc * NW, ok);
     B.dU1 = dalloc<double>(nc * NW, ok);
-    B.hotf = dalloc<double>(nf * kNHot, ok);
+    B.fcon = dalloc<double>(nf * (NW + D), ok);
     B.bcorr = dalloc<double>(nbf * NW, ok);
-    B.dref = dalloc<double>(nf * NW, ok);
     B.resc = dalloc<double>(nc * 7, ok);
     B.scal = dalloc<double>(16, ok);
     B.bpart = dalloc<double>(8 * kSumBlocks, ok);

@@ -12,7 +12,6 @@ namespace gsis {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kWave = 64;
-constexpr int kNHot = 21;  // HoT_sigma (3x3), HoT_qt, HoT_qr, HoT_qv, HoT_qR (3 each)
 
 // Workgroup b of nb is dispatched to XCD b % 8; remap so that XCD x walks the contiguous block range
 // [x nb/8, (x+1) nb/8) (cells and faces are in locality order, so neighbours share that XCD's L2).
@@ -75,6 +74,7 @@ struct MeshDev {
     int *sfid = nullptr;  // per slot: face id if the cell is the face's left cell, -(1 + face id) otherwise
     double *geo = nullptr;
     double *mgeo = nullptr;
+    double *lsq = nullptr;  // per slot: the D least-squares gradient weights of geo, packed (cell gradients)
     double *vol = nullptr, *h = nullptr, *eps2 = nullptr;
     int *nfc = nullptr;
     // boundary faces

@@ -23,7 +23,8 @@ struct MacroBufs {
     double *W = nullptr, *W0 = nullptr, *P = nullptr, *fld = nullptr, *gfld = nullptr;
     double *W2 = nullptr, *P2 = nullptr, *fld2 = nullptr;  // second state of the inner-iteration ping-pong
     double *R = nullptr, *Dg = nullptr, *dU0 = nullptr, *dU1 = nullptr;
-    double *hotf = nullptr, *bcorr = nullptr, *dref = nullptr;
+    double *fcon = nullptr;   // per face: frozen flux constants (dissipation + HoTs), HoT stress along n
+    double *bcorr = nullptr;  // per boundary face: kinetic minus model flux at the start of the solve
     double *Gs = nullptr;                     // per cell slot (interior faces): spectral radii G, G_R
     double *part = nullptr;                   // per-block partial sums of the residual norm
     double *resc = nullptr, *scal = nullptr;  // per-cell scratch, device scalars (res0, mass, ...)

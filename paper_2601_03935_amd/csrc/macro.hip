@@ -286,13 +286,18 @@ __device__ __forceinline__ void positive_update(double *W, const double *dU, con
 #pragma unroll
         for (int i = 0; i < NW; ++i) Wn[i] = W[i] + a * dU[i];
         Wn[D + 1] += a * dU[D + 4];
+        // the bounds on conserved components first: the temperature (divisions) only for a factor
+        // that passes them
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = (i == 0) ? 0 : D + 1 + i;
+            ok = ok && Wn[k] >= 0.5 * W[k] && Wn[k] >= 0.5 * Ws[k] && Wn[k] <= 2 * Ws[k];
+        }
+        if (!ok) continue;
         PrimL p1;
         prim_lite<D>(Wn, p1);
-        if (Wn[0] >= 0.5 * W[0] && p1.Tt >= 0.5 * p0.Tt && Wn[D + 2] >= 0.5 * W[D + 2] &&
-            Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4] && Wn[0] >= 0.5 * Ws[0] &&
-            p1.Tt >= 0.5 * ps.Tt && Wn[D + 2] >= 0.5 * Ws[D + 2] && Wn[D + 3] >= 0.5 * Ws[D + 3] &&
-            Wn[D + 4] >= 0.5 * Ws[D + 4] && Wn[0] <= 2 * Ws[0] && p1.Tt <= 2 * ps.Tt &&
-            Wn[D + 2] <= 2 * Ws[D + 2] && Wn[D + 3] <= 2 * Ws[D + 3] && Wn[D + 4] <= 2 * Ws[D + 4]) {
+        if (p1.Tt >= 0.5 * p0.Tt && p1.Tt >= 0.5 * ps.Tt && p1.Tt <= 2 * ps.Tt) {
 #pragma unroll
             for (int i = 0; i < NW; ++i) W[i] = Wn[i];
             return;
@@ -364,7 +369,7 @@ __device__ __forceinline__ void cell_grad(const double *__restrict__ fld, const 
     for (int s = 0; s < NFM; ++s) {
         const int j = (s < nfc) ? m.nbr[c * NFM + s] : -1;
         if (j < 0) continue;
-        const double *gs = m.geo + (c * NFM + s) * 4 * D + 3 * D;
+        const double *gs = m.lsq + (c * NFM + s) * D;
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
             const double df = fld[(int64_t)j * NF + i] - fld[c * NF + i];
@@ -399,7 +404,7 @@ __device__ __forceinline__ void cell_grad_add(const double *__restrict__ fld, co
     for (int s = 0; s < NFM; ++s) {
         const int j = nb[s];
         if (j < 0) continue;
-        const double *gs = m.geo + (c * NFM + s) * 4 * D + 3 * D;
+        const double *gs = m.lsq + (c * NFM + s) * D;
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
             const double df = fld[(int64_t)j * NF + i] - fld[c * NF + i];
@@ -419,9 +424,9 @@ __device__ __forceinline__ void face_grad_sum(const double *fld, const double gs
     double dl = 0, dh[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) dl += dvec[a] * dvec[a];
-    dl = sqrt(dl);
+    const double idl = 1.0 / sqrt(dl);
 #pragma unroll
-    for (int a = 0; a < D; ++a) dh[a] = dvec[a] / dl;
+    for (int a = 0; a < D; ++a) dh[a] = dvec[a] * idl;
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
         double avg[D], corr = 0;
@@ -430,7 +435,7 @@ __device__ __forceinline__ void face_grad_sum(const double *fld, const double gs
             avg[a] = 0.5 * gs[i][a];
             corr += avg[a] * dh[a];
         }
-        const double jump = (fld[j * NF + i] - fld[c * NF + i]) / dl;
+        const double jump = (fld[j * NF + i] - fld[c * NF + i]) * idl;
 #pragma unroll
         for (int a = 0; a < 3; ++a) g[i][a] = (a < D) ? avg[a] + (jump - corr) * dh[a] : 0.0;
     }
@@ -449,33 +454,72 @@ __device__ __forceinline__ void face_grad(const double *fld, const double *gfld,
     face_grad_sum<D>(fld, gs, c, j, dvec, g);
 }
 
-// face HoTs on interior faces: mean kinetic moments minus NSF with the face gradient (mu from the moments)
+// Per-face constants of the synthetic flux, frozen for the whole solve (interior faces; zero rows on
+// boundary faces): [0, NW) the reference dissipation 0.5 lam* (W0_R - W0_L) plus the HoT part of the
+// viscous flux (HoT stress and heat fluxes along n), [NW, NW + D) the HoT stress along n alone, for the
+// work term u_f . (sigma_HoT n).  The HoTs are the mean kinetic moments of the two cells minus the NSF
+// relations with the face gradient (mu from the moments).
 template <int D>
-__global__ __launch_bounds__(256) void k_face_hot(const double *__restrict__ mom, const double *__restrict__ fld,
-                           const double *__restrict__ gfld, const double *__restrict__ mu, double *__restrict__ hotf,
-                           const MeshDev m, const double *__restrict__ fdvec, const Phys p)
+__global__ __launch_bounds__(256) void k_face_const(const double *__restrict__ mom, const double *__restrict__ fld,
+                                                    const double *__restrict__ gfld, const double *__restrict__ mu,
+                                                    const double *__restrict__ W0, double *__restrict__ fcon,
+                                                    const MeshDev m, const Phys p)
 {
     constexpr MomLayout L{D};
+    constexpr int NW = D + 5, NC = NW + D;
     const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (f >= m.nf) return;
-    double *h = hotf + f * kNHot;
-    for (int i = 0; i < kNHot; ++i) h[i] = 0;
+    double *h = fcon + f * NC;
     const int64_t c = m.f_L[f], j = m.f_R[f];
-    if (j < 0) return;
+    if (j < 0) {
+        for (int i = 0; i < NC; ++i) h[i] = 0;
+        return;
+    }
+    double n[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) n[a] = m.f_n[f * D + a];
     double g[D + 4][3], sig[3][3], q[4][3];
-    face_grad<D>(fld, gfld, c, j, fdvec + f * D, g);
+    face_grad<D>(fld, gfld, c, j, m.f_d + f * D, g);
     constitutive<D>(0.5 * (mu[c] + mu[j]), g, nullptr, p, sig, q);
     const double *Mc = mom + c * L.size(), *Mj = mom + j * L.size();
+    double hs[D], hq[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
+        hs[a] = 0;
 #pragma unroll
         for (int b = 0; b < D; ++b)
-            h[a * 3 + b] = 0.5 * (Mc[L.sig() + a * D + b] + Mj[L.sig() + a * D + b]) - sig[a][b];
-        h[9 + a] = 0.5 * (Mc[L.qt() + a] + Mj[L.qt() + a]) - q[0][a];
-        h[12 + a] = 0.5 * (Mc[L.qr() + a] + Mj[L.qr() + a]) - q[1][a];
-        h[15 + a] = 0.5 * (Mc[L.qv() + a] + Mj[L.qv() + a]) - q[2][a];
-        h[18 + a] = 0.5 * (Mc[L.qR() + a] + Mj[L.qR() + a]) - q[3][a];
+            hs[a] += (0.5 * (Mc[L.sig() + a * D + b] + Mj[L.sig() + a * D + b]) - sig[a][b]) * n[b];
+        hq[0] += (0.5 * (Mc[L.qt() + a] + Mj[L.qt() + a]) - q[0][a]) * n[a];
+        hq[1] += (0.5 * (Mc[L.qr() + a] + Mj[L.qr() + a]) - q[1][a]) * n[a];
+        hq[2] += (0.5 * (Mc[L.qv() + a] + Mj[L.qv() + a]) - q[2][a]) * n[a];
+        hq[3] += (0.5 * (Mc[L.qR() + a] + Mj[L.qR() + a]) - q[3][a]) * n[a];
     }
+    // reference dissipation (first-order face states of W0)
+    const double *WL = W0 + c * NW, *WR = W0 + j * NW;
+    Prim qL, qR;
+    prim_of<D>(WL, p, qL);
+    prim_of<D>(WR, p, qR);
+    double unL = 0, unR = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        unL += qL.u[a] * n[a];
+        unR += qR.u[a] * n[a];
+    }
+    const double lam = fmax(fabs(unL) + qL.cs, fabs(unR) + qR.cs);
+    double F[NW];
+#pragma unroll
+    for (int i = 0; i < NW - 1; ++i) F[i] = 0.5 * lam * (WR[i] - WL[i]);
+    F[NW - 1] = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[1 + a] += hs[a];
+    F[D + 1] += hq[0] + hq[1] + hq[2] + hq[3];
+    F[D + 2] += hq[1];
+    F[D + 3] += hq[2];
+    F[D + 4] += hq[3];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) h[i] = F[i];
+#pragma unroll
+    for (int a = 0; a < D; ++a) h[NW + a] = hs[a];
 }
 
 // frozen boundary corrections: kinetic boundary flux minus the model flux at W0
@@ -490,33 +534,6 @@ __global__ void k_bcorr(const double *__restrict__ W0, const double *__restrict_
     bmodel_flux<D>(m, (int)b, W0 + (int64_t)m.bf_cell[b] * NW, p, F, &g1, &g2);
 #pragma unroll
     for (int i = 0; i < NW; ++i) bcorr[b * NW + i] = bflux[b * NW + i] - F[i];
-}
-
-// reference dissipation 0.5 lam* (W0_R - W0_L) along the face normal (first-order face states)
-template <int D>
-__global__ void k_dref(const double *__restrict__ W0, double *__restrict__ dref, const MeshDev m, const Phys p)
-{
-    constexpr int NW = D + 5;
-    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (f >= m.nf) return;
-    const int64_t c = m.f_L[f], j = m.f_R[f];
-    for (int i = 0; i < NW; ++i) dref[f * NW + i] = 0;
-    if (j < 0) return;
-    const double *WL = W0 + c * NW, *WR = W0 + j * NW;
-    double n[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) n[a] = m.f_n[f * D + a];
-    Prim qL, qR;
-    prim_of<D>(WL, p, qL);
-    prim_of<D>(WR, p, qR);
-    double unL = 0, unR = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        unL += qL.u[a] * n[a];
-        unR += qR.u[a] * n[a];
-    }
-    const double lam = fmax(fabs(unL) + qL.cs, fabs(unR) + qR.cs);
-    for (int i = 0; i < NW - 1; ++i) dref[f * NW + i] = 0.5 * lam * (WR[i] - WL[i]);
 }
 
 // ------------------------------------------------------------------ inner-iteration kernels
@@ -576,8 +593,8 @@ __global__ void k_mprim(const double *__restrict__ W, double *__restrict__ P, do
 // this same expression and the right side negates it, so the discrete flux is exactly odd.
 template <int D, int NFM>
 __device__ __forceinline__ void face_flux(const double *__restrict__ W, const double *__restrict__ P,
-                                          const double *__restrict__ fld, const double *__restrict__ hotf,
-                                          const double *__restrict__ dref, const MeshDev &m, const Phys &p,
+                                          const double *__restrict__ fld, const double *__restrict__ fcon,
+                                          const MeshDev &m, const Phys &p,
                                           const int64_t fid, const int64_t cL, const int64_t cR,
                                           const int *nbL, const int *nbR, double *F, double *G, double *GR)
 {
@@ -595,8 +612,9 @@ __device__ __forceinline__ void face_flux(const double *__restrict__ W, const do
     prim_load<D>(Pj, qj);
     double Fc[NW];
     rusanov_q<D>(W + cL * NW, qc, Pc[D + 6], W + cR * NW, qj, Pj[D + 6], n, Fc);
+    const double *fc = fcon + fid * (NW + D);
 #pragma unroll
-    for (int i = 0; i < NW; ++i) Fc[i] += dref[fid * NW + i];
+    for (int i = 0; i < NW; ++i) Fc[i] += fc[i];
     double gsum[NF][D], g[NF][3], sig[3][3], q[4][3], Fv[NW], uf[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < NF; ++i)
@@ -607,10 +625,14 @@ __device__ __forceinline__ void face_flux(const double *__restrict__ W, const do
     face_grad_sum<D>(fld, gsum, cL, cR, dvec, g);
 #pragma unroll
     for (int a = 0; a < D; ++a) uf[a] = 0.5 * (Pc[1 + a] + Pj[1 + a]);
-    constitutive<D>(0.5 * (Pc[D + 5] + Pj[D + 5]), g, hotf + fid * kNHot, p, sig, q);
+    constitutive<D>(0.5 * (Pc[D + 5] + Pj[D + 5]), g, nullptr, p, sig, q);
     viscous_flux<D>(sig, q, uf, n, Fv);
+    double wh = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) wh += fc[NW + a] * uf[a];
 #pragma unroll
     for (int i = 0; i < NW; ++i) F[i] = Fc[i] + Fv[i];
+    F[D + 1] += wh;
     double ufn = 0, nd = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -672,7 +694,7 @@ __device__ __forceinline__ bool inner_converged(const double pr[kPartRegs], cons
 template <int D, int NFM, bool PRE>
 __global__ __launch_bounds__(kSBlk) void k_mres(
     const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ fld,
-    const double *__restrict__ hotf, const double *__restrict__ dref, const double *__restrict__ bcorr,
+    const double *__restrict__ fcon, const double *__restrict__ bcorr,
     double *__restrict__ Gs, double *__restrict__ R, double *__restrict__ Dg, double *__restrict__ dU,
     double *__restrict__ part, const int *__restrict__ flags, const MeshDev m, const Phys p, const double cfl_macro)
 {
@@ -725,7 +747,7 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
             const bool left = sf >= 0;
             const int64_t fid = left ? sf : -(int64_t)sf - 1;
             double G, GR;
-            face_flux<D, NFM>(W, P, fld, hotf, dref, m, p, fid, left ? c : j, left ? j : c, left ? nbc : nbj,
+            face_flux<D, NFM>(W, P, fld, fcon, m, p, fid, left ? c : j, left ? j : c, left ? nbc : nbj,
                               left ? nbj : nbc, Fs, &G, &GR);
             if (!left) {
 #pragma unroll
@@ -771,10 +793,11 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
         Q[D + 2] = (etr - er) / (p.Z_r * tau);
         Q[D + 3] = (etv - ev) / (p.Z_v * tau) - p.keff * (evR - eR);
         Q[D + 4] = p.keff * (evR - eR);
+        const double iV = 1.0 / V;
         double Rc[NW], rs = 0;
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
-            Rc[i] = -acc[i] / V + Q[i];
+            Rc[i] = Q[i] - acc[i] * iV;
             rs += Rc[i] * Rc[i];
         }
         contrib = V * rs;
@@ -789,10 +812,10 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
                           p.keff * 16 * p.sigma_R * Tv * Tv * Tv * 2.0 / (p.d_v * rho);
         double Dc[NW];
 #pragma unroll
-        for (int i = 0; i < NW; ++i) Dc[i] = 1.0 / dt + gs / V;
+        for (int i = 0; i < NW; ++i) Dc[i] = 1.0 / dt + gs * iV;
         Dc[D + 2] -= jr;
         Dc[D + 3] -= jv;
-        Dc[D + 4] = 1.0 / dt + gsR / V + p.keff;
+        Dc[D + 4] = 1.0 / dt + gsR * iV + p.keff;
         Rc[D + 1] -= Rc[D + 4];
         double d0[NW];
         local_solve<D>(Rc, Dc, rho, Tv, p, d0);
@@ -874,11 +897,11 @@ __global__ __launch_bounds__(kSBlk) void k_msweep(
     }
     if (!cell || s != 0) return;
     const double *Pc = P + c * NP;
-    const double V = m.vol[c];
+    const double ihV = 0.5 / m.vol[c];
     double rhs[NW], Dc[NW], d1[NW];
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-        rhs[i] = R[c * NW + i] - acc[i] / (2 * V);
+        rhs[i] = R[c * NW + i] - acc[i] * ihV;
         Dc[i] = Dg[c * NW + i];
     }
     local_solve<D>(rhs, Dc, Pc[0], Pc[D + 3], p, d1);
@@ -1010,9 +1033,8 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     // face HoTs from the kinetic moments (mu kept in P[0..nc))
     hipLaunchKernelGGL(k_fld_from_mom<D>, gc, blk, 0, st, mom, B.fld, B.P, nc, p);
     hipLaunchKernelGGL((k_cell_grad<D, NFM>), gc, blk, 0, st, B.fld, B.gfld, m);
-    hipLaunchKernelGGL(k_face_hot<D>, gf, blk, 0, st, mom, B.fld, B.gfld, B.P, B.hotf, m, m.f_d, p);
+    hipLaunchKernelGGL(k_face_const<D>, gf, blk, 0, st, mom, B.fld, B.gfld, B.P, B.W0, B.fcon, m, p);
     if (m.nbf > 0) hipLaunchKernelGGL(k_bcorr<D>, gb, blk, 0, st, B.W0, bflux, B.bcorr, m, p);
-    hipLaunchKernelGGL(k_dref<D>, gf, blk, 0, st, B.W0, B.dref, m, p);
     const dim3 gci((nc + kMBlk - 1) / kMBlk), bi(kMBlk);
     const int npart = (int)macro_nparts(nc, NFM);
     const dim3 gsl(npart), bsl(kSBlk);
@@ -1031,10 +1053,10 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
         const int cur = pingpong ? (it & 1) : 0, nxt = cur ^ 1;
         double *W = Wb[cur], *P = Pb[cur], *fld = Fb[cur];
         if (one_round)
-            hipLaunchKernelGGL((k_mres<D, NFM, true>), gsl, bsl, 0, st, W, P, fld, B.hotf, B.dref, B.bcorr, B.Gs, B.R,
+            hipLaunchKernelGGL((k_mres<D, NFM, true>), gsl, bsl, 0, st, W, P, fld, B.fcon, B.bcorr, B.Gs, B.R,
                                B.Dg, B.dU0, B.part, B.flags, m, p, o.cfl_macro);
         else
-            hipLaunchKernelGGL((k_mres<D, NFM, false>), gsl, bsl, 0, st, W, P, fld, B.hotf, B.dref, B.bcorr, B.Gs,
+            hipLaunchKernelGGL((k_mres<D, NFM, false>), gsl, bsl, 0, st, W, P, fld, B.fcon, B.bcorr, B.Gs,
                                B.R, B.Dg, B.dU0, B.part, B.flags, m, p, o.cfl_macro);
         double *din = B.dU0, *dout = B.dU1;
         const int ns = o.n_sweeps;

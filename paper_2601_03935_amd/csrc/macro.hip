@@ -305,6 +305,45 @@ __device__ __forceinline__ void positive_update(double *W, const double *dU, con
     }
 }
 
+// The same update with the trial factors spread over the LS lanes of a cell's group (all of them call it
+// with identical W, dU, Ws): round r tests m = LS r + s on lane s, and the lowest passing m of the first
+// round with a pass is taken, which is the factor the serial halving above accepts.
+template <int D, int LS>
+__device__ __forceinline__ void positive_update_lanes(double *W, const double *dU, const double *Ws, const int s,
+                                                      const int base)
+{
+    constexpr int NW = D + 5;
+    PrimL p0, ps;
+    prim_lite<D>(W, p0);
+    prim_lite<D>(Ws, ps);
+    for (int r = 0; LS * r <= 20; ++r) {
+        const int mm = LS * r + s;
+        const double a = ldexp(1.0, -mm);
+        double Wn[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) Wn[i] = W[i] + a * dU[i];
+        Wn[D + 1] += a * dU[D + 4];
+        bool ok = mm <= 20;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = (i == 0) ? 0 : D + 1 + i;
+            ok = ok && Wn[k] >= 0.5 * W[k] && Wn[k] >= 0.5 * Ws[k] && Wn[k] <= 2 * Ws[k];
+        }
+        if (ok) {
+            PrimL p1;
+            prim_lite<D>(Wn, p1);
+            ok = p1.Tt >= 0.5 * p0.Tt && p1.Tt >= 0.5 * ps.Tt && p1.Tt <= 2 * ps.Tt;
+        }
+        const unsigned grp = (unsigned)((__ballot(ok) >> base) & ((1ull << LS) - 1));
+        if (grp) {
+            const int sw = __builtin_ctz(grp);
+#pragma unroll
+            for (int i = 0; i < NW; ++i) W[i] = __shfl(Wn[i], base + sw, 64);
+            return;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ setup kernels
 template <int D>
 __global__ void k_W_from_mom(const double *__restrict__ mom, double *__restrict__ W, double *__restrict__ W0,
@@ -548,28 +587,33 @@ __device__ __forceinline__ double wave_sum64(double v)
     return __shfl(v, 0, 64);
 }
 
+// Stores of the inner-iteration kernels' outputs bypass the L2: the next kernel, a dependent launch,
+// starts with the L2s of the other XCDs cold for these lines anyway, and lines left dirty would be
+// written back when the kernel ends.
+__device__ __forceinline__ void st_nt(double *p, double v) { __builtin_nontemporal_store(v, p); }
+
 // primitive record and gradient fields of W
 template <int D>
 __device__ __forceinline__ void store_prim(const double *Wc, const Phys &p, double *pc, double *fc)
 {
     Prim q;
     prim_of<D>(Wc, p, q);
-    pc[0] = q.rho;
+    st_nt(pc, q.rho);
 #pragma unroll
-    for (int a = 0; a < D; ++a) pc[1 + a] = q.u[a];
-    pc[D + 1] = q.Tt;
-    pc[D + 2] = q.Tr;
-    pc[D + 3] = q.Tv;
-    pc[D + 4] = q.eR;
-    pc[D + 5] = q.mu;
-    pc[D + 6] = q.cs;
-    pc[D + 7] = 0;
+    for (int a = 0; a < D; ++a) st_nt(pc + 1 + a, q.u[a]);
+    st_nt(pc + D + 1, q.Tt);
+    st_nt(pc + D + 2, q.Tr);
+    st_nt(pc + D + 3, q.Tv);
+    st_nt(pc + D + 4, q.eR);
+    st_nt(pc + D + 5, q.mu);
+    st_nt(pc + D + 6, q.cs);
+    st_nt(pc + D + 7, 0.0);
 #pragma unroll
-    for (int a = 0; a < D; ++a) fc[a] = q.u[a];
-    fc[D] = q.Tt;
-    fc[D + 1] = q.Tr;
-    fc[D + 2] = q.Tv;
-    fc[D + 3] = q.eR;
+    for (int a = 0; a < D; ++a) st_nt(fc + a, q.u[a]);
+    st_nt(fc + D, q.Tt);
+    st_nt(fc + D + 1, q.Tr);
+    st_nt(fc + D + 2, q.Tv);
+    st_nt(fc + D + 3, q.eR);
 }
 
 template <int D>
@@ -753,8 +797,8 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
 #pragma unroll
                 for (int i = 0; i < NW; ++i) Fs[i] = -Fs[i];
             }
-            Gs[(c * NFM + s) * 2] = G;
-            Gs[(c * NFM + s) * 2 + 1] = GR;
+            st_nt(Gs + (c * NFM + s) * 2, G);
+            st_nt(Gs + (c * NFM + s) * 2 + 1, GR);
             gS = G * S;
             gRS = GR * S;
         }
@@ -821,9 +865,9 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
         local_solve<D>(Rc, Dc, rho, Tv, p, d0);
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
-            R[c * NW + i] = Rc[i];
-            Dg[c * NW + i] = Dc[i];
-            dU[c * NW + i] = d0[i];
+            st_nt(R + c * NW + i, Rc[i]);
+            st_nt(Dg + c * NW + i, Dc[i]);
+            st_nt(dU + c * NW + i, d0[i]);
         }
     }
     const double ws = wave_sum64(contrib);
@@ -895,7 +939,9 @@ __global__ __launch_bounds__(kSBlk) void k_msweep(
     if constexpr (FIRST) {
         if (inner_converged(pr, rest, it, tol, scal, flags)) return;
     }
-    if (!cell || s != 0) return;
+    // the last sweep runs the point solve on every lane of the cell (identical results) so that the
+    // safeguard's trial factors can be spread over them; the others on the cell's first lane
+    if (!cell || (!LAST && s != 0)) return;
     const double *Pc = P + c * NP;
     const double ihV = 0.5 / m.vol[c];
     double rhs[NW], Dc[NW], d1[NW];
@@ -907,14 +953,15 @@ __global__ __launch_bounds__(kSBlk) void k_msweep(
     local_solve<D>(rhs, Dc, Pc[0], Pc[D + 3], p, d1);
     if constexpr (!LAST) {
 #pragma unroll
-        for (int i = 0; i < NW; ++i) dUout[c * NW + i] = d1[i];
+        for (int i = 0; i < NW; ++i) st_nt(dUout + c * NW + i, d1[i]);
     } else {
         double Wc[NW];
 #pragma unroll
         for (int i = 0; i < NW; ++i) Wc[i] = W[c * NW + i];
-        positive_update<D>(Wc, d1, W0 + c * NW);
+        positive_update_lanes<D, LS>(Wc, d1, W0 + c * NW, s, base);
+        if (s != 0) return;
 #pragma unroll
-        for (int i = 0; i < NW; ++i) Wn_out[c * NW + i] = Wc[i];
+        for (int i = 0; i < NW; ++i) st_nt(Wn_out + c * NW + i, Wc[i]);
         store_prim<D>(Wc, p, Pn_out + c * NP, fn_out + c * NF);
     }
 }

@@ -433,7 +433,8 @@ __global__ void k_cell_grad(const double *__restrict__ fld, double *__restrict__
 }
 
 // adds the least-squares gradient of cell c (as cell_grad) to g, with the neighbour list of c given
-// (nb[s] < 0: boundary or padded slot)
+// (nb[s] < 0: boundary or padded slot).  Branch-free, so that all loads are in flight together: a slot
+// without a neighbour reads cell c itself, whose difference is exactly zero.
 template <int D, int NFM>
 __device__ __forceinline__ void cell_grad_add(const double *__restrict__ fld, const MeshDev &m, const int64_t c,
                                               const int *nb, double g[][D])
@@ -441,8 +442,7 @@ __device__ __forceinline__ void cell_grad_add(const double *__restrict__ fld, co
     constexpr int NF = D + 4;
 #pragma unroll
     for (int s = 0; s < NFM; ++s) {
-        const int j = nb[s];
-        if (j < 0) continue;
+        const int64_t j = (nb[s] >= 0) ? (int64_t)nb[s] : c;
         const double *gs = m.lsq + (c * NFM + s) * D;
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
@@ -752,26 +752,32 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
     const bool cell = c < m.nc;
     const bool slot = cell && s < NFM;
     // every index this lane needs is read here (one level of dependent loads): the slot, the cell's own
-    // neighbour list and the neighbour's (for the two cell gradients), and the cell's point-solve data
-    const int j = slot ? m.nbr[c * NFM + s] : INT32_MIN;
-    const int sf = slot ? m.sfid[c * NFM + s] : 0;
-    const double Sl = slot ? m.mgeo[(c * NFM + s) * MG + D] : 0.0;
+    // neighbour list and the neighbour's (for the two cell gradients), and the cell's point-solve data.
+    // The loads are unconditional, from a clamped cell and slot (always in bounds), so that they issue
+    // without branches; the values of lanes without a cell or slot are replaced afterwards.
+    const int64_t cc = cell ? c : m.nc - 1;
+    const int ss = (s < NFM) ? s : 0;
+    const int jr = m.nbr[cc * NFM + ss];
+    const int sfr = m.sfid[cc * NFM + ss];
+    const double Slr = m.mgeo[(cc * NFM + ss) * MG + D];
+    const int j = slot ? jr : INT32_MIN;
+    const int sf = slot ? sfr : 0;
+    const double Sl = slot ? Slr : 0.0;
     int nbc[NFM], nbj[NFM];
 #pragma unroll
     for (int q = 0; q < NFM; ++q) {
-        nbc[q] = cell ? m.nbr[c * NFM + q] : INT32_MIN;
-        nbj[q] = slot ? m.nb2[(c * NFM + s) * NFM + q] : INT32_MIN;
+        const int a = m.nbr[cc * NFM + q], b = m.nb2[(cc * NFM + ss) * NFM + q];
+        nbc[q] = cell ? a : INT32_MIN;
+        nbj[q] = slot ? b : INT32_MIN;
     }
     double Wc[NW], Pc[D + 7], V = 1, hc = 1;
     if constexpr (PRE) {
 #pragma unroll
-        for (int i = 0; i < NW; ++i) Wc[i] = cell ? W[c * NW + i] : 1.0;
+        for (int i = 0; i < NW; ++i) Wc[i] = W[cc * NW + i];
 #pragma unroll
-        for (int i = 0; i < D + 7; ++i) Pc[i] = cell ? P[c * NP + i] : 1.0;
-        if (cell) {
-            V = m.vol[c];
-            hc = m.h[c];
-        }
+        for (int i = 0; i < D + 7; ++i) Pc[i] = P[cc * NP + i];
+        V = m.vol[cc];
+        hc = m.h[cc];
     }
     if (done) return;
     double Fs[NW], S = 0, gS = 0, gRS = 0;

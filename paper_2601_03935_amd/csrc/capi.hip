@@ -61,6 +61,8 @@ struct gsis_s {
     std::string err;
     HostMesh hm;
     MeshDev m;
+    std::vector<int> bf_tag;     // boundary-condition tag of each boundary face (host copy)
+    std::vector<BcDev> bf_bc;    // host copy of MeshDev::bf_bc
     bool have_mesh = false, have_vel = false, have_ord = false, have_gas = false, have_flow = false;
     bool have_opts = false, have_state = false;
     int64_t nv = 0, no = 0;
@@ -161,6 +163,7 @@ static void free_mesh(MeshDev &m)
     dfree(m.f_n);
     dfree(m.f_d);
     dfree(m.bcs);
+    dfree(m.bf_bc);
 }
 
 template <typename T>
@@ -322,6 +325,10 @@ static int32_t build_mesh(gsis_t *h)
     }
     for (int64_t b = 0; b < nbf; ++b)
         if (hm.bcs[bf_tag[b]].kind != GSIS_BC_WALL) closed = 0;
+    std::vector<BcDev> bf_bc(nbf);
+    for (int64_t b = 0; b < nbf; ++b) bf_bc[b] = bcs[bf_tag[b]];
+    h->bf_tag = bf_tag;
+    h->bf_bc = bf_bc;
     free_mesh(h->m);
     MeshDev &m = h->m;
     m.D = D;
@@ -348,7 +355,7 @@ static int32_t build_mesh(gsis_t *h)
               upload(m.h, hh) && upload(m.eps2, eps2) && upload(m.nfc, nfc) && upload(m.bf_face, bf_face) &&
               upload(m.bf_cell, bf_cell) && upload(m.bf_tag, bf_tag) && upload(m.bf_n, bf_n) &&
               upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.f_L, fL) && upload(m.f_R, fR) &&
-              upload(m.f_n, f_n) && upload(m.f_d, f_d) && upload(m.bcs, bcs);
+              upload(m.f_n, f_n) && upload(m.f_d, f_d) && upload(m.bcs, bcs) && upload(m.bf_bc, bf_bc);
     if (!ok) return fail(h, GSIS_E_OOM, "device allocation of mesh tables failed");
     return GSIS_OK;
 }
@@ -855,6 +862,11 @@ int32_t gsis_set_boundary(gsis_t *h, int32_t tag, const gsis_bc *bc)
         (void)hipSetDevice(h->device);
         HIPCHECK(h, hipStreamSynchronize(h->stream));
         HIPCHECK(h, hipMemcpy(h->m.bcs + tag, &d, sizeof(BcDev), hipMemcpyHostToDevice));
+        for (size_t b = 0; b < h->bf_tag.size(); ++b)
+            if (h->bf_tag[b] == tag) h->bf_bc[b] = d;
+        if (!h->bf_bc.empty())
+            HIPCHECK(h, hipMemcpy(h->m.bf_bc, h->bf_bc.data(), h->bf_bc.size() * sizeof(BcDev),
+                                  hipMemcpyHostToDevice));
     }
     return GSIS_OK;
 }

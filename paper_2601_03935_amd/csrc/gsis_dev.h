@@ -87,6 +87,7 @@ struct MeshDev {
     double *f_n = nullptr;               // unit normal L -> R, D per face
     double *f_d = nullptr;               // x_R - x_L, D per face (interior faces)
     BcDev *bcs = nullptr;
+    BcDev *bf_bc = nullptr;  // per boundary face: its condition (the tag's entry of bcs, expanded)
     int nbc = 0;
     int closed = 1;
 };

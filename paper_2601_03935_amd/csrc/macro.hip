@@ -113,15 +113,6 @@ __device__ __forceinline__ double rusanov_q(const double *WL, const PrimL &qL, d
 }
 
 template <int D>
-__device__ __forceinline__ double rusanov(const double *WL, const double *WR, const double *n, double *F)
-{
-    PrimL qL, qR;
-    prim_lite<D>(WL, qL);
-    prim_lite<D>(WR, qR);
-    return rusanov_q<D>(WL, qL, sqrt(5.0 / 3.0 * qL.Tt), WR, qR, sqrt(5.0 / 3.0 * qR.Tt), n, F);
-}
-
-template <int D>
 __device__ __forceinline__ void W_of_state(double rho, const double *u, double T, const Phys &p, double *W)
 {
     double ek = 0;
@@ -194,14 +185,13 @@ __device__ __forceinline__ void viscous_flux(const double sig[3][3], const doubl
 
 // model flux of a boundary face for the cell state Wc (wall: impermeable NSF-type wall flux; far field:
 // Rusanov against the prescribed state; both with radiative diffusion towards B_R(T_b)); g1/g2 spectral radii
+// (q: the primitives of Wc, as prim_of gives them)
 template <int D>
-__device__ __forceinline__ void bmodel_flux(const MeshDev &m, int bfi, const double *Wc, const Phys &p, double *F,
-                                            double *g1, double *g2)
+__device__ __forceinline__ void bmodel_flux_q(const MeshDev &m, int bfi, const double *Wc, const Prim &q,
+                                              const Phys &p, double *F, double *g1, double *g2)
 {
     constexpr int NW = D + 5;
-    const BcDev bc = m.bcs[m.bf_tag[bfi]];
-    Prim q;
-    prim_of<D>(Wc, p, q);
+    const BcDev bc = m.bf_bc[bfi];
     double n[D], delta = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -244,10 +234,26 @@ __device__ __forceinline__ void bmodel_flux(const MeshDev &m, int bfi, const dou
     } else {
         double Wb[NW];
         W_of_state<D>(bc.rho, bc.u, Tb, p, Wb);
-        rusanov<D>(Wc, Wb, n, F);
+        PrimL qL, qR;
+        qL.rho = q.rho;
+        qL.u[0] = q.u[0];
+        qL.u[1] = q.u[1];
+        qL.u[2] = q.u[2];
+        qL.Tt = q.Tt;
+        prim_lite<D>(Wb, qR);
+        rusanov_q<D>(Wc, qL, q.cs, Wb, qR, sqrt(5.0 / 3.0 * qR.Tt), n, F);
         F[D + 1] += qRn;
         F[D + 4] = qRn;
     }
+}
+
+template <int D>
+__device__ __forceinline__ void bmodel_flux(const MeshDev &m, int bfi, const double *Wc, const Phys &p, double *F,
+                                            double *g1, double *g2)
+{
+    Prim q;
+    prim_of<D>(Wc, p, q);
+    bmodel_flux_q<D>(m, bfi, Wc, q, p, F, g1, g2);
 }
 
 // point solve of the implicit operator in U = (rho, rho u, e_gas, e_r, e_v, e_R): diagonal except for the
@@ -788,7 +794,22 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
         if (j < 0) {
             const int bfi = -j - 1;
             double g1, g2;
-            bmodel_flux<D>(m, bfi, PRE ? Wc : W + c * NW, p, Fs, &g1, &g2);
+            // the cell's primitives are its record in P (written from W by the same prim_of)
+            double Pb[D + 7];
+#pragma unroll
+            for (int i = 0; i < D + 7; ++i) Pb[i] = PRE ? Pc[i] : P[c * NP + i];
+            Prim q;
+            q.rho = Pb[0];
+            q.u[0] = q.u[1] = q.u[2] = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) q.u[a] = Pb[1 + a];
+            q.Tt = Pb[D + 1];
+            q.Tr = Pb[D + 2];
+            q.Tv = Pb[D + 3];
+            q.eR = Pb[D + 4];
+            q.mu = Pb[D + 5];
+            q.cs = Pb[D + 6];
+            bmodel_flux_q<D>(m, bfi, PRE ? Wc : W + c * NW, q, p, Fs, &g1, &g2);
 #pragma unroll
             for (int i = 0; i < NW; ++i) Fs[i] += bcorr[(int64_t)bfi * NW + i];
             gS = g1 * S;

@@ -102,10 +102,16 @@ struct Prof {
 
 constexpr int kMBlk = 64;   // threads per block of the per-cell macro kernels (one wave)
 constexpr int kSBlk = 256;  // threads per block of the slot-parallel inner-iteration kernels
-// lanes per cell in the slot-parallel kernels (a power of two >= the number of face slots)
-__host__ __device__ constexpr int slot_lanes(int nfm) { return nfm <= 2 ? 2 : (nfm <= 4 ? 4 : 8); }
+// lanes per cell in the slot-parallel kernels (one per face slot) and cells per wave (the last
+// 64 mod NFM lanes of a wave idle: 21 triangles or 10 hexahedra per wave)
+__host__ __device__ constexpr int slot_lanes(int nfm) { return nfm; }
+__host__ __device__ constexpr int cells_per_wave(int nfm) { return kWave / nfm; }
 // blocks of the slot-parallel kernels = number of per-block partial sums of the inner residual norm
-inline int64_t macro_nparts(int64_t nc, int nfm) { return (nc * slot_lanes(nfm) + kSBlk - 1) / kSBlk; }
+inline int64_t macro_nparts(int64_t nc, int nfm)
+{
+    const int64_t waves = (nc + cells_per_wave(nfm) - 1) / cells_per_wave(nfm);
+    return (waves + kSBlk / kWave - 1) / (kSBlk / kWave);
+}
 
 struct MacroOpts {
     double cfl_macro, inner_tol;

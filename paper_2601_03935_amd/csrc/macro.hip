@@ -632,8 +632,10 @@ __global__ void k_mprim(const double *__restrict__ W, double *__restrict__ P, do
     store_prim<D>(W + c * NW, p, P + c * NP, fld + c * NF);
 }
 
-// ---- slot-parallel inner-iteration kernels: kSBlk threads per block, slot_lanes(NFM) consecutive lanes per
-// cell, lane s of a cell's group handling its face slot s (padded slots hold nbr = INT32_MIN).  The per-face
+// ---- slot-parallel inner-iteration kernels: kSBlk threads per block, slot_lanes(NFM) = NFM consecutive lanes
+// per cell, cells_per_wave(NFM) cells per wave, lane s of a cell's group handling its face slot s (padded
+// slots hold nbr = INT32_MIN).  Packing the groups without power-of-two padding keeps the number of waves
+// at or below the SIMD count for the largest 2D grids that fit the GPU at one wave per SIMD.  The per-face
 // work runs on separate lanes; the cell's sums are gathered from its lanes in slot order with shuffles and
 // the per-cell point solve runs on the group's first lane.
 
@@ -751,11 +753,11 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
     constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2, LS = slot_lanes(NFM);
     __shared__ double sh[kSBlk / 64];
     const int done = flags[0];
-    const int t = threadIdx.x, lane = t & 63, base = lane & ~(LS - 1);
-    const int64_t gi = xcd_remap(blockIdx.x, gridDim.x) * kSBlk + t;
-    const int64_t c = gi / LS;
-    const int s = (int)(gi % LS);
-    const bool cell = c < m.nc;
+    constexpr int CPW = cells_per_wave(NFM);
+    const int t = threadIdx.x, lane = t & 63, grp = lane / LS, s = lane - grp * LS, base = grp * LS;
+    const int64_t wv = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * (kSBlk / 64) + (t >> 6);
+    const int64_t c = wv * CPW + grp;
+    const bool cell = grp < CPW && c < m.nc;
     const bool slot = cell && s < NFM;
     // every index this lane needs is read here (one level of dependent loads): the slot, the cell's own
     // neighbour list and the neighbour's (for the two cell gradients), and the cell's point-solve data.
@@ -924,11 +926,11 @@ __global__ __launch_bounds__(kSBlk) void k_msweep(
     const int done = flags[0];
     double pr[kPartRegs], rest = 0;
     if constexpr (FIRST) part_load(part, npart, pr, &rest);
-    const int t = threadIdx.x, lane = t & 63, base = lane & ~(LS - 1);
-    const int64_t gi = xcd_remap(blockIdx.x, gridDim.x) * kSBlk + t;
-    const int64_t c = gi / LS;
-    const int s = (int)(gi % LS);
-    const bool cell = c < m.nc;
+    constexpr int CPW = cells_per_wave(NFM);
+    const int t = threadIdx.x, lane = t & 63, grp = lane / LS, s = lane - grp * LS, base = grp * LS;
+    const int64_t wv = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * (kSBlk / 64) + (t >> 6);
+    const int64_t c = wv * CPW + grp;
+    const bool cell = grp < CPW && c < m.nc;
     const bool slot = cell && s < NFM;
     const int j = slot ? m.nbr[c * NFM + s] : INT32_MIN;
     if (done) return;

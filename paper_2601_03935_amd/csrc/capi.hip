@@ -160,8 +160,7 @@ static void free_mesh(MeshDev &m)
     dfree(m.bcells);
     dfree(m.f_L);
     dfree(m.f_R);
-    dfree(m.f_n);
-    dfree(m.f_d);
+    dfree(m.fgeo);
     dfree(m.bcs);
     dfree(m.bf_bc);
 }
@@ -306,13 +305,24 @@ static int32_t build_mesh(gsis_t *h)
         }
     }
     std::vector<int> fL(nf), fR(nf);
-    std::vector<double> f_n(nf * D), f_d(nf * D, 0.0);
+    const int FG = 2 * D + 2;
+    std::vector<double> fgeo(nf * FG, 0.0);
     for (int64_t f = 0; f < nf; ++f) {
         fL[f] = (int)hm.fc[2 * f];
         fR[f] = (int)hm.fc[2 * f + 1];
-        for (int a = 0; a < D; ++a) {
-            f_n[f * D + a] = hm.fn[f * D + a];
-            if (fR[f] >= 0) f_d[f * D + a] = hm.ctr[(int64_t)fR[f] * D + a] - hm.ctr[(int64_t)fL[f] * D + a];
+        double *g = &fgeo[f * FG];
+        for (int a = 0; a < D; ++a) g[a] = hm.fn[f * D + a];
+        if (fR[f] >= 0) {
+            double d[3] = {0, 0, 0}, dl = 0, nd = 0;
+            for (int a = 0; a < D; ++a) {
+                d[a] = hm.ctr[(int64_t)fR[f] * D + a] - hm.ctr[(int64_t)fL[f] * D + a];
+                dl += d[a] * d[a];
+                nd += g[a] * d[a];
+            }
+            dl = std::sqrt(dl);
+            for (int a = 0; a < D; ++a) g[D + a] = d[a] / dl;
+            g[2 * D] = 1.0 / dl;
+            g[2 * D + 1] = 1.0 / std::fabs(nd);
         }
     }
     std::vector<BcDev> bcs(hm.bcs.size());
@@ -355,7 +365,7 @@ static int32_t build_mesh(gsis_t *h)
               upload(m.h, hh) && upload(m.eps2, eps2) && upload(m.nfc, nfc) && upload(m.bf_face, bf_face) &&
               upload(m.bf_cell, bf_cell) && upload(m.bf_tag, bf_tag) && upload(m.bf_n, bf_n) &&
               upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.f_L, fL) && upload(m.f_R, fR) &&
-              upload(m.f_n, f_n) && upload(m.f_d, f_d) && upload(m.bcs, bcs) && upload(m.bf_bc, bf_bc);
+              upload(m.fgeo, fgeo) && upload(m.bcs, bcs) && upload(m.bf_bc, bf_bc);
     if (!ok) return fail(h, GSIS_E_OOM, "device allocation of mesh tables failed");
     return GSIS_OK;
 }
@@ -401,6 +411,7 @@ static void free_macro(MacroBufs &B)
     dfree(B.Gs);
     dfree(B.part);
     dfree(B.bpart);
+    dfree(B.Ts);
     dfree(B.gfld);
     dfree(B.R);
     dfree(B.Dg);
@@ -488,6 +499,7 @@ static bool alloc_macro(gsis_t *h)
     B.resc = dalloc<double>(nc * 7, ok);
     B.scal = dalloc<double>(16, ok);
     B.bpart = dalloc<double>(8 * kSumBlocks, ok);
+    B.Ts = dalloc<double>(nc, ok);
     B.flags = dalloc<int>(4, ok);
     const MomLayout L{D};
     h->mom0 = dalloc<double>(nc * L.size(), ok);

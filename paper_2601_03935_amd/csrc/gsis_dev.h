@@ -84,8 +84,9 @@ struct MeshDev {
     int64_t nbcells = 0;
     // interior faces (for face HoTs / reference dissipation)
     int *f_L = nullptr, *f_R = nullptr;  // R < 0 on boundary faces
-    double *f_n = nullptr;               // unit normal L -> R, D per face
-    double *f_d = nullptr;               // x_R - x_L, D per face (interior faces)
+    // per face, 2D + 2 values: the unit normal n (L -> R), and on interior faces with d = x_R - x_L the unit
+    // vector d / |d|, 1 / |d| and 1 / |n . d| (zeros on boundary faces)
+    double *fgeo = nullptr;
     BcDev *bcs = nullptr;
     BcDev *bf_bc = nullptr;  // per boundary face: its condition (the tag's entry of bcs, expanded)
     int nbc = 0;

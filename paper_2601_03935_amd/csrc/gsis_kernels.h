@@ -29,6 +29,7 @@ struct MacroBufs {
     double *part = nullptr;                   // per-block partial sums of the residual norm
     double *resc = nullptr, *scal = nullptr;  // per-cell scratch, device scalars (res0, mass, ...)
     double *bpart = nullptr;                  // partial sums of launch_block_sum (8 * kSumBlocks)
+    double *Ts = nullptr;                     // per cell: translational temperature of W0
     int *flags = nullptr;                     // [0] done, [1] inner count, [2] block arrival counter
 };
 

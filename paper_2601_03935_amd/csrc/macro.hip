@@ -313,15 +313,16 @@ __device__ __forceinline__ void positive_update(double *W, const double *dU, con
 
 // The same update with the trial factors spread over the LS lanes of a cell's group (all of them call it
 // with identical W, dU, Ws): round r tests m = LS r + s on lane s, and the lowest passing m of the first
-// round with a pass is taken, which is the factor the serial halving above accepts.
+// round with a pass is taken, which is the factor the serial halving above accepts.  T0 and Ts are the
+// translational temperatures of W and Ws as prim_lite gives them (taken from the primitive records).
 template <int D, int LS>
-__device__ __forceinline__ void positive_update_lanes(double *W, const double *dU, const double *Ws, const int s,
-                                                      const int base)
+__device__ __forceinline__ void positive_update_lanes(double *W, const double *dU, const double *Ws, const double T0,
+                                                      const double Ts, const int s, const int base)
 {
     constexpr int NW = D + 5;
     PrimL p0, ps;
-    prim_lite<D>(W, p0);
-    prim_lite<D>(Ws, ps);
+    p0.Tt = T0;
+    ps.Tt = Ts;
     for (int r = 0; LS * r <= 20; ++r) {
         const int mm = LS * r + s;
         const double a = ldexp(1.0, -mm);
@@ -460,18 +461,17 @@ __device__ __forceinline__ void cell_grad_add(const double *__restrict__ fld, co
 }
 
 // face gradient from the sum gs of the two cell gradients: their mean with the component along the
-// centroid line replaced by the centroid difference quotient (dvec = x_j - x_c)
+// centroid line replaced by the centroid difference quotient (fg: the face's geometry record, with the
+// unit vector dh along d = x_j - x_c and 1 / |d|)
 template <int D>
 __device__ __forceinline__ void face_grad_sum(const double *fld, const double gs[][D], int64_t c, int64_t j,
-                                              const double *dvec, double g[][3])
+                                              const double *fg, double g[][3])
 {
     constexpr int NF = D + 4;
-    double dl = 0, dh[D];
+    double dh[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) dl += dvec[a] * dvec[a];
-    const double idl = 1.0 / sqrt(dl);
-#pragma unroll
-    for (int a = 0; a < D; ++a) dh[a] = dvec[a] * idl;
+    for (int a = 0; a < D; ++a) dh[a] = fg[D + a];
+    const double idl = fg[2 * D];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
         double avg[D], corr = 0;
@@ -488,7 +488,7 @@ __device__ __forceinline__ void face_grad_sum(const double *fld, const double gs
 
 template <int D>
 __device__ __forceinline__ void face_grad(const double *fld, const double *gfld, int64_t c, int64_t j,
-                                          const double *dvec, double g[][3])
+                                          const double *fg, double g[][3])
 {
     constexpr int NF = D + 4;
     double gs[NF][D];
@@ -496,7 +496,7 @@ __device__ __forceinline__ void face_grad(const double *fld, const double *gfld,
     for (int i = 0; i < NF; ++i)
 #pragma unroll
         for (int a = 0; a < D; ++a) gs[i][a] = gfld[(c * NF + i) * D + a] + gfld[(j * NF + i) * D + a];
-    face_grad_sum<D>(fld, gs, c, j, dvec, g);
+    face_grad_sum<D>(fld, gs, c, j, fg, g);
 }
 
 // Per-face constants of the synthetic flux, frozen for the whole solve (interior faces; zero rows on
@@ -522,9 +522,9 @@ __global__ __launch_bounds__(256) void k_face_const(const double *__restrict__ m
     }
     double n[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) n[a] = m.f_n[f * D + a];
+    for (int a = 0; a < D; ++a) n[a] = m.fgeo[f * (2 * D + 2) + a];
     double g[D + 4][3], sig[3][3], q[4][3];
-    face_grad<D>(fld, gfld, c, j, m.f_d + f * D, g);
+    face_grad<D>(fld, gfld, c, j, m.fgeo + f * (2 * D + 2), g);
     constitutive<D>(0.5 * (mu[c] + mu[j]), g, nullptr, p, sig, q);
     const double *Mc = mom + c * L.size(), *Mj = mom + j * L.size();
     double hs[D], hq[4] = {0, 0, 0, 0};
@@ -624,12 +624,16 @@ __device__ __forceinline__ void store_prim(const double *Wc, const Phys &p, doub
 
 template <int D>
 __global__ void k_mprim(const double *__restrict__ W, double *__restrict__ P, double *__restrict__ fld,
+                        double *__restrict__ Ts,
                         const int64_t nc, const Phys p)
 {
     constexpr int NW = D + 5, NF = D + 4, NP = D + 8;
     const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     store_prim<D>(W + c * NW, p, P + c * NP, fld + c * NF);
+    PrimL l;
+    prim_lite<D>(W + c * NW, l);
+    Ts[c] = l.Tt;
 }
 
 // ---- slot-parallel inner-iteration kernels: kSBlk threads per block, slot_lanes(NFM) = NFM consecutive lanes
@@ -652,12 +656,11 @@ __device__ __forceinline__ void face_flux(const double *__restrict__ W, const do
 {
     constexpr int NW = D + 5, NP = D + 8, NF = D + 4;
     const double kR = (p.keff > 0) ? 1.0 / (3 * p.keff) : 0.0;
-    double n[D], dvec[D];
+    const double *fg = m.fgeo + fid * (2 * D + 2);
+    double n[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-        n[a] = m.f_n[fid * D + a];
-        dvec[a] = m.f_d[fid * D + a];
-    }
+    for (int a = 0; a < D; ++a) n[a] = fg[a];
+    const double ind = fg[2 * D + 1];
     const double *Pc = P + cL * NP, *Pj = P + cR * NP;
     PrimL qc, qj;
     prim_load<D>(Pc, qc);
@@ -674,7 +677,7 @@ __device__ __forceinline__ void face_flux(const double *__restrict__ W, const do
         for (int a = 0; a < D; ++a) gsum[i][a] = 0;
     cell_grad_add<D, NFM>(fld, m, cL, nbL, gsum);
     cell_grad_add<D, NFM>(fld, m, cR, nbR, gsum);
-    face_grad_sum<D>(fld, gsum, cL, cR, dvec, g);
+    face_grad_sum<D>(fld, gsum, cL, cR, fg, g);
 #pragma unroll
     for (int a = 0; a < D; ++a) uf[a] = 0.5 * (Pc[1 + a] + Pj[1 + a]);
     constitutive<D>(0.5 * (Pc[D + 5] + Pj[D + 5]), g, nullptr, p, sig, q);
@@ -685,15 +688,12 @@ __device__ __forceinline__ void face_flux(const double *__restrict__ W, const do
 #pragma unroll
     for (int i = 0; i < NW; ++i) F[i] = Fc[i] + Fv[i];
     F[D + 1] += wh;
-    double ufn = 0, nd = 0;
+    double ufn = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-        ufn += uf[a] * n[a];
-        nd += n[a] * dvec[a];
-    }
-    nd = fabs(nd);
-    *G = fabs(ufn) + 0.5 * (Pc[D + 6] + Pj[D + 6]) + 2 * 0.5 * (Pc[D + 5] + Pj[D + 5]) / (0.5 * (Pc[0] + Pj[0]) * nd);
-    *GR = 2 * kR / nd;
+    for (int a = 0; a < D; ++a) ufn += uf[a] * n[a];
+    // 2 mu_f / (rho_f |n . d|) with face means of mu and rho
+    *G = fabs(ufn) + 0.5 * (Pc[D + 6] + Pj[D + 6]) + 2 * (Pc[D + 5] + Pj[D + 5]) * ind / (Pc[0] + Pj[0]);
+    *GR = 2 * kR * ind;
 }
 
 // Sum over the 64 partial sums per lane stride of the per-block residual sums, in a fixed order (every
@@ -919,8 +919,9 @@ __global__ __launch_bounds__(kSBlk) void k_msweep(
     const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ R,
     const double *__restrict__ Dg, const double *__restrict__ Gs, const double *__restrict__ dUin,
     double *__restrict__ dUout, double *__restrict__ Wn_out, double *__restrict__ Pn_out, double *__restrict__ fn_out,
-    const double *__restrict__ W0, const MeshDev m, const Phys p, const double *__restrict__ part, const int npart,
-    const int it, const double tol, double *__restrict__ scal, int *__restrict__ flags)
+    const double *__restrict__ W0, const double *__restrict__ Ts, const MeshDev m, const Phys p,
+    const double *__restrict__ part, const int npart, const int it, const double tol, double *__restrict__ scal,
+    int *__restrict__ flags)
 {
     constexpr int NW = D + 5, NP = D + 8, NF = D + 4, MG = 2 * D + 2, LS = slot_lanes(NFM);
     const int done = flags[0];
@@ -933,6 +934,29 @@ __global__ __launch_bounds__(kSBlk) void k_msweep(
     const bool cell = grp < CPW && c < m.nc;
     const bool slot = cell && s < NFM;
     const int j = slot ? m.nbr[c * NFM + s] : INT32_MIN;
+    // the point-solve data of the cell is requested now, with the neighbour index, on the lanes that
+    // solve (the last sweep solves on every lane of the cell, the others on its first lane)
+    const bool solver = LAST ? cell : (cell && s == 0);
+    double Rc[NW], Dc[NW], Wc[NW], Ws[NW], rho = 1, Tv = 1, vol = 1, T0 = 1, T0s = 1;
+    if (solver) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            Rc[i] = R[c * NW + i];
+            Dc[i] = Dg[c * NW + i];
+        }
+        rho = P[c * NP];
+        Tv = P[c * NP + D + 3];
+        vol = m.vol[c];
+        if constexpr (LAST) {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                Wc[i] = W[c * NW + i];
+                Ws[i] = W0[c * NW + i];
+            }
+            T0 = P[c * NP + D + 1];
+            T0s = Ts[c];
+        }
+    }
     if (done) return;
     double x[NW], S = 0;
 #pragma unroll
@@ -970,24 +994,17 @@ __global__ __launch_bounds__(kSBlk) void k_msweep(
     }
     // the last sweep runs the point solve on every lane of the cell (identical results) so that the
     // safeguard's trial factors can be spread over them; the others on the cell's first lane
-    if (!cell || (!LAST && s != 0)) return;
-    const double *Pc = P + c * NP;
-    const double ihV = 0.5 / m.vol[c];
-    double rhs[NW], Dc[NW], d1[NW];
+    if (!solver) return;
+    const double ihV = 0.5 / vol;
+    double rhs[NW], d1[NW];
 #pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        rhs[i] = R[c * NW + i] - acc[i] * ihV;
-        Dc[i] = Dg[c * NW + i];
-    }
-    local_solve<D>(rhs, Dc, Pc[0], Pc[D + 3], p, d1);
+    for (int i = 0; i < NW; ++i) rhs[i] = Rc[i] - acc[i] * ihV;
+    local_solve<D>(rhs, Dc, rho, Tv, p, d1);
     if constexpr (!LAST) {
 #pragma unroll
         for (int i = 0; i < NW; ++i) st_nt(dUout + c * NW + i, d1[i]);
     } else {
-        double Wc[NW];
-#pragma unroll
-        for (int i = 0; i < NW; ++i) Wc[i] = W[c * NW + i];
-        positive_update_lanes<D, LS>(Wc, d1, W0 + c * NW, s, base);
+        positive_update_lanes<D, LS>(Wc, d1, Ws, T0, T0s, s, base);
         if (s != 0) return;
 #pragma unroll
         for (int i = 0; i < NW; ++i) st_nt(Wn_out + c * NW + i, Wc[i]);
@@ -1119,7 +1136,7 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const bool one_round = (int64_t)npart * (kSBlk / kWave) <= (int64_t)ncu * 4 * 2;
-    hipLaunchKernelGGL(k_mprim<D>, gci, bi, 0, st, B.W, B.P, B.fld, nc, p);
+    hipLaunchKernelGGL(k_mprim<D>, gci, bi, 0, st, B.W, B.P, B.fld, B.Ts, nc, p);
     // inner iteration `it` starts from the state in buffer `it % 2` when the sweeps ping-pong
     double *Wb[2] = {B.W, B.W2}, *Pb[2] = {B.P, B.P2}, *Fb[2] = {B.fld, B.fld2};
     const bool pingpong = o.n_sweeps > 0;
@@ -1141,8 +1158,8 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
             auto kern = first ? (last ? k_msweep<D, NFM, true, true> : k_msweep<D, NFM, true, false>)
                               : (last ? k_msweep<D, NFM, false, true> : k_msweep<D, NFM, false, false>);
             hipLaunchKernelGGL(kern, gsl, bsl, 0, st, W, P, B.R, B.Dg, B.Gs, din, last ? nullptr : dout,
-                               last ? Wb[nxt] : nullptr, last ? Pb[nxt] : nullptr, last ? Fb[nxt] : nullptr, B.W0, m,
-                               p, B.part, npart, it, o.inner_tol, B.scal, B.flags);
+                               last ? Wb[nxt] : nullptr, last ? Pb[nxt] : nullptr, last ? Fb[nxt] : nullptr, B.W0,
+                               B.Ts, m, p, B.part, npart, it, o.inner_tol, B.scal, B.flags);
             std::swap(din, dout);
         }
         if (!pingpong)

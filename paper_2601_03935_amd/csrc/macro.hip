@@ -1061,37 +1061,51 @@ __global__ void k_mass_scale(double *__restrict__ W, const double *__restrict__ 
     W[c * NW + D + 1] -= (sc - 1.0) * W[c * NW + D + 4];
 }
 
-// Deterministic sums of k interleaved components over n rows (in[i * k + comp]): kSumBlocks blocks each
-// reduce a contiguous row range in a fixed tree order into part[comp * kSumBlocks + block]; a single
-// wave then adds the partials of each component in block order.
+// Deterministic sums of k <= 8 interleaved components over n rows (in[i * k + comp]): kSumBlocks blocks
+// each reduce a contiguous row range (per thread in row order, then a fixed butterfly in each wave and
+// the block's waves in order) into part[comp * kSumBlocks + block]; a single wave then adds the
+// partials of each component with a fixed butterfly.  Same order every run, no atomics.
 __global__ __launch_bounds__(256) void k_block_sum1(const double *__restrict__ in, const int64_t n, const int k,
                                                     double *__restrict__ part)
 {
-    __shared__ double sh[256];
+    __shared__ double sh[8][4];
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t lo = blockIdx.x * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
-    for (int comp = 0; comp < k; ++comp) {
-        double v = 0;
-        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) v += in[i * k + comp];
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[comp * gridDim.x + blockIdx.x] = sh[0];
-        __syncthreads();
+    const int t = threadIdx.x, w = t >> 6;
+    double v[8];
+#pragma unroll
+    for (int comp = 0; comp < 8; ++comp) v[comp] = 0;
+    for (int64_t i = lo + t; i < hi; i += 256)
+#pragma unroll
+        for (int comp = 0; comp < 8; ++comp)
+            if (comp < k) v[comp] += in[i * k + comp];
+#pragma unroll
+    for (int comp = 0; comp < 8; ++comp) {
+        if (comp >= k) break;
+        const double ws = wave_sum64(v[comp]);
+        if ((t & 63) == 0) sh[comp][w] = ws;
     }
+    __syncthreads();
+    if (t < k) part[t * gridDim.x + blockIdx.x] = ((sh[t][0] + sh[t][1]) + sh[t][2]) + sh[t][3];
 }
 
 __global__ __launch_bounds__(64) void k_block_sum2(const double *__restrict__ part, const int nb, const int k,
                                                    double *__restrict__ out)
 {
-    const int comp = threadIdx.x;
-    if (comp >= k) return;
-    double v = 0;
-    for (int b = 0; b < nb; ++b) v += part[comp * nb + b];
-    out[comp] = v;
+    const int lane = threadIdx.x;
+    double v[8];
+#pragma unroll
+    for (int comp = 0; comp < 8; ++comp) {
+        v[comp] = 0;
+        if (comp < k)
+            for (int b = lane; b < nb; b += 64) v[comp] += part[comp * nb + b];
+    }
+#pragma unroll
+    for (int comp = 0; comp < 8; ++comp) {
+        if (comp >= k) break;
+        const double s = wave_sum64(v[comp]);
+        if (lane == 0) out[comp] = s;
+    }
 }
 
 void launch_block_sum(const double *in, int64_t n, int k, double *out, double *part, hipStream_t st)

@@ -80,6 +80,7 @@ struct gsis_s {
     std::vector<double> hist;
     double cnt_updates = 0, cnt_bytes = 0, cnt_seconds = 0;
     int last_inner = 0;
+    hipEvent_t tev[3] = {nullptr, nullptr, nullptr};  // outer-iteration timing: start, kinetic done, GSIS done
     Prof prof;
 };
 
@@ -422,6 +423,13 @@ static void free_macro(MacroBufs &B)
     dfree(B.resc);
     dfree(B.scal);
     dfree(B.flags);
+    if (B.hflags) (void)hipHostFree(B.hflags);
+    B.hflags = nullptr;
+    for (auto &e : B.pev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
 }
 
 static int ndist(int D) { return D == 3 ? 3 : 4; }
@@ -501,6 +509,9 @@ static bool alloc_macro(gsis_t *h)
     B.bpart = dalloc<double>(8 * kSumBlocks, ok);
     B.Ts = dalloc<double>(nc, ok);
     B.flags = dalloc<int>(4, ok);
+    if (hipHostMalloc((void **)&B.hflags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) ok = false;
+    for (auto &e : B.pev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) ok = false;
     const MomLayout L{D};
     h->mom0 = dalloc<double>(nc * L.size(), ok);
     h->mom1 = dalloc<double>(nc * L.size(), ok);
@@ -642,9 +653,8 @@ static void sync_params(gsis_t *h, const double *mom, const double *W, int from_
     else launch_sync_params<3>(mom, W, h->sp, h->hm.nc, h->phys, from_W, h->stream);
 }
 
-static int macro_T(gsis_t *h, const double *mom, const double *bflux, const double *mom_mass)
+static void macro_T(gsis_t *h, const double *mom, const double *bflux, const double *mom_mass)
 {
-    int it = 0;
     h->prof.st = h->stream;
     const int ev = h->prof.begin(7, 0.0);
     struct End {
@@ -654,10 +664,9 @@ static int macro_T(gsis_t *h, const double *mom, const double *bflux, const doub
     } end_{h->prof, ev};
     const MacroOpts o = mopts(h);
     dispatch_dn(h->hm.D, h->m.NFM, [&](auto Dc, auto Nc) {
-        it = macro_solve<decltype(Dc)::value, decltype(Nc)::value>(h->Mb, h->m, h->phys, o, mom, bflux, mom_mass,
-                                                                   h->stream);
+        macro_solve<decltype(Dc)::value, decltype(Nc)::value>(h->Mb, h->m, h->phys, o, mom, bflux, mom_mass,
+                                                              h->stream);
     });
-    return it;
 }
 
 static double epsilon_of(gsis_t *h, const double *m1, const double *m0)
@@ -699,14 +708,13 @@ static double iterate_T(gsis_t *h, KinBufs<T> &B, bool gsis, int *inner, double 
         h->mom0_valid = true;
     }
     (void)uref;
-    auto t0 = std::chrono::steady_clock::now();
+    // timed with events on the stream: the host waits once per outer iteration (for epsilon)
+    if (!h->tev[0])
+        for (auto &ev : h->tev) (void)hipEventCreate(&ev);
+    (void)hipEventRecord(h->tev[0], h->stream);
     prologue_T(h, B, h->mom0);
     kinetic_T(h, B);
-    (void)hipStreamSynchronize(h->stream);
-    auto t1 = std::chrono::steady_clock::now();
-    const double dk = std::chrono::duration<double>(t1 - t0).count();
-    if (tk) *tk += dk;
-    h->cnt_seconds += dk;
+    (void)hipEventRecord(h->tev[1], h->stream);
     h->cnt_updates += (double)h->hm.nc * h->nv;
     h->cnt_bytes += kinetic_alg_bytes(h);
     if (inner) *inner = 0;
@@ -720,18 +728,24 @@ static double iterate_T(gsis_t *h, KinBufs<T> &B, bool gsis, int *inner, double 
         launch_scale<T>(B.f, (int64_t)h->hm.nc * ndist(h->hm.D) * h->nv, h->Mb.scal + 3, h->Mb.scal + 2, h->stream);
     }
     if (gsis) {
-        auto t2 = std::chrono::steady_clock::now();
         moments_T(h, B, h->mom0, h->momh);
         boundary_T(h, B);
-        const int it = macro_T(h, h->momh, B.bflux, h->mom0);
-        if (inner) *inner = it;
+        macro_T(h, h->momh, B.bflux, h->mom0);
         sync_params(h, h->momh, h->Mb.W, 1);
         sync_T(h, B, h->sp, 0);
-        (void)hipStreamSynchronize(h->stream);
-        if (tm) *tm += std::chrono::duration<double>(std::chrono::steady_clock::now() - t2).count();
+        (void)hipEventRecord(h->tev[2], h->stream);
     }
     moments_T(h, B, h->mom0, h->mom1);
-    const double e = epsilon_of(h, h->mom1, h->mom0);
+    const double e = epsilon_of(h, h->mom1, h->mom0);  // synchronises the stream
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, h->tev[0], h->tev[1]) == hipSuccess) {
+        if (tk) *tk += 1e-3 * ms;
+        h->cnt_seconds += 1e-3 * ms;
+    }
+    if (gsis) {
+        if (tm && hipEventElapsedTime(&ms, h->tev[1], h->tev[2]) == hipSuccess) *tm += 1e-3 * ms;
+        if (inner) *inner = macro_count(h->Mb, mopts(h).max_inner, h->stream);
+    }
     std::swap(h->mom0, h->mom1);
     h->prof.collect();
     return e;
@@ -805,6 +819,8 @@ void gsis_destroy(gsis_t *h)
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     h->prof.destroy();
+    for (auto &ev : h->tev)
+        if (ev) (void)hipEventDestroy(ev);
     free_state(h);
     free_mesh(h->m);
     delete h;
@@ -1120,10 +1136,11 @@ int32_t gsis_macro_solve(gsis_t *h, double *W, int32_t *inner)
     auto run = [&](auto &B) {
         moments_T(h, B, nullptr, h->momh);
         boundary_T(h, B);
-        it = macro_T(h, h->momh, B.bflux, h->momh);
+        macro_T(h, h->momh, B.bflux, h->momh);
     };
     if (h->prec == GSIS_FP32) run(h->Bf);
     else run(h->Bd);
+    it = macro_count(h->Mb, mopts(h).max_inner, h->stream);
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     HIPCHECK(h, hipGetLastError());
     if (W) HIPCHECK(h, hipMemcpy(W, h->Mb.W, (size_t)h->hm.nc * (h->hm.D + 5) * sizeof(double), hipMemcpyDeviceToHost));

@@ -30,6 +30,8 @@ struct MacroBufs {
     double *resc = nullptr, *scal = nullptr;  // per-cell scratch, device scalars (res0, mass, ...)
     double *bpart = nullptr;                  // partial sums of launch_block_sum (8 * kSumBlocks)
     double *Ts = nullptr;                     // per cell: translational temperature of W0
+    int *hflags = nullptr;                    // pinned host memory: two copies of flags[0..1] (progress polls)
+    hipEvent_t pev[2] = {nullptr, nullptr};   // completion of those copies
     int *flags = nullptr;                     // [0] done, [1] inner count, [2] block arrival counter
 };
 
@@ -136,11 +138,14 @@ void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_
                  hipStream_t st);
 
 // synthetic-equation solve from the moments mom (M^{k+1/2}); bflux: boundary flux moments of the same state;
-// mom_mass: moments whose total mass a closed domain keeps.  Returns the inner iteration count
-// (host-synchronising at the end).
+// mom_mass: moments whose total mass a closed domain keeps.  Launches only: the solution ends in Mb.W (P,
+// fld) whatever the inner count, and the host waits on the stream only to throttle itself (never with an
+// empty queue); macro_count gives the inner iteration count afterwards.
 template <int D, int NFM>
-int macro_solve(MacroBufs &Mb, const MeshDev &m, const Phys &p, const MacroOpts &o, const double *mom,
-                const double *bflux, const double *mom_mass, hipStream_t st);
+void macro_solve(MacroBufs &Mb, const MeshDev &m, const Phys &p, const MacroOpts &o, const double *mom,
+                 const double *bflux, const double *mom_mass, hipStream_t st);
+// inner iteration count of the last solve on the stream (synchronises the stream)
+int macro_count(const MacroBufs &Mb, int max_inner, hipStream_t st);
 // total masses of two moment arrays: B.scal[3] = sum V rho(mom_num), B.scal[2] = sum V rho(mom_den)
 template <int D>
 void launch_mass_ratio(MacroBufs &B, const MeshDev &m, const double *mom_num, const double *mom_den, hipStream_t st);

@@ -1129,9 +1129,35 @@ void rescale_mass(MacroBufs &B, const MeshDev &m, const double *mom_mass, hipStr
 }
 
 // ------------------------------------------------------------------ driver of one macro solve
+// After the inner loop: the solution of an odd inner count sits in the second buffer of the ping-pong;
+// it is copied into the first, so that the host needs no count (and no wait) to find it.
+template <int D>
+__global__ void k_mfinal(double *__restrict__ W, double *__restrict__ P, double *__restrict__ fld,
+                         const double *__restrict__ W2, const double *__restrict__ P2,
+                         const double *__restrict__ fld2, const int *__restrict__ flags, const int max_inner,
+                         const int64_t nc)
+{
+    constexpr int NW = D + 5, NP = D + 8, NF = D + 4;
+    const int count = flags[0] ? flags[1] : max_inner;
+    if (!(count & 1)) return;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    for (int i = 0; i < NW; ++i) W[c * NW + i] = W2[c * NW + i];
+    for (int i = 0; i < NP; ++i) P[c * NP + i] = P2[c * NP + i];
+    for (int i = 0; i < NF; ++i) fld[c * NF + i] = fld2[c * NF + i];
+}
+
+int macro_count(const MacroBufs &B, int max_inner, hipStream_t st)
+{
+    int hf[2] = {0, 0};
+    (void)hipMemcpyAsync(hf, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    return hf[0] ? hf[1] : max_inner;
+}
+
 template <int D, int NFM>
-int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &o, const double *mom,
-                const double *bflux, const double *mom_mass, hipStream_t st)
+void macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &o, const double *mom,
+                 const double *bflux, const double *mom_mass, hipStream_t st)
 {
     const int64_t nc = m.nc;
     const dim3 gc((nc + 255) / 256), gf((m.nf + 255) / 256), gb((m.nbf + 255) / 256), blk(256);
@@ -1154,8 +1180,11 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
     // inner iteration `it` starts from the state in buffer `it % 2` when the sweeps ping-pong
     double *Wb[2] = {B.W, B.W2}, *Pb[2] = {B.P, B.P2}, *Fb[2] = {B.fld, B.fld2};
     const bool pingpong = o.n_sweeps > 0;
-    const int poll = 32;
-    int host_flags[2] = {0, 0};
+    // progress polls: every `poll` iterations the flags are copied to pinned host memory behind the
+    // launches; the host then waits for the previous poll's copy, which keeps at least `poll` iterations
+    // queued ahead of the GPU while bounding how far the host runs ahead of a converged solve
+    const int poll = 16;
+    int npoll = 0;
     for (int it = 0; it < o.max_inner; ++it) {
         const int cur = pingpong ? (it & 1) : 0, nxt = cur ^ 1;
         double *W = Wb[cur], *P = Pb[cur], *fld = Fb[cur];
@@ -1179,23 +1208,22 @@ int macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts &
         if (!pingpong)
             hipLaunchKernelGGL(k_mupdate<D>, gci, bi, 0, st, W, B.dU0, P, fld, B.W0, nc, p, B.part, npart, it,
                                o.inner_tol, B.scal, B.flags);
-        if ((it + 1) % poll == 0) {
-            (void)hipMemcpyAsync(host_flags, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
-            (void)hipStreamSynchronize(st);
-            if (host_flags[0]) break;
+        if ((it + 1) % poll == 0 && it + 1 < o.max_inner) {
+            const int k = npoll & 1;
+            (void)hipMemcpyAsync(B.hflags + 2 * k, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+            (void)hipEventRecord(B.pev[k], st);
+            ++npoll;
+            if (npoll >= 2) {
+                (void)hipEventSynchronize(B.pev[k ^ 1]);
+                if (B.hflags[2 * (k ^ 1)]) break;
+            }
         }
     }
-    (void)hipMemcpyAsync(host_flags, B.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
-    (void)hipStreamSynchronize(st);
-    const int count = host_flags[0] ? host_flags[1] : o.max_inner;
-    if (pingpong && (count & 1)) {
-        std::swap(B.W, B.W2);
-        std::swap(B.P, B.P2);
-        std::swap(B.fld, B.fld2);
-    }
+    if (pingpong)
+        hipLaunchKernelGGL(k_mfinal<D>, gc, blk, 0, st, B.W, B.P, B.fld, B.W2, B.P2, B.fld2, B.flags, o.max_inner,
+                           nc);
     // reading: closed domains keep the mass of mom_mass (the state the outer iteration started from)
     if (m.closed) rescale_mass<D>(B, m, mom_mass, st);
-    return count;
 }
 
 template <int D>
@@ -1282,8 +1310,8 @@ void launch_residual(const double *mom1, const double *mom0, const double *vol, 
 }
 
 #define GSIS_INST_M(D, NFM)                                                                                      \
-    template int macro_solve<D, NFM>(MacroBufs &, const MeshDev &, const Phys &, const MacroOpts &, const double *, \
-                                     const double *, const double *, hipStream_t);
+    template void macro_solve<D, NFM>(MacroBufs &, const MeshDev &, const Phys &, const MacroOpts &,               \
+                                      const double *, const double *, const double *, hipStream_t);
 GSIS_INST_M(1, 2)
 GSIS_INST_M(2, 3)
 GSIS_INST_M(2, 4)

@@ -1171,11 +1171,15 @@ void macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts 
     const dim3 gci((nc + kMBlk - 1) / kMBlk), bi(kMBlk);
     const int npart = (int)macro_nparts(nc, NFM);
     const dim3 gsl(npart), bsl(kSBlk);
-    // the preloading residual kernel runs two waves per SIMD: use it while its blocks fit the GPU at once
-    int dev = 0, ncu = 256;
+    // the residual kernel that preloads the cell's state (more registers) runs while all its blocks are
+    // resident at once; above that the lean variant, which fits more blocks per compute unit
+    int dev = 0, ncu = 256, per_cu = 1;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const bool one_round = (int64_t)npart * (kSBlk / kWave) <= (int64_t)ncu * 4 * 2;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mres<D, NFM, true>, kSBlk, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const bool one_round = (int64_t)npart <= (int64_t)ncu * per_cu;
     hipLaunchKernelGGL(k_mprim<D>, gci, bi, 0, st, B.W, B.P, B.fld, B.Ts, nc, p);
     // inner iteration `it` starts from the state in buffer `it % 2` when the sweeps ping-pong
     double *Wb[2] = {B.W, B.W2}, *Pb[2] = {B.P, B.P2}, *Fb[2] = {B.fld, B.fld2};

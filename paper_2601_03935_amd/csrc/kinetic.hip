@@ -39,6 +39,26 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// rho (2 pi T)^(-D/2), the normalisation of a D-dimensional Maxwellian, with a division and a square root
+template <int D>
+__device__ __forceinline__ double gauss_norm(const double rho, const double T)
+{
+    const double x = 2 * kPi * T;
+    if constexpr (D == 1) return rho / sqrt(x);
+    else if constexpr (D == 2) return rho / x;
+    else return rho / (x * sqrt(x));
+}
+
+// fixed-order sum over the 4 waves of a 256-thread block of per-wave sums (sh: 4 doubles of shared memory
+// per value); every thread gets the same result
+__device__ __forceinline__ double block4_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
 // Wave w of a (cell, velocity chunk) grid: cells are taken in groups of G consecutive cells and each group
 // is traversed chunk-major (chunk 0 of its cells, then chunk 1, ...), so the rows a wave's neighbours
 // touch in the same chunk were read shortly before.  G = 1 is cell-major, G >= ncell fully chunk-major.
@@ -1306,18 +1326,22 @@ __global__ void k_prologue(const double *__restrict__ mom, T *__restrict__ coef,
 }
 
 // ------------------------------------------------------------------ wall re-emission densities
+// Wall density of each diffuse-wall face (zero net mass flux): outgoing flux of the reconstructed f over
+// the incoming flux of the unit-density wall Maxwellian.  One 256-thread block per boundary face; the
+// loop body is branch-free (both sides evaluated, the sign of xi.n selects), so the loads of several
+// velocities are in flight together.
 template <typename T, int D, int NFM>
-__global__ __launch_bounds__(64) void k_wall_density(const T *__restrict__ f, const T *__restrict__ gf,
-                                                     const double *__restrict__ xi, const double *__restrict__ w,
-                                                     T *__restrict__ rhow, const MeshDev m, const int64_t nv)
+__global__ __launch_bounds__(256) void k_wall_density(const T *__restrict__ f, const T *__restrict__ gf,
+                                                      const double *__restrict__ xi, const double *__restrict__ w,
+                                                      T *__restrict__ rhow, const MeshDev m, const int64_t nv)
 {
     constexpr int ND = (D == 3) ? 3 : 4;
+    __shared__ double sh[2][4];
     const int bfi = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int tag = m.bf_tag[bfi];
-    const BcDev bc = m.bcs[tag];
+    const int t = threadIdx.x;
+    const BcDev bc = m.bf_bc[bfi];
     if (bc.kind != 0) {
-        if (lane == 0) rhow[bfi] = (T)0;
+        if (t == 0) rhow[bfi] = (T)0;
         return;
     }
     const int64_t c = m.bf_cell[bfi];
@@ -1327,10 +1351,10 @@ __global__ __launch_bounds__(64) void k_wall_density(const T *__restrict__ f, co
         n[a] = m.bf_n[(int64_t)bfi * D + a];
         dx[a] = m.bf_dxc[(int64_t)bfi * D + a];
     }
+    const double gn = gauss_norm<D>(1.0, bc.T);
     double out = 0, in = 0;
-    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
-        const int64_t k = k0 + lane;
-        if (k >= nv) break;
+#pragma unroll 4
+    for (int64_t k = t; k < nv; k += 256) {
         double xn = 0, c2 = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -1338,38 +1362,37 @@ __global__ __launch_bounds__(64) void k_wall_density(const T *__restrict__ f, co
             const double cc = xi[k * D + a] - bc.u[a];
             c2 += cc * cc;
         }
-        if (xn > 0) {
-            T v = f[(c * ND + 0) * nv + k];
+        T v = f[(c * ND + 0) * nv + k];
 #pragma unroll
-            for (int a = 0; a < D; ++a) v += gf[((c * ND + 0) * D + a) * nv + k] * (T)dx[a];
-            out += w[k] * xn * (double)v;
-        } else {
-            in += w[k] * (-xn) * pow(2 * kPi * bc.T, -0.5 * D) * exp(-c2 / (2 * bc.T));
-        }
+        for (int a = 0; a < D; ++a) v += gf[((c * ND + 0) * D + a) * nv + k] * (T)dx[a];
+        const double mw = w[k] * (-xn) * gn * exp(-c2 / (2 * bc.T));
+        if (xn > 0) out += w[k] * xn * (double)v;
+        else in += mw;
     }
-    out = wave_sum(out);
-    in = wave_sum(in);
-    if (lane == 0) rhow[bfi] = (T)(out / in);
+    out = block4_sum(out, sh[0]);
+    in = block4_sum(in, sh[1]);
+    if (t == 0) rhow[bfi] = (T)(out / in);
 }
 
 // ------------------------------------------------------------------ boundary flux moments of a state
 // per boundary face: NW outward fluxes (mass, momentum D, total energy, e_r, e_v, e_R) per unit area and
 // the surface output (q_conv, q_rad, p_w)
 template <typename T, int D>
-__global__ __launch_bounds__(64) void k_boundary_flux(const T *__restrict__ f, const T *__restrict__ gf,
-                                                      const T *__restrict__ I, const T *__restrict__ gI,
-                                                      const double *__restrict__ xi, const double *__restrict__ w,
-                                                      const double *__restrict__ om, const double *__restrict__ wo,
-                                                      const T *__restrict__ rhow, double *__restrict__ bflux,
-                                                      double *__restrict__ bsurf, const MeshDev m, const int64_t nv,
-                                                      const int64_t no, const double dr, const double dv,
-                                                      const double sigR)
+__global__ __launch_bounds__(256) void k_boundary_flux(const T *__restrict__ f, const T *__restrict__ gf,
+                                                       const T *__restrict__ I, const T *__restrict__ gI,
+                                                       const double *__restrict__ xi, const double *__restrict__ w,
+                                                       const double *__restrict__ om, const double *__restrict__ wo,
+                                                       const T *__restrict__ rhow, double *__restrict__ bflux,
+                                                       double *__restrict__ bsurf, const MeshDev m, const int64_t nv,
+                                                       const int64_t no, const double dr, const double dv,
+                                                       const double sigR)
 {
     constexpr int ND = (D == 3) ? 3 : 4;
     constexpr int NW = D + 5;
+    __shared__ double sh[NW + 3][4];
     const int bfi = blockIdx.x;
-    const int lane = threadIdx.x;
-    const BcDev bc = m.bcs[m.bf_tag[bfi]];
+    const int t = threadIdx.x;
+    const BcDev bc = m.bf_bc[bfi];
     const int64_t c = m.bf_cell[bfi];
     double n[D], dx[D];
 #pragma unroll
@@ -1378,33 +1401,38 @@ __global__ __launch_bounds__(64) void k_boundary_flux(const T *__restrict__ f, c
         dx[a] = m.bf_dxc[(int64_t)bfi * D + a];
     }
     const double rho_in = (bc.kind == 0) ? (double)rhow[bfi] : bc.rho;
+    const double gn = gauss_norm<D>(rho_in, bc.T);
     double F[NW], qconv = 0, pw = 0;
 #pragma unroll
     for (int i = 0; i < NW; ++i) F[i] = 0;
-    for (int64_t k0 = 0; k0 < nv; k0 += kWave) {
-        const int64_t k = k0 + lane;
-        if (k >= nv) break;
-        double x[D], xn = 0, x2 = 0;
+    // branch-free body (both sides evaluated, the sign of xi.n selects) so that the loads of several
+    // velocities are in flight together
+#pragma unroll 2
+    for (int64_t k = t; k < nv; k += 256) {
+        double x[D], xn = 0, x2 = 0, c2 = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             x[a] = xi[k * D + a];
             xn += x[a] * n[a];
             x2 += x[a] * x[a];
+            c2 += (x[a] - bc.u[a]) * (x[a] - bc.u[a]);
         }
-        double fv[4] = {0, 0, 0, 0};
+        double fo[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            T v = f[(c * ND + d) * nv + k];
+#pragma unroll
+            for (int a = 0; a < D; ++a) v += gf[((c * ND + d) * D + a) * nv + k] * (T)dx[a];
+            fo[d] = (double)v;
+        }
+        const double G = gn * exp(-c2 / (2 * bc.T));
+        double fv[4];
         if (xn > 0) {
-#pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                T v = f[(c * ND + d) * nv + k];
-#pragma unroll
-                for (int a = 0; a < D; ++a) v += gf[((c * ND + d) * D + a) * nv + k] * (T)dx[a];
-                fv[d] = (double)v;
-            }
+            fv[0] = fo[0];
+            fv[1] = fo[1];
+            fv[2] = fo[2];
+            fv[3] = fo[3];
         } else {
-            double c2 = 0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) c2 += (x[a] - bc.u[a]) * (x[a] - bc.u[a]);
-            const double G = rho_in * pow(2 * kPi * bc.T, -0.5 * D) * exp(-c2 / (2 * bc.T));
             fv[0] = G;
             fv[1] = 0.5 * dr * bc.T * G;
             fv[2] = 0.5 * dv * bc.T * G;
@@ -1423,9 +1451,7 @@ __global__ __launch_bounds__(64) void k_boundary_flux(const T *__restrict__ f, c
         pw += wk * xn * xn * fv[0];
     }
     double qrad = 0;
-    for (int64_t q0 = 0; q0 < no; q0 += kWave) {
-        const int64_t q = q0 + lane;
-        if (q >= no) break;
+    for (int64_t q = t; q < no; q += 256) {
         double on = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) on += om[q * D + a] * n[a];
@@ -1441,11 +1467,11 @@ __global__ __launch_bounds__(64) void k_boundary_flux(const T *__restrict__ f, c
         qrad += wo[q] * on * Iv;
     }
 #pragma unroll
-    for (int i = 0; i < NW; ++i) F[i] = wave_sum(F[i]);
-    qconv = wave_sum(qconv);
-    pw = wave_sum(pw);
-    qrad = wave_sum(qrad);
-    if (lane == 0) {
+    for (int i = 0; i < NW; ++i) F[i] = block4_sum(F[i], sh[i]);
+    qconv = block4_sum(qconv, sh[NW]);
+    pw = block4_sum(pw, sh[NW + 1]);
+    qrad = block4_sum(qrad, sh[NW + 2]);
+    if (t == 0) {
         double *out = bflux + (int64_t)bfi * NW;
         for (int i = 0; i < NW; ++i) out[i] = F[i];
         out[D + 4] = qrad;
@@ -1457,16 +1483,6 @@ __global__ __launch_bounds__(64) void k_boundary_flux(const T *__restrict__ f, c
 }
 
 // ------------------------------------------------------------------ synchronisation and initialisation
-// rho (2 pi T)^(-D/2), the normalisation of a D-dimensional Maxwellian, with a division and a square root
-template <int D>
-__device__ __forceinline__ double gauss_norm(const double rho, const double T)
-{
-    const double x = 2 * kPi * T;
-    if constexpr (D == 1) return rho / sqrt(x);
-    else if constexpr (D == 2) return rho / x;
-    else return rho / (x * sqrt(x));
-}
-
 // f += f^eq(M1) - f^eq(M0) with f^eq the multi-temperature equilibrium; I += (eR1 - eR0)/(4 pi).
 // sp per cell: [rho, u[D], Tt, Tr, Tv, eR] for M0 then M1.
 template <typename T, int D, int VW>
@@ -1626,7 +1642,7 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
     P.end(ev);
     ev = P.begin(5, 0.0);
     if (m.nbf > 0)
-        hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(64), 0, st, B.f, B.gf, B.xi_d, B.w_d,
+        hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(256), 0, st, B.f, B.gf, B.xi_d, B.w_d,
                            B.rhow, m, nv);
     P.end(ev);
     const int ks = o.kin_sweeps;
@@ -1708,9 +1724,9 @@ void launch_boundary_state(KinBufs<T> &B, const MeshDev &m, const Phys &p, int s
     if (m.nbf <= 0) return;
     launch_grad<T, D, NFM>(B.f, B.gf, m, nv, so, m.bcells, m.nbcells, st);
     launch_grad_I<T, D, NFM>(B.I, B.gI, m, no, so, m.bcells, m.nbcells, st);
-    hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(64), 0, st, B.f, B.gf, B.xi_d, B.w_d,
+    hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(256), 0, st, B.f, B.gf, B.xi_d, B.w_d,
                        B.rhow, m, nv);
-    hipLaunchKernelGGL((k_boundary_flux<T, D>), dim3(m.nbf), dim3(64), 0, st, B.f, B.gf, B.I, B.gI, B.xi_d, B.w_d,
+    hipLaunchKernelGGL((k_boundary_flux<T, D>), dim3(m.nbf), dim3(256), 0, st, B.f, B.gf, B.I, B.gI, B.xi_d, B.w_d,
                        B.om_d, B.wo_d, B.rhow, B.bflux, B.bsurf, m, nv, no, p.d_r, p.d_v, p.sigma_R);
 }
 

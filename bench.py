@@ -343,10 +343,10 @@ def main():
     eps = []
     torch.cuda.synchronize()
     ev0.record(stream)
-    for _ in range(a.steps):
-        e, it = s.iterate(gsis=True)
-        eps.append(e)
-        inner.append(it)
+    # one batch of a.steps whole GSIS iterations (each computes its residual; the host waits once)
+    e, it = s.iterate(gsis=True, n=a.steps)
+    eps.append(e)
+    inner.append(it)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
@@ -393,7 +393,7 @@ def main():
         "kinetic_step": {"ms": kin_ms, "ideal_bytes": kin_bytes_ideal,
                          "ideal_gbs": kin_bytes_ideal / (kin_ms * 1e-3) / 1e9},
         "kernels": kernels,
-        "inner_iterations_per_step": float(np.mean(inner)),
+        "inner_iterations_last_step": int(inner[-1]),
         "eps_last": eps[-1],
     }
     if not a.no_time_to_tol:

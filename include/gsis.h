@@ -164,8 +164,10 @@ int32_t gsis_init_fields(gsis_t *h, const double *rho, const double *u, const do
 int32_t gsis_set_state(gsis_t *h, const double *f, const double *I);
 int32_t gsis_get_state(gsis_t *h, double *f, double *I);
 
-/* Outer iterations (Sec. 3).  gsis_iterate runs n iterations of the given scheme and returns the
- * last epsilon in *eps (and the macro inner count of the last iteration in *inner, may be NULL).
+/* Outer iterations (Sec. 3).  gsis_iterate runs n iterations of the given scheme back to back (each
+ * computes its residual; the host waits for the GPU once, after the last) and returns the last
+ * epsilon in *eps, or a NaN of any iteration of the batch with GSIS_E_DIVERGED (the macro inner count
+ * of the last iteration in *inner, may be NULL).
  * gsis_solve: n_precond CIS iterations, then opts.scheme until epsilon < tol or max_outer;
  * returns GSIS_OK, GSIS_W_NOT_CONVERGED or GSIS_E_DIVERGED. */
 int32_t gsis_iterate(gsis_t *h, int32_t scheme, int32_t n, double *eps, int32_t *inner);

@@ -80,7 +80,15 @@ struct gsis_s {
     std::vector<double> hist;
     double cnt_updates = 0, cnt_bytes = 0, cnt_seconds = 0;
     int last_inner = 0;
-    hipEvent_t tev[3] = {nullptr, nullptr, nullptr};  // outer-iteration timing: start, kinetic done, GSIS done
+    // outer-iteration timing with events (start, kinetic step done, GSIS part done), read when the host
+    // next waits for the stream
+    struct TRec {
+        hipEvent_t a, b, c;
+    };
+    std::vector<TRec> tpend;
+    std::vector<hipEvent_t> tpool;
+    double *red_h = nullptr;  // pinned host memory: the 7 residual sums of each iteration of a batch
+    int64_t red_cap = 0;      // capacity in iterations
     Prof prof;
 };
 
@@ -669,16 +677,37 @@ static void macro_T(gsis_t *h, const double *mom, const double *bflux, const dou
     });
 }
 
-static double epsilon_of(gsis_t *h, const double *m1, const double *m0)
+// pinned room for the residual sums of n iterations (called with no copy into it pending)
+static bool reserve_red(gsis_t *h, int64_t n)
+{
+    if (n <= h->red_cap) return true;
+    if (h->red_h) (void)hipHostFree(h->red_h);
+    h->red_h = nullptr;
+    h->red_cap = 0;
+    if (hipHostMalloc((void **)&h->red_h, (size_t)n * 7 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        h->red_h = nullptr;
+        return false;
+    }
+    h->red_cap = n;
+    return true;
+}
+
+// enqueues the residual sums of (m1 against m0) and their copy into slot `slot` of the pinned buffer
+static void epsilon_launch(gsis_t *h, const double *m1, const double *m0, int64_t slot)
 {
     const int D = h->hm.D;
     if (D == 1) launch_residual<1>(m1, m0, h->m.vol, h->cellbuf, h->red, h->Mb.bpart, h->hm.nc, h->phys, h->stream);
     else if (D == 2) launch_residual<2>(m1, m0, h->m.vol, h->cellbuf, h->red, h->Mb.bpart, h->hm.nc,
                                          h->phys, h->stream);
     else launch_residual<3>(m1, m0, h->m.vol, h->cellbuf, h->red, h->Mb.bpart, h->hm.nc, h->phys, h->stream);
+    (void)hipMemcpyAsync(h->red_h + 7 * slot, h->red, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+}
+
+// epsilon from the 7 sums of one iteration
+static double epsilon_value(const double *sums)
+{
     double s[7];
-    (void)hipMemcpyAsync(s, h->red, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    (void)hipStreamSynchronize(h->stream);
+    for (int i = 0; i < 7; ++i) s[i] = sums[i];
     if (s[3] < s[6]) s[3] = s[6];
     double e = 0;
     for (int i = 0; i < 3; ++i) {
@@ -697,9 +726,41 @@ static double kinetic_alg_bytes(const gsis_t *h)
     return (double)h->hm.nc * (2.0 * ndist(h->hm.D) * h->nv + 2.0 * h->no) * es;
 }
 
-// one outer iteration on storage type T; returns epsilon
+static hipEvent_t tget(gsis_t *h)
+{
+    if (!h->tpool.empty()) {
+        hipEvent_t e = h->tpool.back();
+        h->tpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// adds the timed intervals of the pending outer iterations (the stream has been synchronised)
+static void tflush(gsis_t *h, double *tk, double *tm)
+{
+    for (auto &r : h->tpend) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            if (tk) *tk += 1e-3 * ms;
+            h->cnt_seconds += 1e-3 * ms;
+        }
+        if (r.c && tm && hipEventElapsedTime(&ms, r.b, r.c) == hipSuccess) *tm += 1e-3 * ms;
+        h->tpool.push_back(r.a);
+        h->tpool.push_back(r.b);
+        if (r.c) h->tpool.push_back(r.c);
+    }
+    h->tpend.clear();
+}
+
+// One outer iteration on storage type T, its residual sums copied into slot `slot` of the pinned buffer.
+// With wait the host waits for the stream (once) and the iteration's epsilon is returned; without, the
+// iteration is only enqueued (0 is returned), so that a batch of iterations runs back to back.
 template <typename T>
-static double iterate_T(gsis_t *h, KinBufs<T> &B, bool gsis, int *inner, double *tk, double *tm)
+static double iterate_T(gsis_t *h, KinBufs<T> &B, bool gsis, int *inner, double *tk, double *tm, bool wait,
+                        int64_t slot = 0)
 {
     const double *uref = h->mom0_valid ? h->mom0 : nullptr;
     if (!h->mom0_valid) {
@@ -708,13 +769,11 @@ static double iterate_T(gsis_t *h, KinBufs<T> &B, bool gsis, int *inner, double 
         h->mom0_valid = true;
     }
     (void)uref;
-    // timed with events on the stream: the host waits once per outer iteration (for epsilon)
-    if (!h->tev[0])
-        for (auto &ev : h->tev) (void)hipEventCreate(&ev);
-    (void)hipEventRecord(h->tev[0], h->stream);
+    gsis_s::TRec r{tget(h), tget(h), gsis ? tget(h) : nullptr};
+    (void)hipEventRecord(r.a, h->stream);
     prologue_T(h, B, h->mom0);
     kinetic_T(h, B);
-    (void)hipEventRecord(h->tev[1], h->stream);
+    (void)hipEventRecord(r.b, h->stream);
     h->cnt_updates += (double)h->hm.nc * h->nv;
     h->cnt_bytes += kinetic_alg_bytes(h);
     if (inner) *inner = 0;
@@ -733,21 +792,20 @@ static double iterate_T(gsis_t *h, KinBufs<T> &B, bool gsis, int *inner, double 
         macro_T(h, h->momh, B.bflux, h->mom0);
         sync_params(h, h->momh, h->Mb.W, 1);
         sync_T(h, B, h->sp, 0);
-        (void)hipEventRecord(h->tev[2], h->stream);
+        (void)hipEventRecord(r.c, h->stream);
     }
     moments_T(h, B, h->mom0, h->mom1);
-    const double e = epsilon_of(h, h->mom1, h->mom0);  // synchronises the stream
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, h->tev[0], h->tev[1]) == hipSuccess) {
-        if (tk) *tk += 1e-3 * ms;
-        h->cnt_seconds += 1e-3 * ms;
-    }
-    if (gsis) {
-        if (tm && hipEventElapsedTime(&ms, h->tev[1], h->tev[2]) == hipSuccess) *tm += 1e-3 * ms;
-        if (inner) *inner = macro_count(h->Mb, mopts(h).max_inner, h->stream);
+    h->tpend.push_back(r);
+    epsilon_launch(h, h->mom1, h->mom0, slot);
+    double e = 0;
+    if (wait) {
+        (void)hipStreamSynchronize(h->stream);
+        e = epsilon_value(h->red_h + 7 * slot);
+        tflush(h, tk, tm);
+        if (gsis && inner) *inner = macro_count(h->Mb, mopts(h).max_inner, h->stream);
+        h->prof.collect();
     }
     std::swap(h->mom0, h->mom1);
-    h->prof.collect();
     return e;
 }
 
@@ -819,8 +877,13 @@ void gsis_destroy(gsis_t *h)
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     h->prof.destroy();
-    for (auto &ev : h->tev)
-        if (ev) (void)hipEventDestroy(ev);
+    for (auto &r : h->tpend) {
+        h->tpool.push_back(r.a);
+        h->tpool.push_back(r.b);
+        if (r.c) h->tpool.push_back(r.c);
+    }
+    for (auto &ev : h->tpool) (void)hipEventDestroy(ev);
+    if (h->red_h) (void)hipHostFree(h->red_h);
     free_state(h);
     free_mesh(h->m);
     delete h;
@@ -1050,10 +1113,19 @@ int32_t gsis_iterate(gsis_t *h, int32_t scheme, int32_t n, double *eps, int32_t 
     if (n < 0 || (scheme != GSIS_CIS && scheme != GSIS_GSIS)) return fail(h, GSIS_E_ARG, "gsis_iterate: invalid args");
     double e = 0;
     int in = 0;
+    // the batch runs back to back: every iteration computes its residual, only the last waits
+    if (!reserve_red(h, n)) return fail(h, GSIS_E_OOM, "gsis_iterate: pinned host allocation failed");
     for (int k = 0; k < n; ++k) {
-        e = (h->prec == GSIS_FP32) ? iterate_T(h, h->Bf, scheme == GSIS_GSIS, &in, nullptr, nullptr)
-                                   : iterate_T(h, h->Bd, scheme == GSIS_GSIS, &in, nullptr, nullptr);
-        if (e != e) break;
+        const bool wait = (k + 1 == n);
+        e = (h->prec == GSIS_FP32) ? iterate_T(h, h->Bf, scheme == GSIS_GSIS, &in, nullptr, nullptr, wait, k)
+                                   : iterate_T(h, h->Bd, scheme == GSIS_GSIS, &in, nullptr, nullptr, wait, k);
+    }
+    for (int k = 0; k + 1 < n; ++k) {
+        const double ek = epsilon_value(h->red_h + 7 * k);
+        if (ek != ek) {
+            e = ek;
+            break;
+        }
     }
     hipError_t herr = hipGetLastError();
     if (herr != hipSuccess) return fail(h, GSIS_E_DEVICE, std::string("gsis_iterate: ") + hipGetErrorString(herr));
@@ -1068,6 +1140,7 @@ int32_t gsis_solve(gsis_t *h, gsis_report *rep)
 {
     int32_t rc = check_ready(h, "gsis_solve");
     if (rc) return rc;
+    if (!reserve_red(h, 1)) return fail(h, GSIS_E_OOM, "gsis_solve: pinned host allocation failed");
     h->hist.clear();
     double tk = 0, tm = 0, e = 0;
     int64_t inner_total = 0;
@@ -1079,7 +1152,8 @@ int32_t gsis_solve(gsis_t *h, gsis_report *rep)
         const bool g = (h->opts.scheme == GSIS_GSIS) && k >= h->opts.n_precond;
         h->opts.second_order = (k < h->opts.first_order_iters) ? 0 : so_user;
         int in = 0;
-        e = (h->prec == GSIS_FP32) ? iterate_T(h, h->Bf, g, &in, &tk, &tm) : iterate_T(h, h->Bd, g, &in, &tk, &tm);
+        e = (h->prec == GSIS_FP32) ? iterate_T(h, h->Bf, g, &in, &tk, &tm, true)
+                                   : iterate_T(h, h->Bd, g, &in, &tk, &tm, true);
         inner_total += in;
         h->hist.push_back(e);
         if (e != e) {

@@ -108,6 +108,30 @@ def test_gsis_iterations_fp64(name, case):
     assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-8
 
 
+def test_iteration_batch_matches_single_iterations():
+    """gsis_iterate(n) enqueues the n iterations back to back and waits once; every iteration still
+    computes its residual.  Its state, epsilon and inner count equal those of n single iterations bit for
+    bit (no atomics anywhere), and epsilon matches the oracle's."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1)
+    s1, o = _pair(case, precision="fp64", max_inner=60)
+    s2 = Solver(case, precision="fp64", max_inner=60)
+    s1.iterate(gsis=False, n=2)
+    for _ in range(2):
+        s2.iterate(gsis=False)
+    e1, i1 = s1.iterate(gsis=True, n=4)
+    for _ in range(4):
+        e2, i2 = s2.iterate(gsis=True)
+    assert e1 == e2 and i1 == i2
+    f1, I1 = s1.get_state()
+    f2, I2 = s2.get_state()
+    assert np.array_equal(f1, f2) and np.array_equal(I1, I2)
+    for k in range(6):
+        eo, io = o.iterate(gsis=k >= 2)
+    assert io == i1
+    assert abs(e1 - eo) <= 1e-8 * abs(eo) + 1e-14
+    assert _relerr(f1, o.get_state()[0]) < 1e-8
+
+
 @pytest.mark.parametrize("kw", [dict(tau_opt=0.0), dict(sigma_R=0.0)], ids=["optically_thin_limit", "no_radiation"])
 def test_decoupled_radiation_macro_solve_and_iterations(kw):
     """Degenerate radiation: optical thickness 0 (absorption and emission off; the synthetic solve keeps

@@ -10,7 +10,8 @@ import pytest
 
 from oracle import Oracle, field_names
 from paper_2601_03935_amd.gsis import Solver, oracle_opts
-from workloads import case_capsule, case_cavity, case_cylinder, case_fourier_1d, mesh_annulus, mesh_cavity
+from workloads import (case_capsule, case_cavity, case_cylinder, case_fourier_1d, case_normal_shock, mesh_annulus,
+                       mesh_cavity)
 
 pytestmark = pytest.mark.gpu
 
@@ -106,6 +107,22 @@ def test_gsis_iterations_fp64(name, case):
         assert io == ig
         assert abs(eg - eo) <= 1e-8 * abs(eo) + 1e-14
     assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-8
+
+
+def test_normal_shock_iterations_fp64():
+    """Ma 5 normal shock (Sec. 4.1) on a short domain: far-field equilibria at both ends of a 1D mesh, a
+    discontinuous start; conventional then GSIS iterations agree with the oracle (epsilon, inner counts,
+    state) while the shock forms."""
+    case = case_normal_shock(x0=-10.0, x1=20.0, nv=32, no=8)
+    s, o = _pair(case, precision="fp64", max_inner=60)
+    for k in range(8):
+        g = k >= 3
+        eo, io = o.iterate(gsis=g)
+        eg, ig = s.iterate(gsis=g)
+        assert io == ig
+        assert abs(eg - eo) <= 1e-8 * abs(eo) + 1e-14
+    assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-8
+    assert _relerr(s.get_state()[1], o.get_state()[1]) < 1e-8
 
 
 def test_iteration_batch_matches_single_iterations():

@@ -14,7 +14,7 @@ from oracle import Oracle, field_names
 from oracle import fourier as FA
 from workloads import (BC_WALL, case_cavity, case_fourier_1d, gauss_hermite_grid, mesh_1d, mesh_cavity,
                        ordinates_hemisphere, ordinates_slab)
-from workloads.cases import Case, Flow, Gas
+from workloads.cases import Case, Flow, Gas, rankine_hugoniot
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -400,3 +400,22 @@ def test_heat_flux_hots_scale_with_kn_squared():
         vals.append(np.sqrt((H[inner][core][:, 9:18] ** 2).sum()))
     slope = np.polyfit(np.log(Kns), np.log(vals), 1)[0]
     assert abs(slope - 2.0) < 0.3, (vals, slope)
+
+
+@pytest.mark.parametrize("Ma", [1.5, 5.0, 10.0])
+def test_rankine_hugoniot_states_carry_equal_fluxes(Ma):
+    """Inputs of the normal-shock case (Sec. 4.1): the upstream state (rho = 1, T = 1, u = sqrt(gamma) Ma)
+    and the closed-form downstream state carry the same mass, momentum and energy fluxes of a gas with
+    p = rho T and internal energy (3 + d_r + d_v) T / 2 per unit mass (gamma = (5 + d_r + d_v) /
+    (3 + d_r + d_v)); the jump is compressive and the downstream flow subsonic."""
+    gas = Gas()
+    g = gas.gamma
+    assert g == pytest.approx((5 + gas.d_r + gas.d_v) / (3 + gas.d_r + gas.d_v))
+    rho_d, u_d, T_d = rankine_hugoniot(Ma, g)
+    u_u = np.sqrt(g) * Ma
+    cv = 0.5 * (3 + gas.d_r + gas.d_v)
+    flux = lambda r, u, T: np.array([r * u, r * u * u + r * T, r * u * (0.5 * u * u + cv * T + T)])
+    np.testing.assert_allclose(flux(rho_d, u_d, T_d), flux(1.0, u_u, 1.0), rtol=1e-12)
+    assert rho_d > 1 and T_d > 1 and u_d < u_u
+    assert u_d / np.sqrt(g * T_d) < 1
+

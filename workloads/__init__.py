@@ -26,6 +26,8 @@ from .cases import (  # noqa: F401
     case_cavity,
     case_cylinder,
     case_capsule,
+    case_normal_shock,
+    rankine_hugoniot,
     warmstart_case_params,
     warmstart_cavity_params,
     warmstart_cylinder_params,

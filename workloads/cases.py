@@ -132,6 +132,43 @@ def case_capsule(Kn: float = 0.01, tau_opt: float = 1.0, Ma: float = 10.0, nvx: 
                 ordinates_sphere(n_theta, n_phi), gas, flow, bcs, r, u, T, meta=dict(Ma=Ma))
 
 
+def rankine_hugoniot(Ma: float, gamma: float):
+    """Downstream (rho_d, u_d, T_d) of a normal shock with upstream rho = 1, T = 1, u = sqrt(gamma) Ma,
+    for a gas of constant specific-heat ratio gamma (the jump relations stated with the normal-shock case
+    of Sec. 4.1)."""
+    u_u = np.sqrt(gamma) * Ma
+    rho_d = (gamma + 1) * Ma ** 2 / (2 + (gamma - 1) * Ma ** 2)
+    T_d = (2 + (gamma - 1) * Ma ** 2) * (2 * gamma * Ma ** 2 - (gamma - 1)) / ((gamma + 1) ** 2 * Ma ** 2)
+    return rho_d, u_u / rho_d, T_d
+
+
+def case_normal_shock(Ma: float = 5.0, Z_r: float = 2.6, Z_v: float = 26.0, x0: float = -60.0, x1: float = 140.0,
+                      dx: float = 0.25, nv: int = 64, xmax: float = 15.0, no: int = 48, Kn_photon: float = 10.0,
+                      sigma_R: float = 0.01) -> Case:
+    """Planar normal shock (Sec. 4.1): Kn_gas = 5 pi / 16 (reference length from the upstream mean free
+    path), upstream rho = 1, T = 1, u = sqrt(gamma) Ma and the Rankine-Hugoniot downstream state as fixed
+    far-field equilibria at the two ends, initial discontinuity at x = 0 with both sides at equilibrium
+    (I = sigma_R T^4 / pi).  Uniform mesh of spacing dx on [x0, x1]; uniform 1D velocity grid on
+    [-xmax, xmax] (the reduced model is exact for a planar flow, so only the xi_x points of the paper's
+    reduced 2D grid are needed); Gauss-Legendre ordinates in mu = cos(theta)."""
+    n = int(round((x1 - x0) / dx))
+    mesh = mesh_1d(n, x0, x1, 0, 1)
+    gas = Gas(Z_r=Z_r, Z_v=Z_v, sigma_R=sigma_R)
+    g = gas.gamma
+    u_u = np.sqrt(g) * Ma
+    rho_d, u_d, T_d = rankine_hugoniot(Ma, g)
+    flow = Flow(Kn_gas=5 * np.pi / 16, k_eff=1.0 / Kn_photon, rho_inf=1.0, T_inf=1.0, u_inf=(u_u, 0.0, 0.0))
+    bcs = [dict(kind=BC_FARFIELD, rho=1.0, T=1.0, u=(u_u, 0.0, 0.0)),
+           dict(kind=BC_FARFIELD, rho=rho_d, T=T_d, u=(u_d, 0.0, 0.0))]
+    x = mesh.ctr[:, 0]
+    up = x <= 0.0
+    r = np.where(up, 1.0, rho_d)
+    u = np.where(up, u_u, u_d)[:, None]
+    T = np.where(up, 1.0, T_d)
+    return Case(f"shock_Ma{Ma}_Z{Z_r}_{Z_v}_n{n}", mesh, newton_cotes_grid(nv, 1, xmax, a=1.0), ordinates_slab(no),
+                gas, flow, bcs, r, u, T, meta=dict(Ma=Ma, rho_d=rho_d, u_d=u_d, T_d=T_d))
+
+
 def warmstart_case_params(n: int = 256, seed: int = 2):
     """Seeded (Ma, Kn, optical thickness) draws for the warm-start data set."""
     rng = np.random.default_rng(seed)

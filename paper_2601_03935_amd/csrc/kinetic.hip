@@ -49,6 +49,18 @@ __device__ __forceinline__ double gauss_norm(const double rho, const double T)
     else return rho / (x * sqrt(x));
 }
 
+// sum over aligned groups of G lanes (butterfly within the group)
+template <int G>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// lanes per cell of the moment reduction
+constexpr int kMomLanes = 16;
+
 // fixed-order sum over the 4 waves of a 256-thread block of per-wave sums (sh: 4 doubles of shared memory
 // per value); every thread gets the same result
 __device__ __forceinline__ double block4_sum(double v, double *sh)
@@ -1149,11 +1161,13 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
 {
     constexpr int ND = (D == 3) ? 3 : 4;
     constexpr MomLayout L{D};
+    // kMomLanes lanes per cell, 16 cells per block: the four cells of a wave share each load of the
+    // velocity nodes and weights, and one butterfly step of the final sums serves all four
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x & 63;
-    const int64_t ci = b * 4 + (threadIdx.x >> 6);
-    if (ci >= nc) return;
-    const int c = uni_i((int)ci);
+    const int lane = threadIdx.x & (kMomLanes - 1);
+    const int64_t ci = b * (256 / kMomLanes) + (threadIdx.x / kMomLanes);
+    const bool valid = ci < nc;
+    const int64_t c = valid ? ci : nc - 1;  // clamped: the group runs, only its store is skipped
     double ur[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) ur[a] = uref ? uref[(int64_t)c * L.size() + L.u() + a] : 0.0;
@@ -1166,12 +1180,12 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
         for (int bb = 0; bb < D; ++bb) m2[a][bb] = 0;
     }
 #pragma unroll 4
-    for (int64_t kb = (int64_t)lane * VW; kb < nv; kb += kWave * VW) {
+    for (int64_t kb = (int64_t)lane * VW; kb < nv; kb += kMomLanes * VW) {
       T fG[VW], fR[VW], fV[VW], fH[VW];
-      load_vw<T, VW>(f + ((int64_t)c * ND + 0) * nv + kb, fG);
-      load_vw<T, VW>(f + ((int64_t)c * ND + 1) * nv + kb, fR);
-      load_vw<T, VW>(f + ((int64_t)c * ND + 2) * nv + kb, fV);
-      if (ND == 4) load_vw<T, VW>(f + ((int64_t)c * ND + (ND == 4 ? 3 : 0)) * nv + kb, fH);
+      load_vw<T, VW>(f + (c * ND + 0) * nv + kb, fG);
+      load_vw<T, VW>(f + (c * ND + 1) * nv + kb, fR);
+      load_vw<T, VW>(f + (c * ND + 2) * nv + kb, fV);
+      if (ND == 4) load_vw<T, VW>(f + (c * ND + (ND == 4 ? 3 : 0)) * nv + kb, fH);
 #pragma unroll
       for (int e = 0; e < VW; ++e) {
         const int64_t k = kb + e;
@@ -1203,36 +1217,34 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
         }
       }
     }
-    m0 = wave_sum(m0);
-    h0 = wave_sum(h0);
-    r0 = wave_sum(r0);
-    v0 = wave_sum(v0);
+    m0 = group_sum<kMomLanes>(m0);
+    h0 = group_sum<kMomLanes>(h0);
+    r0 = group_sum<kMomLanes>(r0);
+    v0 = group_sum<kMomLanes>(v0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        m1[a] = wave_sum(m1[a]);
-        m3[a] = wave_sum(m3[a]);
-        h1[a] = wave_sum(h1[a]);
-        r1[a] = wave_sum(r1[a]);
-        v1[a] = wave_sum(v1[a]);
+        m1[a] = group_sum<kMomLanes>(m1[a]);
+        m3[a] = group_sum<kMomLanes>(m3[a]);
+        h1[a] = group_sum<kMomLanes>(h1[a]);
+        r1[a] = group_sum<kMomLanes>(r1[a]);
+        v1[a] = group_sum<kMomLanes>(v1[a]);
 #pragma unroll
-        for (int bb = 0; bb < D; ++bb) m2[a][bb] = wave_sum(m2[a][bb]);
+        for (int bb = 0; bb < D; ++bb) m2[a][bb] = group_sum<kMomLanes>(m2[a][bb]);
     }
     double eR = 0, qR[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) qR[a] = 0;
-    for (int64_t q0 = 0; q0 < no; q0 += kWave) {
-        const int64_t q = q0 + lane;
-        if (q >= no) break;
-        const double Iq = wo[q] * (double)I[(int64_t)c * no + q];
+    for (int64_t q = lane; q < no; q += kMomLanes) {
+        const double Iq = wo[q] * (double)I[c * no + q];
         eR += Iq;
 #pragma unroll
         for (int a = 0; a < D; ++a) qR[a] += om[q * D + a] * Iq;
     }
-    eR = wave_sum(eR);
+    eR = group_sum<kMomLanes>(eR);
 #pragma unroll
-    for (int a = 0; a < D; ++a) qR[a] = wave_sum(qR[a]);
-    if (lane == 0) {
-        double *M = mom + (int64_t)c * L.size();
+    for (int a = 0; a < D; ++a) qR[a] = group_sum<kMomLanes>(qR[a]);
+    if (lane == 0 && valid) {
+        double *M = mom + c * L.size();
         const double rho = m0;
         double dl[D], d2 = 0, S2 = 0;
 #pragma unroll
@@ -1702,12 +1714,13 @@ void launch_moments(const KinBufs<T> &B, const double *uref, double *mom, int64_
                     const Phys &p, hipStream_t st)
 {
     constexpr int VW = 16 / sizeof(T);
+    const int64_t mom_blocks = (nc + 256 / kMomLanes - 1) / (256 / kMomLanes);
     if (nv % VW == 0)
-        hipLaunchKernelGGL((k_moments<T, D, VW>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d,
-                           B.om_d, B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
+        hipLaunchKernelGGL((k_moments<T, D, VW>), dim3(mom_blocks), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d, B.om_d,
+                           B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
     else
-        hipLaunchKernelGGL((k_moments<T, D, 1>), dim3(wave_blocks(nc)), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d,
-                           B.om_d, B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
+        hipLaunchKernelGGL((k_moments<T, D, 1>), dim3(mom_blocks), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d, B.om_d,
+                           B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
 }
 
 template <typename T, int D>

@@ -97,6 +97,22 @@ def test_macro_solve_and_sync_fp64(name, case):
     assert _relerr(Ig, Io) < 1e-11
 
 
+@pytest.mark.parametrize("inner_tol", [0.9, 0.7, 0.5, 0.3])
+def test_macro_solve_stops_early(inner_tol):
+    """Loose inner tolerances, reached after 2, 7, 16 and 48 inner iterations on this mesh (oracle): the
+    stopping iteration, which the host learns from the pinned-memory polls, and the solution, which sits in
+    the second buffer of the ping-pong after an odd count and is copied back on the device, match the
+    oracle's; the launches issued after convergence change nothing."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1)
+    s, o = _pair(case, precision="fp64", max_inner=100, inner_tol=inner_tol)
+    _warm(o, s, n=4)
+    Wo, ito = o.macro_solve()
+    Wg, itg = s.macro_solve()
+    assert 0 < ito < 100
+    assert ito == itg
+    assert _relerr(Wg, Wo) < 1e-9
+
+
 @pytest.mark.parametrize("name,case", _cases_small(), ids=[c[0] for c in _cases_small()])
 def test_gsis_iterations_fp64(name, case):
     s, o = _pair(case, precision="fp64", max_inner=_MAX_INNER[name])

@@ -385,7 +385,10 @@ def main():
     for _ in range(a.warmup):
         s.iterate(gsis=True)
     torch.cuda.synchronize()
-    s.set_profiling(True)
+    # events in the timed region around the dominant kernel only (the Jacobi sweep): timing every kind
+    # adds ~52 event records per iteration (about 0.18 ms of 4.8); the table of all kinds comes from a
+    # separate profiled pass after the timed region
+    s.set_profiling(True, kinds=["sweep"])
     s.counters()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -400,6 +403,10 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
+    stats_timed = s.kernel_stats()
+    nprof = 5
+    s.set_profiling(True)
+    s.iterate(gsis=True, n=nprof)
     stats = s.kernel_stats()
     s.set_profiling(False)
     step_ms = ms / a.steps
@@ -409,12 +416,12 @@ def main():
         tms, n, by = stats[k]
         if n == 0:
             continue
-        kernels[k] = dict(ms_per_step=tms / a.steps, launches_per_step=n / a.steps,
+        kernels[k] = dict(ms_per_step=tms / nprof, launches_per_step=n / nprof,
                           gbs=(by / (tms * 1e-3) / 1e9) if by > 0 and tms > 0 else None)
-    dom = max((k for k in kernels if stats[k][2] > 0), key=lambda k: stats[k][0])
-    tms, n, by = stats[dom]
+    dom = "sweep"
+    tms, n, by = stats_timed[dom]
     achieved = by / n / (tms / n * 1e-3) / 1e9
-    kin_ms = sum(stats[k][0] for k in ("grad", "residual", "sweep", "rad", "boundary")) / a.steps
+    kin_ms = sum(stats[k][0] for k in ("grad", "residual", "sweep", "rad", "boundary")) / nprof
     kin_bytes_ideal = nc * (2 * 4 * nv + 2 * no) * (4 if a.precision == "fp32" else 8)
     out = {
         "metric": "DVM cell·velocity updates/s + HBM GB/s; wall time to 1e-6 residual",

@@ -197,9 +197,12 @@ int32_t gsis_get_residual_history(gsis_t *h, double *buf, int64_t cap, int64_t *
 int32_t gsis_get_surface_flux(gsis_t *h, double *q_conv, double *q_rad, double *p_w);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around each launch (off by default).
- * gsis_set_profiling(h, 1) clears and enables the counters; gsis_get_kernel_stats returns, for one kernel
- * kind, the summed device time in ms, the number of launches and the summed algorithmic bytes (each array
- * the kernel must read or write, counted once; 0 for kinds whose traffic is negligible). */
+ * gsis_set_profiling(h, 1) clears and enables the counters for every kind; gsis_set_profiling(h,
+ * GSIS_PROF_SELECT | (1 << kind) | ...) for the listed kinds only (fewer events in the timed stream);
+ * 0 disables.  gsis_get_kernel_stats returns, for one kernel kind, the summed device time in ms, the
+ * number of launches and the summed algorithmic bytes (each array the kernel must read or write, counted
+ * once; 0 for kinds whose traffic is negligible). */
+enum { GSIS_PROF_SELECT = 0x100 };
 enum {
     GSIS_K_GRAD = 0,     /* limited gradients of the distributions */
     GSIS_K_RESIDUAL = 1, /* kinetic residual: fluxes, relaxation source, first increment */

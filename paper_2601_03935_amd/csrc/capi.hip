@@ -1328,6 +1328,7 @@ int32_t gsis_set_profiling(gsis_t *h, int32_t on)
     h->prof.st = h->stream;
     h->prof.reset();
     h->prof.on = (on != 0);
+    h->prof.mask = (on & GSIS_PROF_SELECT) ? (unsigned)(on & 0xff) : 0xffu;
     return GSIS_OK;
 }
 

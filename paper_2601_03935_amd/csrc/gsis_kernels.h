@@ -41,6 +41,7 @@ struct MacroBufs {
 struct Prof {
     static constexpr int kKinds = 8;
     bool on = false;
+    unsigned mask = 0xffu;  // kinds timed while on
     hipStream_t st = nullptr;
     struct Rec {
         int kind;
@@ -65,7 +66,7 @@ struct Prof {
     // returns an index to pass to end(); -1 when profiling is off
     int begin(int kind, double by)
     {
-        if (!on) return -1;
+        if (!on || !(mask & (1u << kind))) return -1;
         Rec r{kind, by, get(), get()};
         (void)hipEventRecord(r.a, st);
         pend.push_back(r);

@@ -304,8 +304,14 @@ class Solver:
         self._check(self.L.gsis_get_surface_flux(self.h, _p(qc), _p(qr), _p(pw)), "gsis_get_surface_flux")
         return qc, qr, pw
 
-    def set_profiling(self, on=True):
-        self._check(self.L.gsis_set_profiling(self.h, int(bool(on))), "gsis_set_profiling")
+    def set_profiling(self, on=True, kinds=None):
+        """Per-kernel event timing: every kind, or only the named kinds (e.g. ["sweep"])."""
+        v = int(bool(on))
+        if on and kinds is not None:
+            v = 0x100
+            for k in kinds:
+                v |= 1 << KERNEL_KINDS.index(k)
+        self._check(self.L.gsis_set_profiling(self.h, v), "gsis_set_profiling")
 
     def kernel_stats(self):
         """{kind: (ms_total, launches, bytes_total)} of the kernels timed since profiling was enabled."""

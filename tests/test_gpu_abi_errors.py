@@ -108,3 +108,22 @@ def test_argument_and_order_errors():
         assert rc in (G.GSIS_OK, G.GSIS_W_NOT_CONVERGED) and rep.iters == 5 and np.isfinite(rep.eps_final)
     finally:
         L.gsis_destroy(h)
+
+
+def test_profiling_kind_selection():
+    """gsis_set_profiling with GSIS_PROF_SELECT times only the selected kernel kinds; with 1, every kind
+    of a GSIS iteration; timings and launch counts are positive where kernels ran."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1)
+    s = G.Solver(case, precision="fp32", max_inner=20)
+    s.iterate(gsis=False, n=2)
+    s.set_profiling(True, kinds=["sweep"])
+    s.iterate(gsis=True, n=2)
+    st = s.kernel_stats()
+    assert st["sweep"][1] == 2 * 8 and st["sweep"][0] > 0 and st["sweep"][2] > 0
+    assert all(st[k][1] == 0 for k in G.KERNEL_KINDS if k != "sweep")
+    s.set_profiling(True)
+    s.iterate(gsis=True, n=1)
+    st = s.kernel_stats()
+    assert all(st[k][1] > 0 for k in ("grad", "residual", "sweep", "rad", "moments", "sync", "macro"))
+    s.set_profiling(False)
+    s.close()

@@ -50,6 +50,13 @@ enum { GSIS_BC_WALL = 0, GSIS_BC_FARFIELD = 1 };
 enum { GSIS_CIS = 0, GSIS_GSIS = 1 };
 enum { GSIS_FP64 = 0, GSIS_FP32 = 1 };
 enum { GSIS_INIT_FIELDS = 0, GSIS_INIT_FREESTREAM = 1 };
+/* Point relaxation of the first-order implicit kinetic operator (Sec. 6, Eq. delta_micro).  JACOBI:
+ * kin_sweeps Jacobi sweeps (order-independent).  SGS: kin_sweeps symmetric Gauss-Seidel sweeps, the paper's
+ * forward and backward sweep, taken colour by colour over a greedy distance-1 colouring of the cells (cells
+ * in index order, each takes the smallest colour none of its face neighbours holds); the forward pass visits
+ * the colours in ascending order, the backward pass in descending order.  One SGS sweep runs in place and
+ * needs no increment buffer (the smallest memory footprint: f, its gradients and one residual buffer). */
+enum { GSIS_SWEEP_JACOBI = 0, GSIS_SWEEP_SGS = 1 };
 
 typedef struct gsis_s gsis_t;
 
@@ -78,7 +85,7 @@ typedef struct {
 
 /* Iteration options.  Defaults (gsis_default_opts): GSIS, FP32, tol 1e-6, max_outer 1000,
  * n_precond 10, cfl_meso 1e5, cfl_v 5, kin_sweeps 8, kin_omega 1, limiter_K 5, second_order 1,
- * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2, first_order_iters 0. */
+ * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2, first_order_iters 0, sweep JACOBI. */
 typedef struct {
     int32_t scheme;       /* GSIS_CIS or GSIS_GSIS */
     int32_t precision;    /* GSIS_FP64 or GSIS_FP32: storage and arithmetic of f and I */
@@ -97,6 +104,7 @@ typedef struct {
     int32_t n_sweeps;     /* Jacobi sweeps of the macro implicit operator */
     int32_t first_order_iters; /* gsis_solve: the first this many outer iterations use first-order
                                   reconstruction (start-up of strongly non-equilibrium flows); 0 = none */
+    int32_t sweep;        /* GSIS_SWEEP_JACOBI or GSIS_SWEEP_SGS (kin_sweeps counts the sweeps of either) */
 } gsis_opts;
 
 typedef struct {
@@ -145,8 +153,10 @@ int32_t gsis_set_gas(gsis_t *h, const gsis_gas *gas);
 int32_t gsis_set_flow(gsis_t *h, const gsis_flow *flow);
 
 /* Options; allocates the device state for the chosen precision (mesh, grids, gas and flow must be
- * set first, else GSIS_E_STATE).  Changing the precision discards the state (re-initialise afterwards).
- * GSIS_E_ARG for an unknown scheme or precision, negative counts (sweeps, iteration limits,
+ * set first, else GSIS_E_STATE).  Changing the precision discards the state: every call that reads the
+ * state then returns GSIS_E_STATE until gsis_init_* or gsis_set_state initialises it again.  Other
+ * changes (limiter constant, relaxation, counts) keep the state.
+ * GSIS_E_ARG for an unknown scheme, precision or sweep, negative counts (sweeps, iteration limits,
  * n_precond, first_order_iters), second_order outside {0, 1}, negative tolerances, or a non-positive
  * limiter constant, relaxation factor or CFL number. */
 int32_t gsis_set_opts(gsis_t *h, const gsis_opts *opts);

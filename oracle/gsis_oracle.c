@@ -70,12 +70,16 @@ typedef struct {
     /* options */
     double cfl_meso, cfl_macro, limK, inner_tol, cfl_v, kin_omega;
     int kin_sweeps, diss_ref, macro_order2;
+    int sweep; /* 0: Jacobi sweeps of the implicit kinetic operator; 1: colored symmetric Gauss-Seidel */
     int max_inner, n_sweeps, second_order;
     /* derived constants */
     double A[3][3], Qm[3][3], K0[3][3];
     /* adjacency */
     int64_t *cptr, *cface;
     int *csign;
+    int *color;   /* distance-1 colour of each cell (greedy, cells in index order) */
+    int ncolor;
+    int64_t *col_ptr, *col_cells; /* cells of colour q: col_cells[col_ptr[q] .. col_ptr[q+1]) */
     double *lsq; /* per slot: D coefficients (interior slots) */
     double *h;
     /* state */
@@ -181,6 +185,32 @@ static void build_mesh(orc_t *o)
         }
     }
     free(fill);
+    /* Distance-1 colouring for the ordered (Gauss-Seidel) point relaxation: cells visited in index order,
+     * each takes the smallest colour none of its face neighbours already holds. */
+    o->color = (int *)malloc(nc * sizeof(int));
+    o->ncolor = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        int used[64] = {0};
+        for (int64_t s = o->cptr[c]; s < o->cptr[c + 1]; ++s) {
+            int64_t f = o->cface[s];
+            int64_t j = (o->csign[s] > 0) ? o->fc[2 * f + 1] : o->fc[2 * f];
+            if (j >= 0 && j < c) used[o->color[j]] = 1;
+        }
+        int q = 0;
+        while (used[q]) ++q;
+        o->color[c] = q;
+        if (q + 1 > o->ncolor) o->ncolor = q + 1;
+    }
+    o->col_ptr = (int64_t *)calloc(o->ncolor + 1, sizeof(int64_t));
+    o->col_cells = (int64_t *)malloc(nc * sizeof(int64_t));
+    for (int64_t c = 0; c < nc; ++c) o->col_ptr[o->color[c] + 1]++;
+    for (int q = 0; q < o->ncolor; ++q) o->col_ptr[q + 1] += o->col_ptr[q];
+    {
+        int64_t *pos = (int64_t *)malloc(o->ncolor * sizeof(int64_t));
+        for (int q = 0; q < o->ncolor; ++q) pos[q] = o->col_ptr[q];
+        for (int64_t c = 0; c < nc; ++c) o->col_cells[pos[o->color[c]]++] = c;
+        free(pos);
+    }
     o->h = (double *)malloc(nc * sizeof(double));
     o->lsq = (double *)calloc(ns * 3, sizeof(double));
     for (int64_t c = 0; c < nc; ++c) {
@@ -664,9 +694,69 @@ static void kinetic_step(orc_t *o, double *fout, double *Iout, double *racc /* o
     /* Jacobi sweeps of the first-order implicit operator, Eq. (delta_micro) with the upwind increment
      * xi_n Delta f_ij = xi_n^+ Delta f_i + xi_n^- Delta f_j: Delta^s_i = (r_i - (1/V) sum xi_n^- S Delta^{s-1}_j) / d_i.
      * reading: boundary faces carry no increment; the update is f + omega Delta. */
+    if (o->sweep == 1) {
+        /* Symmetric Gauss-Seidel sweep of the same first-order implicit operator, the paper's forward and
+         * backward point relaxation (Sec. 6), taken colour by colour (cells of one colour have no face in
+         * common, so the order inside a colour does not matter).  With the lower part L (neighbours of a
+         * smaller colour), the upper part U (a larger colour) and the diagonal d:
+         *   forward, colours ascending:   Delta*_i = (r_i - (1/V) sum_{j in L} xi_n^- S Delta*_j) / d_i,
+         *   backward, colours descending: Delta_i = Delta*_i - (1/(V d_i)) sum_{j in U} xi_n^- S Delta_j,
+         * i.e. (D + L) D^-1 (D + U) Delta = r. */
+        const int npass = 2 * (o->kin_sweeps > 0 ? o->kin_sweeps : 1);
+        for (int ip = 0; ip < npass; ++ip) {
+            const int pass = ip & 1, first = ip < 2;
+            for (int qq = 0; qq < o->ncolor; ++qq) {
+                const int q = pass == 0 ? qq : o->ncolor - 1 - qq;
+#pragma omp parallel for schedule(static)
+                for (int64_t ic = o->col_ptr[q]; ic < o->col_ptr[q + 1]; ++ic) {
+                    const int64_t c = o->col_cells[ic];
+                    double V = o->vol[c];
+                    for (int64_t k = 0; k < nv; ++k) {
+                        double acc[4] = {0, 0, 0, 0};
+                        for (int64_t s = o->cptr[c]; s < o->cptr[c + 1]; ++s) {
+                            int64_t f = o->cface[s];
+                            int64_t j = other_cell(o, s);
+                            if (j < 0) continue;
+                            if (first && (pass == 0 ? !(o->color[j] < q) : !(o->color[j] > q))) continue;
+                            double xn = 0;
+                            for (int a = 0; a < D; ++a) xn += o->xi[k * D + a] * o->csign[s] * o->fn[f * D + a];
+                            if (xn >= 0) continue;
+                            for (int sl = 0; sl < ND; ++sl) acc[sl] += xn * o->fa[f] * fout[(j * ND + sl) * nv + k];
+                        }
+                        for (int sl = 0; sl < ND; ++sl) {
+                            const double dg = dco[c * nv + k] + (sl == DV ? d[c].radd : 0.0);
+                            double *x = &fout[(c * ND + sl) * nv + k];
+                            if (pass == 0 || !first)
+                                *x = (rr[(c * ND + sl) * nv + k] - acc[sl] / V) / dg;
+                            else
+                                *x -= acc[sl] / (V * dg);
+                        }
+                    }
+                    for (int64_t qo = 0; qo < no; ++qo) {
+                        double acc = 0;
+                        for (int64_t s = o->cptr[c]; s < o->cptr[c + 1]; ++s) {
+                            int64_t f = o->cface[s];
+                            int64_t j = other_cell(o, s);
+                            if (j < 0) continue;
+                            if (first && (pass == 0 ? !(o->color[j] < q) : !(o->color[j] > q))) continue;
+                            double on = 0;
+                            for (int a = 0; a < D; ++a) on += o->om[qo * 3 + a] * o->csign[s] * o->fn[f * D + a];
+                            if (on >= 0) continue;
+                            acc += on * o->fa[f] * Iout[j * no + qo];
+                        }
+                        double *x = &Iout[c * no + qo];
+                        if (pass == 0 || !first)
+                            *x = (rI[c * no + qo] - acc / V) / dcoR[c * no + qo];
+                        else
+                            *x -= acc / (V * dcoR[c * no + qo]);
+                    }
+                }
+            }
+        }
+    }
     double *tmp = (double *)malloc((size_t)nc * ND * nv * sizeof(double));
     double *tmpI = (double *)malloc((size_t)nc * no * sizeof(double));
-    for (int sw = 0; sw < o->kin_sweeps; ++sw) {
+    for (int sw = 0; sw < (o->sweep == 1 ? 0 : o->kin_sweeps); ++sw) {
 #pragma omp parallel for schedule(static)
         for (int64_t c = 0; c < nc; ++c) {
             double V = o->vol[c];
@@ -1525,6 +1615,7 @@ orc_t *orc_create(int D, int64_t nc, int64_t nf, const double *vol, const double
     o->kin_omega = opts[9];
     o->diss_ref = (int)opts[10];
     o->macro_order2 = (int)opts[11];
+    o->sweep = (int)opts[12];
     model_constants(o);
     build_mesh(o);
     o->f = (double *)calloc((size_t)nc * o->ND * nv, sizeof(double));
@@ -1539,7 +1630,7 @@ void orc_destroy(orc_t *o)
 {
     if (!o) return;
     void *ptrs[] = {o->vol, o->ctr, o->fc, o->fn, o->fa, o->fctr, o->bck, o->bcrho, o->bcT, o->bcu, o->xi, o->w,
-                    o->om, o->wo, o->cptr, o->cface, o->csign, o->lsq, o->h, o->f, o->I, o->bflux, o->bsurf, o->rhow};
+                    o->om, o->wo, o->cptr, o->cface, o->csign, o->color, o->col_ptr, o->col_cells, o->lsq, o->h, o->f, o->I, o->bflux, o->bsurf, o->rhow};
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(ptrs[i]);
     free(o);
 }

@@ -65,6 +65,8 @@ struct gsis_s {
     std::vector<BcDev> bf_bc;    // host copy of MeshDev::bf_bc
     bool have_mesh = false, have_vel = false, have_ord = false, have_gas = false, have_flow = false;
     bool have_opts = false, have_state = false;
+    bool have_init = false;  // f and I hold an initialised state (set by init_fields / set_state)
+    std::vector<int64_t> col_ptr;  // cells of colour q: m.col_cells[col_ptr[q] .. col_ptr[q + 1])
     int64_t nv = 0, no = 0;
     std::vector<double> xi, w, om, wo;  // om: D components per ordinate
     gsis_gas gas{};
@@ -172,6 +174,8 @@ static void free_mesh(MeshDev &m)
     dfree(m.fgeo);
     dfree(m.bcs);
     dfree(m.bf_bc);
+    dfree(m.color);
+    dfree(m.col_cells);
 }
 
 template <typename T>
@@ -366,6 +370,29 @@ static int32_t build_mesh(gsis_t *h)
     for (int64_t k = 0; k < nc * NFM; ++k)
         if (nbr[k] >= 0)
             for (int t = 0; t < NFM; ++t) nb2[k * NFM + t] = nbr[(int64_t)nbr[k] * NFM + t];
+    // Distance-1 colouring for the colored Gauss-Seidel sweeps: cells visited in index order, each takes the
+    // smallest colour none of its face neighbours already holds; then the cells grouped by colour (ascending
+    // cell index inside a colour).
+    std::vector<int> color(nc, 0), col_cells(nc);
+    int ncolor = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        unsigned used = 0;
+        for (int s = 0; s < nfc[c]; ++s) {
+            const int j = nbr[c * NFM + s];
+            if (j >= 0 && j < c) used |= 1u << color[j];
+        }
+        int q = 0;
+        while (used & (1u << q)) ++q;
+        color[c] = q;
+        ncolor = std::max(ncolor, q + 1);
+    }
+    h->col_ptr.assign(ncolor + 1, 0);
+    for (int64_t c = 0; c < nc; ++c) h->col_ptr[color[c] + 1]++;
+    for (int q = 0; q < ncolor; ++q) h->col_ptr[q + 1] += h->col_ptr[q];
+    {
+        std::vector<int64_t> pos(h->col_ptr.begin(), h->col_ptr.end() - 1);
+        for (int64_t c = 0; c < nc; ++c) col_cells[pos[color[c]]++] = (int)c;
+    }
     std::vector<double> lsq(nc * NFM * D);
     for (int64_t k = 0; k < nc * NFM; ++k)
         for (int a = 0; a < D; ++a) lsq[k * D + a] = geo[k * 4 * D + 3 * D + a];
@@ -374,7 +401,8 @@ static int32_t build_mesh(gsis_t *h)
               upload(m.h, hh) && upload(m.eps2, eps2) && upload(m.nfc, nfc) && upload(m.bf_face, bf_face) &&
               upload(m.bf_cell, bf_cell) && upload(m.bf_tag, bf_tag) && upload(m.bf_n, bf_n) &&
               upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.f_L, fL) && upload(m.f_R, fR) &&
-              upload(m.fgeo, fgeo) && upload(m.bcs, bcs) && upload(m.bf_bc, bf_bc);
+              upload(m.fgeo, fgeo) && upload(m.bcs, bcs) && upload(m.bf_bc, bf_bc) && upload(m.color, color) &&
+              upload(m.col_cells, col_cells);
     if (!ok) return fail(h, GSIS_E_OOM, "device allocation of mesh tables failed");
     return GSIS_OK;
 }
@@ -443,6 +471,35 @@ static void free_macro(MacroBufs &B)
 static int ndist(int D) { return D == 3 ? 3 : 4; }
 static int coef_sz(int D) { return D + 6 + 3 * (5 + 3 * D); }
 
+// Distribution-sized buffers beyond f, its gradients and r that the chosen relaxation needs: Jacobi sweeps
+// two increment buffers (the last sweep writes f in place), no sweeps a second f; colored Gauss-Seidel with
+// one symmetric sweep none (it runs in place in r), with more sweeps one increment buffer.  Buffers the
+// options no longer need are released, so that switching the relaxation keeps the state.
+struct KinPlan {
+    bool dl0, dl1, f2;
+};
+static KinPlan kin_plan(const gsis_opts &o)
+{
+    if (o.sweep == GSIS_SWEEP_SGS) return {o.kin_sweeps > 1, false, false};
+    return {o.kin_sweeps > 0, o.kin_sweeps > 0, o.kin_sweeps == 0};
+}
+template <typename T>
+static bool plan_kin(gsis_t *h, KinBufs<T> &B)
+{
+    const int D = h->hm.D, ND = ndist(D);
+    const size_t nc = h->hm.nc, nv = h->nv;
+    const KinPlan pl = kin_plan(h->opts);
+    bool ok = true;
+    auto want = [&](T *&p, bool need) {
+        if (need && !p) p = dalloc<T>(nc * ND * nv, ok);
+        if (!need) dfree(p);
+    };
+    want(B.dl0, pl.dl0);
+    want(B.dl1, pl.dl1);
+    want(B.f2, pl.f2);
+    return ok;
+}
+
 template <typename T>
 static bool alloc_kin(gsis_t *h, KinBufs<T> &B)
 {
@@ -450,11 +507,9 @@ static bool alloc_kin(gsis_t *h, KinBufs<T> &B)
     const size_t nc = h->hm.nc, nv = h->nv, no = h->no, nbf = h->m.nbf;
     bool ok = true;
     B.f = dalloc<T>(nc * ND * nv, ok);
-    B.f2 = dalloc<T>(nc * ND * nv, ok);
     B.gf = dalloc<T>(nc * ND * D * nv, ok);
     B.r = dalloc<T>(nc * ND * nv, ok);
-    B.dl0 = dalloc<T>(nc * ND * nv, ok);
-    B.dl1 = dalloc<T>(nc * ND * nv, ok);
+    if (ok) ok = plan_kin(h, B);
     B.I = dalloc<T>(nc * no, ok);
     B.I2 = dalloc<T>(nc * no, ok);
     B.gI = dalloc<T>(nc * D * no, ok);
@@ -548,6 +603,7 @@ static void free_state(gsis_t *h)
     dfree(h->cellbuf);
     dfree(h->red);
     h->have_state = false;
+    h->have_init = false;
     h->mom0_valid = false;
 }
 
@@ -571,6 +627,9 @@ static KinOpts kopts(const gsis_t *h)
     o.limK = h->opts.limiter_K;
     o.kin_sweeps = h->opts.kin_sweeps;
     o.second_order = h->opts.second_order;
+    o.sweep = h->opts.sweep;
+    o.col_ptr = h->col_ptr.data();
+    o.ncolor = (int)h->col_ptr.size() - 1;
     return o;
 }
 
@@ -854,6 +913,7 @@ void gsis_default_opts(gsis_opts *o)
     o->max_inner = 100;
     o->first_order_iters = 0;
     o->n_sweeps = 2;
+    o->sweep = GSIS_SWEEP_JACOBI;
 }
 
 int32_t gsis_create(int32_t device, gsis_t **out)
@@ -1023,13 +1083,15 @@ int32_t gsis_set_opts(gsis_t *h, const gsis_opts *o)
         o->kin_sweeps < 0 || o->max_inner < 0 || o->max_outer < 0 || o->n_precond < 0 || o->n_sweeps < 0 ||
         o->first_order_iters < 0 || (o->second_order != 0 && o->second_order != 1) || !(o->tol >= 0) ||
         !(o->inner_tol >= 0) || !(o->limiter_K > 0) || !(o->kin_omega > 0) || !(o->cfl_v > 0) ||
-        !(o->cfl_meso > 0) || !(o->cfl_macro > 0))
+        !(o->cfl_meso > 0) || !(o->cfl_macro > 0) || (o->sweep != GSIS_SWEEP_JACOBI && o->sweep != GSIS_SWEEP_SGS))
         return fail(h, GSIS_E_ARG, "gsis_set_opts: invalid options");
     // the kinetic kernels index waves over (cell, 64-velocity chunk) pairs with 32-bit integers
     if (h->hm.nc * ((h->nv + 63) / 64 + 1) > (int64_t)(INT32_MAX / 8))
         return fail(h, GSIS_E_ARG, "gsis_set_opts: mesh x velocity grid too large for one device");
     (void)hipSetDevice(h->device);
-    const bool realloc = !h->have_state || o->precision != h->prec || o->limiter_K != h->opts.limiter_K;
+    // a new precision reallocates the state (which must then be initialised again); other changes keep it
+    const bool realloc = !h->have_state || o->precision != h->prec;
+    const bool newK = !realloc && o->limiter_K != h->opts.limiter_K;
     h->opts = *o;
     h->have_opts = true;
     if (realloc) {
@@ -1044,7 +1106,18 @@ int32_t gsis_set_opts(gsis_t *h, const gsis_opts *o)
             return fail(h, GSIS_E_OOM, "gsis_set_opts: device allocation failed");
         }
         h->have_state = true;
+        return GSIS_OK;
     }
+    if (newK) {
+        std::vector<double> eps2(h->hm.nc);
+        for (int64_t c = 0; c < h->hm.nc; ++c)
+            eps2[c] = std::pow(o->limiter_K * std::pow(h->hm.vol[c], 1.0 / h->hm.D), 3);
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        HIPCHECK(h, hipMemcpy(h->m.eps2, eps2.data(), eps2.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    const bool ok = (h->prec == GSIS_FP32) ? plan_kin(h, h->Bf) : plan_kin(h, h->Bd);
+    if (!ok) return fail(h, GSIS_E_OOM, "gsis_set_opts: device allocation of the relaxation buffers failed");
     return GSIS_OK;
 }
 
@@ -1073,6 +1146,7 @@ int32_t gsis_init_fields(gsis_t *h, const double *rho, const double *u, const do
     else sync_T(h, h->Bd, h->sp, 1);
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     h->mom0_valid = false;
+    h->have_init = true;
     return GSIS_OK;
 }
 
@@ -1087,13 +1161,15 @@ int32_t gsis_set_state(gsis_t *h, const double *f, const double *I)
     if (!h->have_state) return fail(h, GSIS_E_STATE, "gsis_set_state: call gsis_set_opts first");
     (void)hipSetDevice(h->device);
     h->mom0_valid = false;
-    return (h->prec == GSIS_FP32) ? set_state_T(h, h->Bf, f, I) : set_state_T(h, h->Bd, f, I);
+    const int32_t rc = (h->prec == GSIS_FP32) ? set_state_T(h, h->Bf, f, I) : set_state_T(h, h->Bd, f, I);
+    if (rc == GSIS_OK) h->have_init = true;
+    return rc;
 }
 
 int32_t gsis_get_state(gsis_t *h, double *f, double *I)
 {
     if (!h) return GSIS_E_ARG;
-    if (!h->have_state) return fail(h, GSIS_E_STATE, "gsis_get_state: no state");
+    if (!h->have_state || !h->have_init) return fail(h, GSIS_E_STATE, "gsis_get_state: no initialised state");
     (void)hipSetDevice(h->device);
     return (h->prec == GSIS_FP32) ? get_state_T(h, h->Bf, f, I) : get_state_T(h, h->Bd, f, I);
 }
@@ -1101,7 +1177,8 @@ int32_t gsis_get_state(gsis_t *h, double *f, double *I)
 static int32_t check_ready(gsis_t *h, const char *who)
 {
     if (!h) return GSIS_E_ARG;
-    if (!h->have_state) return fail(h, GSIS_E_STATE, std::string(who) + ": call gsis_set_opts and initialise first");
+    if (!h->have_state || !h->have_init)
+        return fail(h, GSIS_E_STATE, std::string(who) + ": call gsis_set_opts and initialise the state first");
     (void)hipSetDevice(h->device);
     return GSIS_OK;
 }

@@ -53,6 +53,9 @@ struct Phys {
 struct KinOpts {
     double cfl_meso, cfl_v, kin_omega, limK;
     int kin_sweeps, second_order;
+    int sweep;               // 0: Jacobi sweeps; 1: colored symmetric Gauss-Seidel sweeps
+    const int64_t *col_ptr;  // host: cells of colour q are col_cells[col_ptr[q] .. col_ptr[q + 1])
+    int ncolor;
 };
 
 // Boundary tag data on the device.
@@ -77,6 +80,8 @@ struct MeshDev {
     double *lsq = nullptr;  // per slot: the D least-squares gradient weights of geo, packed (cell gradients)
     double *vol = nullptr, *h = nullptr, *eps2 = nullptr;
     int *nfc = nullptr;
+    // distance-1 colouring (greedy, cells in index order): colour per cell, and the cells sorted by colour
+    int *color = nullptr, *col_cells = nullptr;
     // boundary faces
     int *bf_face = nullptr, *bf_cell = nullptr, *bf_tag = nullptr;
     double *bf_n = nullptr, *bf_dxc = nullptr;  // outward unit normal, x_f - x_c

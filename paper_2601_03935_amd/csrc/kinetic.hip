@@ -447,7 +447,7 @@ __global__ __launch_bounds__(256) void k_residual(const T *__restrict__ f, const
                 fout[o] = fc[d] + omega * (rr / dd);
             } else {
                 r[o] = rr;
-                dl[o] = rr / dd;
+                if (dl) dl[o] = rr / dd;
             }
         }
     }
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(256) void k_residual_v(const T *__restrict__ f, con
                 __builtin_nontemporal_store(fc[d] + omega * (rr[d] / dd[d]), (V *)(fout + o));
             } else {
                 __builtin_nontemporal_store(rr[d], (V *)(r + o));
-                __builtin_nontemporal_store(rr[d] / dd[d], (V *)(dl + o));
+                if (dl) __builtin_nontemporal_store(rr[d] / dd[d], (V *)(dl + o));
             }
         }
     }
@@ -744,6 +744,194 @@ __global__ __launch_bounds__(256) void k_sweep_v(const T *__restrict__ r, const 
     }
 }
 
+// vector load / store of VW consecutive values (16-byte aligned when VW > 1; any alignment for VW = 1)
+template <typename T, int VW>
+__device__ __forceinline__ vec_t<T, VW> ldv(const T *p)
+{
+    if constexpr (VW == 1) {
+        vec_t<T, 1> v;
+        v[0] = p[0];
+        return v;
+    } else {
+        return *(const vec_t<T, VW> *)p;
+    }
+}
+template <typename T, int VW>
+__device__ __forceinline__ void stv(T *p, const vec_t<T, VW> v)
+{
+    if constexpr (VW == 1)
+        p[0] = v[0];
+    else
+        *(vec_t<T, VW> *)p = v;
+}
+
+// ------------------------------------------------------------------ colored symmetric Gauss-Seidel passes
+// The paper's forward and backward point relaxation of the first-order implicit operator (Sec. 6), taken
+// colour by colour: cells of one colour share no face, so one launch updates a whole colour.  With
+// a_j = xi_n^- S / V on the face to neighbour j (xi_n < 0) and d the diagonal of the Jacobi kernels:
+//   MODE 0, first forward pass:   D_c = (r_c - sum_{j lower} a_j D_j) / d
+//   MODE 1, first backward pass:  D_c = D_c - (1 / d) sum_{j upper} a_j D_j
+//   MODE 2, later passes:         D_c = (r_c - sum_{all j} a_j D_j) / d
+// (lower / upper: the neighbour's colour is below / above the colour q of the launch).  The first symmetric
+// sweep starts from D = 0, so MODE 0 + MODE 1 is (D + L) D^-1 (D + U) D = r and needs no separate r: with
+// one sweep r and dl are the same buffer (hence no __restrict__ on them).  With update_f, f_c += omega D_c.
+// One wave per (cell of the colour list, chunk of 64 VW velocities), as the Jacobi kernel.
+template <typename T, int D, int NFM, int VW, int MODE>
+__global__ __launch_bounds__(256) void k_sgs_v(const T *r, T *dl, T *__restrict__ f, const T *__restrict__ coef,
+                                               const T *__restrict__ xiT, const MeshDev m, const int64_t nv,
+                                               const int nchunk, const int cgroup, const T cflv_fac, const T omega,
+                                               const int *__restrict__ cells, const int ncl, const int q,
+                                               const int update_f)
+{
+    using V = vec_t<T, VW>;
+    constexpr int ND = (D == 3) ? 3 : 4;
+    const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
+    int idx, ch;
+    if (!wave_cell_chunk(w, ncl, nchunk, cgroup, idx, ch)) return;
+    const int64_t k = ((int64_t)ch * kWave + (threadIdx.x & 63)) * VW;
+    const int c = uni_i(cells[idx]);
+    int nb[NFM];
+    bool use[NFM];
+    T nsv[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = m.nbr[(int64_t)c * NFM + s];
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) nsv[s][a] = (T)g[a];
+        bool u = nb[s] >= 0;
+        if (u && MODE != 2) {
+            const int qj = m.color[nb[s]];
+            u = (MODE == 0) ? (qj < q) : (qj > q);
+        }
+        use[s] = u;
+    }
+    const T base = coef[(int64_t)c * coef_size(D) + D + 1] + coef[(int64_t)c * coef_size(D) + D];
+    const T radd = coef[(int64_t)c * coef_size(D) + D + 5];
+    if (k >= nv) return;
+    V x[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = ldv<T, VW>(xiT + a * nv + k);
+    V nbv[NFM][ND];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s)
+        if (use[s]) {
+#pragma unroll
+            for (int d = 0; d < ND; ++d) nbv[s][d] = ldv<T, VW>(dl + ((int64_t)nb[s] * ND + d) * nv + k);
+        }
+    V own[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+        own[d] = ldv<T, VW>((MODE == 1 ? (const T *)dl : r) + ((int64_t)c * ND + d) * nv + k);
+    V acc[ND], dsum = T(0);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[d] = T(0);
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        if (nb[s] == INT32_MIN) continue;
+        V xn = T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            if (xn[e] > T(0)) {
+                dsum[e] += xn[e];
+            } else if (xn[e] < T(0) && use[s]) {
+#pragma unroll
+                for (int d = 0; d < ND; ++d) acc[d][e] += xn[e] * nbv[s][d][e];
+            }
+        }
+    }
+    V inv0, inv2;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+        const T dc = base + dsum[e] * cflv_fac;
+        inv0[e] = T(1) / dc;
+        inv2[e] = T(1) / (dc + radd);
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int64_t o = ((int64_t)c * ND + d) * nv + k;
+        const V iv = (d == 2) ? inv2 : inv0;
+        const V dn = (MODE == 1) ? own[d] - acc[d] * iv : (own[d] - acc[d]) * iv;
+        stv<T, VW>(dl + o, dn);
+        if (update_f) {
+            V fo;
+            fo = ldv<T, VW>(f + o);
+            fo = fo + omega * dn;
+            stv<T, VW>(f + o, fo);
+        }
+    }
+}
+
+// Ordinate form of the colored symmetric Gauss-Seidel pass (same modes), packed like the other ordinate
+// kernels: 2^lsh lanes per cell of the colour list, each lane VW consecutive ordinates per step.
+template <typename T, int D, int NFM, int VW, int MODE>
+__global__ __launch_bounds__(256) void k_sgs_Iv(const T *r, T *dl, T *__restrict__ I, const T *__restrict__ coef,
+                                                const T *__restrict__ om, const MeshDev m, const int64_t no,
+                                                const int lsh, const T cflv_fac, const T omega, const T keff,
+                                                const int *__restrict__ cells, const int ncl, const int q,
+                                                const int update_I)
+{
+    using V = vec_t<T, VW>;
+    const int64_t gi = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int64_t idx = gi >> lsh;
+    if (idx >= ncl) return;
+    const int lg = (int)(gi & ((1 << lsh) - 1));
+    const int64_t c = cells[idx];
+    int nb[NFM];
+    bool use[NFM];
+    T nsv[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = m.nbr[c * NFM + s];
+        const double *g = m.geo + (c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) nsv[s][a] = (T)g[a];
+        bool u = nb[s] >= 0;
+        if (u && MODE != 2) {
+            const int qj = m.color[nb[s]];
+            u = (MODE == 0) ? (qj < q) : (qj > q);
+        }
+        use[s] = u;
+    }
+    const T base = coef[c * coef_size(D) + D + 4] + keff;
+    for (int64_t qo = (int64_t)lg * VW; qo < no; qo += (int64_t)VW << lsh) {
+        V nd[NFM];
+#pragma unroll
+        for (int s = 0; s < NFM; ++s)
+            if (use[s]) nd[s] = ldv<T, VW>(dl + (int64_t)nb[s] * no + qo);
+        const int64_t ix = c * no + qo;
+        V ov;
+        ov = ldv<T, VW>((MODE == 1 ? (const T *)dl : r) + ix);
+        V dn;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            T acc = T(0), dsum = T(0);
+#pragma unroll
+            for (int s = 0; s < NFM; ++s) {
+                if (nb[s] == INT32_MIN) continue;
+                T on = T(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) on += om[(qo + e) * D + a] * nsv[s][a];
+                if (on > T(0))
+                    dsum += on;
+                else if (on < T(0) && use[s])
+                    acc += on * nd[s][e];
+            }
+            const T dc = base + dsum * cflv_fac;
+            dn[e] = (MODE == 1) ? ov[e] - acc / dc : (ov[e] - acc) / dc;
+        }
+        stv<T, VW>(dl + ix, dn);
+        if (update_I) {
+            V io;
+            io = ldv<T, VW>(I + ix);
+            io = io + omega * dn;
+            stv<T, VW>(I + ix, io);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ radiation: gradients, residual, sweep
 template <typename T, int D, int NFM>
 __global__ __launch_bounds__(256) void k_grad_I(const T *__restrict__ I, T *__restrict__ gI, const MeshDev m,
@@ -879,7 +1067,7 @@ __global__ __launch_bounds__(256) void k_residual_I(const T *__restrict__ I, con
             Iout[idx] = Ic + omega * (rr / dcoef);
         } else {
             r[idx] = rr;
-            dl[idx] = rr / dcoef;
+            if (dl) dl[idx] = rr / dcoef;
         }
     }
 }
@@ -1090,7 +1278,7 @@ __global__ __launch_bounds__(256) void k_residual_Iv(const T *__restrict__ I, co
             *(V *)(Iout + idx) = Ic + omega * (rr / dd);
         } else {
             *(V *)(r + idx) = rr;
-            *(V *)(dl + idx) = rr / dd;
+            if (dl) *(V *)(dl + idx) = rr / dd;
         }
     }
 }
@@ -1633,6 +1821,65 @@ void launch_scale(T *f, int64_t n, const double *num, const double *den, hipStre
 template void launch_scale<float>(float *, int64_t, const double *, const double *, hipStream_t);
 template void launch_scale<double>(double *, int64_t, const double *, const double *, hipStream_t);
 
+// one colored Gauss-Seidel pass over the cells cl[0..ncl) of colour q (mode 0, 1 or 2 of k_sgs_v)
+template <typename T, int D, int NFM, int VW>
+static void sgs_pass_vw(int mode, const T *r, T *dl, T *f, const T *coef, const T *xiT, const MeshDev &m,
+                        int64_t nv, T fac, T om, const int *cl, int ncl, int q, int upd, hipStream_t st)
+{
+    const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
+    const dim3 g((unsigned)(((int64_t)ncl * nchunk + 3) / 4)), blk(256);
+    const int cg = chunk_group(CG::sweep, D, ncl);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_sgs_v<T, D, NFM, VW, 0>), g, blk, 0, st, r, dl, f, coef, xiT, m, nv, nchunk, cg, fac, om,
+                           cl, ncl, q, upd);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_sgs_v<T, D, NFM, VW, 1>), g, blk, 0, st, r, dl, f, coef, xiT, m, nv, nchunk, cg, fac, om,
+                           cl, ncl, q, upd);
+    else
+        hipLaunchKernelGGL((k_sgs_v<T, D, NFM, VW, 2>), g, blk, 0, st, r, dl, f, coef, xiT, m, nv, nchunk, cg, fac, om,
+                           cl, ncl, q, upd);
+}
+
+template <typename T, int D, int NFM>
+static void sgs_pass(int mode, const T *r, T *dl, T *f, const T *coef, const T *xiT, const MeshDev &m, int64_t nv,
+                     T fac, T om, const int *cl, int ncl, int q, int upd, hipStream_t st)
+{
+    constexpr int VW = 16 / sizeof(T);
+    if (nv % VW == 0)
+        sgs_pass_vw<T, D, NFM, VW>(mode, r, dl, f, coef, xiT, m, nv, fac, om, cl, ncl, q, upd, st);
+    else
+        sgs_pass_vw<T, D, NFM, 1>(mode, r, dl, f, coef, xiT, m, nv, fac, om, cl, ncl, q, upd, st);
+}
+
+template <typename T, int D, int NFM, int VW>
+static void sgs_pass_I_vw(int mode, const T *r, T *dl, T *I, const T *coef, const T *om_, const MeshDev &m,
+                          int64_t no, T fac, T om, T keff, const int *cl, int ncl, int q, int upd, hipStream_t st)
+{
+    const int lsh = ord_lsh(no, VW);
+    const dim3 g((unsigned)packed_blocks(ncl, lsh)), blk(256);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_sgs_Iv<T, D, NFM, VW, 0>), g, blk, 0, st, r, dl, I, coef, om_, m, no, lsh, fac, om, keff,
+                           cl, ncl, q, upd);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_sgs_Iv<T, D, NFM, VW, 1>), g, blk, 0, st, r, dl, I, coef, om_, m, no, lsh, fac, om, keff,
+                           cl, ncl, q, upd);
+    else
+        hipLaunchKernelGGL((k_sgs_Iv<T, D, NFM, VW, 2>), g, blk, 0, st, r, dl, I, coef, om_, m, no, lsh, fac, om, keff,
+                           cl, ncl, q, upd);
+}
+
+template <typename T, int D, int NFM>
+static void sgs_pass_I(int mode, const T *r, T *dl, T *I, const T *coef, const T *om_, const MeshDev &m, int64_t no,
+                       T fac, T om, T keff, const int *cl, int ncl, int q, int upd, hipStream_t st)
+{
+    if (no <= 0) return;
+    constexpr int VW = 16 / sizeof(T);
+    if (no % VW == 0)
+        sgs_pass_I_vw<T, D, NFM, VW>(mode, r, dl, I, coef, om_, m, no, fac, om, keff, cl, ncl, q, upd, st);
+    else
+        sgs_pass_I_vw<T, D, NFM, 1>(mode, r, dl, I, coef, om_, m, no, fac, om, keff, cl, ncl, q, upd, st);
+}
+
 template <typename T, int D, int NFM>
 void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpts &o, int64_t nv, int64_t no,
                     hipStream_t st, Prof *pf)
@@ -1658,55 +1905,89 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
                            B.rhow, m, nv);
     P.end(ev);
     const int ks = o.kin_sweeps;
-    ev = P.begin(1, ks == 0 ? cv * (2 + D) : cv * (3 + D));
+    ev = P.begin(1, (ks == 0 || o.sweep == 1) ? cv * (2 + D) : cv * (3 + D));
     constexpr int VW = 16 / sizeof(T);
     // vector kernels with one wave per (cell, chunk of kWave * VW velocities)
     const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
     const dim3 chunk_grid((unsigned)((m.nc * nchunk + 3) / 4));
+    const bool sgs = (o.sweep == 1);
+    const bool direct = (!sgs && ks == 0);  // no sweeps: the residual writes f + omega r / d into f2
     if (nv % VW == 0)
         hipLaunchKernelGGL((k_residual_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.f, B.gf, B.coef, B.xiT, B.rhow,
-                           B.r, B.dl0, ks == 0 ? B.f2 : nullptr, m, nv, nchunk, chunk_group(CG::residual, D, m.nc),
-                           fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
+                           B.r, sgs ? nullptr : B.dl0, direct ? B.f2 : nullptr, m, nv, nchunk,
+                           chunk_group(CG::residual, D, m.nc), fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
     else
-        hipLaunchKernelGGL((k_residual<T, D, NFM>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xi, B.rhow, B.r, B.dl0,
-                           ks == 0 ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
+        hipLaunchKernelGGL((k_residual<T, D, NFM>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xi, B.rhow, B.r,
+                           sgs ? nullptr : B.dl0, direct ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r,
+                           (T)p.d_v);
     P.end(ev);
     ev = P.begin(3, ks == 0 ? co * (2 + D) : co * (3 + D));
     const bool ovec = (no % VW == 0);
     const int olsh = ord_lsh(no, VW);
     const dim3 ogrid((unsigned)packed_blocks(m.nc, olsh));
     if (ovec)
-        hipLaunchKernelGGL((k_residual_Iv<T, D, NFM, VW>), ogrid, blk, 0, st, B.I, B.gI, B.coef, B.om, B.rI, B.dI0,
-                           ks == 0 ? B.I2 : nullptr, m, no, olsh, fac, om, (T)p.keff, (T)p.sigma_R);
+        hipLaunchKernelGGL((k_residual_Iv<T, D, NFM, VW>), ogrid, blk, 0, st, B.I, B.gI, B.coef, B.om, B.rI,
+                           sgs ? nullptr : B.dI0, direct ? B.I2 : nullptr, m, no, olsh, fac, om, (T)p.keff,
+                           (T)p.sigma_R);
     else
-        hipLaunchKernelGGL((k_residual_I<T, D, NFM>), grid, blk, 0, st, B.I, B.gI, B.coef, B.om, B.rI, B.dI0,
-                           ks == 0 ? B.I2 : nullptr, m, no, fac, om, (T)p.keff, (T)p.sigma_R);
+        hipLaunchKernelGGL((k_residual_I<T, D, NFM>), grid, blk, 0, st, B.I, B.gI, B.coef, B.om, B.rI,
+                           sgs ? nullptr : B.dI0, direct ? B.I2 : nullptr, m, no, fac, om, (T)p.keff, (T)p.sigma_R);
     P.end(ev);
+    if (o.sweep == 1) {
+        // colored symmetric Gauss-Seidel: nsw symmetric sweeps, each a forward pass over the colours in
+        // ascending order and a backward pass in descending order; one sweep runs in place in r
+        const int nsw = ks > 0 ? ks : 1;
+        T *dbuf = (nsw == 1) ? B.r : B.dl0;
+        T *dIbuf = (nsw == 1) ? B.rI : B.dI0;
+        for (int sw = 0; sw < nsw; ++sw)
+            for (int pass = 0; pass < 2; ++pass)
+                for (int qq = 0; qq < o.ncolor; ++qq) {
+                    const int q = (pass == 0) ? qq : o.ncolor - 1 - qq;
+                    const int mode = (sw == 0) ? pass : 2;
+                    const int last = (sw == nsw - 1 && pass == 1) ? 1 : 0;
+                    const int ncl = (int)(o.col_ptr[q + 1] - o.col_ptr[q]);
+                    if (ncl <= 0) continue;
+                    const int *cl = m.col_cells + o.col_ptr[q];
+                    const double own = (double)ncl * nv * ND * es;
+                    ev = P.begin(2, own * (last ? 4 : 2));
+                    sgs_pass<T, D, NFM>(mode, B.r, dbuf, B.f, B.coef, B.xiT, m, nv, fac, om, cl, ncl, q, last, st);
+                    P.end(ev);
+                    ev = P.begin(3, (double)ncl * no * es * (last ? 4 : 2));
+                    sgs_pass_I<T, D, NFM>(mode, B.rI, dIbuf, B.I, B.coef, B.om, m, no, fac, om, (T)p.keff, cl, ncl, q,
+                                          last, st);
+                    P.end(ev);
+                }
+        return;
+    }
+    // Jacobi sweeps; the last one writes f + omega Delta in place (each element is read and written by the
+    // same lane, and no sweep reads f of another cell)
     T *din = B.dl0, *dout = B.dl1, *dIin = B.dI0, *dIout = B.dI1;
     for (int s = 0; s < ks; ++s) {
         const bool last = (s == ks - 1);
         ev = P.begin(2, last ? 4 * cv : 3 * cv);
         if (nv % VW == 0)
             hipLaunchKernelGGL((k_sweep_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.r, din, dout, B.f,
-                               last ? B.f2 : nullptr, B.coef, B.xiT, m, nv, nchunk,
+                               last ? B.f : nullptr, B.coef, B.xiT, m, nv, nchunk,
                                chunk_group(CG::sweep, D, m.nc), fac, om);
         else
-            hipLaunchKernelGGL((k_sweep<T, D, NFM>), grid, blk, 0, st, B.r, din, dout, B.f, last ? B.f2 : nullptr,
+            hipLaunchKernelGGL((k_sweep<T, D, NFM>), grid, blk, 0, st, B.r, din, dout, B.f, last ? B.f : nullptr,
                                B.coef, B.xi, m, nv, fac, om);
         P.end(ev);
         ev = P.begin(3, last ? 4 * co : 3 * co);
         if (ovec)
             hipLaunchKernelGGL((k_sweep_Iv<T, D, NFM, VW>), ogrid, blk, 0, st, B.rI, dIin, dIout, B.I,
-                               last ? B.I2 : nullptr, B.coef, B.om, m, no, olsh, fac, om, (T)p.keff);
+                               last ? B.I : nullptr, B.coef, B.om, m, no, olsh, fac, om, (T)p.keff);
         else
             hipLaunchKernelGGL((k_sweep_I<T, D, NFM>), grid, blk, 0, st, B.rI, dIin, dIout, B.I,
-                               last ? B.I2 : nullptr, B.coef, B.om, m, no, fac, om, (T)p.keff);
+                               last ? B.I : nullptr, B.coef, B.om, m, no, fac, om, (T)p.keff);
         P.end(ev);
         std::swap(din, dout);
         std::swap(dIin, dIout);
     }
-    std::swap(B.f, B.f2);
-    std::swap(B.I, B.I2);
+    if (ks == 0) {
+        std::swap(B.f, B.f2);
+        std::swap(B.I, B.I2);
+    }
 }
 
 template <typename T, int D>

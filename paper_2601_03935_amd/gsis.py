@@ -21,6 +21,7 @@ GSIS_W_NOT_CONVERGED = 1
 GSIS_BC_WALL, GSIS_BC_FARFIELD = 0, 1
 GSIS_CIS, GSIS_GSIS = 0, 1
 GSIS_FP64, GSIS_FP32 = 0, 1
+GSIS_SWEEP_JACOBI, GSIS_SWEEP_SGS = 0, 1
 
 # every entry point declared in include/gsis.h
 EXPORTS = [
@@ -51,7 +52,8 @@ class gsis_opts(C.Structure):
                 ("n_precond", C.c_int32), ("cfl_meso", C.c_double), ("cfl_v", C.c_double),
                 ("kin_sweeps", C.c_int32), ("kin_omega", C.c_double), ("limiter_K", C.c_double),
                 ("second_order", C.c_int32), ("cfl_macro", C.c_double), ("inner_tol", C.c_double),
-                ("max_inner", C.c_int32), ("n_sweeps", C.c_int32), ("first_order_iters", C.c_int32)]
+                ("max_inner", C.c_int32), ("n_sweeps", C.c_int32), ("first_order_iters", C.c_int32),
+                ("sweep", C.c_int32)]
 
 
 class gsis_report(C.Structure):
@@ -126,6 +128,8 @@ def default_opts(**kw) -> gsis_opts:
             v = {"fp32": GSIS_FP32, "fp64": GSIS_FP64}[v]
         if k == "scheme" and isinstance(v, str):
             v = {"cis": GSIS_CIS, "gsis": GSIS_GSIS}[v]
+        if k == "sweep" and isinstance(v, str):
+            v = {"jacobi": GSIS_SWEEP_JACOBI, "sgs": GSIS_SWEEP_SGS}[v]
         setattr(o, k, v)
     return o
 
@@ -212,14 +216,16 @@ class Solver:
         return its, np.asarray(hist), ok
 
     def set_opts(self, **kw):
-        """Change options between iterations; the state is kept unless the precision or the limiter
-        constant changes (those reallocate and need a new initial state)."""
+        """Change options between iterations; the state is kept unless the precision changes (that
+        reallocates and needs a new initial state)."""
         o = self.opts
         for k, v in kw.items():
             if k == "precision" and isinstance(v, str):
                 v = {"fp32": GSIS_FP32, "fp64": GSIS_FP64}[v]
             if k == "scheme" and isinstance(v, str):
                 v = {"cis": GSIS_CIS, "gsis": GSIS_GSIS}[v]
+            if k == "sweep" and isinstance(v, str):
+                v = {"jacobi": GSIS_SWEEP_JACOBI, "sgs": GSIS_SWEEP_SGS}[v]
             setattr(o, k, v)
         self._check(self.L.gsis_set_opts(self.h, C.byref(o)), "gsis_set_opts")
 
@@ -333,4 +339,4 @@ def oracle_opts(opts: gsis_opts) -> dict:
     """The oracle option set equivalent to a library option set (for parity runs)."""
     return dict(cfl_meso=opts.cfl_meso, cfl_macro=opts.cfl_macro, limiter_K=opts.limiter_K, inner_tol=opts.inner_tol,
                 max_inner=opts.max_inner, n_sweeps=opts.n_sweeps, second_order=opts.second_order, cfl_v=opts.cfl_v,
-                kin_sweeps=opts.kin_sweeps, kin_omega=opts.kin_omega, diss_ref=1, macro_order2=0)
+                kin_sweeps=opts.kin_sweeps, kin_omega=opts.kin_omega, diss_ref=1, macro_order2=0, sweep=opts.sweep)

@@ -26,15 +26,31 @@ def _relerr(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-def _field_rel_l2(Fg, Fo, vol, names):
-    """Relative L2 per field with the volume weight; fields that vanish use a unit floor."""
+def _u_scale(case):
+    """Velocity scale of a case: the largest wall or free-stream speed, or the sound speed sqrt(gamma T)
+    of the reference state when nothing moves (the 1D Fourier flow)."""
+    _, _, _, u = case.bc_arrays()
+    s = float(np.sqrt((u ** 2).sum(axis=1)).max()) if len(u) else 0.0
+    return s if s > 0 else float(np.sqrt(case.gas.gamma * case.flow.T_inf))
+
+
+def _field_rel_l2(Fg, Fo, vol, names, u_scale):
+    """Relative L2 per field with the volume weight.  Velocity components are measured against the case's
+    velocity scale (the denominator is at least u_scale ||1||_V); other fields that vanish use a floor of
+    1e-2 ||1||_V.  Every field of both sides must be finite."""
+    assert np.isfinite(Fg).all() and np.isfinite(Fo).all(), "non-finite field"
     out = {}
     w = vol / vol.sum()
     for i, n in enumerate(names):
         num = np.sqrt((w * (Fg[:, i] - Fo[:, i]) ** 2).sum())
-        den = max(np.sqrt((w * Fo[:, i] ** 2).sum()), 1.0 if n[0] in "u" else 1e-2)
+        den = max(np.sqrt((w * Fo[:, i] ** 2).sum()), u_scale if n[0] == "u" else 1e-2)
         out[n] = num / den
     return out
+
+
+def _max_err(errs):
+    """Largest value of a dict of errors; NaN if any is NaN."""
+    return float(np.max(np.array(list(errs.values()))))
 
 
 def _cases_small():
@@ -232,8 +248,8 @@ def test_converged_gsis_fields(prec, stol, tol):
     rc, rep, hist = s.solve()
     assert rc == 0 and no > 0, (rc, rep.iters, hist[-5:])
     names = field_names(1)
-    errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, names)
-    assert max(errs.values()) < tol, errs
+    errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, names, _u_scale(case))
+    assert _max_err(errs) < tol, errs
 
 
 def test_converged_gsis_cavity_fp32():
@@ -243,8 +259,8 @@ def test_converged_gsis_cavity_fp32():
     rc, rep, hist = s.solve()
     assert rc == 0 and no > 0
     names = field_names(2)
-    errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, names)
-    assert max(errs.values()) < 1e-5, errs
+    errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, names, _u_scale(case))
+    assert _max_err(errs) < 1e-5, errs
 
 
 def test_full_size_cavity_stages():
@@ -298,9 +314,9 @@ def test_precision_form_full_size_cavity():
         out[prec] = (s.fields(), rep.iters)
         s.close()
     assert out["fp32"][1] == out["fp64"][1]
-    errs = _field_rel_l2(out["fp32"][0], out["fp64"][0], case.mesh.vol, field_names(2))
+    errs = _field_rel_l2(out["fp32"][0], out["fp64"][0], case.mesh.vol, field_names(2), _u_scale(case))
     print("iterations", out["fp32"][1], "largest field differences", sorted(errs.items(), key=lambda kv: -kv[1])[:3])
-    assert max(errs.values()) < 1e-5, errs
+    assert _max_err(errs) < 1e-5, errs
 
 
 def test_surface_flux_matches_oracle():
@@ -340,9 +356,9 @@ def test_hypersonic_cylinder_converges_to_oracle():
     rc, rep, hist = s.solve()
     assert no > 0 and rc == 0, (no, rc, rep.iters)
     names = field_names(2)
-    errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, names)
+    errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, names, _u_scale(case))
     print("iterations", no, rep.iters, "field errors", sorted(errs.items(), key=lambda kv: -kv[1])[:4])
-    assert max(errs.values()) < 1e-5, errs
+    assert _max_err(errs) < 1e-5, errs
 
 
 def test_capsule_converges_to_oracle_first_order():
@@ -356,7 +372,72 @@ def test_capsule_converges_to_oracle_first_order():
     no, ho = o.solve(gsis=True, n_precond=20, tol=1e-8, max_outer=200)
     rc, rep, hist = s.solve()
     assert no > 0 and rc == 0, (no, rc, rep.iters)
-    errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, field_names(3))
+    errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, field_names(3), _u_scale(case))
     print("iterations", no, rep.iters, "field errors", sorted(errs.items(), key=lambda kv: -kv[1])[:4])
-    assert max(errs.values()) < 1e-6, errs
+    assert _max_err(errs) < 1e-6, errs
+    s.close()
+
+
+@pytest.mark.parametrize("nsw", [1, 2])
+@pytest.mark.parametrize("name,case", _cases_small(), ids=[c[0] for c in _cases_small()])
+def test_kinetic_step_sgs_fp64(name, case, nsw):
+    """Colored symmetric Gauss-Seidel relaxation (one sweep in place, two sweeps with an increment buffer):
+    one kinetic step element by element against the oracle's colour-by-colour sweep."""
+    s, o = _pair(case, precision="fp64", sweep="sgs", kin_sweeps=nsw)
+    _warm(o, s)
+    o.kinetic_step()
+    s.kinetic_step()
+    fo, Io = o.get_state()
+    fg, Ig = s.get_state()
+    assert _relerr(fg, fo) < 1e-10, name
+    assert _relerr(Ig, Io) < 1e-10, name
+
+
+@pytest.mark.parametrize("name,case", [c for c in _cases_small() if c[0] in ("cavity", "capsule")],
+                         ids=["cavity", "capsule"])
+def test_gsis_iterations_sgs_fp64(name, case):
+    s, o = _pair(case, precision="fp64", sweep="sgs", kin_sweeps=1, max_inner=_MAX_INNER[name])
+    for k in range(6):
+        g = k >= 2
+        eo, io = o.iterate(gsis=g)
+        eg, ig = s.iterate(gsis=g)
+        assert io == ig
+        assert abs(eg - eo) <= 1e-8 * abs(eo) + 1e-14
+    assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-8
+
+
+def test_kinetic_step_sgs_fp32_ragged():
+    """FP32 colored Gauss-Seidel on the ragged grid (nv = 81: the one-value-per-lane velocity pass; 69
+    ordinates: the one-value-per-lane ordinate pass) against the FP64 oracle."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=9, n_theta=3, n_phi=23, Kn=0.05)
+    s, o = _pair(case, precision="fp32", sweep="sgs", kin_sweeps=1)
+    _warm(o, s, n=2)
+    o.kinetic_step()
+    s.kinetic_step()
+    fo, Io = o.get_state()
+    fg, Ig = s.get_state()
+    assert np.abs(fg - fo).max() < 2e-6 * np.abs(fo).max()
+    assert np.abs(Ig - Io).max() < 2e-6 * np.abs(Io).max()
+
+
+def test_option_changes_keep_the_state():
+    """Switching the relaxation (Jacobi -> colored Gauss-Seidel -> Jacobi with no sweeps) and the limiter
+    constant between iterations keeps the state: the iterations match an oracle restarted from the same
+    state with the new options."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1)
+    s = Solver(case, precision="fp64", max_inner=60)
+    o = Oracle(case, **oracle_opts(s.opts))
+    for _ in range(2):
+        o.iterate(gsis=False)
+        s.iterate(gsis=False)
+    for kw in (dict(sweep="sgs", kin_sweeps=1), dict(sweep="jacobi", kin_sweeps=0, limiter_K=2.0),
+               dict(sweep="jacobi", kin_sweeps=8, limiter_K=5.0)):
+        s.set_opts(**kw)
+        f, I = o.get_state()
+        o = Oracle(case, **oracle_opts(s.opts))
+        o.set_state(f, I)
+        eo, _ = o.iterate(gsis=True)
+        eg, _ = s.iterate(gsis=True)
+        assert abs(eg - eo) <= 1e-8 * abs(eo) + 1e-14, kw
+        assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-8, kw
     s.close()

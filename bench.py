@@ -133,7 +133,7 @@ def bench_cylinder(a):
     """Ma 5 flow past a cylinder on 40,960 triangles with 64 x 64 Newton-Cotes velocities (|xi| <= 12) and 64
     ordinates, Kn 0.01 (--cyl-Kn), optical thickness 1, sigma_R 0.1, FP32, from the uniform free stream: Mach
     continuation 2 -> 3 -> 4 -> 5 (each stage to 1e-4, the last to the tolerance; 40 conventional and 60
-    first-order iterations at the start, 10 first-order iterations after each Mach step, limiter K = 1);
+    first-order iterations at the start, 10 first-order iterations after each Mach step);
     then 5 profiled GSIS iterations at the converged state for the kernel table."""
     import numpy as np
     import torch
@@ -147,7 +147,7 @@ def bench_cylinder(a):
     gam = case.gas.gamma
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    s = Solver(case, device=0, stream=stream.cuda_stream, precision=a.precision, limiter_K=1.0)
+    s = Solver(case, device=0, stream=stream.cuda_stream, precision=a.precision)
     states = [(1.0, 1.0, (Ma * np.sqrt(gam), 0.0, 0.0)) for Ma in (2.0, 3.0, 4.0, 5.0)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -252,7 +252,7 @@ def cylinder_warmstart_leg(a, case, stream, plain_fields):
     cases = [case_cylinder(mesh=coarse, Ma=m, Kn=k, tau_opt=t, nvx=32, xmax=12.0, sigma_R=0.1, n_theta=2, n_phi=8)
              for m, k, t in P]
     t0 = time.perf_counter()
-    X, Y, info = WS.cylinder_training_set(cases, stream=st, limiter_K=1.0, precision=a.precision)
+    X, Y, info = WS.cylinder_training_set(cases, stream=st, precision=a.precision)
     t_data = time.perf_counter() - t0
     ws = WS.WarmStart(width=256, bf16=True, seed=0, stream=st, family="cylinder")
     t0 = time.perf_counter()
@@ -260,7 +260,7 @@ def cylinder_warmstart_leg(a, case, stream, plain_fields):
     t_train = time.perf_counter() - t0
     target = case_cylinder(mesh=case.mesh, Ma=5.0, Kn=case.flow.Kn_gas, tau_opt=case.flow.k_eff, nvx=64, xmax=12.0,
                            n_theta=4, n_phi=16, sigma_R=case.gas.sigma_R)
-    s = Solver(target, device=0, stream=st, precision=a.precision, limiter_K=1.0, n_precond=10, first_order_iters=20,
+    s = Solver(target, device=0, stream=st, precision=a.precision, n_precond=10, first_order_iters=20,
                tol=a.tol, max_outer=a.max_outer)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -41,14 +41,39 @@ def _grids(nx=160, nt=6, nmu=64):
     return xi, w, mu, 2 * np.pi * wm
 
 
-def cis_matrix(theta, Kn_gas, Kn_photon, sigma_R, d_r=2.0, d_v=1.0, Z_r=2.67, Z_v=26.7, Sc=0.8, grids=None):
-    """C(theta) for a wave number theta along x."""
+def product_grids(x, wx, mu, wmu, nt=6):
+    """Velocity grid for the error integrals built from a 1D rule (x, wx) along the wave vector and exact
+    Gauss-Hermite rules across it, with the ordinate rule (mu, wmu): the grids of a planar (reduced 1D)
+    discrete-velocity run, whose transverse velocity integrals are exact."""
+    y, Wy = np.polynomial.hermite.hermgauss(nt)
+    ys, wys = np.sqrt(2) * y, np.sqrt(2) * Wy * np.exp(y * y)
+    X, Y, Z = np.meshgrid(np.asarray(x, float), ys, ys, indexing="ij")
+    WX, WY, WZ = np.meshgrid(np.asarray(wx, float), wys, wys, indexing="ij")
+    return (np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1), (WX * WY * WZ).ravel(), np.asarray(mu, float),
+            np.asarray(wmu, float))
+
+
+def upwind_symbol(theta, h):
+    """Fourier symbol of the first-order upwind difference for advection with speed v on a uniform grid of
+    spacing h: for a mode exp(i theta x), v (1 - exp(-i theta h)) / h when v > 0 and v (exp(i theta h) - 1) / h
+    when v < 0 (the continuous symbol is i theta v)."""
+    def s(v):
+        v = np.asarray(v, float)
+        return np.where(v > 0, v * (1 - np.exp(-1j * theta * h)) / h, v * (np.exp(1j * theta * h) - 1) / h)
+    return s
+
+
+def cis_matrix(theta, Kn_gas, Kn_photon, sigma_R, d_r=2.0, d_v=1.0, Z_r=2.67, Z_v=26.7, Sc=0.8, grids=None,
+               symbol=None):
+    """C(theta) for a wave number theta along x.  `symbol(v)` replaces the transport symbol i theta v (e.g. the
+    upwind_symbol of a discrete scheme)."""
     xi, w, mu, wmu = grids if grids is not None else _grids()
     A = mason_A(d_r, d_v, Z_r, Z_v, Sc)
     x2 = (xi ** 2).sum(axis=1)
     f0 = (2 * np.pi) ** -1.5 * np.exp(-0.5 * x2)
-    den = 1 + 1j * np.sqrt(2 / np.pi) * Kn_gas * theta * xi[:, 0]
-    denR = 1 + 1j * Kn_photon * theta * mu
+    sym = symbol if symbol is not None else (lambda v: 1j * theta * np.asarray(v, float))
+    den = 1 + np.sqrt(2 / np.pi) * Kn_gas * sym(xi[:, 0])
+    denR = 1 + Kn_photon * sym(mu)
     ar = d_r / ((3 + d_r) * Z_r)
     av = d_v / ((3 + d_v) * Z_v)
     Pt = 0.5 * x2 - 1.5
@@ -89,6 +114,11 @@ def cis_matrix(theta, Kn_gas, Kn_photon, sigma_R, d_r=2.0, d_v=1.0, Z_r=2.67, Z_
         col[7] += (wmu * yR).sum()
         C[:, j] = col
     return C
+
+
+# the longitudinal moments of a wave along x (density, u_x, T_t, T_r, T_v, e_R, q_tx, q_rx, q_vx): the block of
+# C(theta) that a planar (1D) run carries; the transverse moments decouple from it
+LONGITUDINAL = [NAMES.index(n) for n in ("rho", "ux", "Tt", "Tr", "Tv", "eR", "qtx", "qrx", "qvx")]
 
 
 def spectral_radius(M):

@@ -55,7 +55,7 @@ typedef struct {
     double Ttr, Ttv, T, tau, q0[3], q1[3], q2[3], evR, B, cs, dt, dtR, radd;
 } der_t;
 
-typedef struct {
+typedef struct orc_s {
     int D, ND;
     int64_t nc, nf;
     double *vol, *ctr, *fn, *fa, *fctr;
@@ -71,6 +71,8 @@ typedef struct {
     double cfl_meso, cfl_macro, limK, inner_tol, cfl_v, kin_omega;
     int kin_sweeps, diss_ref, macro_order2;
     int sweep; /* 0: Jacobi sweeps of the implicit kinetic operator; 1: colored symmetric Gauss-Seidel */
+    double period;    /* > 0: the mesh is periodic along x with this length (test meshes of the Fourier analysis) */
+    int rad_implicit; /* 1: the emission part of the gas-photon exchange joins the diagonal of f2 (default) */
     int max_inner, n_sweeps, second_order;
     /* derived constants */
     double A[3][3], Qm[3][3], K0[3][3];
@@ -92,6 +94,18 @@ typedef struct {
 } orc_t;
 
 static int NWof(int D) { return D + 5; }
+
+/* Difference a - b of two coordinates along axis k.  On a mesh that is periodic along x (length o->period)
+ * the nearest periodic image is taken, so that the face between the last and the first cell sees its two
+ * cells at the distance they have across the period. */
+static inline double gdiff(const struct orc_s *o, double a, double b, int k);
+
+static inline double gdiff(const orc_t *o, double a, double b, int k)
+{
+    double d = a - b;
+    if (k == 0 && o->period > 0) d -= o->period * floor(d / o->period + 0.5);
+    return d;
+}
 
 /* ---------------------------------------------------------------- small linear algebra */
 static int inv3(int n, const double *a, double *r)
@@ -223,7 +237,7 @@ static void build_mesh(orc_t *o)
             int64_t j = (o->csign[s] > 0) ? o->fc[2 * f + 1] : o->fc[2 * f];
             double d[3] = {0, 0, 0}, d2 = 0;
             for (int a = 0; a < D; ++a) {
-                d[a] = (j >= 0 ? o->ctr[j * D + a] : o->fctr[f * D + a]) - o->ctr[c * D + a];
+                d[a] = gdiff(o, j >= 0 ? o->ctr[j * D + a] : o->fctr[f * D + a], o->ctr[c * D + a], a);
                 d2 += d[a] * d[a];
             }
             double wgt = 1.0 / d2;
@@ -237,7 +251,7 @@ static void build_mesh(orc_t *o)
             int64_t j = (o->csign[s] > 0) ? o->fc[2 * f + 1] : o->fc[2 * f];
             double d[3] = {0, 0, 0}, d2 = 0;
             for (int a = 0; a < D; ++a) {
-                d[a] = (j >= 0 ? o->ctr[j * D + a] : o->fctr[f * D + a]) - o->ctr[c * D + a];
+                d[a] = gdiff(o, j >= 0 ? o->ctr[j * D + a] : o->fctr[f * D + a], o->ctr[c * D + a], a);
                 d2 += d[a] * d[a];
             }
             for (int a = 0; a < D; ++a) {
@@ -268,24 +282,28 @@ static void lsq_grad(const orc_t *o, const double *a, int64_t stride, int64_t of
     }
 }
 
-/* Venkatakrishnan limiter (reading: eps^2 = (K h)^3, h = V^(1/D), phi per face capped at 1) */
+/* Venkatakrishnan limiter.  Reading: eps^2 = (K h)^3 M^2 with h = V^(1/D) and M the largest magnitude of
+ * the limited variable over the cell and its face neighbours, so that the threshold follows the local size
+ * of each variable (distributions at every velocity and intensities at every ordinate span many orders of
+ * magnitude; an unscaled (K h)^3 leaves the small ones unlimited); phi per face capped at 1. */
 static double venkat(const orc_t *o, const double *a, int64_t stride, int64_t off, int64_t c, const double g[3])
 {
-    double ac = a[c * stride + off], dmax = 0, dmin = 0;
+    double ac = a[c * stride + off], dmax = 0, dmin = 0, M = fabs(ac);
     for (int64_t s = o->cptr[c]; s < o->cptr[c + 1]; ++s) {
         int64_t j = other_cell(o, s);
         if (j < 0) continue;
-        double da = a[j * stride + off] - ac;
+        double aj = a[j * stride + off], da = aj - ac;
         if (da > dmax) dmax = da;
         if (da < dmin) dmin = da;
+        if (fabs(aj) > M) M = fabs(aj);
     }
     double kh = o->limK * o->h[c];
-    double eps2 = kh * kh * kh;
+    double eps2 = kh * kh * kh * M * M;
     double phi = 1.0;
     for (int64_t s = o->cptr[c]; s < o->cptr[c + 1]; ++s) {
         int64_t f = o->cface[s];
         double d2 = 0;
-        for (int k = 0; k < o->D; ++k) d2 += g[k] * (o->fctr[f * o->D + k] - o->ctr[c * o->D + k]);
+        for (int k = 0; k < o->D; ++k) d2 += g[k] * gdiff(o, o->fctr[f * o->D + k], o->ctr[c * o->D + k], k);
         double p = 1.0;
         if (d2 != 0.0) {
             double d1 = (d2 > 0) ? dmax : dmin;
@@ -384,7 +402,7 @@ static void derived(const orc_t *o, const mom_t *m, int64_t c, der_t *d)
      * relaxation: its linearised rate d(k_eff e_vR)/d e_v = 4 k_eff e_vR / e_v joins the diagonal of f2.
      * This changes the iteration path only (the residual is unchanged) and keeps T_v positive where the
      * emission rate per unit vibrational energy is large (low density). */
-    d->radd = 4 * o->keff * d->evR / m->ev;
+    d->radd = o->rad_implicit ? 4 * o->keff * d->evR / m->ev : 0.0;
     d->B = o->sigR * Tv2 * Tv2 / PI;
     d->cs = sqrt(5.0 / 3.0 * m->Tt);
     double un = 0;
@@ -491,7 +509,7 @@ static void wall_densities(orc_t *o, const double *gl)
             double xn = 0, dx = 0, c2 = 0;
             for (int a = 0; a < D; ++a) xn += o->xi[k * D + a] * o->fn[f * D + a];
             const double *g = gl + ((c * ND + DG) * nv + k) * 3;
-            for (int a = 0; a < D; ++a) dx += g[a] * (o->fctr[f * D + a] - o->ctr[c * D + a]);
+            for (int a = 0; a < D; ++a) dx += g[a] * gdiff(o, o->fctr[f * D + a], o->ctr[c * D + a], a);
             for (int a = 0; a < D; ++a) c2 += (o->xi[k * D + a] - o->bcu[b * 3 + a]) * (o->xi[k * D + a] - o->bcu[b * 3 + a]);
             if (xn > 0)
                 out += o->w[k] * xn * (o->f[(c * ND + DG) * nv + k] + dx);
@@ -529,7 +547,7 @@ static void record_boundary(orc_t *o, const double *gl, const double *glI)
                 for (int sl = 0; sl < ND; ++sl) {
                     const double *g = gl + ((c * ND + sl) * nv + k) * 3;
                     double dx = 0;
-                    for (int a = 0; a < D; ++a) dx += g[a] * (o->fctr[f * D + a] - o->ctr[c * D + a]);
+                    for (int a = 0; a < D; ++a) dx += g[a] * gdiff(o, o->fctr[f * D + a], o->ctr[c * D + a], a);
                     fv[sl] = o->f[(c * ND + sl) * nv + k] + dx;
                 }
             } else {
@@ -557,7 +575,7 @@ static void record_boundary(orc_t *o, const double *gl, const double *glI)
             if (on > 0) {
                 const double *g = glI + (c * no + q) * 3;
                 double dx = 0;
-                for (int a = 0; a < D; ++a) dx += g[a] * (o->fctr[f * D + a] - o->ctr[c * D + a]);
+                for (int a = 0; a < D; ++a) dx += g[a] * gdiff(o, o->fctr[f * D + a], o->ctr[c * D + a], a);
                 Iv = o->I[c * no + q] + dx;
             } else {
                 double Tb = o->bcT[b];
@@ -616,7 +634,7 @@ static void kinetic_step(orc_t *o, double *fout, double *Iout, double *racc /* o
                     for (int sl = 0; sl < ND; ++sl) {
                         const double *g = gl + ((c * ND + sl) * nv + k) * 3;
                         double dx = 0;
-                        for (int a = 0; a < D; ++a) dx += g[a] * (o->fctr[f * D + a] - o->ctr[c * D + a]);
+                        for (int a = 0; a < D; ++a) dx += g[a] * gdiff(o, o->fctr[f * D + a], o->ctr[c * D + a], a);
                         fv[sl] = o->f[(c * ND + sl) * nv + k] + dx;
                     }
                 } else {
@@ -625,7 +643,7 @@ static void kinetic_step(orc_t *o, double *fout, double *Iout, double *racc /* o
                         for (int sl = 0; sl < ND; ++sl) {
                             const double *g = gl + ((j * ND + sl) * nv + k) * 3;
                             double dx = 0;
-                            for (int a = 0; a < D; ++a) dx += g[a] * (o->fctr[f * D + a] - o->ctr[j * D + a]);
+                            for (int a = 0; a < D; ++a) dx += g[a] * gdiff(o, o->fctr[f * D + a], o->ctr[j * D + a], a);
                             fv[sl] = o->f[(j * ND + sl) * nv + k] + dx;
                         }
                     } else {
@@ -664,14 +682,14 @@ static void kinetic_step(orc_t *o, double *fout, double *Iout, double *racc /* o
                 if (on > 0) {
                     const double *g = glI + (c * no + q) * 3;
                     double dx = 0;
-                    for (int a = 0; a < D; ++a) dx += g[a] * (o->fctr[f * D + a] - o->ctr[c * D + a]);
+                    for (int a = 0; a < D; ++a) dx += g[a] * gdiff(o, o->fctr[f * D + a], o->ctr[c * D + a], a);
                     Iv = o->I[c * no + q] + dx;
                 } else {
                     int64_t j = other_cell(o, s);
                     if (j >= 0) {
                         const double *g = glI + (j * no + q) * 3;
                         double dx = 0;
-                        for (int a = 0; a < D; ++a) dx += g[a] * (o->fctr[f * D + a] - o->ctr[j * D + a]);
+                        for (int a = 0; a < D; ++a) dx += g[a] * gdiff(o, o->fctr[f * D + a], o->ctr[j * D + a], a);
                         Iv = o->I[j * no + q] + dx;
                     } else {
                         int b = (int)(-j - 1);
@@ -916,7 +934,7 @@ static void face_grads(const orc_t *o, const double *fld, const double *gf, int6
     int D = o->D, nfld = D + 4;
     double dvec[3] = {0, 0, 0}, dl = 0;
     for (int a = 0; a < D; ++a) {
-        dvec[a] = o->ctr[j * D + a] - o->ctr[c * D + a];
+        dvec[a] = gdiff(o, o->ctr[j * D + a], o->ctr[c * D + a], a);
         dl += dvec[a] * dvec[a];
     }
     dl = sqrt(dl);
@@ -1109,7 +1127,7 @@ static void bmodel_flux(const orc_t *o, int64_t f, const double *Wc, double *F, 
     prim_of(o, Wc, &p);
     const double *n = o->fn + f * D;
     double delta = 0;
-    for (int a = 0; a < D; ++a) delta += n[a] * (o->fctr[f * D + a] - o->ctr[c * D + a]);
+    for (int a = 0; a < D; ++a) delta += n[a] * gdiff(o, o->fctr[f * D + a], o->ctr[c * D + a], a);
     delta = fabs(delta);
     double kR = (o->keff > 0) ? 1.0 / (3 * o->keff) : 0.0;
     double Tb = o->bcT[b];
@@ -1145,6 +1163,24 @@ static void bmodel_flux(const orc_t *o, int64_t f, const double *Wc, double *F, 
         F[D + 1] += qRn;
         F[D + 4] = qRn;
     }
+}
+
+/* Sources Q of the synthetic equations (Eq. macroscopic_equation): none for mass, momentum and total
+ * energy; rotational (e_tr - e_r)/(Z_r tau), vibrational (e_tv - e_v)/(Z_v tau) - k_eff (e_vR - e_R) and
+ * radiative k_eff (e_vR - e_R) with e_vR = 4 sigma_R T_v^4 and tau = mu / (rho T_t). */
+static void macro_source(const orc_t *o, const prim_t *p, const double *Wc, double *Q)
+{
+    int D = o->D, NW = NWof(D);
+    double rho = p->rho, Tt = p->Tt, Tr = p->Tr, Tv = p->Tv;
+    double tau = p->mu / (rho * Tt);
+    double Ttr = (3 * Tt + o->dr * Tr) / (3 + o->dr), Ttv = (3 * Tt + o->dv * Tv) / (3 + o->dv);
+    double etr = 0.5 * o->dr * rho * Ttr, etv = 0.5 * o->dv * rho * Ttv;
+    double evR = 4 * o->sigR * Tv * Tv * Tv * Tv;
+    double er = Wc[D + 2], ev = Wc[D + 3], eR = Wc[D + 4];
+    for (int i = 0; i < NW; ++i) Q[i] = 0;
+    Q[D + 2] = (etr - er) / (o->Zr * tau);
+    Q[D + 3] = (etv - ev) / (o->Zv * tau) - o->keff * (evR - eR);
+    Q[D + 4] = o->keff * (evR - eR);
 }
 
 /* residual of the synthetic equations, R_i = -(1/V) sum_faces F S + Q (Eq. delta_macro), for the state W,
@@ -1189,8 +1225,8 @@ static void macro_residual(const orc_t *o, const double *hotf, const double *bco
                 for (int i = 0; i < NW; ++i) {
                     double dl = 0, drr = 0;
                     for (int a = 0; a < D; ++a) {
-                        dl += gl[(c * NW + i) * 3 + a] * (o->fctr[f * D + a] - o->ctr[c * D + a]);
-                        drr += gl[(j * NW + i) * 3 + a] * (o->fctr[f * D + a] - o->ctr[j * D + a]);
+                        dl += gl[(c * NW + i) * 3 + a] * gdiff(o, o->fctr[f * D + a], o->ctr[c * D + a], a);
+                        drr += gl[(j * NW + i) * 3 + a] * gdiff(o, o->fctr[f * D + a], o->ctr[j * D + a], a);
                     }
                     WL[i] = W[c * NW + i] + dl;
                     WR[i] = W[j * NW + i] + drr;
@@ -1211,17 +1247,8 @@ static void macro_residual(const orc_t *o, const double *hotf, const double *bco
             }
             for (int i = 0; i < NW; ++i) acc[i] += Ff[i] * S;
         }
-        /* sources Q (Sec. 6) */
-        double rho = P[c].rho, Tt = P[c].Tt, Tr = P[c].Tr, Tv = P[c].Tv;
-        double tau = P[c].mu / (rho * Tt);
-        double Ttr = (3 * Tt + o->dr * Tr) / (3 + o->dr), Ttv = (3 * Tt + o->dv * Tv) / (3 + o->dv);
-        double etr = 0.5 * o->dr * rho * Ttr, etv = 0.5 * o->dv * rho * Ttv;
-        double evR = 4 * o->sigR * Tv * Tv * Tv * Tv;
-        double er = W[c * NW + D + 2], ev = W[c * NW + D + 3], eR = W[c * NW + D + 4];
-        double Q[8] = {0};
-        Q[D + 2] = (etr - er) / (o->Zr * tau);
-        Q[D + 3] = (etv - ev) / (o->Zv * tau) - o->keff * (evR - eR);
-        Q[D + 4] = o->keff * (evR - eR);
+        double Q[8];
+        macro_source(o, &P[c], W + c * NW, Q);
         for (int i = 0; i < NW; ++i) R[c * NW + i] = -acc[i] / o->vol[c] + Q[i];
     }
     free(fld);
@@ -1249,8 +1276,8 @@ static void dissipation_ref(const orc_t *o, const double *W0, double *dref)
         for (int i = 0; i < NW; ++i) {
             double dl = 0, drr = 0;
             for (int a = 0; a < D; ++a) {
-                dl += gl[(c * NW + i) * 3 + a] * (o->fctr[f * D + a] - o->ctr[c * D + a]);
-                drr += gl[(j * NW + i) * 3 + a] * (o->fctr[f * D + a] - o->ctr[j * D + a]);
+                dl += gl[(c * NW + i) * 3 + a] * gdiff(o, o->fctr[f * D + a], o->ctr[c * D + a], a);
+                drr += gl[(j * NW + i) * 3 + a] * gdiff(o, o->fctr[f * D + a], o->ctr[j * D + a], a);
             }
             WL[i] = W0[c * NW + i] + dl;
             WR[i] = W0[j * NW + i] + drr;
@@ -1418,7 +1445,7 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
                 for (int a = 0; a < D; ++a) {
                     n[a] = o->csign[s] * o->fn[f * D + a];
                     ufn += 0.5 * (P[c].u[a] + P[j].u[a]) * n[a];
-                    nd += n[a] * (o->ctr[j * D + a] - o->ctr[c * D + a]);
+                    nd += n[a] * gdiff(o, o->ctr[j * D + a], o->ctr[c * D + a], a);
                 }
                 nd = fabs(nd);
                 double G = fabs(ufn) + 0.5 * (P[c].cs + P[j].cs) +
@@ -1457,7 +1484,7 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
                     for (int a = 0; a < D; ++a) {
                         n[a] = o->csign[s] * o->fn[f * D + a];
                         ufn += 0.5 * (P[c].u[a] + P[j].u[a]) * n[a];
-                        nd += n[a] * (o->ctr[j * D + a] - o->ctr[c * D + a]);
+                        nd += n[a] * gdiff(o, o->ctr[j * D + a], o->ctr[c * D + a], a);
                     }
                     nd = fabs(nd);
                     double G = fabs(ufn) + 0.5 * (P[c].cs + P[j].cs) +
@@ -1616,6 +1643,8 @@ orc_t *orc_create(int D, int64_t nc, int64_t nf, const double *vol, const double
     o->diss_ref = (int)opts[10];
     o->macro_order2 = (int)opts[11];
     o->sweep = (int)opts[12];
+    o->period = opts[13];
+    o->rad_implicit = (int)opts[14];
     model_constants(o);
     build_mesh(o);
     o->f = (double *)calloc((size_t)nc * o->ND * nv, sizeof(double));
@@ -1808,6 +1837,17 @@ void orc_face_hot(orc_t *o, double *hotf)
     all_moments(o, o->f, o->I, m);
     face_hot(o, m, hotf);
     free(m);
+}
+
+/* sources Q of the synthetic equations for the state W [nc*NW] -> Q [nc*NW] */
+void orc_macro_sources(const orc_t *o, const double *W, double *Q)
+{
+    int NW = NWof(o->D);
+    for (int64_t c = 0; c < o->nc; ++c) {
+        prim_t p;
+        prim_of(o, W + c * NW, &p);
+        macro_source(o, &p, W + c * NW, Q + c * NW);
+    }
 }
 
 /* W of the current state's moments [nc*NW] */

@@ -19,6 +19,20 @@ namespace gsis {
 
 __device__ __forceinline__ int uni_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// magnitudes below this are treated as zero by the limiter (their reciprocal would overflow)
+template <typename T>
+__device__ __forceinline__ constexpr T tiny_val();
+template <>
+__device__ __forceinline__ constexpr float tiny_val<float>()
+{
+    return 1e-30f;
+}
+template <>
+__device__ __forceinline__ constexpr double tiny_val<double>()
+{
+    return 1e-290;
+}
+
 template <typename T>
 __device__ __forceinline__ T dexp(T x);
 template <>
@@ -128,11 +142,12 @@ __global__ __launch_bounds__(256) void k_grad(const T *__restrict__ f, T *__rest
             T g[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) g[a] = T(0);
-            T dmax = T(0), dmin = T(0);
+            T dmax = T(0), dmin = T(0), mag = fabs(fc);
 #pragma unroll
             for (int s = 0; s < NFM; ++s) {
                 if (nb[s] >= 0) {
-                    const T df = f[((int64_t)nb[s] * nd + d) * nv + k] - fc;
+                    const T fj = f[((int64_t)nb[s] * nd + d) * nv + k], df = fj - fc;
+                    mag = fabs(fj) > mag ? fabs(fj) : mag;
 #pragma unroll
                     for (int a = 0; a < D; ++a) g[a] += lsq[s][a] * df;
                     dmax = df > dmax ? df : dmax;
@@ -142,6 +157,9 @@ __global__ __launch_bounds__(256) void k_grad(const T *__restrict__ f, T *__rest
             T phi = T(0);
             if (second_order) {
                 phi = T(1);
+                // eps^2 = (K h)^3 M^2 with M the largest |value| of the stencil, applied to the differences divided by M
+                // (no underflow of the squares in FP32 where the distribution is tiny)
+                const T inv = mag > tiny_val<T>() ? T(1) / mag : T(0);
 #pragma unroll
                 for (int s = 0; s < NFM; ++s) {
                     if (s < nfc) {
@@ -150,7 +168,8 @@ __global__ __launch_bounds__(256) void k_grad(const T *__restrict__ f, T *__rest
                         for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
                         if (d2 != T(0)) {
                             const T d1 = d2 > T(0) ? dmax : dmin;
-                            T p = (d1 * d1 + eps2 + T(2) * d1 * d2) / (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2);
+                            const T u1 = d1 * inv, u2 = d2 * inv;
+                            T p = (u1 * u1 + eps2 + T(2) * u1 * u2) / (u1 * u1 + T(2) * u2 * u2 + u1 * u2 + eps2);
                             p = p > T(1) ? T(1) : p;
                             phi = p < phi ? p : phi;
                         }
@@ -239,11 +258,12 @@ __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__re
                 T g[D];
 #pragma unroll
                 for (int a = 0; a < D; ++a) g[a] = T(0);
-                T dmax = T(0), dmin = T(0);
+                T dmax = T(0), dmin = T(0), mag = fabs(fc);
 #pragma unroll
                 for (int s = 0; s < NFM; ++s) {
                     if (nb[s] >= 0) {
-                        const T df = fnv[s][d][e] - fc;
+                        const T fj = fnv[s][d][e], df = fj - fc;
+                        mag = fabs(fj) > mag ? fabs(fj) : mag;
 #pragma unroll
                         for (int a = 0; a < D; ++a) g[a] += lsq[s][a] * df;
                         dmax = df > dmax ? df : dmax;
@@ -253,6 +273,9 @@ __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__re
                 T phi = T(0);
                 if (second_order) {
                     phi = T(1);
+                    // eps^2 = (K h)^3 M^2 with M the largest |value| of the stencil, applied to the differences divided by M
+                // (no underflow of the squares in FP32 where the distribution is tiny)
+                const T inv = mag > tiny_val<T>() ? T(1) / mag : T(0);
 #pragma unroll
                     for (int s = 0; s < NFM; ++s) {
                         if (nb[s] != INT32_MIN) {
@@ -261,8 +284,8 @@ __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__re
                             for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
                             if (d2 != T(0)) {
                                 const T d1 = d2 > T(0) ? dmax : dmin;
-                                T p = (d1 * d1 + eps2 + T(2) * d1 * d2) /
-                                      (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2);
+                                const T u1 = d1 * inv, u2 = d2 * inv;
+                            T p = (u1 * u1 + eps2 + T(2) * u1 * u2) / (u1 * u1 + T(2) * u2 * u2 + u1 * u2 + eps2);
                                 p = p > T(1) ? T(1) : p;
                                 phi = p < phi ? p : phi;
                             }
@@ -964,11 +987,12 @@ __global__ __launch_bounds__(256) void k_grad_I(const T *__restrict__ I, T *__re
         T g[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) g[a] = T(0);
-        T dmax = T(0), dmin = T(0);
+        T dmax = T(0), dmin = T(0), mag = fabs(Ic);
 #pragma unroll
         for (int s = 0; s < NFM; ++s) {
             if (nb[s] >= 0) {
-                const T df = I[(int64_t)nb[s] * no + q] - Ic;
+                const T Ij = I[(int64_t)nb[s] * no + q], df = Ij - Ic;
+                mag = fabs(Ij) > mag ? fabs(Ij) : mag;
 #pragma unroll
                 for (int a = 0; a < D; ++a) g[a] += lsq[s][a] * df;
                 dmax = df > dmax ? df : dmax;
@@ -978,6 +1002,9 @@ __global__ __launch_bounds__(256) void k_grad_I(const T *__restrict__ I, T *__re
         T phi = T(0);
         if (second_order) {
             phi = T(1);
+            // eps^2 = (K h)^3 M^2 with M the largest |value| of the stencil, applied to the differences divided by M
+                // (no underflow of the squares in FP32 where the distribution is tiny)
+                const T inv = mag > tiny_val<T>() ? T(1) / mag : T(0);
 #pragma unroll
             for (int s = 0; s < NFM; ++s) {
                 if (s < nfc) {
@@ -986,7 +1013,8 @@ __global__ __launch_bounds__(256) void k_grad_I(const T *__restrict__ I, T *__re
                     for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
                     if (d2 != T(0)) {
                         const T d1 = d2 > T(0) ? dmax : dmin;
-                        T p = (d1 * d1 + eps2 + T(2) * d1 * d2) / (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2);
+                        const T u1 = d1 * inv, u2 = d2 * inv;
+                            T p = (u1 * u1 + eps2 + T(2) * u1 * u2) / (u1 * u1 + T(2) * u2 * u2 + u1 * u2 + eps2);
                         p = p > T(1) ? T(1) : p;
                         phi = p < phi ? p : phi;
                     }
@@ -1160,11 +1188,12 @@ __global__ __launch_bounds__(256) void k_grad_Iv(const T *__restrict__ I, T *__r
             T g[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) g[a] = T(0);
-            T dmax = T(0), dmin = T(0);
+            T dmax = T(0), dmin = T(0), mag = fabs(Ic[e]);
 #pragma unroll
             for (int s = 0; s < NFM; ++s) {
                 if (nb[s] >= 0) {
-                    const T df = nbv[s][e] - Ic[e];
+                    const T Ij = nbv[s][e], df = Ij - Ic[e];
+                    mag = fabs(Ij) > mag ? fabs(Ij) : mag;
 #pragma unroll
                     for (int a = 0; a < D; ++a) g[a] += lsq[s][a] * df;
                     dmax = df > dmax ? df : dmax;
@@ -1174,6 +1203,9 @@ __global__ __launch_bounds__(256) void k_grad_Iv(const T *__restrict__ I, T *__r
             T phi = T(0);
             if (second_order) {
                 phi = T(1);
+                // eps^2 = (K h)^3 M^2 with M the largest |value| of the stencil, applied to the differences divided by M
+                // (no underflow of the squares in FP32 where the distribution is tiny)
+                const T inv = mag > tiny_val<T>() ? T(1) / mag : T(0);
 #pragma unroll
                 for (int s = 0; s < NFM; ++s) {
                     if (nb[s] != INT32_MIN) {
@@ -1182,7 +1214,8 @@ __global__ __launch_bounds__(256) void k_grad_Iv(const T *__restrict__ I, T *__r
                         for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
                         if (d2 != T(0)) {
                             const T d1 = d2 > T(0) ? dmax : dmin;
-                            T p = (d1 * d1 + eps2 + T(2) * d1 * d2) / (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2);
+                            const T u1 = d1 * inv, u2 = d2 * inv;
+                            T p = (u1 * u1 + eps2 + T(2) * u1 * u2) / (u1 * u1 + T(2) * u2 * u2 + u1 * u2 + eps2);
                             p = p > T(1) ? T(1) : p;
                             phi = p < phi ? p : phi;
                         }

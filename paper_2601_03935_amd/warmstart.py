@@ -255,14 +255,25 @@ def converged_fields(case, device=0, stream=None, **opts):
     return F, int(rep.iters), dt, rc == 0
 
 
-def training_set(cases, device=0, stream=None, family="cavity", **opts):
-    """Features and targets stacked over converged cases (solved from their uniform start)."""
+def training_set(cases, device=0, stream=None, family="cavity", report=None, **opts):
+    """Features and targets stacked over the cases that converge (solved from their uniform start).  A case
+    that does not reach the tolerance, or whose targets are not all finite, is dropped; `report` (a dict)
+    receives the counts of used and dropped cases."""
     feat = FEATURES[family][0]
     X, Y = [], []
-    for c in cases:
+    dropped = []
+    for i, c in enumerate(cases):
         F, _, _, ok = converged_fields(c, device=device, stream=stream, **opts)
+        Yc = field_targets(F) if ok else None
+        if not ok or not np.isfinite(Yc).all():
+            dropped.append(i)
+            continue
         X.append(feat(c))
-        Y.append(field_targets(F))
+        Y.append(Yc)
+    if report is not None:
+        report.update(used=len(X), dropped=len(dropped), dropped_cases=dropped)
+    if not X:
+        raise GsisError("no training case converged with finite fields")
     return np.concatenate(X), np.concatenate(Y)
 
 

@@ -123,7 +123,7 @@ def test_warm_start_replaces_mach_continuation():
     kw = dict(nvx=32, xmax=12.0, sigma_R=0.1, n_theta=2, n_phi=4)
     P = warmstart_cylinder_params(12, seed=3)
     train = [case_cylinder(mesh=mesh, Ma=m, Kn=k, tau_opt=t, **kw) for m, k, t in P]
-    X, Y, info = cylinder_training_set(train, limiter_K=1.0)
+    X, Y, info = cylinder_training_set(train)
     # every case converges: second order, or first order where the coarse-mesh shock does not settle
     assert sum(r["ok"] for r in info) == len(train), info
     ws = WS.WarmStart(width=256, seed=0, family="cylinder")
@@ -131,8 +131,8 @@ def test_warm_start_replaces_mach_continuation():
     tests = [case_cylinder(mesh=mesh, Ma=4.17, Kn=0.062, tau_opt=1.72, **kw),
              case_cylinder(mesh=mesh, Ma=4.48, Kn=0.037, tau_opt=2.27, **kw)]
     for c in tests:
-        F0, it0, _, ok0 = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), limiter_K=1.0, tol=1e-6)
-        s = Solver(c, limiter_K=1.0, tol=1e-6, max_outer=800, n_precond=10, first_order_iters=20)
+        F0, it0, _, ok0 = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), tol=1e-6)
+        s = Solver(c, tol=1e-6, max_outer=800, n_precond=10, first_order_iters=20)
         pred = ws.init_solver(s, c)
         rc, rep, _ = s.solve()
         F1 = s.fields()

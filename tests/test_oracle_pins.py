@@ -445,3 +445,318 @@ def test_gauss_seidel_and_jacobi_reach_the_same_implicit_solve():
     # one symmetric sweep is a partial solve: closer to the converged increment than no relaxation at all
     f1, _ = out["sgs1"]
     assert np.abs(f1 - fj).max() < 0.5 * np.abs(f0 - fj).max()
+
+
+def test_intensity_stays_non_negative_on_the_cavity():
+    """The radiative intensity is a non-negative quantity and the walls emit at 1 and 3 (sigma_R T^4 / pi >=
+    1.6e-3): the limited second-order iteration (limiter threshold scaled with the local magnitude of each
+    variable) keeps every intensity non-negative and every field finite on the 728-triangle cavity."""
+    c = case_cavity(mesh=mesh_cavity(h=0.05), nvx=12, n_theta=2, n_phi=4, Kn=0.1)
+    o = Oracle(c)
+    n, hist = o.solve(gsis=True, n_precond=10, tol=1e-6, max_outer=200)
+    assert n > 0
+    f, I = o.get_state()
+    F = o.fields()
+    assert np.isfinite(F).all()
+    assert I.min() >= 0.0
+    assert F[:, field_names(2).index("TR")].min() > 0.9  # the coldest wall is at T = 1
+
+
+# ---------------------------------------------------------------- collision invariants in 2D and 3D
+def _moments_of_J_nd(c, J, JR):
+    """Velocity-space moments of the sources J (slots G, R, V[, H]) and of the radiative source JR, for the
+    reduced 2D model (slots G, R, V, H) and the full 3D model (f0, f1, f2)."""
+    D = c.mesh.dim
+    xi, w = c.vgrid.xi, c.vgrid.w
+    c2 = (xi ** 2).sum(axis=1)
+    G, R, V = J[0], J[1], J[2]
+    H = J[3] if D < 3 else np.zeros_like(G)
+    out = dict(mass=G @ w, mom=np.array([G @ (w * xi[:, a]) for a in range(D)]))
+    out["energy"] = 0.5 * G @ (w * c2) + 0.5 * H @ w + R @ w + V @ w + JR @ c.ords.w
+    tr = (G @ (w * c2) + H @ w) / 3.0
+    out["stress"] = np.array([[G @ (w * xi[:, a] * xi[:, b]) - (tr if a == b else 0.0) for b in range(D)]
+                              for a in range(D)])
+    out["qt"] = np.array([0.5 * (G @ (w * xi[:, a] * c2) + H @ (w * xi[:, a])) for a in range(D)])
+    out["qr"] = np.array([R @ (w * xi[:, a]) for a in range(D)])
+    out["qv"] = np.array([V @ (w * xi[:, a]) for a in range(D)])
+    out["er"], out["ev"], out["eR"] = R @ w, V @ w, JR @ c.ords.w
+    return out
+
+
+def _noneq_state_nd(c):
+    """Quadrature-exact non-equilibrium state with u = 0 and T_t = T_r = T_v = 1 (rho = 1), carrying stress
+    and all three heat fluxes through polynomial x Gaussian perturbations (2D: slots G, R, V, H; 3D: f0, f1,
+    f2), and a radiation field with e_R != 4 sigma_R T_v^4 and q_R != 0."""
+    D = c.mesh.dim
+    xi = c.vgrid.xi
+    x2 = (xi ** 2).sum(axis=1)
+    M = maxwell(x2, D)
+    d_r, d_v = c.gas.d_r, c.gas.d_v
+    x, y = xi[:, 0], xi[:, 1]
+    if D == 2:
+        b20, b02 = 0.04, -0.02
+        G = M * (1 + b20 * He(2, x) + b02 * He(2, y) + 0.03 * x * y + 0.02 * x * (x2 - 4) - 0.015 * y * (x2 - 4))
+        H = M * (1 - 2 * (b20 + b02) + 0.02 * x - 0.01 * y)
+        slots = [G, 0.5 * d_r * M * (1 + 0.04 * x - 0.02 * y), 0.5 * d_v * M * (1 - 0.03 * x + 0.05 * y), H]
+    else:
+        z = xi[:, 2]
+        G = M * (1 + 0.04 * He(2, x) - 0.01 * He(2, y) - 0.03 * He(2, z) + 0.02 * x * y - 0.01 * y * z
+                 + 0.02 * x * (x2 - 5) - 0.01 * z * (x2 - 5))
+        slots = [G, 0.5 * d_r * M * (1 + 0.04 * x - 0.02 * z), 0.5 * d_v * M * (1 - 0.03 * y + 0.05 * z)]
+    f = np.tile(np.stack(slots)[None], (c.mesh.nc, 1, 1))
+    om = c.ords.omega
+    I = np.tile(c.gas.sigma_R / np.pi * (1.2 + 0.3 * om[:, 0] - 0.2 * om[:, 1]), (c.mesh.nc, 1))
+    return f, I
+
+
+def _case_3d_gh(nvx=10):
+    import dataclasses
+
+    from workloads import case_capsule
+    c = case_capsule(Kn=0.3, Ma=2.0, nvx=8, xmax=8.0, n_theta=2, n_phi=4, sigma_R=0.2, tau_opt=0.7,
+                     mesh_kw=dict(n_s=3, n_phi=4, n_r=2))
+    return dataclasses.replace(c, vgrid=gauss_hermite_grid(nvx, 3))
+
+
+def _case_2d_gh(nvx=16):
+    return case_cavity(mesh=mesh_cavity(h=0.25), nvx=nvx, n_theta=2, n_phi=4, Kn=0.3, tau_opt=0.7, sigma_R=0.2)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_collision_invariants_and_relaxation_rates_nd(dim):
+    """P2 in the reduced 2D model (G, R, V, H) and in 3D (f0, f1, f2) on quadrature-exact states: mass,
+    momentum and gas + radiation energy are conserved by the sources to round-off; the stress relaxes as
+    -sigma / tau; the three heat fluxes as -(1/tau) A q with the Mason matrix A (Sec. 2.1); with all mode
+    temperatures equal, rotational energy is not exchanged and vibrational energy only with the photons."""
+    c = _case_2d_gh() if dim == 2 else _case_3d_gh()
+    o = Oracle(c)
+    f, I = _noneq_state_nd(c)
+    o.set_state(f, I)
+    fl = dict(zip(field_names(dim), o.fields()[0]))
+    assert abs(fl["Tt"] - 1) < 1e-13 and abs(fl["Tr"] - 1) < 1e-13 and abs(fl["Tv"] - 1) < 1e-13
+    assert max(abs(fl["u" + a]) for a in "xyz"[:dim]) < 1e-15
+    J = o.collision()[0]
+    JR = o.rad_source()[0]
+    m = _moments_of_J_nd(c, J, JR)
+    gas = c.gas
+    tau = np.sqrt(2 / np.pi) * c.flow.Kn_gas
+    assert abs(m["mass"]) < 1e-13 and np.abs(m["mom"]).max() < 1e-13 and abs(m["energy"]) < 1e-13
+    ax = "xyz"[:dim]
+    sig = np.array([[fl["sig" + "".join(sorted((ax[a], ax[b]), key=ax.index))] for b in range(dim)]
+                    for a in range(dim)])
+    assert np.abs(sig).max() > 1e-2
+    np.testing.assert_allclose(m["stress"], -sig / tau, rtol=1e-12, atol=1e-13)
+    A = FA.mason_A(gas.d_r, gas.d_v, gas.Z_r, gas.Z_v, gas.Sc)
+    q = np.array([[fl[n + a] for a in ax] for n in ("qt", "qr", "qv")])
+    assert (np.abs(q).max(axis=1) > 1e-2).all()
+    np.testing.assert_allclose(np.stack([m["qt"], m["qr"], m["qv"]]), -(A @ q) / tau, rtol=1e-11, atol=1e-13)
+    e_R = 4 * gas.sigma_R * fl["TR"] ** 4
+    assert abs(m["er"]) < 1e-13
+    np.testing.assert_allclose(m["ev"], -c.flow.k_eff * (4 * gas.sigma_R - e_R), rtol=1e-12)
+    np.testing.assert_allclose(m["eR"], c.flow.k_eff * (4 * gas.sigma_R - e_R), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- P3: synthetic-equation sources
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_macro_sources_are_the_moments_of_the_kinetic_sources(dim):
+    """P3 (Sec. 2.2): the source terms of the synthetic equations evaluated on the moments of a state equal
+    the velocity moments of the kinetic relaxation and emission / absorption sources of that state: zero
+    for mass, momentum and total energy, int J_1 for e_r, int J_2 for e_v, int J_R dOmega for e_R.  States
+    with T_r != T_t != T_v: the reference distributions then sit at T_tr, T_tv != 1, which the Gauss-Hermite
+    rule integrates to near round-off."""
+    if dim == 1:
+        c = _case_1d(nv=64)
+    elif dim == 2:
+        c = _case_2d_gh(nvx=24)
+    else:
+        c = _case_3d_gh(nvx=14)
+    o = Oracle(c)
+    D = c.mesh.dim
+    xi = c.vgrid.xi
+    M = maxwell((xi ** 2).sum(axis=1), D)
+    Tr, Tv = 1.08, 0.93
+    slots = [M, 0.5 * c.gas.d_r * Tr * M, 0.5 * c.gas.d_v * Tv * M] + ([(3 - D) * M] if D < 3 else [])
+    f = np.tile(np.stack(slots)[None], (c.mesh.nc, 1, 1))
+    I = np.full((c.mesh.nc, c.ords.no), 1.3 * c.gas.sigma_R / np.pi)
+    o.set_state(f, I)
+    W = o.macro_state()
+    Q = o.macro_sources(W)[0]
+    m = _moments_of_J_nd(c, o.collision()[0], o.rad_source()[0]) if D > 1 else None
+    if D == 1:
+        J, JR = o.collision()[0], o.rad_source()[0]
+        w = c.vgrid.w
+        m = dict(er=J[1] @ w, ev=J[2] @ w, eR=JR @ c.ords.w, mass=J[0] @ w)
+    NW = D + 5
+    assert np.abs(Q[: D + 2]).max() == 0.0 and abs(m["mass"]) < 1e-13
+    scale = np.abs(Q[D + 2:]).max()
+    assert scale > 1e-2
+    np.testing.assert_allclose(Q[D + 2], m["er"], rtol=1e-10, atol=1e-13 * scale)
+    np.testing.assert_allclose(Q[D + 3], m["ev"], rtol=1e-10, atol=1e-13 * scale)
+    np.testing.assert_allclose(Q[NW - 1], m["eR"], rtol=1e-12, atol=1e-14 * scale)
+
+
+def test_macro_residual_vanishes_for_a_uniform_state():
+    """A uniform equilibrium state (gas at rest, T = 1, radiation at B(T)) bounded only by far fields at the
+    same state satisfies the discrete synthetic equations exactly: every face flux cancels over closed cells,
+    the HoTs vanish, the boundary correction returns the kinetic (Euler) flux and the sources vanish."""
+    import dataclasses
+
+    from workloads import case_cylinder, mesh_annulus
+    c = case_cylinder(mesh=mesh_annulus(n_theta=24, n_r=8), nvx=16, xmax=8.0, Ma=2.0, Kn=0.1, n_theta=2, n_phi=4)
+    ff = dict(kind=1, rho=1.0, T=1.0, u=(0.0, 0.0, 0.0))
+    c = dataclasses.replace(c, vgrid=gauss_hermite_grid(16, 2), bcs=[ff, ff], init_u=np.zeros_like(c.init_u))
+    o = Oracle(c)
+    W = o.macro_state()
+    R = o.macro_residual(W)
+    assert np.abs(R).max() < 1e-12 * np.abs(W).max()
+
+
+# ---------------------------------------------------------------- P6: absorbing-emitting slab, thick limit
+def _frozen_gas_rte(n, k_eff, Tgas, second_order=1, sigma_R=0.1, T=(1.0, 2.0), iters=400):
+    """Radiative transfer alone in the 1D slab between black walls at T[0] and T[1]: the gas is held at the
+    equilibrium of the temperature profile Tgas(x) (its distribution reset after every kinetic step), so the
+    intensity converges to the discrete steady state of the transport equation with emission
+    k_eff sigma_R T_v^4 / pi and absorption k_eff I.  Four Gauss-Legendre ordinates in mu."""
+    c = case_fourier_1d(n=n, nv=16, no=4, Kn=0.1, tau_opt=k_eff, sigma_R=sigma_R, T_left=T[0], T_right=T[1], T0=1.5)
+    x = c.mesh.ctr[:, 0]
+    o = Oracle(c, sweep=1, kin_sweeps=80, second_order=second_order)
+    o.init_equilibrium(np.ones(n), np.zeros((n, 1)), Tgas(x))
+    f0, I = o.get_state()
+    for _ in range(iters):
+        o.kinetic_step()
+        _, In = o.get_state()
+        done = np.abs(In - I).max() < 1e-15
+        I = In
+        o.set_state(f0, I)
+        if done:
+            break
+    return c, x, I, o
+
+
+def test_absorbing_emitting_slab_second_order():
+    """P6: uniform gas at T = 1.5 between black walls at 1 and 2, optical thickness 2: per ordinate the exact
+    intensity is I_w exp(-k s / |mu|) + B (1 - exp(-k s / |mu|)) with s the distance from the emitting wall
+    and B = sigma_R T^4 / pi.  Away from the walls (0.2 < x < 0.8) the limited second-order scheme converges
+    at rate 2 and the first-order scheme at rate 1 under mesh refinement."""
+    k = 2.0
+
+    def exact(c, x):
+        s = c.gas.sigma_R
+        B = s * 1.5 ** 4 / np.pi
+        out = np.empty((len(x), c.ords.no))
+        for q, mu in enumerate(c.ords.omega[:, 0]):
+            d, Iw = (x, s * 1.0 / np.pi) if mu > 0 else (1 - x, s * 16.0 / np.pi)
+            e = np.exp(-k * d / abs(mu))
+            out[:, q] = Iw * e + B * (1 - e)
+        return out
+
+    for so, ns, lo, hi in ((1, (16, 32, 64, 128), 1.6, 2.4), (0, (32, 64, 128), 0.8, 1.2)):
+        err = []
+        for n in ns:
+            c, x, I, _ = _frozen_gas_rte(n, k, lambda x: np.full_like(x, 1.5), second_order=so)
+            Ie = exact(c, x)
+            m = (x > 0.2) & (x < 0.8)
+            err.append(np.abs(I - Ie)[m].max() / np.abs(Ie).max())
+        slopes = np.log2(np.array(err[:-1]) / np.array(err[1:]))
+        assert (slopes > lo).all() and (slopes < hi).all(), (so, err, slopes)
+
+
+def test_optically_thick_limit():
+    """P6, optically thick limit (Sec. 5): with the gas held at T(x) = 1 + x, as the optical thickness grows
+    the radiation temperature tends to T_v and the radiative heat flux to the diffusion (Rosseland) form
+    q_R = -(4 sigma_R / (3 k_eff)) d(T_v^4)/dx away from the walls; the error falls like 1/k_eff^2."""
+    Tg = lambda x: 1.0 + x  # noqa: E731
+    errs = []
+    for k in (10.0, 20.0, 40.0):
+        c, x, I, o = _frozen_gas_rte(100, k, Tg)
+        F = o.fields()
+        nm = field_names(1)
+        s = c.gas.sigma_R
+        m = (x > 0.3) & (x < 0.7)
+        eR, eRd = 4 * s * F[:, nm.index("TR")] ** 4, 4 * s * Tg(x) ** 4
+        qR, qd = F[:, nm.index("qRx")], -(4 * s / (3 * k)) * 4 * Tg(x) ** 3
+        errs.append((np.abs(eR - eRd)[m].max() / eRd[m].max(), np.abs(qR - qd)[m].max() / np.abs(qd[m]).max()))
+    errs = np.array(errs)
+    assert (errs[:-1] / errs[1:] > 3.0).all(), errs
+    assert errs[-1].max() < 1.5e-3, errs
+
+
+# ---------------------------------------------------------------- P7: Fourier analysis on a periodic grid
+def _periodic_cis_sequence(L, Kn, k_eff, sigma_R, mode, n=16, sweeps=200, iters=14, amp=1e-6):
+    """Conventional iterations of the oracle on a periodic 1D grid of n cells (first-order upwind, the
+    implicit transport inverted to round-off, no pseudo-time terms, the emission kept explicit as in the
+    paper's analysis) from a state perturbed about the global equilibrium (rho = T = 1) by one Fourier mode
+    exp(i theta x) in every longitudinal moment.  Returns the case, theta and the complex amplitudes of the
+    nine longitudinal moment errors (rho, u_x, T_t, T_r, T_v, e_R, q_tx, q_rx, q_vx) per iteration."""
+    import dataclasses
+
+    from workloads import mesh_periodic_1d
+    c = case_fourier_1d(n=n, nv=48, no=16, Kn=Kn, tau_opt=k_eff, sigma_R=sigma_R)
+    m = mesh_periodic_1d(n, L)
+    c = dataclasses.replace(c, mesh=m, bcs=[], init_rho=np.ones(n), init_u=np.zeros((n, 1)), init_T=np.ones(n))
+    o = Oracle(c, period=L, rad_implicit=0, second_order=0, cfl_meso=1e16, cfl_v=1e16, sweep=1, kin_sweeps=sweeps)
+    x, xi, g = m.ctr[:, 0], c.vgrid.xi[:, 0], c.gas
+    th = 2 * np.pi * mode / L
+
+    def ph(p):
+        return amp * np.cos(th * x + p)
+
+    rho, u, Tt, Tr, Tv = 1 + ph(0), ph(1), 1 + ph(2), 1 + ph(3), 1 + ph(4)
+    G = rho[:, None] * np.exp(-(xi[None] - u[:, None]) ** 2 / (2 * Tt[:, None])) / np.sqrt(2 * np.pi * Tt[:, None])
+    M = maxwell(xi * xi, 1)
+    G = G + ph(5)[:, None] * (xi * (xi ** 2 - 3) * M)[None]
+    f = np.stack([G, 0.5 * g.d_r * Tr[:, None] * G + ph(6)[:, None] * (xi * M)[None],
+                  0.5 * g.d_v * Tv[:, None] * G + ph(1.5)[:, None] * (xi * M)[None], 2 * Tt[:, None] * G], axis=1)
+    I = np.tile(g.sigma_R / np.pi, (n, c.ords.no)) * (1 + 4 * ph(2.5))[:, None]
+    o.set_state(f, I)
+    nm = field_names(1)
+    cols = [nm.index(k) for k in ("rho", "ux", "Tt", "Tr", "Tv", "TR", "qtx", "qrx", "qvx")]
+    eq = np.array([1, 0, 1, 1, 1, 1, 0, 0, 0.0])
+    V = []
+    for _ in range(iters):
+        d = o.fields()[:, cols] - eq
+        d[:, 5] *= 16 * g.sigma_R  # T_R error -> e_R error (e_R = 4 sigma_R T_R^4 about T_R = 1)
+        V.append((d * np.exp(-1j * th * x)[:, None]).sum(axis=0) / n)
+        o.kinetic_step()
+    return c, th, np.array(V).T
+
+
+def _discrete_cis_block(c, th, L, Kn, k_eff, sigma_R):
+    g = c.gas
+    grids = FA.product_grids(c.vgrid.xi[:, 0], c.vgrid.w, c.ords.omega[:, 0], c.ords.w)
+    C = FA.cis_matrix(th, Kn, 1.0 / k_eff, sigma_R, d_r=g.d_r, d_v=g.d_v, Z_r=g.Z_r, Z_v=g.Z_v, Sc=g.Sc, grids=grids,
+                      symbol=FA.upwind_symbol(th, L / c.mesh.nc))
+    return C[np.ix_(FA.LONGITUDINAL, FA.LONGITUDINAL)]
+
+
+@pytest.mark.parametrize("L,Kn,k_eff,sigma_R,sweeps", [(1.0, 0.05, 2.0, 0.2, 200), (2.0, 1.0, 0.5, 0.1, 400)],
+                         ids=["near_continuum", "transitional"])
+def test_periodic_cis_matches_discrete_fourier_analysis(L, Kn, k_eff, sigma_R, sweeps):
+    """P7 (Sec. 4.2): the error propagation matrix C(theta) of the conventional iteration, built from the
+    paper's linearised error equations with the discrete upwind symbol and the oracle's own velocity and
+    ordinate rules, predicts the oracle's iterations on a periodic grid: each iterate's moment errors are
+    C(theta) times the previous ones (to the 1e-6 linearisation level of the perturbation), and the spectral
+    radius fitted from the sequence equals that of C(theta)."""
+    c, th, V = _periodic_cis_sequence(L, Kn, k_eff, sigma_R, mode=1, sweeps=sweeps)
+    Cl = _discrete_cis_block(c, th, L, Kn, k_eff, sigma_R)
+    res = np.abs(V[:, 2:] - Cl @ V[:, 1:-1]).max() / np.abs(V[:, 1:-1]).max()
+    assert res < 1e-6, res
+    Chat = V[:, 2:] @ np.linalg.pinv(V[:, 1:-1])
+    rho_fit = np.abs(np.linalg.eigvals(Chat)).max()
+    rho_c = FA.spectral_radius(Cl)
+    assert 0.2 < rho_c < 0.99
+    assert abs(rho_fit - rho_c) < 1e-5 * rho_c, (rho_fit, rho_c)
+
+
+def test_periodic_cis_diverges_at_strong_coupling():
+    """The conventional iteration diverges for strong gas-photon coupling ((Kn_gas / Kn_photon) sigma_R = 0.5,
+    Sec. 4.2): on the periodic grid the oracle's error grows by the spectral radius of C(theta) (> 1) per
+    iteration while the perturbation stays linear."""
+    L, Kn, k_eff, sigma_R = 1.0, 0.1, 10.0, 0.5
+    c, th, V = _periodic_cis_sequence(L, Kn, k_eff, sigma_R, mode=2, iters=7)
+    rho_c = FA.spectral_radius(_discrete_cis_block(c, th, L, Kn, k_eff, sigma_R))
+    assert rho_c > 5
+    amp = np.abs(V).max(axis=0)
+    growth = amp[4:] / amp[3:-1]  # after the sub-dominant modes have faded, before the error reaches 1e-2
+    assert amp[-1] < 1e-1
+    np.testing.assert_allclose(growth, rho_c, rtol=1e-3)

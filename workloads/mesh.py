@@ -29,6 +29,7 @@ class Mesh:
     face_area: np.ndarray
     face_ctr: np.ndarray
     name: str = ""
+    period: float = 0.0  # > 0: periodic along x with this length (mesh_periodic_1d)
 
     @property
     def nc(self) -> int:
@@ -281,8 +282,21 @@ def mesh_annulus(r0: float = 1.0, r1: float = 6.0, n_theta: int = 256, n_r: int 
     return _tri_mesh_from_points(pts, keep, classify, f"annulus_{n_theta}x{n_r}")
 
 
-def mesh_periodic_1d(*args, **kwargs):  # pragma: no cover - periodic FV meshes are not used
-    raise NotImplementedError("periodic finite-volume meshes are not part of this package")
+def mesh_periodic_1d(n: int, length: float = 1.0) -> Mesh:
+    """Uniform periodic 1D mesh of ``n`` cells on [0, length): face i (at x = i h) joins cell i - 1 (mod n) to
+    cell i, unit normal +x; no boundary faces.  The geometry across the face at x = 0 is only meaningful to a
+    solver that takes coordinate differences modulo ``length`` (``Mesh.period``)."""
+    h = length / n
+    xs = np.arange(n + 1) * h
+    vol = np.full(n, h)
+    ctr = (0.5 * (xs[1:] + xs[:-1]))[:, None]
+    fc = np.array([((i - 1) % n, i) for i in range(n)], dtype=np.int64)
+    fn = np.ones((n, 1))
+    fa = np.ones(n)
+    fctr = xs[:n, None].copy()
+    m = Mesh(1, vol, ctr, fc, fn, fa, fctr, f"periodic{n}", period=float(length))
+    m.check()
+    return m
 
 
 def mesh_capsule(n_s: int = 40, n_phi: int = 24, n_r: int = 24, r_nose: float = 1.0, cone_deg: float = 33.0,

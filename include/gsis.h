@@ -84,7 +84,7 @@ typedef struct {
 } gsis_flow;
 
 /* Iteration options.  Defaults (gsis_default_opts): GSIS, FP32, tol 1e-6, max_outer 1000,
- * n_precond 10, cfl_meso 1e5, cfl_v 5, kin_sweeps 8, kin_omega 1, limiter_K 5, second_order 1,
+ * n_precond 10, cfl_meso 1e5, cfl_v 5, kin_sweeps 8, kin_omega 1, limiter_K 10, second_order 1,
  * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2, first_order_iters 0, sweep JACOBI. */
 typedef struct {
     int32_t scheme;       /* GSIS_CIS or GSIS_GSIS */
@@ -96,7 +96,8 @@ typedef struct {
     double cfl_v;         /* per-velocity pseudo time step CFL of the Jacobi point relaxation */
     int32_t kin_sweeps;   /* Jacobi sweeps of the first-order implicit kinetic operator */
     double kin_omega;     /* relaxation of the kinetic increment */
-    double limiter_K;     /* Venkatakrishnan constant, eps^2 = (K h)^3 */
+    double limiter_K;     /* Venkatakrishnan constant: eps^2 = (K h)^3 M^2, h = V^(1/D), M the largest |value| of the
+                             limited variable over the cell and its face neighbours */
     int32_t second_order; /* limited second-order reconstruction of f and I */
     double cfl_macro;     /* pseudo time step CFL of the synthetic equations */
     double inner_tol;     /* relative drop of the macro residual that ends the inner solve */

@@ -18,7 +18,7 @@ from .build import LIB, build
 _lib = None
 
 # option vector layout of orc_create
-DEFAULT_OPTS = dict(cfl_meso=1e5, cfl_macro=1e3, limiter_K=5.0, inner_tol=1e-7, max_inner=100, n_sweeps=2,
+DEFAULT_OPTS = dict(cfl_meso=1e5, cfl_macro=1e3, limiter_K=10.0, inner_tol=1e-7, max_inner=100, n_sweeps=2,
                     second_order=1, cfl_v=5.0, kin_sweeps=8, kin_omega=1.0, diss_ref=1, macro_order2=0, sweep=0, period=0.0,
                     rad_implicit=1)
 
@@ -57,6 +57,8 @@ def _load():
         lib.orc_solve.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_int, P]
         lib.orc_solve.restype = C.c_int
         lib.orc_set_second_order.argtypes = [P, C.c_int]
+        lib.orc_safeguard_hits.argtypes = [P]
+        lib.orc_safeguard_hits.restype = C.c_int64
         _lib = lib
     return _lib
 
@@ -190,6 +192,10 @@ class Oracle:
         inner = C.c_int(0)
         e = self.lib.orc_iterate(self.h, int(bool(gsis)), C.byref(inner))
         return e, inner.value
+
+    def safeguard_hits(self):
+        """Cell updates of the last synthetic solve that the positivity / trust-region safeguard shortened."""
+        return int(self.lib.orc_safeguard_hits(self.h))
 
     def set_second_order(self, so: int):
         """Switch the face reconstruction order between iterations (start-up protocols)."""

@@ -91,6 +91,7 @@ typedef struct orc_s {
     double *bsurf; /* 3 per face: q_conv, q_rad, p_w */
     double *rhow;  /* per face: wall re-emission density */
     int last_inner;
+    int64_t safeguard_hits; /* cell updates the positivity / trust-region safeguard shortened (last solve) */
 } orc_t;
 
 static int NWof(int D) { return D + 5; }
@@ -1342,7 +1343,7 @@ static void local_solve(const orc_t *o, const prim_t *p, const double *rhs, cons
  * never acts once the outer iteration is near its fixed point (the macro state then stays close to the
  * kinetic moments), but it keeps hypersonic start-ups (Ma 5 cylinder) from driving the synthetic solve to
  * vanishing temperatures in the expansion or to overflow. */
-static void positive_update(const orc_t *o, double *W, const double *dU, const double *Ws)
+static int positive_update(const orc_t *o, double *W, const double *dU, const double *Ws)
 {
     int D = o->D, NW = NWof(D);
     prim_t p0, ps;
@@ -1355,15 +1356,17 @@ static void positive_update(const orc_t *o, double *W, const double *dU, const d
         Wn[D + 1] += a * dU[D + 4];
         prim_t p1;
         prim_of(o, Wn, &p1);
+        const double lo = 0.5, hi = 2.0;
         if (Wn[0] >= 0.5 * W[0] && p1.Tt >= 0.5 * p0.Tt && Wn[D + 2] >= 0.5 * W[D + 2] &&
-            Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4] && Wn[0] >= 0.5 * Ws[0] &&
-            p1.Tt >= 0.5 * ps.Tt && Wn[D + 2] >= 0.5 * Ws[D + 2] && Wn[D + 3] >= 0.5 * Ws[D + 3] &&
-            Wn[D + 4] >= 0.5 * Ws[D + 4] && Wn[0] <= 2 * Ws[0] && p1.Tt <= 2 * ps.Tt &&
-            Wn[D + 2] <= 2 * Ws[D + 2] && Wn[D + 3] <= 2 * Ws[D + 3] && Wn[D + 4] <= 2 * Ws[D + 4]) {
+            Wn[D + 3] >= 0.5 * W[D + 3] && Wn[D + 4] >= 0.5 * W[D + 4] && Wn[0] >= lo * Ws[0] &&
+            p1.Tt >= lo * ps.Tt && Wn[D + 2] >= lo * Ws[D + 2] && Wn[D + 3] >= lo * Ws[D + 3] &&
+            Wn[D + 4] >= lo * Ws[D + 4] && Wn[0] <= hi * Ws[0] && p1.Tt <= hi * ps.Tt &&
+            Wn[D + 2] <= hi * Ws[D + 2] && Wn[D + 3] <= hi * Ws[D + 3] && Wn[D + 4] <= hi * Ws[D + 4]) {
             for (int i = 0; i < NW; ++i) W[i] = Wn[i];
-            return;
+            return m > 0;
         }
     }
+    return 1;
 }
 
 /* 1 when every boundary face is a wall */
@@ -1412,6 +1415,7 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
     face_hot(o, m, hotf);
     boundary_corr(o, W, bcorr);
     if (dref) dissipation_ref(o, W, dref);
+    o->safeguard_hits = 0;
     double kR = (o->keff > 0) ? 1.0 / (3 * o->keff) : 0.0;
     double res0 = 0;
     int it;
@@ -1506,7 +1510,7 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
             dW = dW2;
             dW2 = t;
         }
-        for (int64_t c = 0; c < nc; ++c) positive_update(o, W + c * NW, dW + c * NW, W0 + c * NW);
+        for (int64_t c = 0; c < nc; ++c) o->safeguard_hits += positive_update(o, W + c * NW, dW + c * NW, W0 + c * NW);
     }
     /* reading: in a domain closed by walls the solution is rescaled to the mass the outer iteration
      * started from (see rescale_mass) */
@@ -1913,6 +1917,9 @@ double orc_iterate(orc_t *o, int gsis, int *inner)
     free(m1);
     return e;
 }
+
+/* number of cell updates the safeguard of the last synthetic solve shortened or refused */
+int64_t orc_safeguard_hits(const orc_t *o) { return o->safeguard_hits; }
 
 /* Switch the face reconstruction between first (0) and second (1) order between iterations. */
 void orc_set_second_order(orc_t *o, int so) { o->second_order = so; }

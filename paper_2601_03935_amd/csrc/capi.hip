@@ -906,7 +906,7 @@ void gsis_default_opts(gsis_opts *o)
     o->cfl_v = 5.0;
     o->kin_sweeps = 8;
     o->kin_omega = 1.0;
-    o->limiter_K = 5.0;
+    o->limiter_K = 10.0;
     o->second_order = 1;
     o->cfl_macro = 1e3;
     o->inner_tol = 1e-7;

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_opts():
     o = G.default_opts()
     assert o.scheme == G.GSIS_GSIS and o.precision == G.GSIS_FP32
-    assert o.kin_sweeps == 8 and o.max_inner == 100 and o.n_precond == 10 and o.limiter_K == 5.0
+    assert o.kin_sweeps == 8 and o.max_inner == 100 and o.n_precond == 10 and o.limiter_K == 10.0
     o2 = G.default_opts(precision="fp64", scheme="cis", tol=1e-8)
     assert o2.precision == G.GSIS_FP64 and o2.scheme == G.GSIS_CIS and o2.tol == 1e-8
 

@@ -257,7 +257,7 @@ def test_converged_gsis_cavity_fp32():
     against the FP64 oracle within 1e-5 relative L2 on every field, every field finite, every intensity
     non-negative and e_R positive (the limiter threshold follows the local magnitude of each variable)."""
     case = case_cavity(mesh=mesh_cavity(h=0.05), nvx=12, n_theta=2, n_phi=4, Kn=0.1)
-    s, o = _pair(case, precision="fp32", tol=1e-6, max_outer=300)
+    s, o = _pair(case, precision="fp32", tol=1e-6, max_outer=300, limiter_K=5.0)
     no, _ = o.solve(gsis=True, n_precond=10, tol=1e-6, max_outer=300)
     rc, rep, hist = s.solve()
     assert rc == 0 and no > 0

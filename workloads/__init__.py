@@ -15,6 +15,7 @@ from .quadrature import (  # noqa: F401
     ordinates_slab,
     ordinates_hemisphere,
     ordinates_sphere,
+    uniform_box_grid,
 )
 from .cases import (  # noqa: F401
     Gas,

@@ -21,6 +21,7 @@ from .quadrature import (
     ordinates_slab,
     ordinates_hemisphere,
     ordinates_sphere,
+    uniform_box_grid,
 )
 
 BC_WALL = 0  # diffuse, fully accommodating wall; black for radiation
@@ -120,16 +121,23 @@ def case_cylinder(Kn: float = 0.01, tau_opt: float = 1.0, Ma: float = 5.0, nvx: 
 
 def case_capsule(Kn: float = 0.01, tau_opt: float = 1.0, Ma: float = 10.0, nvx: int = 24, xmax: float = 20.0,
                  n_theta: int = 8, n_phi: int = 12, sigma_R: float = 0.045, T_w: float = 2.0,
-                 mesh_kw: dict | None = None) -> Case:
-    """Hypersonic flow past a blunt capsule (spherical cap + 33 degree cone), tetrahedra, full 3D velocities."""
+                 mesh_kw: dict | None = None, vgrid: str = "nc") -> Case:
+    """Hypersonic flow past a blunt capsule (spherical cap + 33 degree cone), tetrahedra, full 3D velocities.
+    vgrid "nc": Newton-Cotes grid on [-xmax, xmax]^3 clustered at 0; "box": uniform nvx^3 grid on
+    [-15, u_inf + 9] x [-15, 15]^2, which resolves the T = 1 free stream (spacing ~1.5 at Ma 10) and hot gas at
+    rest (stagnation temperature ~17 at Ma 10, thermal speed ~4)."""
     mesh = mesh_capsule(**(mesh_kw or {}))
     gas = Gas(sigma_R=sigma_R)
     u_inf = Ma * np.sqrt(gas.gamma * 1.0)
+    if vgrid == "box":
+        vg = uniform_box_grid(nvx, [(-15.0, u_inf + 9.0), (-15.0, 15.0), (-15.0, 15.0)])
+    else:
+        vg = newton_cotes_grid(nvx, 3, xmax)
     flow = Flow(Kn_gas=Kn, k_eff=tau_opt, rho_inf=1.0, T_inf=1.0, u_inf=(u_inf, 0.0, 0.0))
     bcs = [dict(kind=BC_WALL, T=T_w), dict(kind=BC_FARFIELD, rho=1.0, T=1.0, u=(u_inf, 0.0, 0.0))]
     r, u, T = _uniform_init(mesh, 1.0, (u_inf, 0.0, 0.0), 1.0)
-    return Case(f"capsule_nc{mesh.nc}_Ma{Ma}_Kn{Kn}", mesh, newton_cotes_grid(nvx, 3, xmax),
-                ordinates_sphere(n_theta, n_phi), gas, flow, bcs, r, u, T, meta=dict(Ma=Ma))
+    return Case(f"capsule_nc{mesh.nc}_Ma{Ma}_Kn{Kn}", mesh, vg, ordinates_sphere(n_theta, n_phi), gas, flow, bcs, r,
+                u, T, meta=dict(Ma=Ma))
 
 
 def rankine_hugoniot(Ma: float, gamma: float):

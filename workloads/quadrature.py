@@ -99,6 +99,24 @@ def newton_cotes_grid(n: int, dimv: int, xmax: float, a: float = 0.3) -> Velocit
     return VelocityGrid(dimv, np.ascontiguousarray(xi), np.ascontiguousarray(ww), f"NC{n}^{dimv}_x{xmax}")
 
 
+def uniform_box_grid(n: int, ranges) -> VelocityGrid:
+    """n points per axis, uniform on each axis's [lo, hi] with trapezoid weights (spectrally accurate for a
+    Maxwellian whose thermal speed is comparable to or above the spacing and whose tails fall inside the
+    box).  ``ranges`` gives (lo, hi) per axis; a box shifted along the free stream resolves both the cold
+    free stream and the hot gas at rest behind a shock with the same node count."""
+    xs, ws = [], []
+    for lo, hi in ranges:
+        x = np.linspace(lo, hi, n)
+        w = np.full(n, (hi - lo) / (n - 1))
+        w[0] *= 0.5
+        w[-1] *= 0.5
+        xs.append(x)
+        ws.append(w)
+    dimv = len(ranges)
+    xi, ww = _product(xs, ws, dimv)
+    return VelocityGrid(dimv, np.ascontiguousarray(xi), np.ascontiguousarray(ww), f"U{n}^{dimv}")
+
+
 def ordinates_slab(n: int) -> Ordinates:
     """Plane-parallel set: Gauss-Legendre in mu = cos(theta), azimuth integrated (weight 2 pi w)."""
     mu, w = np.polynomial.legendre.leggauss(n)

@@ -1,14 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark of the GSIS / DVM hot path on one MI355X.
 
-Workload: 2D radiative lid-driven, heated cavity with a concentric square obstacle on ~20k unstructured
-triangles (Delaunay of seeded jittered points), 32x32 Gauss-Hermite reduced velocity grid, 32 gray
-ordinates (4 x 8, z-mirrored), Kn = 0.1, optical thickness 1, FP32 distributions with FP64 moments and
-macro solve.  Synthetic inputs, no data files.
+Default workload: the 3D radiative Mach-10 blunt capsule (spherical-cap forebody of radius 1, 33 degree
+cone) on 213,976 tetrahedra with a 24^3 velocity grid (three distributions per node) and 96 gray
+ordinates, Kn 0.01, optical thickness 1, sigma_R 0.045: FP32 distributions (35.5 GB per copy) with FP64
+moments, synthetic-equation solve and residual.  Synthetic inputs, no data files.
 
-One step = one GSIS outer iteration: kinetic step (gradients, residual with upwind fluxes and the
-relaxation source, Jacobi sweeps), moments, boundary flux moments, synthetic-equation solve,
-synchronisation, moments and residual.  Prints one JSON line.
+One step = one GSIS outer iteration: per-cell prologue, kinetic step (limited gradients, wall densities,
+residual with upwind fluxes and the relaxation source, Jacobi sweeps, radiation), moments, boundary flux
+moments, synthetic-equation solve, synchronisation, moments and residual.  Prints one JSON line.  Other
+workloads (--workload): the 2D cavity, the Ma 5 cylinder, the normal shock, one velocity shard of the
+capsule.
 """
 
 from __future__ import annotations
@@ -24,7 +26,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a copy)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_cavity20k_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2601_03935_amd", "csrc", "kinetic.hip")
 
 
@@ -39,13 +40,17 @@ def kernel_source_sha256(path=KERNEL_SOURCE, name="k_sweep_v"):
     return hashlib.sha256(src[i:j].encode()).hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the sweep kernel from the committed counter summary, or None when the kernel
-    definition has changed since the counters were taken."""
+KERNEL_NAMES = {"sweep": "k_sweep_v", "residual": "k_residual_v", "grad": "k_grad_v"}
+
+
+def measured_traffic(kind="sweep", workload="capsule"):
+    """HBM bytes per launch of a DVM kernel from the committed counter summary of the workload, or None when
+    there is none or the kernel definition has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL_NAMES.get(kind, kind)}_{workload}_traffic.json")
     try:
-        t = json.load(open(TRAFFIC_FILE))
-        sha = kernel_source_sha256()
-    except (OSError, ValueError):
+        t = json.load(open(path))
+        sha = kernel_source_sha256(name=KERNEL_NAMES[kind])
+    except (OSError, ValueError, KeyError):
         return None
     return t["bytes_per_launch"] if t.get("kernel_source_sha256") == sha else None
 
@@ -53,8 +58,9 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None, help="timed GSIS iterations (capsule 10, cavity 20)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed iterations before (capsule 3: two conventional and one GSIS; cavity 5)")
     ap.add_argument("--Kn", type=float, default=0.1)
     ap.add_argument("--tau", type=float, default=1.0, help="optical thickness (= 1 / Kn_photon)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
@@ -63,8 +69,9 @@ def parse():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-outer", type=int, default=600)
-    ap.add_argument("--workload", default="cavity", choices=["cavity", "capsule-shard", "cylinder", "shock"],
-                    help="cavity: GSIS iterations of the 2D radiative cavity (default); capsule-shard: kinetic steps "
+    ap.add_argument("--workload", default="capsule", choices=["capsule", "cavity", "capsule-shard", "cylinder", "shock"],
+                    help="capsule: GSIS iterations of the 3D Ma 10 capsule at full size (default); cavity: GSIS "
+                         "iterations of the 2D radiative cavity; capsule-shard: kinetic steps "
                          "of the 3D capsule on one eighth of its velocity space (one GPU's share); cylinder: the "
                          "Ma 5 cylinder solved from the free stream to the tolerance; shock: iterations to 2e-6 of "
                          "the Ma 5 normal shock, GSIS and conventional")
@@ -72,9 +79,192 @@ def parse():
     ap.add_argument("--max-stage", type=int, default=400, help="iteration limit per Mach stage (cylinder)")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--ws-cases", type=int, default=24, help="training cases of the warm-start network")
+    ap.add_argument("--no-fp64", action="store_true", help="capsule: skip the FP64 leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibration of the HBM byte counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.steps is None:
+        a.steps = 10 if a.workload == "capsule" else 20
+    if a.warmup is None:
+        a.warmup = 3 if a.workload == "capsule" else 5
+    return a
+
+
+def capsule_case(nvx=24, mesh_kw=None):
+    """The 3D capsule workload: Ma 10, Kn 0.01, optical thickness 1, sigma_R 0.045, 96 ordinates (8
+    Gauss-Legendre polar x 12 azimuths), nvx^3 velocities on the box [-15, u_inf + 9] x [-15, 15]^2."""
+    from workloads import case_capsule
+
+    return case_capsule(Kn=0.01, tau_opt=1.0, Ma=10.0, nvx=nvx, n_theta=8, n_phi=12, sigma_R=0.045,
+                        mesh_kw=mesh_kw or dict(n_s=46, n_phi=28, n_r=28), vgrid="box")
+
+
+# Limiter constant of the capsule runs: the limiter acts through (K h)^1.5 and the tetrahedra of the capsule
+# mesh are ~10x larger than the cavity's triangles; K = 1 keeps (K h)^1.5 near the cavity's value, where the
+# default K = 10 leaves the reconstruction unlimited and the second-order iteration unstable on tetrahedra.
+CAPSULE_K = 1.0
+
+
+def _start_capsule(s, case):
+    """Gas at rest (rho = T = 1) inside, the Ma 10 free stream at the far field: the impulsive start from the
+    uniform free stream empties the wake within two iterations on this velocity grid, the start from rest
+    keeps every cell a gas state for the ~15 iterations the benchmark runs."""
+    import numpy as np
+
+    n = case.mesh.nc
+    s.init_equilibrium(np.ones(n), np.zeros((n, 3)), np.ones(n))
+
+
+def kernel_table(stats, steps):
+    out = {}
+    for k, (tms, n, by) in stats.items():
+        if n:
+            out[k] = dict(ms_per_step=tms / steps, launches_per_step=n / steps,
+                          alg_gbs=(by / (tms * 1e-3) / 1e9) if by > 0 and tms > 0 else None)
+    return out
+
+
+def bench_capsule(a):
+    """GSIS iterations of the 3D capsule at full size (see capsule_case): two conventional and a+ GSIS warm-up
+    iterations from the start from rest, then a.steps timed GSIS iterations run back to back (one host wait),
+    with HIP events around every kernel kind on the library's stream."""
+    import numpy as np
+    import torch
+
+    from paper_2601_03935_amd.gsis import Solver
+
+    case = capsule_case()
+    nc, nv, no = case.mesh.nc, case.vgrid.nv, case.ords.no
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    s = Solver(case, device=0, stream=stream.cuda_stream, precision=a.precision, limiter_K=CAPSULE_K)
+    _start_capsule(s, case)
+    free, total = torch.cuda.mem_get_info()
+    mem_gb = (total - free) / 1e9
+    s.iterate(gsis=False, n=2)
+    if a.warmup > 2:
+        s.iterate(gsis=True, n=a.warmup - 2)
+    torch.cuda.synchronize()
+    s.set_profiling(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    eps, inner = s.iterate(gsis=True, n=a.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    stats = s.kernel_stats()
+    s.set_profiling(False)
+    F = s.fields()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    kernels = kernel_table(stats, a.steps)
+    es = 4 if a.precision == "fp32" else 8
+    unit_bytes = 2 * 3 * es  # per cell-velocity per kinetic step: read and write f once, three distributions
+    units = nc * nv
+    # dominant DVM kernel by time; its launches each cover every cell and velocity
+    dom = max(("grad", "residual", "sweep"), key=lambda k: stats[k][0])
+    tms, n, _ = stats[dom]
+    achieved = unit_bytes * units / (tms / n * 1e-3) / 1e9
+    kin_ms = sum(stats[k][0] for k in ("grad", "residual", "sweep", "rad", "boundary")) / a.steps
+    kin_gbs = unit_bytes * units / (kin_ms * 1e-3) / 1e9
+    out = {
+        "metric": "DVM cell·velocity updates/s + HBM GB/s; wall time to 1e-6 residual",
+        "value": units * a.steps / (ms * 1e-3), "unit": "cell-velocity updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if a.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "3D Ma 10 blunt capsule (spherical cap radius 1 + 33 deg cone), full size",
+                   "cells": nc, "cell_type": "tetrahedra", "velocities": nv, "velocity_grid": "24^3 uniform box",
+                   "distributions_per_velocity": 3, "ordinates": no, "Kn_gas": 0.01, "Mach": 10.0,
+                   "optical_thickness": 1.0, "sigma_R": 0.045, "scheme": "GSIS", "kinetic_relaxation": "8 Jacobi sweeps",
+                   "max_inner": 100, "limiter_K": CAPSULE_K, "start": "gas at rest, Ma 10 far field",
+                   "storage": a.precision + " distributions, fp64 moments, synthetic solve and residual",
+                   "device_memory_gb": mem_gb},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "algorithmic_bytes_per_launch": unit_bytes * units,
+                     "accounting": "24 B per cell-velocity (f read and written once, 3 distributions, FP32) x "
+                                   "cells x velocities per launch / mean launch time"},
+        "kinetic_step": {"ms": kin_ms, "algorithmic_bytes": unit_bytes * units, "gbs": kin_gbs,
+                         "frac": kin_gbs / HBM_PEAK_GBS},
+        "kernels": kernels,
+        "inner_iterations_last_step": int(inner), "eps_last": eps,
+        "fields_finite": bool(np.isfinite(F).all()),
+    }
+    return out
+
+
+def bench_capsule_fp64(a):
+    """FP64 distributions on the same capsule mesh with one eighth of the velocities (12^3 on the same box;
+    24^3 in FP64 would need ~500 GB): GSIS iterations from the same start, for a per-step FP64 figure."""
+    import torch
+
+    from paper_2601_03935_amd.gsis import Solver
+
+    case = capsule_case(nvx=12)
+    nc, nv = case.mesh.nc, case.vgrid.nv
+    stream = torch.cuda.current_stream()
+    s = Solver(case, device=0, stream=stream.cuda_stream, precision="fp64", limiter_K=CAPSULE_K)
+    _start_capsule(s, case)
+    s.iterate(gsis=False, n=2)
+    s.iterate(gsis=True, n=1)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = 4
+    ev0.record(stream)
+    s.iterate(gsis=True, n=steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    s.close()
+    torch.cuda.empty_cache()
+    return {"velocities": nv, "cells": nc, "steps": steps, "ms_per_step": ms / steps,
+            "cell_velocity_updates_per_s": nc * nv * steps / (ms * 1e-3)}
+
+
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def capsule_cpu_baseline(a):
+    """The FP64 oracle (OpenMP over cells, OMP_NUM_THREADS threads) on a bounded sample of the capsule
+    workload: a reduced mesh (16 x 12 x 16 structured cells split into 18,432 tetrahedra) with 12^3
+    velocities, same physics and start; two untimed conventional iterations, then GSIS iterations timed until
+    a.cpu_seconds."""
+    import time as _t
+
+    from oracle import Oracle
+    from paper_2601_03935_amd.gsis import oracle_opts, default_opts
+
+    case = capsule_case(nvx=12, mesh_kw=dict(n_s=16, n_phi=12, n_r=16))
+    import numpy as np
+
+    o = Oracle(case, **oracle_opts(default_opts(limiter_K=CAPSULE_K)))
+    n = case.mesh.nc
+    o.init_equilibrium(np.ones(n), np.zeros((n, 3)), np.ones(n))
+    o.iterate(gsis=False)
+    o.iterate(gsis=False)
+    t0 = _t.perf_counter()
+    k = 0
+    while True:
+        o.iterate(gsis=True)
+        k += 1
+        if _t.perf_counter() - t0 > a.cpu_seconds:
+            break
+    dt = _t.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    return {"value": n * case.vgrid.nv * k / dt, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_info(),
+            "sample": f"{k} FP64 GSIS iterations (after 2 untimed conventional ones) of the capsule on {n} "
+                      f"tetrahedra x {case.vgrid.nv} velocities ({dt:.1f} s)"}
 
 
 def bench_capsule_shard(a):
@@ -334,6 +524,36 @@ def warmstart_leg(a, case, stream, plain_fields):
             "network": "4-layer MLP 7-256-256-256-7, tanh, BF16 weights, FP32 accumulation, Adam"}
 
 
+def cavity_time_to_tol(a, case=None, stream=None):
+    """Wall time to the residual tolerance on the 2D cavity from the uniform start (10 conventional iterations
+    first): the configured precision, plain FP64 GSIS, and the configured precision started from the
+    warm-start network's prediction."""
+    import torch
+
+    from paper_2601_03935_amd.gsis import Solver
+    from workloads import case_cavity
+
+    case = case or case_cavity(Kn=a.Kn, tau_opt=a.tau)
+    stream = stream or torch.cuda.current_stream()
+    out = {"workload": f"2D radiative cavity, {case.mesh.nc} triangles x {case.vgrid.nv} velocities, Kn {a.Kn}"}
+    plain_fields = None
+    for prec in dict.fromkeys((a.precision, "fp64")):
+        s2 = Solver(case, device=0, stream=stream.cuda_stream, precision=prec, tol=a.tol, max_outer=a.max_outer)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, rep, hist = s2.solve()
+        torch.cuda.synchronize()
+        out[prec] = {"tol": a.tol, "seconds": time.perf_counter() - t0, "iterations": int(rep.iters),
+                     "converged": bool(rc == 0), "eps_final": float(rep.eps_final),
+                     "t_kinetic_s": rep.t_kinetic_s, "t_macro_s": rep.t_macro_s}
+        if prec == a.precision:
+            plain_fields = s2.fields()
+        s2.close()
+    if not a.no_warmstart:
+        out[a.precision + "+warmstart"] = warmstart_leg(a, case, stream, plain_fields)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -343,6 +563,16 @@ def main():
     import numpy as np
     import torch
 
+    if a.workload == "capsule":
+        out = bench_capsule(a)
+        if not a.no_fp64:
+            out["fp64_same_mesh_12cubed_velocities"] = bench_capsule_fp64(a)
+        if not a.no_time_to_tol:
+            out["time_to_tol_cavity"] = cavity_time_to_tol(a)
+        if not a.no_cpu_baseline:
+            out["cpu_baseline"] = capsule_cpu_baseline(a)
+        print(json.dumps(out), flush=True)
+        return
     if a.workload == "capsule-shard":
         print(json.dumps(bench_capsule_shard(a)), flush=True)
         return
@@ -445,7 +675,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if dom == "sweep" and a.precision == "fp32" else None,
+                     "traffic": measured_traffic("sweep", "cavity20k") if a.precision == "fp32" else None,
                      "algorithmic_bytes_per_launch": by / n},
         "kinetic_step": {"ms": kin_ms, "ideal_bytes": kin_bytes_ideal,
                          "ideal_gbs": kin_bytes_ideal / (kin_ms * 1e-3) / 1e9},
@@ -454,24 +684,7 @@ def main():
         "eps_last": eps[-1],
     }
     if not a.no_time_to_tol:
-        # wall time to the residual tolerance from the uniform start (10 conventional iterations first),
-        # the configured precision and plain FP64 GSIS on the same GPU
-        out["time_to_tol"] = {}
-        plain_fields = None
-        for prec in dict.fromkeys((a.precision, "fp64")):
-            s2 = Solver(case, device=0, stream=stream.cuda_stream, precision=prec, tol=a.tol, max_outer=a.max_outer)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rc, rep, hist = s2.solve()
-            torch.cuda.synchronize()
-            out["time_to_tol"][prec] = {"tol": a.tol, "seconds": time.perf_counter() - t0, "iterations": int(rep.iters),
-                                        "converged": bool(rc == 0), "eps_final": float(rep.eps_final),
-                                        "t_kinetic_s": rep.t_kinetic_s, "t_macro_s": rep.t_macro_s}
-            if prec == a.precision:
-                plain_fields = s2.fields()
-            s2.close()
-        if not a.no_warmstart:
-            out["time_to_tol"][a.precision + "+warmstart"] = warmstart_leg(a, case, stream, plain_fields)
+        out["time_to_tol"] = cavity_time_to_tol(a, case, stream)
     if not a.no_cpu_baseline:
         from oracle import Oracle
 

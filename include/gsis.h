@@ -175,6 +175,15 @@ int32_t gsis_init_fields(gsis_t *h, const double *rho, const double *u, const do
 int32_t gsis_set_state(gsis_t *h, const double *f, const double *I);
 int32_t gsis_get_state(gsis_t *h, double *f, double *I);
 
+/* Checkpoint of the iteration state: f, I (in the storage precision, so a restore continues bit for bit)
+ * and the residual history of the last gsis_solve, written to `path` (a binary file of the documented
+ * layout, overwritten).  gsis_restore reads it into a handle set up with the same mesh, grids and
+ * precision (GSIS_E_ARG otherwise, or for a missing, foreign or truncated file) and marks the state
+ * initialised; the following iterations equal those the saved handle would have run.  GSIS_E_STATE before
+ * gsis_set_opts (restore) or without an initialised state (checkpoint). */
+int32_t gsis_checkpoint(gsis_t *h, const char *path);
+int32_t gsis_restore(gsis_t *h, const char *path);
+
 /* Outer iterations (Sec. 3).  gsis_iterate runs n iterations of the given scheme back to back (each
  * computes its residual; the host waits for the GPU once, after the last) and returns the last
  * epsilon in *eps, or a NaN of any iteration of the batch with GSIS_E_DIVERGED (the macro inner count

@@ -26,6 +26,8 @@
 
 #include <stdint.h>
 
+#include "gsis.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -66,6 +68,42 @@ int32_t gsis_mlp_adam_step(gsis_mlp_t *m, const gsis_mlp_train_opts *o, int64_t 
  * last epoch's batches (may be NULL). */
 int32_t gsis_mlp_train(gsis_mlp_t *m, int64_t n, const float *x, const float *t, const gsis_mlp_train_opts *o,
                        double *final_loss);
+
+/* ------------------------------------------------------------------ warm start of the solver
+ * Standardisation of the network's inputs and outputs: x_n = (x - x_mean) / x_scale per feature and
+ * y = y_n y_scale + y_mean per output (n_in, n_out at most 64). */
+typedef struct {
+    int32_t n_in, n_out;
+    double x_mean[64], x_scale[64], y_mean[64], y_scale[64];
+} gsis_ws_norm;
+
+/* Mean and standard deviation (population, plus 1e-12) of every column of the host rows x [n][n_in] and
+ * t [n][n_out], summed in row order in FP64. */
+int32_t gsis_ws_fit_norm(int64_t n, int32_t n_in, const double *x, int32_t n_out, const double *t,
+                         gsis_ws_norm *norm);
+/* Minibatch Adam training (as gsis_mlp_train) on raw host rows x [n][n_in], t [n][n_out]: both are
+ * standardised with `norm` on the device. */
+int32_t gsis_ws_train(gsis_mlp_t *m, const gsis_ws_norm *norm, int64_t n, const double *x, const double *t,
+                      const gsis_mlp_train_opts *o, double *final_loss);
+/* Prediction on raw host rows: standardisation, forward pass and de-standardisation on the device;
+ * y [n][n_out] (host). */
+int32_t gsis_ws_predict(gsis_mlp_t *m, const gsis_ws_norm *norm, int64_t n, const double *x, double *y);
+/* Network parameters and standardisation in one binary file (tag, dimensions, FP32 parameters, norm);
+ * gsis_ws_load requires a handle of the same dimensions (GSIS_E_ARG otherwise or for a foreign file) and
+ * resets its Adam state. */
+int32_t gsis_ws_save(gsis_mlp_t *m, const gsis_ws_norm *norm, const char *path);
+int32_t gsis_ws_load(gsis_mlp_t *m, gsis_ws_norm *norm, const char *path);
+
+/* Training targets of the solver's current state, [nc][D + 5]: log rho, u (D), log T_t, log T_r, log T_v,
+ * log T_R (GSIS_E_DIVERGED if a density or temperature is not positive). */
+int32_t gsis_ws_targets(gsis_t *h, double *t);
+/* Initial state from the network (the learned warm start; the paper's analogue is its Euler-solution start
+ * of the capsule case, Sec. 7.4): per-cell features x [nc][n_in] of the solver's mesh are standardised and
+ * passed through the network on the device, the outputs read as the targets above (n_out = D + 5), and the
+ * multi-temperature equilibrium of the predicted fields becomes f and I (as gsis_init_fields).  In a domain
+ * closed by walls the predicted density is scaled to the mass of the solver's current state, which the
+ * iteration conserves.  Runs on the solver's stream. */
+int32_t gsis_init_warmstart(gsis_t *h, gsis_mlp_t *m, const gsis_ws_norm *norm, const double *x);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/gsis.h"
+#include "../../include/gsis_warmstart.h"
 #include "gsis_dev.h"
 #include "gsis_kernels.h"
 
@@ -55,6 +56,9 @@ void dfree(T *&p)
 
 }  // namespace
 
+// residual sums per outer iteration: 7 for epsilon, then the count of cells that are not a physical gas state
+constexpr int kRed = 8;
+
 struct gsis_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -89,7 +93,7 @@ struct gsis_s {
     };
     std::vector<TRec> tpend;
     std::vector<hipEvent_t> tpool;
-    double *red_h = nullptr;  // pinned host memory: the 7 residual sums of each iteration of a batch
+    double *red_h = nullptr;  // pinned host memory: the kRed residual sums of each iteration of a batch
     int64_t red_cap = 0;      // capacity in iterations
     Prof prof;
 };
@@ -580,7 +584,7 @@ static bool alloc_macro(gsis_t *h)
     h->mom1 = dalloc<double>(nc * L.size(), ok);
     h->momh = dalloc<double>(nc * L.size(), ok);
     h->sp = dalloc<double>(nc * 2 * (D + 5), ok);
-    h->cellbuf = dalloc<double>(nc * 7, ok);
+    h->cellbuf = dalloc<double>(nc * kRed, ok);
     h->red = dalloc<double>(16, ok);
     if (ok) {
         (void)hipMemset(B.flags, 0, 4 * sizeof(int));
@@ -743,7 +747,7 @@ static bool reserve_red(gsis_t *h, int64_t n)
     if (h->red_h) (void)hipHostFree(h->red_h);
     h->red_h = nullptr;
     h->red_cap = 0;
-    if (hipHostMalloc((void **)&h->red_h, (size_t)n * 7 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&h->red_h, (size_t)n * kRed * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         h->red_h = nullptr;
         return false;
     }
@@ -759,10 +763,10 @@ static void epsilon_launch(gsis_t *h, const double *m1, const double *m0, int64_
     else if (D == 2) launch_residual<2>(m1, m0, h->m.vol, h->cellbuf, h->red, h->Mb.bpart, h->hm.nc,
                                          h->phys, h->stream);
     else launch_residual<3>(m1, m0, h->m.vol, h->cellbuf, h->red, h->Mb.bpart, h->hm.nc, h->phys, h->stream);
-    (void)hipMemcpyAsync(h->red_h + 7 * slot, h->red, 7 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    (void)hipMemcpyAsync(h->red_h + kRed * slot, h->red, kRed * sizeof(double), hipMemcpyDeviceToHost, h->stream);
 }
 
-// epsilon from the 7 sums of one iteration
+// epsilon from the sums of one iteration
 static double epsilon_value(const double *sums)
 {
     double s[7];
@@ -859,7 +863,7 @@ static double iterate_T(gsis_t *h, KinBufs<T> &B, bool gsis, int *inner, double 
     double e = 0;
     if (wait) {
         (void)hipStreamSynchronize(h->stream);
-        e = epsilon_value(h->red_h + 7 * slot);
+        e = epsilon_value(h->red_h + kRed * slot);
         tflush(h, tk, tm);
         if (gsis && inner) *inner = macro_count(h->Mb, mopts(h).max_inner, h->stream);
         h->prof.collect();
@@ -888,6 +892,131 @@ static int32_t get_state_T(gsis_t *h, KinBufs<T> &B, double *f, double *I)
     HIPCHECK(h, hipMemcpy(ti.data(), B.I, ni * sizeof(T), hipMemcpyDeviceToHost));
     if (f) std::copy(tf.begin(), tf.end(), f);
     if (I) std::copy(ti.begin(), ti.end(), I);
+    return GSIS_OK;
+}
+
+// ------------------------------------------------------------------ checkpoint / restore
+// File layout (native byte order): 8-byte tag "GSISCKP1"; int32 D, ND, precision, reserved; int64 nc, nv,
+// no, history length; f [nc][ND][nv] and I [nc][no] in the storage type of the precision; the residual
+// history (doubles).
+namespace {
+struct CkptHead {
+    char tag[8];
+    int32_t D, ND, prec, pad;
+    int64_t nc, nv, no, nhist;
+};
+}  // namespace
+
+template <typename T>
+static int32_t checkpoint_T(gsis_t *h, KinBufs<T> &B, FILE *fp, const CkptHead &hd)
+{
+    const size_t nfv = (size_t)hd.nc * hd.ND * hd.nv, ni = (size_t)hd.nc * hd.no;
+    std::vector<T> buf(std::max(nfv, ni));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipMemcpy(buf.data(), B.f, nfv * sizeof(T), hipMemcpyDeviceToHost));
+    if (fwrite(buf.data(), sizeof(T), nfv, fp) != nfv) return fail(h, GSIS_E_ARG, "gsis_checkpoint: write failed");
+    HIPCHECK(h, hipMemcpy(buf.data(), B.I, ni * sizeof(T), hipMemcpyDeviceToHost));
+    if (fwrite(buf.data(), sizeof(T), ni, fp) != ni) return fail(h, GSIS_E_ARG, "gsis_checkpoint: write failed");
+    return GSIS_OK;
+}
+
+template <typename T>
+static int32_t restore_T(gsis_t *h, KinBufs<T> &B, FILE *fp, const CkptHead &hd)
+{
+    const size_t nfv = (size_t)hd.nc * hd.ND * hd.nv, ni = (size_t)hd.nc * hd.no;
+    std::vector<T> buf(std::max(nfv, ni));
+    if (fread(buf.data(), sizeof(T), nfv, fp) != nfv) return fail(h, GSIS_E_ARG, "gsis_restore: truncated file");
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipMemcpy(B.f, buf.data(), nfv * sizeof(T), hipMemcpyHostToDevice));
+    if (fread(buf.data(), sizeof(T), ni, fp) != ni) return fail(h, GSIS_E_ARG, "gsis_restore: truncated file");
+    HIPCHECK(h, hipMemcpy(B.I, buf.data(), ni * sizeof(T), hipMemcpyHostToDevice));
+    return GSIS_OK;
+}
+
+// ------------------------------------------------------------------ learned warm start (device side)
+// sync parameters (second slot of sp) of the predicted fields: the network outputs y_n [nc][D + 5] are
+// de-standardised (y = y_n y_scale + y_mean) and read as log rho, u (D), log T_t, log T_r, log T_v, log T_R;
+// resc[c] = V rho (for the mass of the prediction)
+template <int D>
+__global__ void k_ws_fields(const float *__restrict__ Y, const double *__restrict__ ym, const double *__restrict__ ys,
+                            double *__restrict__ sp, double *__restrict__ resc, const double *__restrict__ vol,
+                            const int64_t nc, const double sigR)
+{
+    constexpr int NO = D + 5;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double y[NO];
+    for (int j = 0; j < NO; ++j) y[j] = (double)Y[c * NO + j] * ys[j] + ym[j];
+    double *s1 = sp + c * 2 * (D + 5) + (D + 5);
+    s1[0] = exp(y[0]);
+    for (int a = 0; a < D; ++a) s1[1 + a] = y[1 + a];
+    s1[D + 1] = exp(y[D + 1]);
+    s1[D + 2] = exp(y[D + 2]);
+    s1[D + 3] = exp(y[D + 3]);
+    const double TR = exp(y[D + 4]);
+    s1[D + 4] = 4 * sigR * TR * TR * TR * TR;
+    resc[c] = vol[c] * s1[0];
+}
+
+template <int D>
+__global__ void k_ws_mass(double *__restrict__ sp, const double *__restrict__ num, const double *__restrict__ den,
+                          const int64_t nc)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    sp[c * 2 * (D + 5) + (D + 5)] *= num[0] / den[0];
+}
+
+template <int D>
+static int32_t init_warmstart_D(gsis_t *h, gsis_mlp_t *m, const gsis_ws_norm *norm, const double *x)
+{
+    const int64_t nc = h->hm.nc;
+    int n_in = 0, n_out = 0;
+    mlp_dims(m, &n_in, &n_out);
+    if (n_out != D + 5 || norm->n_in != n_in || norm->n_out != n_out)
+        return fail(h, GSIS_E_ARG, "gsis_init_warmstart: the network must map n_in features to D + 5 outputs");
+    for (int j = 0; j < n_in; ++j)
+        if (!(norm->x_scale[j] > 0)) return fail(h, GSIS_E_ARG, "gsis_init_warmstart: non-positive input scale");
+    bool ok = true;
+    double *xd = dalloc<double>((size_t)nc * n_in, ok), *nd = dalloc<double>(4 * 64, ok);
+    struct Guard {
+        double *&a, *&b;
+        ~Guard()
+        {
+            dfree(a);
+            dfree(b);
+        }
+    } guard{xd, nd};
+    float *X = ok ? mlp_input_rows(m, nc) : nullptr;
+    if (!ok || !X) return fail(h, GSIS_E_OOM, "gsis_init_warmstart: device allocation failed");
+    hipStream_t st = h->stream;
+    HIPCHECK(h, hipMemcpyAsync(xd, x, (size_t)nc * n_in * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHECK(h, hipMemcpyAsync(nd, norm->x_mean, 64 * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHECK(h, hipMemcpyAsync(nd + 64, norm->x_scale, 64 * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHECK(h, hipMemcpyAsync(nd + 128, norm->y_mean, 64 * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHECK(h, hipMemcpyAsync(nd + 192, norm->y_scale, 64 * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_standardize(xd, nd, nd + 64, X, nc, n_in, st);
+    const float *Y = mlp_forward_rows(m, nc, st);
+    const dim3 g((unsigned)((nc + 255) / 256)), b(256);
+    const bool rescale = h->m.closed && h->have_init;
+    if (rescale) {
+        // closed domain: the prediction's density is scaled to the mass of the current state (Mb.scal[3])
+        if (h->prec == GSIS_FP32) moments_T(h, h->Bf, nullptr, h->momh);
+        else moments_T(h, h->Bd, nullptr, h->momh);
+        launch_mass_ratio<D>(h->Mb, h->m, h->momh, h->momh, st);
+    }
+    hipLaunchKernelGGL((k_ws_fields<D>), g, b, 0, st, Y, nd + 128, nd + 192, h->sp, h->Mb.resc, h->m.vol, nc,
+                       h->gas.sigma_R);
+    if (rescale) {
+        launch_block_sum(h->Mb.resc, nc, 1, h->Mb.scal + 2, h->Mb.bpart, st);
+        hipLaunchKernelGGL((k_ws_mass<D>), g, b, 0, st, h->sp, h->Mb.scal + 3, h->Mb.scal + 2, nc);
+    }
+    if (h->prec == GSIS_FP32) sync_T(h, h->Bf, h->sp, 1);
+    else sync_T(h, h->Bd, h->sp, 1);
+    HIPCHECK(h, hipStreamSynchronize(st));
+    HIPCHECK(h, hipGetLastError());
+    h->mom0_valid = false;
+    h->have_init = true;
     return GSIS_OK;
 }
 
@@ -1183,6 +1312,56 @@ static int32_t check_ready(gsis_t *h, const char *who)
     return GSIS_OK;
 }
 
+int32_t gsis_checkpoint(gsis_t *h, const char *path)
+{
+    int32_t rc = check_ready(h, "gsis_checkpoint");
+    if (rc) return rc;
+    if (!path) return fail(h, GSIS_E_ARG, "gsis_checkpoint: null path");
+    CkptHead hd{};
+    memcpy(hd.tag, "GSISCKP1", 8);
+    hd.D = h->hm.D;
+    hd.ND = ndist(hd.D);
+    hd.prec = h->prec;
+    hd.nc = h->hm.nc;
+    hd.nv = h->nv;
+    hd.no = h->no;
+    hd.nhist = (int64_t)h->hist.size();
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return fail(h, GSIS_E_ARG, std::string("gsis_checkpoint: cannot open ") + path);
+    rc = (fwrite(&hd, sizeof(hd), 1, fp) == 1) ? GSIS_OK : fail(h, GSIS_E_ARG, "gsis_checkpoint: write failed");
+    if (rc == GSIS_OK) rc = (h->prec == GSIS_FP32) ? checkpoint_T(h, h->Bf, fp, hd) : checkpoint_T(h, h->Bd, fp, hd);
+    if (rc == GSIS_OK && hd.nhist > 0 && fwrite(h->hist.data(), sizeof(double), hd.nhist, fp) != (size_t)hd.nhist)
+        rc = fail(h, GSIS_E_ARG, "gsis_checkpoint: write failed");
+    if (fclose(fp) != 0 && rc == GSIS_OK) rc = fail(h, GSIS_E_ARG, "gsis_checkpoint: close failed");
+    return rc;
+}
+
+int32_t gsis_restore(gsis_t *h, const char *path)
+{
+    if (!h || !path) return GSIS_E_ARG;
+    if (!h->have_state) return fail(h, GSIS_E_STATE, "gsis_restore: call gsis_set_opts first");
+    (void)hipSetDevice(h->device);
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return fail(h, GSIS_E_ARG, std::string("gsis_restore: cannot open ") + path);
+    CkptHead hd{};
+    int32_t rc = GSIS_OK;
+    if (fread(&hd, sizeof(hd), 1, fp) != 1 || memcmp(hd.tag, "GSISCKP1", 8) != 0)
+        rc = fail(h, GSIS_E_ARG, "gsis_restore: not a checkpoint file");
+    else if (hd.D != h->hm.D || hd.nc != h->hm.nc || hd.nv != h->nv || hd.no != h->no || hd.prec != h->prec ||
+             hd.nhist < 0)
+        rc = fail(h, GSIS_E_ARG, "gsis_restore: mesh, grids or precision differ from the checkpoint");
+    if (rc == GSIS_OK) rc = (h->prec == GSIS_FP32) ? restore_T(h, h->Bf, fp, hd) : restore_T(h, h->Bd, fp, hd);
+    std::vector<double> hist(hd.nhist > 0 ? hd.nhist : 0);
+    if (rc == GSIS_OK && hd.nhist > 0 && fread(hist.data(), sizeof(double), hd.nhist, fp) != (size_t)hd.nhist)
+        rc = fail(h, GSIS_E_ARG, "gsis_restore: truncated file");
+    fclose(fp);
+    if (rc != GSIS_OK) return rc;
+    h->hist = hist;
+    h->mom0_valid = false;
+    h->have_init = true;
+    return GSIS_OK;
+}
+
 int32_t gsis_iterate(gsis_t *h, int32_t scheme, int32_t n, double *eps, int32_t *inner)
 {
     int32_t rc = check_ready(h, "gsis_iterate");
@@ -1198,17 +1377,23 @@ int32_t gsis_iterate(gsis_t *h, int32_t scheme, int32_t n, double *eps, int32_t 
                                    : iterate_T(h, h->Bd, scheme == GSIS_GSIS, &in, nullptr, nullptr, wait, k);
     }
     for (int k = 0; k + 1 < n; ++k) {
-        const double ek = epsilon_value(h->red_h + 7 * k);
+        const double ek = epsilon_value(h->red_h + kRed * k);
         if (ek != ek) {
             e = ek;
             break;
         }
     }
+    int64_t bad = 0, bad_it = -1;
+    for (int k = 0; k < n && bad_it < 0; ++k)
+        if (h->red_h[kRed * k + 7] > 0) bad = (int64_t)h->red_h[kRed * k + 7], bad_it = k;
     hipError_t herr = hipGetLastError();
     if (herr != hipSuccess) return fail(h, GSIS_E_DEVICE, std::string("gsis_iterate: ") + hipGetErrorString(herr));
     if (eps) *eps = e;
     if (inner) *inner = in;
     h->last_inner = in;
+    if (bad > 0)
+        return fail(h, GSIS_E_DIVERGED, "gsis_iterate: non-positive density or temperature in " + std::to_string(bad) +
+                                            " cells after iteration " + std::to_string(bad_it + 1) + " of the batch");
     if (e != e) return fail(h, GSIS_E_DIVERGED, "gsis_iterate: NaN residual");
     return GSIS_OK;
 }
@@ -1223,6 +1408,8 @@ int32_t gsis_solve(gsis_t *h, gsis_report *rep)
     int64_t inner_total = 0;
     int k = 0;
     int32_t status = GSIS_W_NOT_CONVERGED;
+    double emin = INFINITY;
+    std::string why;
     auto t0 = std::chrono::steady_clock::now();
     const int32_t so_user = h->opts.second_order;
     for (k = 0; k < h->opts.max_outer; ++k) {
@@ -1233,11 +1420,18 @@ int32_t gsis_solve(gsis_t *h, gsis_report *rep)
                                    : iterate_T(h, h->Bd, g, &in, &tk, &tm, true);
         inner_total += in;
         h->hist.push_back(e);
-        if (e != e) {
+        const double nbad = h->red_h[7];
+        // divergence: NaN, a state that is no gas state, or a residual that has grown by 1e3 over the smallest
+        // one of this solve and exceeds 1 (the relative change of the fields per iteration)
+        if (e != e || nbad > 0 || (e > 1.0 && e > 1e3 * emin)) {
             status = GSIS_E_DIVERGED;
+            why = (e != e) ? "NaN residual"
+                           : (nbad > 0 ? "non-positive density or temperature in " + std::to_string((int64_t)nbad) + " cells"
+                                       : "residual grew above 1e3 times its smallest value");
             ++k;
             break;
         }
+        emin = std::min(emin, e);
         if (e < h->opts.tol) {
             status = GSIS_OK;
             ++k;
@@ -1258,7 +1452,8 @@ int32_t gsis_solve(gsis_t *h, gsis_report *rep)
         rep->t_other_s = tt - tk - tm;
         rep->inner_total = inner_total;
     }
-    if (status == GSIS_E_DIVERGED) return fail(h, GSIS_E_DIVERGED, "gsis_solve: NaN residual");
+    if (status == GSIS_E_DIVERGED)
+        return fail(h, GSIS_E_DIVERGED, "gsis_solve: " + why + " at iteration " + std::to_string(k));
     return status;
 }
 
@@ -1426,6 +1621,38 @@ int32_t gsis_get_counters(gsis_t *h, double *cellvel_updates, double *kinetic_by
     if (kinetic_bytes) *kinetic_bytes = h->cnt_bytes;
     if (kinetic_seconds) *kinetic_seconds = h->cnt_seconds;
     h->cnt_updates = h->cnt_bytes = h->cnt_seconds = 0;
+    return GSIS_OK;
+}
+
+
+int32_t gsis_init_warmstart(gsis_t *h, gsis_mlp_t *m, const gsis_ws_norm *norm, const double *x)
+{
+    if (!h || !m || !norm || !x) return GSIS_E_ARG;
+    if (!h->have_state) return fail(h, GSIS_E_STATE, "gsis_init_warmstart: call gsis_set_opts first");
+    (void)hipSetDevice(h->device);
+    if (h->hm.D == 1) return init_warmstart_D<1>(h, m, norm, x);
+    if (h->hm.D == 2) return init_warmstart_D<2>(h, m, norm, x);
+    return init_warmstart_D<3>(h, m, norm, x);
+}
+
+int32_t gsis_ws_targets(gsis_t *h, double *t)
+{
+    if (!h || !t) return GSIS_E_ARG;
+    const int D = h->hm.D, nf = gsis_nfields(h);
+    if (nf <= 0) return fail(h, GSIS_E_STATE, "gsis_ws_targets: no mesh");
+    std::vector<double> F((size_t)h->hm.nc * nf);
+    int32_t rc = gsis_get_fields(h, F.data());
+    if (rc != GSIS_OK) return rc;
+    for (int64_t c = 0; c < h->hm.nc; ++c) {
+        const double *f = &F[c * nf];
+        double *o = t + c * (D + 5);
+        // fields: rho, u (D), T_t, T_r, T_v, T_R, ...
+        if (!(f[0] > 0 && f[D + 1] > 0 && f[D + 2] > 0 && f[D + 3] > 0 && f[D + 4] > 0))
+            return fail(h, GSIS_E_DIVERGED, "gsis_ws_targets: non-positive density or temperature");
+        o[0] = std::log(f[0]);
+        for (int a = 0; a < D; ++a) o[1 + a] = f[1 + a];
+        for (int j = 0; j < 4; ++j) o[D + 1 + j] = std::log(f[D + 1 + j]);
+    }
     return GSIS_OK;
 }
 

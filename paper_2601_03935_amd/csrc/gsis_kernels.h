@@ -2,6 +2,7 @@
 #pragma once
 
 #include "gsis_dev.h"
+#include "../../include/gsis_warmstart.h"
 
 #include <vector>
 
@@ -157,13 +158,23 @@ void launch_scale(T *f, int64_t n, const double *num, const double *den, hipStre
 template <int D>
 void launch_sync_params(const double *mom, const double *W, double *sp, int64_t nc, const Phys &p, int from_W,
                         hipStream_t st);
-// epsilon contributions per cell between two moment arrays: 7 values (num rho, den rho, num u, den u,
-// num T, den T, V) and their deterministic sum
+// epsilon contributions per cell between two moment arrays: 8 values (num rho, den rho, num u, den u,
+// num T, den T, V, 1 if the new state is not a physical gas state) and their deterministic sum
 template <int D>
 void launch_residual(const double *mom1, const double *mom0, const double *vol, double *cellbuf, double *out7,
                      double *part, int64_t nc, const Phys &p, hipStream_t st);
 // deterministic sums of n rows of k interleaved values (k sums); part: k * kSumBlocks doubles of scratch
 constexpr int kSumBlocks = 128;
 void launch_block_sum(const double *in, int64_t n, int k, double *out, double *part, hipStream_t st);
+
+// warm-start network internals used by the solver's warm-start initialisation (mlp.hip): device row
+// buffer of n standardised inputs, the forward pass on stream st (returns the device outputs [n][n_out]),
+// and the dimensions
+float *mlp_input_rows(gsis_mlp_t *m, int64_t n);
+const float *mlp_forward_rows(gsis_mlp_t *m, int64_t n, hipStream_t st);
+void mlp_dims(const gsis_mlp_t *m, int *n_in, int *n_out);
+// x_out[i][j] = (x[i][j] - mean[j]) / scale[j] for n rows of k values (device arrays, FP64 in, FP32 out)
+void launch_standardize(const double *x, const double *mean, const double *scale, float *out, int64_t n, int k,
+                        hipStream_t st);
 
 }  // namespace gsis

@@ -1287,7 +1287,7 @@ __global__ void k_resid_terms(const double *__restrict__ m1, const double *__res
     if (c >= nc) return;
     const double *A = m1 + c * L.size(), *B = m0 + c * L.size();
     const double V = vol[c];
-    double *o = out + c * 7;
+    double *o = out + c * 8;
     o[0] = V * (A[L.rho()] - B[L.rho()]) * (A[L.rho()] - B[L.rho()]);
     o[1] = V * B[L.rho()] * B[L.rho()];
     double nu = 0, du = 0;
@@ -1303,6 +1303,10 @@ __global__ void k_resid_terms(const double *__restrict__ m1, const double *__res
     o[4] = V * (Tn - To) * (Tn - To);
     o[5] = V * To * To;
     o[6] = V;
+    // cells of the new state that are not a physical gas state (density or a mode temperature not positive,
+    // or not finite): counted, so that the driver reports divergence instead of iterating on
+    const bool ok = A[L.rho()] > 0 && A[L.Tt()] > 0 && A[L.Tr()] > 0 && A[L.Tv()] > 0 && Tn < 1e300;
+    o[7] = ok ? 0.0 : 1.0;
 }
 
 template <int D>
@@ -1310,7 +1314,7 @@ void launch_residual(const double *mom1, const double *mom0, const double *vol, 
                      double *part, int64_t nc, const Phys &p, hipStream_t st)
 {
     hipLaunchKernelGGL(k_resid_terms<D>, dim3((nc + 255) / 256), dim3(256), 0, st, mom1, mom0, vol, cellbuf, nc, p);
-    launch_block_sum(cellbuf, nc, 7, out7, part, st);
+    launch_block_sum(cellbuf, nc, 8, out7, part, st);
 }
 
 #define GSIS_INST_M(D, NFM)                                                                                      \

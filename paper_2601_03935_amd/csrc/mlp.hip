@@ -16,6 +16,7 @@
 
 #include "../../include/gsis.h"
 #include "../../include/gsis_warmstart.h"
+#include "gsis_kernels.h"
 
 namespace {
 
@@ -507,7 +508,118 @@ int32_t upload_rows(gsis_mlp_t *m, int64_t n, const float *x, const float *t)
     return GSIS_OK;
 }
 
+// minibatch Adam over n device rows Xall [n][n_in], Tall [n][n_out] (host-shuffled order per epoch)
+int32_t train_device(gsis_mlp_t *m, int64_t n, const float *Xall, const float *Tall, const gsis_mlp_train_opts *o,
+                     double *final_loss)
+{
+    const int64_t bs = std::min<int64_t>(o->batch, n);
+    const int64_t nbat = (n + bs - 1) / bs;
+    if (!ensure_batch(m, bs)) return fail(m, GSIS_E_OOM, "training: device allocation failed");
+    int *idx = nullptr;
+    double *lossv = nullptr;
+    struct Guard {
+        int *&c;
+        double *&d;
+        ~Guard()
+        {
+            dfree(c);
+            dfree(d);
+        }
+    } guard{idx, lossv};
+    if (!(dalloc(idx, n) && dalloc(lossv, nbat))) return fail(m, GSIS_E_OOM, "training: device allocation failed");
+    std::vector<int> perm(n);
+    uint64_t s = o->seed;
+    for (int ep = 0; ep < o->epochs; ++ep) {
+        for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
+        for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[(int64_t)(uniform01(s) * (double)(i + 1))]);
+        MCHECK(m, hipMemcpyAsync(idx, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, m->st));
+        for (int64_t b = 0; b < nbat; ++b) {
+            const int64_t r0 = b * bs, nr = std::min(bs, n - r0);
+            hipLaunchKernelGGL(k_gather_rows, dim3((nr * m->n_in + 255) / 256), dim3(256), 0, m->st, nr, idx + r0,
+                               m->n_in, Xall, m->X);
+            hipLaunchKernelGGL(k_gather_rows, dim3((nr * m->n_out + 255) / 256), dim3(256), 0, m->st, nr, idx + r0,
+                               m->n_out, Tall, m->T);
+            forward(m, (int)nr);
+            backward(m, (int)nr);
+            adam(m, o);
+            MCHECK(m, hipMemcpyAsync(lossv + b, m->loss, sizeof(double), hipMemcpyDeviceToDevice, m->st));
+        }
+        // the permutation buffer is rewritten next epoch: wait for this epoch's gathers
+        MCHECK(m, hipStreamSynchronize(m->st));
+    }
+    if (final_loss) {
+        std::vector<double> lv(nbat);
+        MCHECK(m, hipMemcpy(lv.data(), lossv, nbat * sizeof(double), hipMemcpyDeviceToHost));
+        double sum = 0;
+        for (double v : lv) sum += v;
+        *final_loss = o->epochs > 0 ? sum / (double)nbat : 0.0;
+    }
+    return GSIS_OK;
+}
+
+__global__ void k_standardize(const double *__restrict__ x, const double *__restrict__ mean,
+                              const double *__restrict__ scale, float *__restrict__ out, const int64_t n, const int k)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * k) return;
+    const int j = (int)(i % k);
+    out[i] = (float)((x[i] - mean[j]) / scale[j]);
+}
+
+__global__ void k_destandardize(const float *__restrict__ y, const double *__restrict__ mean,
+                                const double *__restrict__ scale, double *__restrict__ out, const int64_t n, const int k)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * k) return;
+    const int j = (int)(i % k);
+    out[i] = (double)y[i] * scale[j] + mean[j];
+}
+
+// the four standardisation vectors of a norm on the device (x_mean, x_scale, y_mean, y_scale, 64 each)
+int32_t upload_norm(gsis_mlp_t *m, const gsis_ws_norm *norm, double *&d)
+{
+    if (!norm || norm->n_in != m->n_in || norm->n_out != m->n_out)
+        return fail(m, GSIS_E_ARG, "standardisation dimensions differ from the network's");
+    for (int j = 0; j < m->n_in; ++j)
+        if (!(norm->x_scale[j] > 0)) return fail(m, GSIS_E_ARG, "non-positive input scale");
+    for (int j = 0; j < m->n_out; ++j)
+        if (!(norm->y_scale[j] > 0)) return fail(m, GSIS_E_ARG, "non-positive output scale");
+    if (!dalloc(d, 4 * 64)) return fail(m, GSIS_E_OOM, "device allocation failed");
+    MCHECK(m, hipMemcpyAsync(d, norm->x_mean, 64 * sizeof(double), hipMemcpyHostToDevice, m->st));
+    MCHECK(m, hipMemcpyAsync(d + 64, norm->x_scale, 64 * sizeof(double), hipMemcpyHostToDevice, m->st));
+    MCHECK(m, hipMemcpyAsync(d + 128, norm->y_mean, 64 * sizeof(double), hipMemcpyHostToDevice, m->st));
+    MCHECK(m, hipMemcpyAsync(d + 192, norm->y_scale, 64 * sizeof(double), hipMemcpyHostToDevice, m->st));
+    return GSIS_OK;
+}
+
 }  // namespace
+
+namespace gsis {
+
+float *mlp_input_rows(gsis_mlp_t *m, int64_t n) { return ensure_batch(m, n) ? m->X : nullptr; }
+
+const float *mlp_forward_rows(gsis_mlp_t *m, int64_t n, hipStream_t st)
+{
+    hipStream_t keep = m->st;
+    m->st = st;
+    forward(m, (int)n);
+    m->st = keep;
+    return m->Y;
+}
+
+void mlp_dims(const gsis_mlp_t *m, int *n_in, int *n_out)
+{
+    *n_in = m->n_in;
+    *n_out = m->n_out;
+}
+
+void launch_standardize(const double *x, const double *mean, const double *scale, float *out, int64_t n, int k,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_standardize, dim3((unsigned)((n * k + 255) / 256)), dim3(256), 0, st, x, mean, scale, out, n, k);
+}
+
+}  // namespace gsis
 
 extern "C" {
 
@@ -655,16 +767,58 @@ int32_t gsis_mlp_train(gsis_mlp_t *m, int64_t n, const float *x, const float *t,
     if (rc != GSIS_OK) return rc;
     if (o->epochs < 0 || o->batch < 1 || !(o->lr > 0)) return fail(m, GSIS_E_ARG, "gsis_mlp_train: invalid options");
     (void)hipSetDevice(m->device);
-    const int64_t bs = std::min<int64_t>(o->batch, n);
-    const int64_t nbat = (n + bs - 1) / bs;
-    if (!ensure_batch(m, bs)) return fail(m, GSIS_E_OOM, "gsis_mlp_train: device allocation failed");
     float *Xall = nullptr, *Tall = nullptr;
-    int *idx = nullptr;
-    double *lossv = nullptr;
     struct Guard {
         float *&a, *&b;
-        int *&c;
-        double *&d;
+        ~Guard()
+        {
+            dfree(a);
+            dfree(b);
+        }
+    } guard{Xall, Tall};
+    if (!(dalloc(Xall, n * m->n_in) && dalloc(Tall, n * m->n_out)))
+        return fail(m, GSIS_E_OOM, "gsis_mlp_train: device allocation failed");
+    MCHECK(m, hipMemcpyAsync(Xall, x, n * m->n_in * sizeof(float), hipMemcpyHostToDevice, m->st));
+    MCHECK(m, hipMemcpyAsync(Tall, t, n * m->n_out * sizeof(float), hipMemcpyHostToDevice, m->st));
+    return train_device(m, n, Xall, Tall, o, final_loss);
+}
+
+int32_t gsis_ws_fit_norm(int64_t n, int32_t n_in, const double *x, int32_t n_out, const double *t,
+                         gsis_ws_norm *norm)
+{
+    if (n <= 0 || !x || !t || !norm || n_in < 1 || n_in > 64 || n_out < 1 || n_out > 64) return GSIS_E_ARG;
+    std::memset(norm, 0, sizeof(*norm));
+    norm->n_in = n_in;
+    norm->n_out = n_out;
+    auto stats = [&](const double *a, int k, double *mean, double *scale) {
+        for (int j = 0; j < k; ++j) {
+            double s1 = 0;
+            for (int64_t i = 0; i < n; ++i) s1 += a[i * k + j];
+            const double mu = s1 / (double)n;
+            double s2 = 0;
+            for (int64_t i = 0; i < n; ++i) s2 += (a[i * k + j] - mu) * (a[i * k + j] - mu);
+            mean[j] = mu;
+            scale[j] = std::sqrt(s2 / (double)n) + 1e-12;
+        }
+    };
+    stats(x, n_in, norm->x_mean, norm->x_scale);
+    stats(t, n_out, norm->y_mean, norm->y_scale);
+    return GSIS_OK;
+}
+
+int32_t gsis_ws_train(gsis_mlp_t *m, const gsis_ws_norm *norm, int64_t n, const double *x, const double *t,
+                      const gsis_mlp_train_opts *o, double *final_loss)
+{
+    if (!m || !o || !t) return GSIS_E_ARG;
+    int32_t rc = check_rows(m, n, x);
+    if (rc != GSIS_OK) return rc;
+    if (o->epochs < 0 || o->batch < 1 || !(o->lr > 0)) return fail(m, GSIS_E_ARG, "gsis_ws_train: invalid options");
+    (void)hipSetDevice(m->device);
+    double *dn = nullptr, *raw = nullptr;
+    float *Xall = nullptr, *Tall = nullptr;
+    struct Guard {
+        double *&a, *&b;
+        float *&c, *&d;
         ~Guard()
         {
             dfree(a);
@@ -672,38 +826,86 @@ int32_t gsis_mlp_train(gsis_mlp_t *m, int64_t n, const float *x, const float *t,
             dfree(c);
             dfree(d);
         }
-    } guard{Xall, Tall, idx, lossv};
-    if (!(dalloc(Xall, n * m->n_in) && dalloc(Tall, n * m->n_out) && dalloc(idx, n) && dalloc(lossv, nbat)))
-        return fail(m, GSIS_E_OOM, "gsis_mlp_train: device allocation failed");
-    MCHECK(m, hipMemcpyAsync(Xall, x, n * m->n_in * sizeof(float), hipMemcpyHostToDevice, m->st));
-    MCHECK(m, hipMemcpyAsync(Tall, t, n * m->n_out * sizeof(float), hipMemcpyHostToDevice, m->st));
-    std::vector<int> perm(n);
-    uint64_t s = o->seed;
-    for (int ep = 0; ep < o->epochs; ++ep) {
-        for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
-        for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[(int64_t)(uniform01(s) * (double)(i + 1))]);
-        MCHECK(m, hipMemcpyAsync(idx, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, m->st));
-        for (int64_t b = 0; b < nbat; ++b) {
-            const int64_t r0 = b * bs, nr = std::min(bs, n - r0);
-            hipLaunchKernelGGL(k_gather_rows, dim3((nr * m->n_in + 255) / 256), dim3(256), 0, m->st, nr, idx + r0,
-                               m->n_in, Xall, m->X);
-            hipLaunchKernelGGL(k_gather_rows, dim3((nr * m->n_out + 255) / 256), dim3(256), 0, m->st, nr, idx + r0,
-                               m->n_out, Tall, m->T);
-            forward(m, (int)nr);
-            backward(m, (int)nr);
-            adam(m, o);
-            MCHECK(m, hipMemcpyAsync(lossv + b, m->loss, sizeof(double), hipMemcpyDeviceToDevice, m->st));
+    } guard{dn, raw, Xall, Tall};
+    if ((rc = upload_norm(m, norm, dn)) != GSIS_OK) return rc;
+    const int64_t k = std::max(m->n_in, m->n_out);
+    if (!(dalloc(raw, n * k) && dalloc(Xall, n * m->n_in) && dalloc(Tall, n * m->n_out)))
+        return fail(m, GSIS_E_OOM, "gsis_ws_train: device allocation failed");
+    MCHECK(m, hipMemcpyAsync(raw, x, n * m->n_in * sizeof(double), hipMemcpyHostToDevice, m->st));
+    gsis::launch_standardize(raw, dn, dn + 64, Xall, n, m->n_in, m->st);
+    MCHECK(m, hipStreamSynchronize(m->st));
+    MCHECK(m, hipMemcpyAsync(raw, t, n * m->n_out * sizeof(double), hipMemcpyHostToDevice, m->st));
+    gsis::launch_standardize(raw, dn + 128, dn + 192, Tall, n, m->n_out, m->st);
+    MCHECK(m, hipStreamSynchronize(m->st));
+    return train_device(m, n, Xall, Tall, o, final_loss);
+}
+
+int32_t gsis_ws_predict(gsis_mlp_t *m, const gsis_ws_norm *norm, int64_t n, const double *x, double *y)
+{
+    if (!m || !y) return GSIS_E_ARG;
+    int32_t rc = check_rows(m, n, x);
+    if (rc != GSIS_OK) return rc;
+    (void)hipSetDevice(m->device);
+    double *dn = nullptr, *raw = nullptr;
+    struct Guard {
+        double *&a, *&b;
+        ~Guard()
+        {
+            dfree(a);
+            dfree(b);
         }
-        // the permutation buffer is rewritten next epoch: wait for this epoch's gathers
-        MCHECK(m, hipStreamSynchronize(m->st));
-    }
-    if (final_loss) {
-        std::vector<double> lv(nbat);
-        MCHECK(m, hipMemcpy(lv.data(), lossv, nbat * sizeof(double), hipMemcpyDeviceToHost));
-        double sum = 0;
-        for (double v : lv) sum += v;
-        *final_loss = o->epochs > 0 ? sum / (double)nbat : 0.0;
-    }
+    } guard{dn, raw};
+    if ((rc = upload_norm(m, norm, dn)) != GSIS_OK) return rc;
+    if (!ensure_batch(m, n) || !dalloc(raw, n * std::max(m->n_in, m->n_out)))
+        return fail(m, GSIS_E_OOM, "gsis_ws_predict: device allocation failed");
+    MCHECK(m, hipMemcpyAsync(raw, x, n * m->n_in * sizeof(double), hipMemcpyHostToDevice, m->st));
+    gsis::launch_standardize(raw, dn, dn + 64, m->X, n, m->n_in, m->st);
+    forward(m, (int)n);
+    hipLaunchKernelGGL(k_destandardize, dim3((unsigned)((n * m->n_out + 255) / 256)), dim3(256), 0, m->st, m->Y,
+                       dn + 128, dn + 192, raw, n, m->n_out);
+    MCHECK(m, hipMemcpyAsync(y, raw, n * m->n_out * sizeof(double), hipMemcpyDeviceToHost, m->st));
+    MCHECK(m, hipStreamSynchronize(m->st));
+    return GSIS_OK;
+}
+
+// file: 8-byte tag "GSISMLP1", int32 n_in, width, n_out, bf16, int64 parameter count, FP32 parameters, norm
+int32_t gsis_ws_save(gsis_mlp_t *m, const gsis_ws_norm *norm, const char *path)
+{
+    if (!m || !norm || !path) return GSIS_E_ARG;
+    if (norm->n_in != m->n_in || norm->n_out != m->n_out) return fail(m, GSIS_E_ARG, "gsis_ws_save: norm dimensions");
+    std::vector<float> P(m->np);
+    int32_t rc = gsis_mlp_get_params(m, P.data());
+    if (rc != GSIS_OK) return rc;
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return fail(m, GSIS_E_ARG, std::string("gsis_ws_save: cannot open ") + path);
+    const int32_t dims[4] = {m->n_in, m->width, m->n_out, m->bf16 ? 1 : 0};
+    const int64_t np = m->np;
+    bool ok = fwrite("GSISMLP1", 1, 8, fp) == 8 && fwrite(dims, sizeof(dims), 1, fp) == 1 &&
+              fwrite(&np, sizeof(np), 1, fp) == 1 && fwrite(P.data(), sizeof(float), np, fp) == (size_t)np &&
+              fwrite(norm, sizeof(*norm), 1, fp) == 1;
+    ok = (fclose(fp) == 0) && ok;
+    return ok ? GSIS_OK : fail(m, GSIS_E_ARG, "gsis_ws_save: write failed");
+}
+
+int32_t gsis_ws_load(gsis_mlp_t *m, gsis_ws_norm *norm, const char *path)
+{
+    if (!m || !norm || !path) return GSIS_E_ARG;
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return fail(m, GSIS_E_ARG, std::string("gsis_ws_load: cannot open ") + path);
+    char tag[8];
+    int32_t dims[4];
+    int64_t np = 0;
+    bool ok = fread(tag, 1, 8, fp) == 8 && memcmp(tag, "GSISMLP1", 8) == 0 && fread(dims, sizeof(dims), 1, fp) == 1 &&
+              fread(&np, sizeof(np), 1, fp) == 1;
+    ok = ok && dims[0] == m->n_in && dims[1] == m->width && dims[2] == m->n_out && np == m->np;
+    std::vector<float> P(ok ? np : 0);
+    gsis_ws_norm nm;
+    ok = ok && fread(P.data(), sizeof(float), np, fp) == (size_t)np && fread(&nm, sizeof(nm), 1, fp) == 1;
+    fclose(fp);
+    if (!ok) return fail(m, GSIS_E_ARG, "gsis_ws_load: not a network file of this handle's dimensions");
+    int32_t rc = gsis_mlp_set_params(m, P.data());
+    if (rc != GSIS_OK) return rc;
+    *norm = nm;
     return GSIS_OK;
 }
 

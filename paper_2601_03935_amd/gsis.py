@@ -30,7 +30,7 @@ EXPORTS = [
     "gsis_init_equilibrium", "gsis_init_fields", "gsis_set_state", "gsis_get_state", "gsis_iterate", "gsis_solve",
     "gsis_kinetic_step", "gsis_macro_solve", "gsis_sync", "gsis_nfields", "gsis_get_fields",
     "gsis_get_residual_history", "gsis_get_surface_flux", "gsis_get_counters", "gsis_set_profiling",
-    "gsis_get_kernel_stats",
+    "gsis_get_kernel_stats", "gsis_checkpoint", "gsis_restore",
 ]
 KERNEL_KINDS = ["grad", "residual", "sweep", "rad", "moments", "boundary", "sync", "macro"]
 
@@ -103,6 +103,8 @@ def lib():
         "gsis_get_counters": ([P, C.POINTER(D), C.POINTER(D), C.POINTER(D)], I32),
         "gsis_set_profiling": ([P, I32], I32),
         "gsis_get_kernel_stats": ([P, I32, C.POINTER(D), C.POINTER(I64), C.POINTER(D)], I32),
+        "gsis_checkpoint": ([P, C.c_char_p], I32),
+        "gsis_restore": ([P, C.c_char_p], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -268,6 +270,12 @@ class Solver:
         I = np.empty((self.nc, self.no))
         self._check(self.L.gsis_get_state(self.h, _p(f), _p(I)), "gsis_get_state")
         return f, I
+
+    def checkpoint(self, path):
+        self._check(self.L.gsis_checkpoint(self.h, str(path).encode()), "gsis_checkpoint")
+
+    def restore(self, path):
+        self._check(self.L.gsis_restore(self.h, str(path).encode()), "gsis_restore")
 
     def fields(self):
         n = self.L.gsis_nfields(self.h)

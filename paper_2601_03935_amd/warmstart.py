@@ -3,8 +3,10 @@
 A 4-layer perceptron maps case parameters and cell geometry to initial macroscopic fields; it is trained
 on the GPU, by the library's own forward/backward/Adam kernels, on converged solutions the solver itself
 produced.  The solver then starts from the multi-temperature equilibrium of the predicted fields
-(``gsis_init_fields``) instead of the uniform start; the converged answer is unchanged (same fixed
-point), only the number of iterations to reach it.
+(``gsis_init_warmstart``: standardisation, network, de-standardisation, the exponential of the log targets,
+the closed-domain mass scaling and the equilibrium fill all run on the device) instead of the uniform start;
+the converged answer is unchanged (same fixed point), only the number of iterations to reach it.  This
+module only builds the per-cell features (inputs) and marshals arguments.
 
 Features here are for the lid-driven cavity family (unit square with the concentric square obstacle):
 log10 Kn, log10 optical thickness, lid speed, x, y, distance to the nearest wall, distance to the lid.
@@ -24,7 +26,8 @@ from .gsis import GsisError, Solver, lib
 EXPORTS = [
     "gsis_mlp_create", "gsis_mlp_destroy", "gsis_mlp_last_error", "gsis_mlp_set_stream", "gsis_mlp_num_params",
     "gsis_mlp_get_params", "gsis_mlp_set_params", "gsis_mlp_forward", "gsis_mlp_loss_grad", "gsis_mlp_adam_step",
-    "gsis_mlp_train",
+    "gsis_mlp_train", "gsis_ws_fit_norm", "gsis_ws_train", "gsis_ws_predict", "gsis_ws_save", "gsis_ws_load",
+    "gsis_ws_targets", "gsis_init_warmstart",
 ]
 
 N_IN, N_OUT = 7, 7
@@ -35,6 +38,11 @@ FEATURES = {}
 class gsis_mlp_train_opts(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
                 ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
+
+
+class gsis_ws_norm(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_out", C.c_int32), ("x_mean", C.c_double * 64), ("x_scale", C.c_double * 64),
+                ("y_mean", C.c_double * 64), ("y_scale", C.c_double * 64)]
 
 
 _registered = False
@@ -57,6 +65,14 @@ def _lib():
             "gsis_mlp_loss_grad": ([P, I64, P, P, C.POINTER(C.c_double), P], I32),
             "gsis_mlp_adam_step": ([P, C.POINTER(gsis_mlp_train_opts), I64, P, P, C.POINTER(C.c_double)], I32),
             "gsis_mlp_train": ([P, I64, P, P, C.POINTER(gsis_mlp_train_opts), C.POINTER(C.c_double)], I32),
+            "gsis_ws_fit_norm": ([I64, I32, P, I32, P, C.POINTER(gsis_ws_norm)], I32),
+            "gsis_ws_train": ([P, C.POINTER(gsis_ws_norm), I64, P, P, C.POINTER(gsis_mlp_train_opts),
+                               C.POINTER(C.c_double)], I32),
+            "gsis_ws_predict": ([P, C.POINTER(gsis_ws_norm), I64, P, P], I32),
+            "gsis_ws_save": ([P, C.POINTER(gsis_ws_norm), C.c_char_p], I32),
+            "gsis_ws_load": ([P, C.POINTER(gsis_ws_norm), C.c_char_p], I32),
+            "gsis_ws_targets": ([P, P], I32),
+            "gsis_init_warmstart": ([P, P, C.POINTER(gsis_ws_norm), P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -202,57 +218,81 @@ def targets_to_fields(Y: np.ndarray) -> dict:
                 Tv=np.exp(Y[:, 5]), TR=np.exp(Y[:, 6]))
 
 
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def solver_targets(solver: Solver) -> np.ndarray:
+    """[nc][D + 5] training targets of a solver's current state (log rho, u, log T_t, log T_r, log T_v,
+    log T_R), computed by the library."""
+    t = np.empty((solver.nc, solver.D + 5))
+    rc = _lib().gsis_ws_targets(solver.h, _ptr(t))
+    if rc < 0:
+        raise GsisError(f"gsis_ws_targets failed with code {rc}: {solver.L.gsis_last_error(solver.h).decode()}")
+    return t
+
+
 class WarmStart:
-    """Standardisation + network; fit on (features, targets) of converged cases, predict initial fields.
-    `family` selects the feature set ("cavity" or "cylinder")."""
+    """Standardisation + network, all in the library; fit on (features, targets) of converged cases, start a
+    solver from the prediction.  `family` selects the feature set ("cavity" or "cylinder")."""
 
     def __init__(self, width=256, bf16=True, seed=0, device=0, stream=None, family="cavity"):
         self.family = family
         self.features, n_in = FEATURES[family]
         self.net = MLP(n_in, width, N_OUT, bf16=bf16, seed=seed, device=device, stream=stream)
-        self.xm = self.xs = self.ym = self.ys = None
+        self.norm = None
 
     def fit(self, X, Y, epochs=40, batch=4096, lr=2e-3, seed=0):
-        X, Y = np.asarray(X, dtype=np.float64), np.asarray(Y, dtype=np.float64)
-        self.xm, self.xs = X.mean(0), X.std(0) + 1e-12
-        self.ym, self.ys = Y.mean(0), Y.std(0) + 1e-12
-        return self.net.train((X - self.xm) / self.xs, (Y - self.ym) / self.ys, epochs=epochs, batch=batch, lr=lr,
-                              seed=seed)
+        X, Y = _f64(X), _f64(Y)
+        L = self.net.L
+        self.norm = gsis_ws_norm()
+        rc = L.gsis_ws_fit_norm(X.shape[0], X.shape[1], _ptr(X), Y.shape[1], _ptr(Y), C.byref(self.norm))
+        if rc < 0:
+            raise GsisError(f"gsis_ws_fit_norm failed with code {rc}")
+        o = train_opts(epochs=epochs, batch=batch, lr=lr, seed=seed)
+        loss = C.c_double(0)
+        self.net._check(L.gsis_ws_train(self.net.h, C.byref(self.norm), X.shape[0], _ptr(X), _ptr(Y), C.byref(o),
+                                        C.byref(loss)), "gsis_ws_train")
+        return loss.value
 
     def predict(self, X):
-        Yn = self.net.forward((np.asarray(X, dtype=np.float64) - self.xm) / self.xs)
-        return Yn.astype(np.float64) * self.ys + self.ym
+        """Raw (de-standardised) network outputs for raw features X."""
+        X = _f64(X)
+        Y = np.empty((X.shape[0], self.net.n_out))
+        self.net._check(self.net.L.gsis_ws_predict(self.net.h, C.byref(self.norm), X.shape[0], _ptr(X), _ptr(Y)),
+                        "gsis_ws_predict")
+        return Y
 
     def init_solver(self, solver: Solver, case):
-        """Start `solver` from the predicted fields.  In a domain closed by walls the total mass is an input
-        (the iteration conserves it), so the predicted density is rescaled to the mass of the case's own
-        initial state."""
-        f = targets_to_fields(self.predict(self.features(case)))
-        if all(b["kind"] == 0 for b in case.bcs):
-            V = case.mesh.vol
-            f["rho"] = f["rho"] * (np.dot(V, case.init_rho) / np.dot(V, f["rho"]))
-        solver.init_fields(f["rho"], f["u"], f["Tt"], f["Tr"], f["Tv"], f["TR"])
-        return f
+        """Start `solver` from the network's prediction for `case` (gsis_init_warmstart); returns the predicted
+        fields (for reporting the prediction error)."""
+        X = _f64(self.features(case))
+        rc = self.net.L.gsis_init_warmstart(solver.h, self.net.h, C.byref(self.norm), _ptr(X))
+        if rc < 0:
+            raise GsisError(f"gsis_init_warmstart failed with code {rc}: {solver.L.gsis_last_error(solver.h).decode()}")
+        return targets_to_fields(self.predict(X))
 
     def save(self, path):
-        np.savez(path, params=self.net.get_params(), xm=self.xm, xs=self.xs, ym=self.ym, ys=self.ys,
-                 width=self.net.width, bf16=self.net.bf16)
+        self.net._check(self.net.L.gsis_ws_save(self.net.h, C.byref(self.norm), str(path).encode()), "gsis_ws_save")
 
     def load(self, path):
-        d = np.load(path)  # plain arrays only (no pickled objects)
-        self.net.set_params(d["params"])
-        self.xm, self.xs, self.ym, self.ys = d["xm"], d["xs"], d["ym"], d["ys"]
+        self.norm = gsis_ws_norm()
+        self.net._check(self.net.L.gsis_ws_load(self.net.h, C.byref(self.norm), str(path).encode()), "gsis_ws_load")
 
 
 def converged_fields(case, device=0, stream=None, **opts):
-    """Solve a case from its uniform start; returns (fields, iterations, seconds, converged)."""
+    """Solve a case from its uniform start; returns (fields, targets or None, iterations, seconds, converged)."""
     s = Solver(case, device=device, stream=stream, **opts)
     t0 = time.perf_counter()
     rc, rep, _ = s.solve()
     dt = time.perf_counter() - t0
     F = s.fields()
+    try:
+        T = solver_targets(s)
+    except GsisError:
+        T = None
     s.close()
-    return F, int(rep.iters), dt, rc == 0
+    return F, T, int(rep.iters), dt, rc == 0
 
 
 def training_set(cases, device=0, stream=None, family="cavity", report=None, **opts):
@@ -263,9 +303,8 @@ def training_set(cases, device=0, stream=None, family="cavity", report=None, **o
     X, Y = [], []
     dropped = []
     for i, c in enumerate(cases):
-        F, _, _, ok = converged_fields(c, device=device, stream=stream, **opts)
-        Yc = field_targets(F) if ok else None
-        if not ok or not np.isfinite(Yc).all():
+        F, Yc, _, _, ok = converged_fields(c, device=device, stream=stream, **opts)
+        if not ok or Yc is None or not np.isfinite(Yc).all():
             dropped.append(i)
             continue
         X.append(feat(c))
@@ -292,8 +331,12 @@ def continuation_fields(case, tag, mach_steps, device=0, stream=None, stage_tol=
     its, hist, ok = s.solve_continuation(tag, states, stage_tol=stage_tol, tol=tol, **(cont or {}))
     dt = time.perf_counter() - t0
     F = s.fields()
+    try:
+        T = solver_targets(s)
+    except GsisError:
+        T, ok = None, False
     s.close()
-    return F, int(sum(its)), dt, ok
+    return F, T, int(sum(its)), dt, ok
 
 
 def mach_steps(Ma):
@@ -315,16 +358,16 @@ def cylinder_training_set(cases, device=0, stream=None, tol=1e-6, first_order_fa
             tries.append((1, dict(opts, second_order=0), dict(first_order_iters=0, first_order_jump=0)))
         for order, o, cont in tries:
             try:
-                F, it, dt, ok = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), device=device, stream=stream,
-                                                    tol=tol, cont=cont, **o)
+                F, Yc, it, dt, ok = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), device=device,
+                                                        stream=stream, tol=tol, cont=cont, **o)
             except GsisError as ex:
                 rec.update(ok=False, order=order, error=str(ex))
                 continue
             rec.update(ok=ok, order=order, iterations=it, seconds=dt)
             rec.pop("error", None)
-            if ok:
+            if ok and np.isfinite(Yc).all():
                 X.append(cylinder_features(c))
-                Y.append(field_targets(F))
+                Y.append(Yc)
                 break
         info.append(rec)
     if not X:

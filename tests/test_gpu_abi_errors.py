@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2601_03935_amd import gsis as G
+from paper_2601_03935_amd.gsis import GSIS_E_DIVERGED, GsisError, Solver, gsis_report
 from workloads import case_cavity, mesh_cavity
 
 pytestmark = pytest.mark.gpu
@@ -126,4 +127,75 @@ def test_profiling_kind_selection():
     st = s.kernel_stats()
     assert all(st[k][1] > 0 for k in ("grad", "residual", "sweep", "rad", "moments", "sync", "macro"))
     s.set_profiling(False)
+    s.close()
+
+
+def test_checkpoint_restore_continues_bit_for_bit(tmp_path):
+    """N + M iterations equal N iterations, a checkpoint, a restore into a fresh handle and M iterations,
+    bit for bit (state and epsilon); the residual history travels with the checkpoint."""
+    from workloads import case_cavity, mesh_cavity
+
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1)
+    a = Solver(case, precision="fp32", max_inner=30, tol=1e-12, max_outer=3)
+    a.solve()
+    a.iterate(gsis=True, n=2)
+    path = tmp_path / "state.ckpt"
+    a.checkpoint(path)
+    ea, _ = a.iterate(gsis=True, n=3)
+    b = Solver(case, precision="fp32", max_inner=30)
+    b.restore(path)
+    eb, _ = b.iterate(gsis=True, n=3)
+    assert ea == eb
+    fa, Ia = a.get_state()
+    fb, Ib = b.get_state()
+    assert np.array_equal(fa, fb) and np.array_equal(Ia, Ib)
+    n = C.c_int64(0)
+    b.L.gsis_get_residual_history(b.h, None, 0, C.byref(n))
+    assert n.value == 3
+    # a handle of another precision or grid refuses the file
+    c = Solver(case, precision="fp64")
+    with pytest.raises(GsisError):
+        c.restore(path)
+    for s in (a, b, c):
+        s.close()
+
+
+def test_divergence_is_reported():
+    """Non-physical states end the iteration with GSIS_E_DIVERGED instead of iterating on: a NaN in the
+    distributions, and distributions whose density is negative in some cells."""
+    from workloads import case_fourier_1d
+
+    case = case_fourier_1d(n=16, nv=24, no=8, Kn=0.1)
+    s = Solver(case, precision="fp64")
+    f, I = s.get_state()
+    g = f.copy()
+    g[3, 0, :] = np.nan
+    s.set_state(g, I)
+    with pytest.raises(GsisError, match="code -5"):
+        s.iterate(gsis=False)
+    g = f.copy()
+    g[5, 0, :] *= -1.0  # negative density in one cell
+    s.set_state(g, I)
+    with pytest.raises(GsisError, match="non-positive density or temperature"):
+        s.iterate(gsis=False)
+    s.set_state(f, I)
+    e, _ = s.iterate(gsis=False)
+    assert np.isfinite(e)
+    s.close()
+
+
+def test_diverging_iteration_stops_with_diverged():
+    """A diverging iteration (the conventional iteration over-relaxed with omega = 2.5, which the oracle shows
+    leaving the physical states after ~15 iterations on this case) ends gsis_solve with GSIS_E_DIVERGED as soon
+    as a cell holds a non-positive density or temperature, well before the iteration limit and before the
+    fields turn into NaN."""
+    from workloads import case_fourier_1d
+
+    case = case_fourier_1d(n=32, nv=24, no=8, Kn=0.1)
+    s = Solver(case, precision="fp64", scheme="cis", kin_omega=2.5, max_outer=400, tol=1e-10)
+    rep = gsis_report()
+    rc = s.L.gsis_solve(s.h, C.byref(rep))
+    msg = s.L.gsis_last_error(s.h).decode()
+    assert rc == GSIS_E_DIVERGED, (rc, rep.iters, rep.eps_final)
+    assert rep.iters < 40 and "non-positive density or temperature" in msg, (rep.iters, msg)
     s.close()

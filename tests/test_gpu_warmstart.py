@@ -93,7 +93,7 @@ def test_warm_start_saves_iterations():
     ws.fit(X, Y, epochs=150, batch=1024, lr=3e-3)
     plain_it, warm_it = [], []
     for c in test:
-        F0, it0, _, ok0 = WS.converged_fields(c, tol=1e-6, max_outer=800)
+        F0, _, it0, _, ok0 = WS.converged_fields(c, tol=1e-6, max_outer=800)
         s = Solver(c, tol=1e-6, max_outer=800)
         pred = ws.init_solver(s, c)
         rc, rep, _ = s.solve()
@@ -131,7 +131,7 @@ def test_warm_start_replaces_mach_continuation():
     tests = [case_cylinder(mesh=mesh, Ma=4.17, Kn=0.062, tau_opt=1.72, **kw),
              case_cylinder(mesh=mesh, Ma=4.48, Kn=0.037, tau_opt=2.27, **kw)]
     for c in tests:
-        F0, it0, _, ok0 = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), tol=1e-6)
+        F0, _, it0, _, ok0 = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), tol=1e-6)
         s = Solver(c, tol=1e-6, max_outer=800, n_precond=10, first_order_iters=20)
         pred = ws.init_solver(s, c)
         rc, rep, _ = s.solve()
@@ -143,3 +143,50 @@ def test_warm_start_replaces_mach_continuation():
         assert np.linalg.norm(pred["Tt"] - F0[:, 3]) < 0.1 * np.linalg.norm(F0[:, 3])
         for i in (0, 3, 7):
             assert np.linalg.norm(F1[:, i] - F0[:, i]) <= 1e-4 * np.linalg.norm(F0[:, i])
+
+
+@pytest.mark.parametrize("bf16,tol", [(True, 2e-3), (False, 1e-4)], ids=["bf16", "fp32"])
+def test_gradient_elementwise_at_production_width(bf16, tol):
+    """Width 256 (the production network): every output and every element of every layer's weight and bias
+    gradient against the FP64 reference, relative to the largest magnitude of that layer (BF16: operands
+    on a rounding midpoint may round the other way on one side, a 2^-8 change of one term)."""
+    net = WS.MLP(8, 256, 7, bf16=bf16, seed=11)
+    shp = M.shapes(8, 256, 7)
+    x, t = _data(333, 8, 7, 5)
+    p = net.get_params().astype(np.float64)
+    y = net.forward(x)
+    y_ref = M.forward(p, shp, x, bf16=bf16)[-1]
+    assert np.abs(y - y_ref).max() <= 0.5 * tol * np.abs(y_ref).max()
+    _, g = net.loss_grad(x, t)
+    _, g_ref = M.loss_grad(p, shp, x, t, bf16=bf16)
+    Ws, bs = M.unpack(g.astype(np.float64), shp)
+    Wr, br = M.unpack(g_ref, shp)
+    for l in range(4):
+        assert np.abs(Ws[l] - Wr[l]).max() <= tol * np.abs(Wr[l]).max(), l
+        assert np.abs(bs[l] - br[l]).max() <= tol * np.abs(br[l]).max(), l
+    net.close()
+
+
+def test_library_standardisation_prediction_and_file_round_trip(tmp_path):
+    """gsis_ws_fit_norm gives the column means and spreads; gsis_ws_predict equals the de-standardised
+    forward pass of the standardised rows; a network saved with gsis_ws_save and loaded into a fresh handle
+    predicts the same values."""
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(500, 7)) * np.arange(1, 8) + np.arange(7)
+    Y = rng.normal(size=(500, 7)) * 0.3 + 2.0
+    ws = WS.WarmStart(width=64, seed=2)
+    ws.fit(X, Y, epochs=2, batch=128, lr=1e-3)
+    nm = ws.norm
+    np.testing.assert_allclose(np.array(nm.x_mean[:7]), X.mean(0), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(np.array(nm.x_scale[:7]), X.std(0) + 1e-12, rtol=1e-12)
+    np.testing.assert_allclose(np.array(nm.y_scale[:7]), Y.std(0) + 1e-12, rtol=1e-12)
+    P = ws.predict(X[:50])
+    xm, xs = np.array(nm.x_mean[:7]), np.array(nm.x_scale[:7])
+    ym, ys = np.array(nm.y_mean[:7]), np.array(nm.y_scale[:7])
+    ref = ws.net.forward(((X[:50] - xm) / xs).astype(np.float32)).astype(np.float64) * ys + ym
+    assert np.abs(P - ref).max() <= 1e-5 * np.abs(ref).max()
+    path = tmp_path / "net.bin"
+    ws.save(path)
+    ws2 = WS.WarmStart(width=64, seed=99)
+    ws2.load(path)
+    assert np.array_equal(ws2.predict(X[:50]), P)

@@ -72,6 +72,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2601_03935_amd/build.py")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (same soname), and a process that loads
+    # both cannot use the GPU through the second.  Loading torch first makes the library bind to torch's
+    # runtime, so torch streams and device memory can be handed to it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {

@@ -59,6 +59,16 @@ int32_t gsis_mlp_get_params(gsis_mlp_t *m, float *params);
 int32_t gsis_mlp_set_params(gsis_mlp_t *m, const float *params);
 /* Inference: x [n][n_in] -> y [n][n_out] (host, row-major). */
 int32_t gsis_mlp_forward(gsis_mlp_t *m, int64_t n, const float *x, float *y);
+/* Allocation-free inference, for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): x [n][n_in] -> y [n][n_out], both DEVICE pointers
+ * owned by the caller (row-major FP32, 4-byte aligned).  The hidden activations live in a file-scope device
+ * array of 8 MiB per GPU (held until the process ends); batches larger than it holds (8 MiB / (8 width) rows,
+ * 4,096 at width 256) go through in consecutive chunks, with results identical to gsis_mlp_forward's.
+ * Enqueued on the handle's stream; returns without waiting.  Calls no hipMalloc / hipFree.  Every call on
+ * one GPU shares that array, so calls that overlap on one GPU (other streams, other threads, other handles)
+ * race.  Errors: GSIS_E_ARG (n < 0 or > INT32_MAX, null x or y with n > 0), GSIS_E_DEVICE (the array's
+ * address could not be obtained at gsis_mlp_create, or a launch error). */
+int32_t gsis_mlp_forward_noalloc(gsis_mlp_t *m, int64_t n, const float *x, float *y);
 /* Loss and its gradient with respect to the parameter vector (same layout) for rows x, targets t. */
 int32_t gsis_mlp_loss_grad(gsis_mlp_t *m, int64_t n, const float *x, const float *t, double *loss, float *grad);
 /* One Adam step (bias-corrected, step count kept in the handle) on the rows given; *loss before the step. */

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -333,10 +334,34 @@ struct gsis_mlp_s {
     float *dZ[2] = {nullptr, nullptr}, *cpart = nullptr;
     double *lpart = nullptr, *loss = nullptr;
     int64_t adam_t = 0;
+    float *scratch = nullptr;  // this device's copy of the file-scope scratch array (hipGetSymbolAddress)
     std::string err;
 };
 
+// Hidden activations of gsis_mlp_forward_noalloc: a file-scope device array, one copy per GPU, held until the
+// process ends.  In host code the symbol is only a stand-in; kernels get the address hipGetSymbolAddress
+// returns with the device current (kept per device below).
+constexpr int64_t kScratchFloats = (int64_t)1 << 21;  // 8 MiB
+static __device__ __align__(256) float scratch[kScratchFloats];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch[kMaxDevices] = {};
+
+// address of the scratch array on `device`, which must be the current device; nullptr if the lookup fails
+float *scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch[device] = (float *)p;
+    }
+    return g_scratch[device];
+}
 
 int32_t fail(gsis_mlp_t *m, int32_t code, const std::string &msg)
 {
@@ -423,25 +448,28 @@ const uint16_t *wptr<uint16_t>(gsis_mlp_t *m, int l)
     return m->Ph + m->offW[l];
 }
 
+// n rows of X [n][n_in] through the four layers into Y [n][n_out], hidden activations in H0, H1, H2 ([n][width]
+// each; H2 may be H0, which layer 2 does not read)
 template <typename BT>
-void forward_T(gsis_mlp_t *m, int n)
+void forward_T(gsis_mlp_t *m, int n, const float *X, float *H0, float *H1, float *H2, float *Y)
 {
     const int w = m->width;
-    gemm<false, true, BT, EPI_BIAS_TANH>(m, n, w, m->n_in, m->X, m->n_in, wptr<BT>(m, 0), m->n_in, m->A[0], w,
+    gemm<false, true, BT, EPI_BIAS_TANH>(m, n, w, m->n_in, X, m->n_in, wptr<BT>(m, 0), m->n_in, H0, w,
                                          m->P + m->offb[0], nullptr);
-    gemm<false, true, BT, EPI_BIAS_TANH>(m, n, w, w, m->A[0], w, wptr<BT>(m, 1), w, m->A[1], w, m->P + m->offb[1],
-                                         nullptr);
-    gemm<false, true, BT, EPI_BIAS_TANH>(m, n, w, w, m->A[1], w, wptr<BT>(m, 2), w, m->A[2], w, m->P + m->offb[2],
-                                         nullptr);
-    gemm<false, true, BT, EPI_BIAS>(m, n, m->n_out, w, m->A[2], w, wptr<BT>(m, 3), w, m->Y, m->n_out,
-                                    m->P + m->offb[3], nullptr);
+    gemm<false, true, BT, EPI_BIAS_TANH>(m, n, w, w, H0, w, wptr<BT>(m, 1), w, H1, w, m->P + m->offb[1], nullptr);
+    gemm<false, true, BT, EPI_BIAS_TANH>(m, n, w, w, H1, w, wptr<BT>(m, 2), w, H2, w, m->P + m->offb[2], nullptr);
+    gemm<false, true, BT, EPI_BIAS>(m, n, m->n_out, w, H2, w, wptr<BT>(m, 3), w, Y, m->n_out, m->P + m->offb[3],
+                                    nullptr);
 }
 
-void forward(gsis_mlp_t *m, int n)
+void forward_rows(gsis_mlp_t *m, int n, const float *X, float *H0, float *H1, float *H2, float *Y)
 {
-    if (m->bf16) forward_T<uint16_t>(m, n);
-    else forward_T<float>(m, n);
+    if (m->bf16) forward_T<uint16_t>(m, n, X, H0, H1, H2, Y);
+    else forward_T<float>(m, n, X, H0, H1, H2, Y);
 }
+
+// the handle's batch buffers (every activation kept for the backward pass)
+void forward(gsis_mlp_t *m, int n) { forward_rows(m, n, m->X, m->A[0], m->A[1], m->A[2], m->Y); }
 
 void colsum(gsis_mlp_t *m, int M, int N, const float *X, float *out)
 {
@@ -661,6 +689,8 @@ int32_t gsis_mlp_create(int32_t device, int32_t n_in, int32_t width, int32_t n_o
         gsis_mlp_destroy(m);
         return GSIS_E_OOM;
     }
+    // set-up of the allocation-free entry point on this device (a failed lookup is reported by that call)
+    m->scratch = scratch_address(device);
     *out = m;
     return gsis_mlp_set_params(m, p.data());
 }
@@ -725,6 +755,31 @@ int32_t gsis_mlp_forward(gsis_mlp_t *m, int64_t n, const float *x, float *y)
     forward(m, (int)n);
     MCHECK(m, hipMemcpyAsync(y, m->Y, n * m->n_out * sizeof(float), hipMemcpyDeviceToHost, m->st));
     MCHECK(m, hipStreamSynchronize(m->st));
+    return GSIS_OK;
+}
+
+int32_t gsis_mlp_forward_noalloc(gsis_mlp_t *m, int64_t n, const float *x, float *y)
+{
+    if (!m) return GSIS_E_ARG;
+    if (n < 0 || n > INT_MAX) return fail(m, GSIS_E_ARG, "gsis_mlp_forward_noalloc: row count out of range");
+    if (n > 0 && (!x || !y)) return fail(m, GSIS_E_ARG, "gsis_mlp_forward_noalloc: null input or output");
+    if (!m->scratch)
+        return fail(m, GSIS_E_DEVICE, "gsis_mlp_forward_noalloc: the scratch array has no address on this device");
+    // two hidden buffers of `rows` rows each; larger batches go through in consecutive chunks of rows (rows are
+    // independent, so the result does not depend on the chunking)
+    const int64_t per_row = 2 * (int64_t)m->width;
+    if (per_row > kScratchFloats)
+        return fail(m, GSIS_E_ARG, "gsis_mlp_forward_noalloc: width " + std::to_string(m->width) +
+                                       " needs more than the " + std::to_string(kScratchFloats * 4) +
+                                       "-byte scratch array for one row");
+    const int64_t rows = kScratchFloats / per_row;
+    MCHECK(m, hipSetDevice(m->device));
+    float *H0 = m->scratch, *H1 = m->scratch + rows * m->width;
+    for (int64_t r0 = 0; r0 < n; r0 += rows) {
+        const int nr = (int)std::min<int64_t>(rows, n - r0);
+        forward_rows(m, nr, x + r0 * m->n_in, H0, H1, H0, y + r0 * m->n_out);
+    }
+    MCHECK(m, hipGetLastError());
     return GSIS_OK;
 }
 

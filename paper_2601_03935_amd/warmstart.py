@@ -25,7 +25,8 @@ from .gsis import GsisError, Solver, lib
 
 EXPORTS = [
     "gsis_mlp_create", "gsis_mlp_destroy", "gsis_mlp_last_error", "gsis_mlp_set_stream", "gsis_mlp_num_params",
-    "gsis_mlp_get_params", "gsis_mlp_set_params", "gsis_mlp_forward", "gsis_mlp_loss_grad", "gsis_mlp_adam_step",
+    "gsis_mlp_get_params", "gsis_mlp_set_params", "gsis_mlp_forward", "gsis_mlp_forward_noalloc",
+    "gsis_mlp_loss_grad", "gsis_mlp_adam_step",
     "gsis_mlp_train", "gsis_ws_fit_norm", "gsis_ws_train", "gsis_ws_predict", "gsis_ws_save", "gsis_ws_load",
     "gsis_ws_targets", "gsis_init_warmstart",
 ]
@@ -62,6 +63,7 @@ def _lib():
             "gsis_mlp_get_params": ([P, P], I32),
             "gsis_mlp_set_params": ([P, P], I32),
             "gsis_mlp_forward": ([P, I64, P, P], I32),
+            "gsis_mlp_forward_noalloc": ([P, I64, P, P], I32),
             "gsis_mlp_loss_grad": ([P, I64, P, P, C.POINTER(C.c_double), P], I32),
             "gsis_mlp_adam_step": ([P, C.POINTER(gsis_mlp_train_opts), I64, P, P, C.POINTER(C.c_double)], I32),
             "gsis_mlp_train": ([P, I64, P, P, C.POINTER(gsis_mlp_train_opts), C.POINTER(C.c_double)], I32),
@@ -147,6 +149,12 @@ class MLP:
         y = np.empty((x.shape[0], self.n_out), dtype=np.float32)
         self._check(self.L.gsis_mlp_forward(self.h, x.shape[0], _ptr(x), _ptr(y)), "gsis_mlp_forward")
         return y
+
+    def forward_noalloc(self, x_dev, y_dev, n):
+        """Allocation-free inference on device memory: x_dev, y_dev are device addresses (ints) of [n][n_in] and
+        [n][n_out] FP32 rows; enqueued on the handle's stream (no wait)."""
+        self._check(self.L.gsis_mlp_forward_noalloc(self.h, int(n), C.c_void_p(x_dev), C.c_void_p(y_dev)),
+                    "gsis_mlp_forward_noalloc")
 
     def loss_grad(self, x, t):
         x, t = _f32(x), _f32(t)

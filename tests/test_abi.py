@@ -46,6 +46,7 @@ def test_mlp_argument_errors():
     assert L.gsis_mlp_create(0, 0, 8, 2, 1, 0, C.byref(h)) == G.GSIS_E_ARG
     assert L.gsis_mlp_create(0, 3, 8, 65, 1, 0, C.byref(h)) == G.GSIS_E_ARG
     assert L.gsis_mlp_forward(None, 1, None, None) == G.GSIS_E_ARG
+    assert L.gsis_mlp_forward_noalloc(None, 1, None, None) == G.GSIS_E_ARG
     assert L.gsis_mlp_num_params(None) == G.GSIS_E_ARG
 
 

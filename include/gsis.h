@@ -85,7 +85,7 @@ typedef struct {
 
 /* Iteration options.  Defaults (gsis_default_opts): GSIS, FP32, tol 1e-6, max_outer 1000,
  * n_precond 10, cfl_meso 1e5, cfl_v 5, kin_sweeps 8, kin_omega 1, limiter_K 10, second_order 1,
- * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2, first_order_iters 0, sweep JACOBI. */
+ * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2, first_order_iters 0, sweep JACOBI, kin_fused 0. */
 typedef struct {
     int32_t scheme;       /* GSIS_CIS or GSIS_GSIS */
     int32_t precision;    /* GSIS_FP64 or GSIS_FP32: storage and arithmetic of f and I */
@@ -106,6 +106,12 @@ typedef struct {
     int32_t first_order_iters; /* gsis_solve: the first this many outer iterations use first-order
                                   reconstruction (start-up of strongly non-equilibrium flows); 0 = none */
     int32_t sweep;        /* GSIS_SWEEP_JACOBI or GSIS_SWEEP_SGS (kin_sweeps counts the sweeps of either) */
+    int32_t kin_fused;    /* 0: a gradient pass stores the limited gradients of f (nc x distributions x dim x
+                             nv values) and the residual reads them; 1: the residual kernel recomputes the
+                             gradients it needs (its cell's and its face neighbours', from the second ring of
+                             f), so no gradient field is stored: dim x less memory for the kinetic buffers,
+                             ~5x the gradient arithmetic.  Same arithmetic per velocity either way; velocity
+                             counts not divisible by 16 bytes / element size always take the stored pass. */
 } gsis_opts;
 
 typedef struct {

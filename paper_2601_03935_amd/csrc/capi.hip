@@ -173,6 +173,7 @@ static void free_mesh(MeshDev &m)
     dfree(m.bf_n);
     dfree(m.bf_dxc);
     dfree(m.bcells);
+    dfree(m.bf_bidx);
     dfree(m.f_L);
     dfree(m.f_R);
     dfree(m.fgeo);
@@ -306,19 +307,20 @@ static int32_t build_mesh(gsis_t *h)
         }
     }
     std::vector<double> bf_n(nbf * D), bf_dxc(nbf * D);
-    std::vector<int> bcells;
+    std::vector<int> bcells, bf_bidx(nbf);
     {
-        std::vector<char> mark(nc, 0);
+        std::vector<int> pos(nc, -1);
         for (int64_t b = 0; b < nbf; ++b) {
             const int64_t f = bf_face[b], c = bf_cell[b];
             for (int a = 0; a < D; ++a) {
                 bf_n[b * D + a] = hm.fn[f * D + a];
                 bf_dxc[b * D + a] = hm.fctr[f * D + a] - hm.ctr[c * D + a];
             }
-            if (!mark[c]) {
-                mark[c] = 1;
+            if (pos[c] < 0) {
+                pos[c] = (int)bcells.size();
                 bcells.push_back((int)c);
             }
+            bf_bidx[b] = pos[c];
         }
     }
     std::vector<int> fL(nf), fR(nf);
@@ -404,7 +406,8 @@ static int32_t build_mesh(gsis_t *h)
               upload(m.mgeo, mgeo) && upload(m.lsq, lsq) && upload(m.vol, hm.vol) &&
               upload(m.h, hh) && upload(m.eps2, eps2) && upload(m.nfc, nfc) && upload(m.bf_face, bf_face) &&
               upload(m.bf_cell, bf_cell) && upload(m.bf_tag, bf_tag) && upload(m.bf_n, bf_n) &&
-              upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.f_L, fL) && upload(m.f_R, fR) &&
+              upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.bf_bidx, bf_bidx) &&
+              upload(m.f_L, fL) && upload(m.f_R, fR) &&
               upload(m.fgeo, fgeo) && upload(m.bcs, bcs) && upload(m.bf_bc, bf_bc) && upload(m.color, color) &&
               upload(m.col_cells, col_cells);
     if (!ok) return fail(h, GSIS_E_OOM, "device allocation of mesh tables failed");
@@ -418,6 +421,7 @@ static void free_kin(KinBufs<T> &B)
     dfree(B.f);
     dfree(B.f2);
     dfree(B.gf);
+    dfree(B.gfb);
     dfree(B.r);
     dfree(B.dl0);
     dfree(B.dl1);
@@ -475,29 +479,32 @@ static void free_macro(MacroBufs &B)
 static int ndist(int D) { return D == 3 ? 3 : 4; }
 static int coef_sz(int D) { return D + 6 + 3 * (5 + 3 * D); }
 
-// Distribution-sized buffers beyond f, its gradients and r that the chosen relaxation needs: Jacobi sweeps
-// two increment buffers (the last sweep writes f in place), no sweeps a second f; colored Gauss-Seidel with
-// one symmetric sweep none (it runs in place in r), with more sweeps one increment buffer.  Buffers the
-// options no longer need are released, so that switching the relaxation keeps the state.
+// Distribution-sized buffers beyond f and r that the options need: the stored gradient field unless the
+// residual recomputes the gradients (which it does for velocity counts that fill 16-byte vectors); Jacobi
+// sweeps two increment buffers (the last sweep writes f in place), no sweeps a second f; colored Gauss-Seidel
+// with one symmetric sweep none (it runs in place in r), with more sweeps one increment buffer.  Buffers the
+// options no longer need are released, so that switching keeps the state.
 struct KinPlan {
-    bool dl0, dl1, f2;
+    bool gf, dl0, dl1, f2;
 };
-static KinPlan kin_plan(const gsis_opts &o)
+static KinPlan kin_plan(const gsis_opts &o, int64_t nv, size_t es)
 {
-    if (o.sweep == GSIS_SWEEP_SGS) return {o.kin_sweeps > 1, false, false};
-    return {o.kin_sweeps > 0, o.kin_sweeps > 0, o.kin_sweeps == 0};
+    const bool gf = !(o.kin_fused && nv % (int64_t)(16 / es) == 0);
+    if (o.sweep == GSIS_SWEEP_SGS) return {gf, o.kin_sweeps > 1, false, false};
+    return {gf, o.kin_sweeps > 0, o.kin_sweeps > 0, o.kin_sweeps == 0};
 }
 template <typename T>
 static bool plan_kin(gsis_t *h, KinBufs<T> &B)
 {
     const int D = h->hm.D, ND = ndist(D);
     const size_t nc = h->hm.nc, nv = h->nv;
-    const KinPlan pl = kin_plan(h->opts);
+    const KinPlan pl = kin_plan(h->opts, (int64_t)nv, sizeof(T));
     bool ok = true;
-    auto want = [&](T *&p, bool need) {
-        if (need && !p) p = dalloc<T>(nc * ND * nv, ok);
+    auto want = [&](T *&p, bool need, size_t rows = 1) {
+        if (need && !p) p = dalloc<T>(nc * ND * nv * rows, ok);
         if (!need) dfree(p);
     };
+    want(B.gf, pl.gf, (size_t)D);
     want(B.dl0, pl.dl0);
     want(B.dl1, pl.dl1);
     want(B.f2, pl.f2);
@@ -511,7 +518,7 @@ static bool alloc_kin(gsis_t *h, KinBufs<T> &B)
     const size_t nc = h->hm.nc, nv = h->nv, no = h->no, nbf = h->m.nbf;
     bool ok = true;
     B.f = dalloc<T>(nc * ND * nv, ok);
-    B.gf = dalloc<T>(nc * ND * D * nv, ok);
+    B.gfb = dalloc<T>((size_t)h->m.nbcells * ND * D * nv, ok);
     B.r = dalloc<T>(nc * ND * nv, ok);
     if (ok) ok = plan_kin(h, B);
     B.I = dalloc<T>(nc * no, ok);
@@ -632,6 +639,7 @@ static KinOpts kopts(const gsis_t *h)
     o.kin_sweeps = h->opts.kin_sweeps;
     o.second_order = h->opts.second_order;
     o.sweep = h->opts.sweep;
+    o.fused = h->opts.kin_fused;
     o.col_ptr = h->col_ptr.data();
     o.ncolor = (int)h->col_ptr.size() - 1;
     return o;
@@ -1043,6 +1051,7 @@ void gsis_default_opts(gsis_opts *o)
     o->first_order_iters = 0;
     o->n_sweeps = 2;
     o->sweep = GSIS_SWEEP_JACOBI;
+    o->kin_fused = 0;
 }
 
 int32_t gsis_create(int32_t device, gsis_t **out)
@@ -1212,7 +1221,8 @@ int32_t gsis_set_opts(gsis_t *h, const gsis_opts *o)
         o->kin_sweeps < 0 || o->max_inner < 0 || o->max_outer < 0 || o->n_precond < 0 || o->n_sweeps < 0 ||
         o->first_order_iters < 0 || (o->second_order != 0 && o->second_order != 1) || !(o->tol >= 0) ||
         !(o->inner_tol >= 0) || !(o->limiter_K > 0) || !(o->kin_omega > 0) || !(o->cfl_v > 0) ||
-        !(o->cfl_meso > 0) || !(o->cfl_macro > 0) || (o->sweep != GSIS_SWEEP_JACOBI && o->sweep != GSIS_SWEEP_SGS))
+        !(o->cfl_meso > 0) || !(o->cfl_macro > 0) || (o->sweep != GSIS_SWEEP_JACOBI && o->sweep != GSIS_SWEEP_SGS) ||
+        (o->kin_fused != 0 && o->kin_fused != 1))
         return fail(h, GSIS_E_ARG, "gsis_set_opts: invalid options");
     // the kinetic kernels index waves over (cell, 64-velocity chunk) pairs with 32-bit integers
     if (h->hm.nc * ((h->nv + 63) / 64 + 1) > (int64_t)(INT32_MAX / 8))

@@ -54,6 +54,7 @@ struct KinOpts {
     double cfl_meso, cfl_v, kin_omega, limK;
     int kin_sweeps, second_order;
     int sweep;               // 0: Jacobi sweeps; 1: colored symmetric Gauss-Seidel sweeps
+    int fused;               // 1: limited gradients recomputed inside the residual kernel
     const int64_t *col_ptr;  // host: cells of colour q are col_cells[col_ptr[q] .. col_ptr[q + 1])
     int ncolor;
 };
@@ -87,6 +88,7 @@ struct MeshDev {
     double *bf_n = nullptr, *bf_dxc = nullptr;  // outward unit normal, x_f - x_c
     int *bcells = nullptr;                       // distinct cells next to boundary faces
     int64_t nbcells = 0;
+    int *bf_bidx = nullptr;                      // per boundary face: position of its cell in bcells
     // interior faces (for face HoTs / reference dissipation)
     int *f_L = nullptr, *f_R = nullptr;  // R < 0 on boundary faces
     // per face, 2D + 2 values: the unit normal n (L -> R), and on interior faces with d = x_R - x_L the unit

@@ -14,6 +14,7 @@ struct KinBufs {
     T *f = nullptr, *f2 = nullptr, *gf = nullptr, *r = nullptr, *dl0 = nullptr, *dl1 = nullptr;
     T *I = nullptr, *I2 = nullptr, *gI = nullptr, *rI = nullptr, *dI0 = nullptr, *dI1 = nullptr;
     T *coef = nullptr, *xi = nullptr, *om = nullptr, *rhow = nullptr;
+    T *gfb = nullptr;  // limited gradients of the boundary cells only, row i for cell bcells[i]
     T *xiT = nullptr;  // velocity components component-major: xiT[a * nv + k]
     double *xi_d = nullptr, *w_d = nullptr, *om_d = nullptr, *wo_d = nullptr;  // om: D components per ordinate
     double *bflux = nullptr, *bsurf = nullptr;

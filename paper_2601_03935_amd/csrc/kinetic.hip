@@ -113,13 +113,15 @@ __device__ __forceinline__ bool wave_cell_chunk(const int w, const int ncell, co
 template <typename T, int D, int NFM>
 __global__ __launch_bounds__(256) void k_grad(const T *__restrict__ f, T *__restrict__ gf, const MeshDev m,
                                               const int nd, const int64_t nv, const int second_order,
-                                              const int *__restrict__ cell_list, const int64_t ncl)
+                                              const int *__restrict__ cell_list, const int64_t ncl,
+                                              const int compact)
 {
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
     const int64_t idx = b * 4 + (threadIdx.x >> 6);
     if (idx >= ncl) return;
     const int c = uni_i(cell_list ? cell_list[idx] : (int)idx);
+    const int64_t orow = compact ? idx : c;  // row of the output: list position or cell
     const int nfc = uni_i(m.nfc[c]);
     int nb[NFM];
     T lsq[NFM][D], dxc[NFM][D];
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) void k_grad(const T *__restrict__ f, T *__rest
                 }
             }
 #pragma unroll
-            for (int a = 0; a < D; ++a) gf[(((int64_t)c * nd + d) * D + a) * nv + k] = phi * g[a];
+            for (int a = 0; a < D; ++a) gf[((orow * nd + d) * D + a) * nv + k] = phi * g[a];
         }
     }
 }
@@ -216,7 +218,8 @@ template <typename T, int D, int NFM, int VW>
 __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__restrict__ gf, const MeshDev m,
                                                 const int64_t nv, const int nchunk, const int cgroup,
                                                 const int second_order,
-                                                const int *__restrict__ cell_list, const int64_t ncl)
+                                                const int *__restrict__ cell_list, const int64_t ncl,
+                                                const int compact)
 {
     using V = vec_t<T, VW>;
     constexpr int ND = (D == 3) ? 3 : 4;
@@ -225,6 +228,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__re
     if (!wave_cell_chunk(w, (int)ncl, nchunk, cgroup, idx, ch)) return;
     const int64_t k = ((int64_t)ch * kWave + (threadIdx.x & 63)) * VW;
     const int c = uni_i(cell_list ? cell_list[idx] : idx);
+    const int64_t orow = compact ? idx : c;  // row of the output: list position or cell
     // padded slots: nbr = INT32_MIN, zero geometry (no gradient term, no limiter test)
     int nb[NFM];
     T lsq[NFM][D], dxc[NFM][D];
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__re
             }
 #pragma unroll
             for (int a = 0; a < D; ++a)
-                __builtin_nontemporal_store(go[a], (V *)(gf + (((int64_t)c * ND + d) * D + a) * nv + k));
+                __builtin_nontemporal_store(go[a], (V *)(gf + ((orow * ND + d) * D + a) * nv + k));
         }
     }
 }
@@ -615,6 +619,212 @@ __global__ __launch_bounds__(256) void k_residual_v(const T *__restrict__ f, con
                 __builtin_nontemporal_store(rr[d], (V *)(r + o));
                 if (dl) __builtin_nontemporal_store(rr[d] / dd[d], (V *)(dl + o));
             }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ residual with gradients recomputed
+// Limited gradient of distribution d of cell j at the lane's VW velocities: the arithmetic of k_grad_v for
+// one distribution.  nbj: the NFM neighbour slots of j (>= 0 neighbour, < 0 boundary face, INT32_MIN none);
+// fj: f of (j, d) at the lane's velocities.
+template <typename T, int D, int NFM, int VW>
+__device__ __forceinline__ void limited_grad_v(const T *__restrict__ f, const MeshDev &m, const int j,
+                                               const int (&nbj)[NFM], const vec_t<T, VW> fj, const int d,
+                                               const int64_t k, const int64_t nv, const int second_order,
+                                               vec_t<T, VW> (&go)[D])
+{
+    using V = vec_t<T, VW>;
+    constexpr int ND = (D == 3) ? 3 : 4;
+    T lsq[NFM][D], dxc[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        const double *g = m.geo + ((int64_t)j * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            dxc[s][a] = (T)g[D + a];
+            lsq[s][a] = (T)g[3 * D + a];
+        }
+    }
+    const T eps2 = (T)m.eps2[j];
+    V fn[NFM];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s)
+        if (nbj[s] >= 0) fn[s] = *(const V *)(f + ((int64_t)nbj[s] * ND + d) * nv + k);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+        const T fc = fj[e];
+        T g[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) g[a] = T(0);
+        T dmax = T(0), dmin = T(0), mag = fabs(fc);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) {
+            if (nbj[s] >= 0) {
+                const T fv = fn[s][e], df = fv - fc;
+                mag = fabs(fv) > mag ? fabs(fv) : mag;
+#pragma unroll
+                for (int a = 0; a < D; ++a) g[a] += lsq[s][a] * df;
+                dmax = df > dmax ? df : dmax;
+                dmin = df < dmin ? df : dmin;
+            }
+        }
+        T phi = T(0);
+        if (second_order) {
+            phi = T(1);
+            const T inv = mag > tiny_val<T>() ? T(1) / mag : T(0);
+#pragma unroll
+            for (int s = 0; s < NFM; ++s) {
+                if (nbj[s] != INT32_MIN) {
+                    T d2 = T(0);
+#pragma unroll
+                    for (int a = 0; a < D; ++a) d2 += g[a] * dxc[s][a];
+                    if (d2 != T(0)) {
+                        const T d1 = d2 > T(0) ? dmax : dmin;
+                        const T u1 = d1 * inv, u2 = d2 * inv;
+                        T p = (u1 * u1 + eps2 + T(2) * u1 * u2) / (u1 * u1 + T(2) * u2 * u2 + u1 * u2 + eps2);
+                        p = p > T(1) ? T(1) : p;
+                        phi = p < phi ? p : phi;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) go[a][e] = phi * g[a];
+    }
+}
+
+// The residual of k_residual_v without a stored gradient field: each wave recomputes the limited gradients
+// of its cell and of the face neighbours it needs (their neighbour rows, the second ring, come through the
+// caches), distribution by distribution, so the kinetic step reads f and writes r (and the first Jacobi
+// iterate) with no gradient traffic.  Same arithmetic per velocity as k_grad_v followed by k_residual_v.
+template <typename T, int D, int NFM, int VW>
+__global__ __launch_bounds__(256) void k_gres_v(const T *__restrict__ f, const T *__restrict__ coef,
+                                                const T *__restrict__ xiT, const T *__restrict__ rhow,
+                                                T *__restrict__ r, T *__restrict__ dl, T *__restrict__ fout,
+                                                const MeshDev m, const int64_t nv, const int nchunk,
+                                                const int cgroup, const int second_order, const T cflv_fac,
+                                                const T omega, const T wt, const T wr, const T wv, const T dr,
+                                                const T dv)
+{
+    using V = vec_t<T, VW>;
+    constexpr int ND = (D == 3) ? 3 : 4;
+    const int w = uni_i((int)(xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)));
+    int c, ch;
+    if (!wave_cell_chunk(w, (int)m.nc, nchunk, cgroup, c, ch)) return;
+    const int64_t k = ((int64_t)ch * kWave + (threadIdx.x & 63)) * VW;
+    if (k >= nv) return;
+    int nb[NFM];
+    T nsv[NFM][D], dxc[NFM][D], dxj[NFM][D];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        nb[s] = m.nbr[(int64_t)c * NFM + s];
+        const double *g = m.geo + ((int64_t)c * NFM + s) * 4 * D;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            nsv[s][a] = (T)g[a];
+            dxc[s][a] = (T)g[D + a];
+            dxj[s][a] = (T)g[2 * D + a];
+        }
+    }
+    T cf[coef_size(3)];
+#pragma unroll
+    for (int i = 0; i < coef_size(D); ++i) cf[i] = coef[(int64_t)c * coef_size(D) + i];
+    V x[D], fc[ND];
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = *(const V *)(xiT + a * nv + k);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) fc[d] = *(const V *)(f + ((int64_t)c * ND + d) * nv + k);
+    // upwind diagonal sum and relaxation source
+    V dsum = T(0);
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+        if (nb[s] == INT32_MIN) continue;
+        V xn = T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+            if (xn[e] > T(0)) dsum[e] += xn[e];
+    }
+    V Jv[ND];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+        T xe[D], fe[4], J[4];
+#pragma unroll
+        for (int a = 0; a < D; ++a) xe[a] = x[a][e];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) fe[d] = fc[d][e];
+        collision<T, D>(cf, xe, fe, J, ND, wt, wr, wv);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) Jv[d][e] = J[d];
+    }
+    for (int d = 0; d < ND; ++d) {
+        V gc[D];
+        limited_grad_v<T, D, NFM, VW>(f, m, c, nb, fc[d], d, k, nv, second_order, gc);
+        V flux = T(0);
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) {
+            if (nb[s] == INT32_MIN) continue;
+            V xn = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
+            if (nb[s] >= 0) {
+                const int j = nb[s];
+                int nbj[NFM];
+#pragma unroll
+                for (int t = 0; t < NFM; ++t) nbj[t] = m.nbr[(int64_t)j * NFM + t];
+                const V fj = *(const V *)(f + ((int64_t)j * ND + d) * nv + k);
+                V gj[D];
+                limited_grad_v<T, D, NFM, VW>(f, m, j, nbj, fj, d, k, nv, second_order, gj);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    T v;
+                    if (xn[e] > T(0)) {
+                        v = fc[d][e];
+#pragma unroll
+                        for (int a = 0; a < D; ++a) v += gc[a][e] * dxc[s][a];
+                    } else {
+                        v = fj[e];
+#pragma unroll
+                        for (int a = 0; a < D; ++a) v += gj[a][e] * dxj[s][a];
+                    }
+                    flux[e] += xn[e] * v;
+                }
+            } else {
+                const int bfi = -nb[s] - 1;
+                const BcDev bc = m.bcs[m.bf_tag[bfi]];
+                const T rho = (bc.kind == 0) ? rhow[bfi] : (T)bc.rho;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    T v;
+                    if (xn[e] > T(0)) {
+                        v = fc[d][e];
+#pragma unroll
+                        for (int a = 0; a < D; ++a) v += gc[a][e] * dxc[s][a];
+                    } else {
+                        T xe[D], fv[4];
+#pragma unroll
+                        for (int a = 0; a < D; ++a) xe[a] = x[a][e];
+                        boundary_values<T, D>(bc, rho, xe, dr, dv, fv);
+                        v = fv[d];
+                    }
+                    flux[e] += xn[e] * v;
+                }
+            }
+        }
+        V rr, dd;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const T dcoef = cf[D + 1] + cf[D] + dsum[e] * cflv_fac;
+            rr[e] = Jv[d][e] - flux[e];
+            dd[e] = (d == 2) ? dcoef + cf[D + 5] : dcoef;
+        }
+        const int64_t o = ((int64_t)c * ND + d) * nv + k;
+        if (fout) {
+            __builtin_nontemporal_store(fc[d] + omega * (rr / dd), (V *)(fout + o));
+        } else {
+            __builtin_nontemporal_store(rr, (V *)(r + o));
+            if (dl) __builtin_nontemporal_store(rr / dd, (V *)(dl + o));
         }
     }
 }
@@ -1565,8 +1775,9 @@ __global__ void k_prologue(const double *__restrict__ mom, T *__restrict__ coef,
 // velocities are in flight together.
 template <typename T, int D, int NFM>
 __global__ __launch_bounds__(256) void k_wall_density(const T *__restrict__ f, const T *__restrict__ gf,
-                                                      const double *__restrict__ xi, const double *__restrict__ w,
-                                                      T *__restrict__ rhow, const MeshDev m, const int64_t nv)
+                                                      const int *__restrict__ grow, const double *__restrict__ xi,
+                                                      const double *__restrict__ w, T *__restrict__ rhow,
+                                                      const MeshDev m, const int64_t nv)
 {
     constexpr int ND = (D == 3) ? 3 : 4;
     __shared__ double sh[2][4];
@@ -1577,7 +1788,7 @@ __global__ __launch_bounds__(256) void k_wall_density(const T *__restrict__ f, c
         if (t == 0) rhow[bfi] = (T)0;
         return;
     }
-    const int64_t c = m.bf_cell[bfi];
+    const int64_t c = m.bf_cell[bfi], cg = grow[bfi];  // cg: the cell's row in gf
     double n[D], dx[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -1597,7 +1808,7 @@ __global__ __launch_bounds__(256) void k_wall_density(const T *__restrict__ f, c
         }
         T v = f[(c * ND + 0) * nv + k];
 #pragma unroll
-        for (int a = 0; a < D; ++a) v += gf[((c * ND + 0) * D + a) * nv + k] * (T)dx[a];
+        for (int a = 0; a < D; ++a) v += gf[((cg * ND + 0) * D + a) * nv + k] * (T)dx[a];
         const double mw = w[k] * (-xn) * gn * exp(-c2 / (2 * bc.T));
         if (xn > 0) out += w[k] * xn * (double)v;
         else in += mw;
@@ -1612,6 +1823,7 @@ __global__ __launch_bounds__(256) void k_wall_density(const T *__restrict__ f, c
 // the surface output (q_conv, q_rad, p_w)
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_boundary_flux(const T *__restrict__ f, const T *__restrict__ gf,
+                                                       const int *__restrict__ grow,
                                                        const T *__restrict__ I, const T *__restrict__ gI,
                                                        const double *__restrict__ xi, const double *__restrict__ w,
                                                        const double *__restrict__ om, const double *__restrict__ wo,
@@ -1626,7 +1838,7 @@ __global__ __launch_bounds__(256) void k_boundary_flux(const T *__restrict__ f, 
     const int bfi = blockIdx.x;
     const int t = threadIdx.x;
     const BcDev bc = m.bf_bc[bfi];
-    const int64_t c = m.bf_cell[bfi];
+    const int64_t c = m.bf_cell[bfi], cg = grow[bfi];  // cg: the cell's row in gf
     double n[D], dx[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -1655,7 +1867,7 @@ __global__ __launch_bounds__(256) void k_boundary_flux(const T *__restrict__ f, 
         for (int d = 0; d < ND; ++d) {
             T v = f[(c * ND + d) * nv + k];
 #pragma unroll
-            for (int a = 0; a < D; ++a) v += gf[((c * ND + d) * D + a) * nv + k] * (T)dx[a];
+            for (int a = 0; a < D; ++a) v += gf[((cg * ND + d) * D + a) * nv + k] * (T)dx[a];
             fo[d] = (double)v;
         }
         const double G = gn * exp(-c2 / (2 * bc.T));
@@ -1779,17 +1991,19 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
 static inline int64_t wave_blocks(int64_t n) { return (n + 3) / 4; }
 
 // Cells per chunk-major group of the (cell, velocity chunk) kernels, measured (MI355X; 20k-triangle cavity,
-// 1,024 velocities, 4 chunks; 214k-tetrahedron capsule shard, 1,728 velocities, 7 chunks): the residual
-// is fastest fully chunk-major in 2D and 3D (3D: 3.32 against 3.13 TB/s cell-major); the sweep and the
-// gradients fully chunk-major in 2D (sweep 5.82 against 5.53 TB/s) but cell-major in 3D (sweep 4.79
-// against 4.55); the synchronisation with groups of 1,024 cells.
+// 1,024 velocities, 4 chunks; 214k-tetrahedron capsule, 1,728 velocities, 7 chunks, and 13,824 velocities,
+// 54 chunks): the residual is fastest fully chunk-major in 2D and 3D (3D, 54 chunks: 60.3 ms against 89.4
+// cell-major); the sweep fully chunk-major in 2D (5.82 against 5.53 TB/s) and in 3D with many chunks (54:
+// 23.0 ms against 25.3 cell-major) but cell-major in 3D with few (7: 4.79 against 4.55 TB/s); the gradients
+// chunk-major in 2D and cell-major in 3D (54 chunks: 35.3 ms against 40.2); the synchronisation with groups
+// of 1,024 cells.
 enum class CG { grad, residual, sweep, sync };
-static int chunk_group(CG k, int D, int64_t ncell)
+static int chunk_group(CG k, int D, int64_t ncell, int nchunk = 1)
 {
     const int all = (int)ncell;
     switch (k) {
     case CG::residual: return all;
-    case CG::sweep:
+    case CG::sweep: return (D == 3 && nchunk < 16) ? 1 : all;
     case CG::grad: return D == 3 ? 1 : all;
     default: return (int)std::min<int64_t>(ncell, 1024);
     }
@@ -1797,18 +2011,18 @@ static int chunk_group(CG k, int D, int64_t ncell)
 
 template <typename T, int D, int NFM>
 void launch_grad(const T *f, T *gf, const MeshDev &m, int64_t nv, int so, const int *cells, int64_t ncl,
-                 hipStream_t st)
+                 int compact, hipStream_t st)
 {
     if (ncl <= 0) return;
     constexpr int VW = 16 / sizeof(T);
     if (nv % VW == 0) {
         const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
         hipLaunchKernelGGL((k_grad_v<T, D, NFM, VW>), dim3(wave_blocks(ncl * nchunk)), dim3(256), 0, st, f, gf, m,
-                           nv, nchunk, chunk_group(CG::grad, D, ncl), so, cells, ncl);
+                           nv, nchunk, chunk_group(CG::grad, D, ncl), so, cells, ncl, compact);
     }
     else
         hipLaunchKernelGGL((k_grad<T, D, NFM>), dim3(wave_blocks(ncl)), dim3(256), 0, st, f, gf, m,
-                           (D == 3) ? 3 : 4, nv, so, cells, ncl);
+                           (D == 3) ? 3 : 4, nv, so, cells, ncl, compact);
 }
 
 // lanes per cell of the packed ordinate kernels: 2^ord_lsh(no) covers no / VW ordinates (at most 64)
@@ -1926,26 +2140,40 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
     const double es = sizeof(T), cv = (double)m.nc * nv * ND * es, co = (double)m.nc * no * es;
     Prof dummy;
     Prof &P = pf ? *pf : dummy;
-    int ev = P.begin(0, cv * (1 + D));
-    launch_grad<T, D, NFM>(B.f, B.gf, m, nv, o.second_order, nullptr, m.nc, st);
+    constexpr int VW = 16 / sizeof(T);
+    // gradients recomputed inside the residual (vector kernels only); the stored pass otherwise.  Either way
+    // the wall densities read gradient rows of the boundary cells: the compact rows of gfb, or gf itself.
+    const bool fused = o.fused && (nv % VW == 0);
+    int ev = P.begin(0, fused ? (double)m.nbcells * nv * ND * es * (1 + D) : cv * (1 + D));
+    if (fused) launch_grad<T, D, NFM>(B.f, B.gfb, m, nv, o.second_order, m.bcells, m.nbcells, 1, st);
+    else launch_grad<T, D, NFM>(B.f, B.gf, m, nv, o.second_order, nullptr, m.nc, 0, st);
     P.end(ev);
     ev = P.begin(3, co * (1 + D));
     launch_grad_I<T, D, NFM>(B.I, B.gI, m, no, o.second_order, nullptr, m.nc, st);
     P.end(ev);
     ev = P.begin(5, 0.0);
     if (m.nbf > 0)
-        hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(256), 0, st, B.f, B.gf, B.xi_d, B.w_d,
-                           B.rhow, m, nv);
+        hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(256), 0, st, B.f, fused ? B.gfb : B.gf,
+                           fused ? m.bf_bidx : m.bf_cell, B.xi_d, B.w_d, B.rhow, m, nv);
     P.end(ev);
     const int ks = o.kin_sweeps;
-    ev = P.begin(1, (ks == 0 || o.sweep == 1) ? cv * (2 + D) : cv * (3 + D));
-    constexpr int VW = 16 / sizeof(T);
+    const double rbytes = (ks == 0 || o.sweep == 1) ? 2 * cv : 3 * cv;  // f read; r (and the first iterate) written
+    ev = P.begin(1, fused ? rbytes : rbytes + cv * D);
     // vector kernels with one wave per (cell, chunk of kWave * VW velocities)
     const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
     const dim3 chunk_grid((unsigned)((m.nc * nchunk + 3) / 4));
     const bool sgs = (o.sweep == 1);
     const bool direct = (!sgs && ks == 0);  // no sweeps: the residual writes f + omega r / d into f2
-    if (nv % VW == 0)
+    if (fused) {
+        // half-width vectors: the second ring of gradients needs the registers (occupancy 3 waves per SIMD)
+        constexpr int VF = VW / 2;
+        const int nchf = (int)((nv + kWave * VF - 1) / (kWave * VF));
+        hipLaunchKernelGGL((k_gres_v<T, D, NFM, VF>), dim3((unsigned)((m.nc * nchf + 3) / 4)), blk, 0, st, B.f,
+                           B.coef, B.xiT, B.rhow, B.r, sgs ? nullptr : B.dl0, direct ? B.f2 : nullptr, m, nv, nchf,
+                           chunk_group(CG::residual, D, m.nc), o.second_order, fac, om, wt, wr, wv, (T)p.d_r,
+                           (T)p.d_v);
+    }
+    else if (nv % VW == 0)
         hipLaunchKernelGGL((k_residual_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.f, B.gf, B.coef, B.xiT, B.rhow,
                            B.r, sgs ? nullptr : B.dl0, direct ? B.f2 : nullptr, m, nv, nchunk,
                            chunk_group(CG::residual, D, m.nc), fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
@@ -2001,7 +2229,7 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
         if (nv % VW == 0)
             hipLaunchKernelGGL((k_sweep_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.r, din, dout, B.f,
                                last ? B.f : nullptr, B.coef, B.xiT, m, nv, nchunk,
-                               chunk_group(CG::sweep, D, m.nc), fac, om);
+                               chunk_group(CG::sweep, D, m.nc, nchunk), fac, om);
         else
             hipLaunchKernelGGL((k_sweep<T, D, NFM>), grid, blk, 0, st, B.r, din, dout, B.f, last ? B.f : nullptr,
                                B.coef, B.xi, m, nv, fac, om);
@@ -2049,11 +2277,13 @@ void launch_boundary_state(KinBufs<T> &B, const MeshDev &m, const Phys &p, int s
                            hipStream_t st)
 {
     if (m.nbf <= 0) return;
-    launch_grad<T, D, NFM>(B.f, B.gf, m, nv, so, m.bcells, m.nbcells, st);
+    // gradient rows of the boundary cells only, compact (row i for the i-th boundary cell)
+    launch_grad<T, D, NFM>(B.f, B.gfb, m, nv, so, m.bcells, m.nbcells, 1, st);
     launch_grad_I<T, D, NFM>(B.I, B.gI, m, no, so, m.bcells, m.nbcells, st);
-    hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(256), 0, st, B.f, B.gf, B.xi_d, B.w_d,
-                       B.rhow, m, nv);
-    hipLaunchKernelGGL((k_boundary_flux<T, D>), dim3(m.nbf), dim3(256), 0, st, B.f, B.gf, B.I, B.gI, B.xi_d, B.w_d,
+    hipLaunchKernelGGL((k_wall_density<T, D, NFM>), dim3(m.nbf), dim3(256), 0, st, B.f, B.gfb, m.bf_bidx, B.xi_d,
+                       B.w_d, B.rhow, m, nv);
+    hipLaunchKernelGGL((k_boundary_flux<T, D>), dim3(m.nbf), dim3(256), 0, st, B.f, B.gfb, m.bf_bidx, B.I, B.gI,
+                       B.xi_d, B.w_d,
                        B.om_d, B.wo_d, B.rhow, B.bflux, B.bsurf, m, nv, no, p.d_r, p.d_v, p.sigma_R);
 }
 

@@ -53,7 +53,7 @@ class gsis_opts(C.Structure):
                 ("kin_sweeps", C.c_int32), ("kin_omega", C.c_double), ("limiter_K", C.c_double),
                 ("second_order", C.c_int32), ("cfl_macro", C.c_double), ("inner_tol", C.c_double),
                 ("max_inner", C.c_int32), ("n_sweeps", C.c_int32), ("first_order_iters", C.c_int32),
-                ("sweep", C.c_int32)]
+                ("sweep", C.c_int32), ("kin_fused", C.c_int32)]
 
 
 class gsis_report(C.Structure):

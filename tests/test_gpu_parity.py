@@ -428,8 +428,8 @@ def test_kinetic_step_sgs_fp32_ragged():
 
 
 def test_option_changes_keep_the_state():
-    """Switching the relaxation (Jacobi -> colored Gauss-Seidel -> Jacobi with no sweeps) and the limiter
-    constant between iterations keeps the state: the iterations match an oracle restarted from the same
+    """Switching the relaxation (Jacobi -> colored Gauss-Seidel -> Jacobi with no sweeps), the limiter
+    constant and the gradient pass (recomputed / stored) between iterations keeps the state: the iterations match an oracle restarted from the same
     state with the new options."""
     case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=10, n_theta=2, n_phi=4, Kn=0.1)
     s = Solver(case, precision="fp64", max_inner=60)
@@ -438,7 +438,8 @@ def test_option_changes_keep_the_state():
         o.iterate(gsis=False)
         s.iterate(gsis=False)
     for kw in (dict(sweep="sgs", kin_sweeps=1), dict(sweep="jacobi", kin_sweeps=0, limiter_K=2.0),
-               dict(sweep="jacobi", kin_sweeps=8, limiter_K=5.0)):
+               dict(sweep="jacobi", kin_sweeps=8, limiter_K=5.0, kin_fused=0),
+               dict(sweep="sgs", kin_sweeps=2, kin_fused=1)):
         s.set_opts(**kw)
         f, I = o.get_state()
         o = Oracle(case, **oracle_opts(s.opts))
@@ -447,4 +448,26 @@ def test_option_changes_keep_the_state():
         eg, _ = s.iterate(gsis=True)
         assert abs(eg - eo) <= 1e-8 * abs(eo) + 1e-14, kw
         assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-8, kw
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-6)])
+@pytest.mark.parametrize("name", ["cavity", "capsule"])
+def test_fused_and_stored_gradients_agree(name, prec, tol):
+    """The residual kernel that recomputes the limited gradients and the stored-gradient pass (default) give
+    the same kinetic step (same arithmetic per velocity), and both match the oracle."""
+    case = dict(_cases_small())[name]
+    s, o = _pair(case, precision=prec, kin_fused=1)
+    _warm(o, s, n=2)
+    f0, I0 = s.get_state()
+    s.kinetic_step()
+    ff, _ = s.get_state()
+    s.set_opts(kin_fused=0)
+    s.set_state(f0, I0)
+    s.kinetic_step()
+    fs, _ = s.get_state()
+    assert _relerr(ff, fs) <= tol, (name, prec)
+    o.kinetic_step()
+    fo, _ = o.get_state()
+    assert _relerr(ff, fo) < (1e-10 if prec == "fp64" else 2e-6), (name, prec)
     s.close()

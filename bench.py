@@ -566,9 +566,35 @@ def cavity_time_to_tol(a, case=None, stream=None):
                      "t_kinetic_s": rep.t_kinetic_s, "t_macro_s": rep.t_macro_s}
         if prec == a.precision:
             plain_fields = s2.fields()
+        out[prec]["fields_rel_l2_vs_oracle"] = fields_vs_fixture(s2.fields(), case, a)
         s2.close()
     if not a.no_warmstart:
         out[a.precision + "+warmstart"] = warmstart_leg(a, case, stream, plain_fields)
+    return out
+
+
+FIELDS_2D = ("rho", "ux", "uy", "Tt", "Tr", "Tv", "TR", "T", "qtx", "qty", "qrx", "qry", "qvx", "qvy", "qRx", "qRy",
+             "sigxx", "sigxy", "sigyy")
+
+
+def fields_vs_fixture(F, case, a):
+    """Relative L2 (volume weights; velocities against the lid speed 0.18, other fields floored at 1e-2) of
+    converged cavity fields against the FP64 oracle's converged fields stored under tests/golden (written by
+    tests/golden/make_cavity_fixtures.py), or None when there is no fixture for this case."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", f"cavity_conv_Kn{a.Kn:g}_tau{a.tau:g}.npz")
+    if not os.path.exists(path) or a.tol != 1e-6:
+        return None
+    Fo = np.load(path)["fields"].astype(np.float64)
+    if Fo.shape != F.shape:
+        return None
+    w = case.mesh.vol / case.mesh.vol.sum()
+    out = {}
+    for i, n in enumerate(FIELDS_2D):
+        num = np.sqrt((w * (F[:, i] - Fo[:, i]) ** 2).sum())
+        den = max(np.sqrt((w * Fo[:, i] ** 2).sum()), 0.18 if n[0] == "u" else 1e-2)
+        out[n] = float(num / den)
     return out
 
 

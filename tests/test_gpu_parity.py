@@ -307,6 +307,46 @@ def test_full_size_cavity_stages():
     s64.close()
 
 
+def test_full_size_cylinder_stages():
+    """The Ma 5 cylinder at its full size (40,960 triangles, 64 x 64 Newton-Cotes velocities, 64 ordinates,
+    Kn 0.01, optical thickness 1): after one conventional oracle iteration from the free stream, one kinetic
+    step element by element (FP32 storage against the FP64 oracle within 2e-6 of the range, FP64 within
+    1e-10) and the synthetic solve with the paper's 100 inner iterations (FP64, 1e-9)."""
+    case = case_cylinder()
+    assert case.mesh.nc == 40960 and case.vgrid.nv == 4096 and case.ords.no == 64
+    s32 = Solver(case, precision="fp32")
+    s64 = Solver(case, precision="fp64")
+    o = Oracle(case, **oracle_opts(s64.opts))
+    o.iterate(gsis=False)
+    f, I = o.get_state()
+    s32.set_state(f, I)
+    s64.set_state(f, I)
+    del f, I
+    o.kinetic_step()
+    s32.kinetic_step()
+    s64.kinetic_step()
+    fo, Io = o.get_state()
+    f32, I32 = s32.get_state()
+    scale = np.abs(fo).max()
+    e32 = np.abs(f32 - fo).max() / scale
+    del f32
+    f64, I64 = s64.get_state()
+    e64 = np.abs(f64 - fo).max() / scale
+    del f64
+    print("kinetic step: FP32", e32, "FP64", e64)
+    assert e32 < 2e-6 and e64 <= 1e-10
+    assert np.abs(I32 - Io).max() < 2e-6 * np.abs(Io).max()
+    assert np.abs(I64 - Io).max() <= 1e-10 * np.abs(Io).max()
+    del fo, Io, I32, I64
+    s32.close()
+    Wo, ito = o.macro_solve()
+    Wg, itg = s64.macro_solve()
+    print("macro solve: inner", ito, itg, "rel err", _relerr(Wg, Wo))
+    assert ito == itg
+    assert _relerr(Wg, Wo) < 1e-9
+    s64.close()
+
+
 def test_precision_form_full_size_cavity():
     """The precision form at the bench size (20,108 triangles, 32 x 32 velocities): GSIS with FP32
     distributions and with FP64 distributions (FP64 moments, synthetic solve and residual in both), each to

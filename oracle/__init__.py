@@ -91,7 +91,7 @@ class Oracle:
         self.nfields = lib.orc_nfields(self.D)
         kind, rho, T, u = case.bc_arrays()
         gas = case.gas
-        gasv = _f64([gas.d_r, gas.d_v, gas.Z_r, gas.Z_v, gas.omega, gas.Sc, gas.sigma_R])
+        gasv = _f64([gas.d_r, gas.d_v, gas.Z_r, gas.Z_v, gas.omega, gas.Sc, gas.sigma_R, gas.Tv_ref])
         flowv = _f64([case.flow.Kn_gas, case.flow.k_eff])
         optv = _f64([o["cfl_meso"], o["cfl_macro"], o["limiter_K"], o["inner_tol"], o["max_inner"], o["n_sweeps"],
                      o["second_order"], o["cfl_v"], o["kin_sweeps"], o["kin_omega"], o["diss_ref"],

@@ -53,6 +53,7 @@ typedef struct {
 
 typedef struct {
     double Ttr, Ttv, T, tau, q0[3], q1[3], q2[3], evR, B, cs, dt, dtR, radd;
+    double ev_v, ev_tv; /* e_v(T_v), e_v(T_tv) */
 } der_t;
 
 typedef struct orc_s {
@@ -67,6 +68,7 @@ typedef struct orc_s {
     double *xi, *w, *om, *wo;
     /* gas / flow */
     double dr, dv, Zr, Zv, omg, Sc, sigR, Kn, keff;
+    double Tvref; /* characteristic vibrational temperature; <= 0: constant d_v */
     /* options */
     double cfl_meso, cfl_macro, limK, inner_tol, cfl_v, kin_omega;
     int kin_sweeps, diss_ref, macro_order2;
@@ -336,6 +338,56 @@ static void limited_grad_o(const orc_t *o, int order2, const double *a, int64_t 
     for (int k = 0; k < 3; ++k) gl[k] = phi * g[k];
 }
 
+/* ---------------------------------------------------------------- vibrational energy (Sec. 2.1)
+ * d_v(T) = 2 (T_ref / T) / (exp(T_ref / T) - 1) for a characteristic temperature T_ref > 0, so the energy per
+ * unit mass e_v(T) = d_v(T) T / 2 = T_ref / (exp(T_ref / T) - 1), with inverse T = T_ref / ln(1 + T_ref / e_v)
+ * and heat capacity c_v(T) = de_v/dT = x^2 / (4 sinh^2(x / 2)), x = T_ref / T.  Without T_ref the model's
+ * constant d_v is used and every formula below reduces to its constant-d_v form. */
+static double ev_of(const orc_t *o, double T) { return o->Tvref > 0 ? o->Tvref / expm1(o->Tvref / T) : 0.5 * o->dv * T; }
+
+static double cv_of(const orc_t *o, double T)
+{
+    if (o->Tvref <= 0) return 0.5 * o->dv;
+    double x = o->Tvref / T, sh = sinh(0.5 * x);
+    return x * x / (4 * sh * sh);
+}
+
+/* rho e_v(T) */
+static double rho_ev(const orc_t *o, double rho, double T) { return o->Tvref > 0 ? rho * ev_of(o, T) : 0.5 * o->dv * rho * T; }
+
+/* T_v of the vibrational energy ev (per unit volume) of a gas of density rho */
+static double Tv_of(const orc_t *o, double ev, double rho)
+{
+    return o->Tvref > 0 ? o->Tvref / log1p(o->Tvref * rho / ev) : 2 * ev / (o->dv * rho);
+}
+
+/* equilibrium temperature T of alpha T + e_v(T) = R (energy shared by modes of alpha = (3 + d)/2 constant
+ * degrees of freedom and the vibrational mode): Newton from T = R / alpha, where alpha T + e_v(T) - R >= 0;
+ * the left side is increasing and convex in T, so the iterates decrease monotonically to the root */
+static double eq_temperature(const orc_t *o, double alpha, double R)
+{
+    double T = R / alpha;
+    for (int it = 0; it < 100; ++it) {
+        double dT = (alpha * T + ev_of(o, T) - R) / (alpha + cv_of(o, T));
+        T -= dT;
+        if (!(fabs(dT) > 1e-15 * T)) break;
+    }
+    return T;
+}
+
+/* T_tv (translational-vibrational equilibrium) and the total temperature T of Sec. 2.1 */
+static double Ttv_of(const orc_t *o, double Tt, double Tv)
+{
+    if (o->Tvref <= 0) return (3 * Tt + o->dv * Tv) / (3 + o->dv);
+    return eq_temperature(o, 1.5, 1.5 * Tt + ev_of(o, Tv));
+}
+
+static double Ttot_of(const orc_t *o, double Tt, double Tr, double Tv)
+{
+    if (o->Tvref <= 0) return (3 * Tt + o->dr * Tr + o->dv * Tv) / (3 + o->dr + o->dv);
+    return eq_temperature(o, 0.5 * (3 + o->dr), 1.5 * Tt + 0.5 * o->dr * Tr + ev_of(o, Tv));
+}
+
 /* ---------------------------------------------------------------- moments (Eq. getmoment) */
 static void cell_moments(const orc_t *o, const double *f, const double *I, int64_t c, mom_t *m)
 {
@@ -374,7 +426,7 @@ static void cell_moments(const orc_t *o, const double *f, const double *I, int64
     m->er = er;
     m->ev = ev;
     m->Tr = 2 * er / (o->dr * rho);
-    m->Tv = 2 * ev / (o->dv * rho);
+    m->Tv = Tv_of(o, ev, rho);
     for (int a = 0; a < D; ++a) m->sig[a][a] -= rho * m->Tt;
     double eR = 0;
     for (int64_t q = 0; q < o->no; ++q) {
@@ -387,10 +439,12 @@ static void cell_moments(const orc_t *o, const double *f, const double *I, int64
 
 static void derived(const orc_t *o, const mom_t *m, int64_t c, der_t *d)
 {
-    double dr = o->dr, dv = o->dv;
+    double dr = o->dr;
     d->Ttr = (3 * m->Tt + dr * m->Tr) / (3 + dr);
-    d->Ttv = (3 * m->Tt + dv * m->Tv) / (3 + dv);
-    d->T = (3 * m->Tt + dr * m->Tr + dv * m->Tv) / (3 + dr + dv);
+    d->Ttv = Ttv_of(o, m->Tt, m->Tv);
+    d->T = Ttot_of(o, m->Tt, m->Tr, m->Tv);
+    d->ev_v = ev_of(o, m->Tv);
+    d->ev_tv = ev_of(o, d->Ttv);
     d->tau = sqrt(2.0 / PI) * pow(m->Tt, o->omg - 1.0) * o->Kn / m->rho;
     for (int a = 0; a < 3; ++a) {
         d->q0[a] = o->Qm[0][0] * m->qt[a] + o->Qm[0][1] * m->qr[a] + o->Qm[0][2] * m->qv[a];
@@ -404,6 +458,7 @@ static void derived(const orc_t *o, const mom_t *m, int64_t c, der_t *d)
      * This changes the iteration path only (the residual is unchanged) and keeps T_v positive where the
      * emission rate per unit vibrational energy is large (low density). */
     d->radd = o->rad_implicit ? 4 * o->keff * d->evR / m->ev : 0.0;
+    if (o->rad_implicit && o->Tvref > 0) d->radd = 4 * o->keff * d->evR / (m->rho * m->Tv * cv_of(o, m->Tv));
     d->B = o->sigR * Tv2 * Tv2 / PI;
     d->cs = sqrt(5.0 / 3.0 * m->Tt);
     double un = 0;
@@ -434,6 +489,7 @@ static void ref_dists(const orc_t *o, const mom_t *m, const der_t *d, const doub
     double TRX[3] = {m->Tr, d->Ttr, m->Tr};
     const double *qRX[3] = {m->qr, d->q1, d->q1};
     double TVX[3] = {m->Tv, m->Tv, d->Ttv};
+    double EVX[3] = {d->ev_v, d->ev_v, d->ev_tv}; /* e_v(T_v), e_v(T_v), e_v(T_tv): d_v(T) T / 2 */
     const double *qVX[3] = {m->qv, d->q2, d->q2};
     for (int X = 0; X < 3; ++X) {
         double T = TX[X], p = m->rho * T;
@@ -448,7 +504,7 @@ static void ref_dists(const orc_t *o, const mom_t *m, const der_t *d, const doub
         double G = m->rho * M * (1 + s * (c2 / (2 * T) - 0.5 * (2 + D)));
         Y[X][DG] = G;
         Y[X][DR] = 0.5 * o->dr * TRX[X] * G + qrc / T * M;
-        Y[X][DV] = 0.5 * o->dv * TVX[X] * G + qvc / T * M;
+        Y[X][DV] = (o->Tvref > 0 ? EVX[X] * G : 0.5 * o->dv * TVX[X] * G) + qvc / T * M;
         Y[X][DH] = (3 - D) * m->rho * T * M * (1 + s * (c2 / (2 * T) - 0.5 * D));
     }
 }
@@ -475,7 +531,7 @@ static void boundary_eq(const orc_t *o, double rho, const double *u, double T, c
     double G = rho * maxw(D, T, c2);
     Y[DG] = G;
     Y[DR] = 0.5 * o->dr * T * G;
-    Y[DV] = 0.5 * o->dv * T * G;
+    Y[DV] = o->Tvref > 0 ? ev_of(o, T) * G : 0.5 * o->dv * T * G;
     Y[DH] = (3 - D) * T * G;
 }
 
@@ -1003,7 +1059,7 @@ static void prim_of(const orc_t *o, const double *W, prim_t *p)
     double e = W[D + 1], er = W[D + 2], ev = W[D + 3], eR = W[D + 4];
     p->Tt = 2.0 / (3.0 * W[0]) * (e - ek - er - ev - eR);
     p->Tr = 2.0 * er / (o->dr * W[0]);
-    p->Tv = 2.0 * ev / (o->dv * W[0]);
+    p->Tv = Tv_of(o, ev, W[0]);
     p->eR = eR;
     p->mu = sqrt(2.0 / PI) * o->Kn * pow(p->Tt, o->omg);
     p->cs = sqrt(5.0 / 3.0 * p->Tt);
@@ -1057,7 +1113,7 @@ static void W_of_moments(const orc_t *o, const mom_t *m, double *W)
         W[1 + a] = m->rho * m->u[a];
         ek += 0.5 * m->rho * m->u[a] * m->u[a];
     }
-    double er = 0.5 * o->dr * m->rho * m->Tr, ev = 0.5 * o->dv * m->rho * m->Tv;
+    double er = 0.5 * o->dr * m->rho * m->Tr, ev = rho_ev(o, m->rho, m->Tv);
     W[D + 1] = ek + 1.5 * m->rho * m->Tt + er + ev + m->eR;
     W[D + 2] = er;
     W[D + 3] = ev;
@@ -1074,7 +1130,7 @@ static void W_of_state(const orc_t *o, double rho, const double *u, double T, do
         ek += 0.5 * rho * u[a] * u[a];
     }
     W[D + 2] = 0.5 * o->dr * rho * T;
-    W[D + 3] = 0.5 * o->dv * rho * T;
+    W[D + 3] = rho_ev(o, rho, T);
     W[D + 4] = 4 * o->sigR * T * T * T * T;
     W[D + 1] = ek + 1.5 * rho * T + W[D + 2] + W[D + 3] + W[D + 4];
 }
@@ -1174,8 +1230,8 @@ static void macro_source(const orc_t *o, const prim_t *p, const double *Wc, doub
     int D = o->D, NW = NWof(D);
     double rho = p->rho, Tt = p->Tt, Tr = p->Tr, Tv = p->Tv;
     double tau = p->mu / (rho * Tt);
-    double Ttr = (3 * Tt + o->dr * Tr) / (3 + o->dr), Ttv = (3 * Tt + o->dv * Tv) / (3 + o->dv);
-    double etr = 0.5 * o->dr * rho * Ttr, etv = 0.5 * o->dv * rho * Ttv;
+    double Ttr = (3 * Tt + o->dr * Tr) / (3 + o->dr), Ttv = Ttv_of(o, Tt, Tv);
+    double etr = 0.5 * o->dr * rho * Ttr, etv = rho_ev(o, rho, Ttv);
     double evR = 4 * o->sigR * Tv * Tv * Tv * Tv;
     double er = Wc[D + 2], ev = Wc[D + 3], eR = Wc[D + 4];
     for (int i = 0; i < NW; ++i) Q[i] = 0;
@@ -1328,7 +1384,8 @@ static void local_solve(const orc_t *o, const prim_t *p, const double *rhs, cons
     for (int i = 0; i < NW; ++i) dU[i] = rhs[i] / Dg[i];
     const int ig = D + 1, iv = D + 3, iR = D + 4;
     const double k = o->keff;
-    const double ep = 32.0 * o->sigR * p->Tv * p->Tv * p->Tv / (o->dv * p->rho);
+    const double ep = o->Tvref > 0 ? 16.0 * o->sigR * p->Tv * p->Tv * p->Tv / (cv_of(o, p->Tv) * p->rho)
+                                   : 32.0 * o->sigR * p->Tv * p->Tv * p->Tv / (o->dv * p->rho);
     const double dv = (rhs[iv] + k * rhs[iR] / Dg[iR]) / (Dg[iv] - k * k * ep / Dg[iR]);
     const double dR = (rhs[iR] + k * ep * dv) / Dg[iR];
     dU[iv] = dv;
@@ -1459,11 +1516,16 @@ static int macro_solve(orc_t *o, const mom_t *m, double mass_target, double *W)
             }
             double rho = P[c].rho, Tt = P[c].Tt, Tr = P[c].Tr, Tv = P[c].Tv;
             double tau = P[c].mu / (rho * Tt);
-            double Ttr = (3 * Tt + o->dr * Tr) / (3 + o->dr), Ttv = (3 * Tt + o->dv * Tv) / (3 + o->dv);
+            double Ttr = (3 * Tt + o->dr * Tr) / (3 + o->dr), Ttv = Ttv_of(o, Tt, Tv);
             double jr = -3.0 / ((3 + o->dr) * o->Zr * tau) + 2 * (o->omg - 1) * (Ttr - Tr) / (3 * o->Zr * tau * Tt);
             /* reading: the printed dQ6/de_v omits the emission term; its exact diagonal part is added */
             double jv = -3.0 / ((3 + o->dv) * o->Zv * tau) + 2 * (o->omg - 1) * (Ttv - Tv) / (3 * o->Zv * tau * Tt) -
                         o->keff * 16 * o->sigR * Tv * Tv * Tv * 2.0 / (o->dv * rho);
+            /* variable d_v: the same diagonal with d_v replaced by the heat capacity 2 c_v (at T_tv in the
+             * relaxation term, at T_v in the emission term) */
+            if (o->Tvref > 0)
+                jv = -3.0 / ((3 + 2 * cv_of(o, Ttv)) * o->Zv * tau) + 2 * (o->omg - 1) * (Ttv - Tv) / (3 * o->Zv * tau * Tt) -
+                     o->keff * 16 * o->sigR * Tv * Tv * Tv / (cv_of(o, Tv) * rho);
             double jR = -o->keff;
             for (int i = 0; i < NW; ++i) Dg[c * NW + i] = 1.0 / dt + gs / o->vol[c];
             Dg[c * NW + D + 2] -= jr;
@@ -1537,7 +1599,7 @@ static void feq(const orc_t *o, double rho, const double *u, double Tt, double T
     double G = rho * maxw(D, Tt, c2);
     Y[DG] = G;
     Y[DR] = 0.5 * o->dr * Tr * G;
-    Y[DV] = 0.5 * o->dv * Tv * G;
+    Y[DV] = o->Tvref > 0 ? ev_of(o, Tv) * G : 0.5 * o->dv * Tv * G;
     Y[DH] = (3 - D) * Tt * G;
 }
 
@@ -1575,8 +1637,8 @@ static double residual(const orc_t *o, const mom_t *mn, const mom_t *mo)
             num[1] += V * (mn[c].u[a] - mo[c].u[a]) * (mn[c].u[a] - mo[c].u[a]);
             den[1] += V * mo[c].u[a] * mo[c].u[a];
         }
-        double Tn = (3 * mn[c].Tt + o->dr * mn[c].Tr + o->dv * mn[c].Tv) / (3 + o->dr + o->dv);
-        double To = (3 * mo[c].Tt + o->dr * mo[c].Tr + o->dv * mo[c].Tv) / (3 + o->dr + o->dv);
+        double Tn = Ttot_of(o, mn[c].Tt, mn[c].Tr, mn[c].Tv);
+        double To = Ttot_of(o, mo[c].Tt, mo[c].Tr, mo[c].Tv);
         num[2] += V * (Tn - To) * (Tn - To);
         den[2] += V * To * To;
     }
@@ -1632,6 +1694,7 @@ orc_t *orc_create(int D, int64_t nc, int64_t nf, const double *vol, const double
     o->omg = gas[4];
     o->Sc = gas[5];
     o->sigR = gas[6];
+    o->Tvref = gas[7];
     o->Kn = flow[0];
     o->keff = flow[1];
     o->cfl_meso = opts[0];
@@ -1709,7 +1772,7 @@ static void fields_of(const orc_t *o, const mom_t *m, double *out)
     out[p++] = m->Tr;
     out[p++] = m->Tv;
     out[p++] = (o->sigR > 0) ? pow(m->eR / (4 * o->sigR), 0.25) : 0.0;
-    d.T = (3 * m->Tt + o->dr * m->Tr + o->dv * m->Tv) / (3 + o->dr + o->dv);
+    d.T = Ttot_of(o, m->Tt, m->Tr, m->Tv);
     out[p++] = d.T;
     for (int a = 0; a < D; ++a) out[p++] = m->qt[a];
     for (int a = 0; a < D; ++a) out[p++] = m->qr[a];

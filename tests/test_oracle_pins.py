@@ -263,10 +263,15 @@ def test_optically_thin_slab():
     assert q_R < 0  # radiation flows from the hot wall at x = 1 towards x = 0
 
 
-def test_sync_restores_macro_state():
+@pytest.mark.parametrize("Tv_ref", [0.0, 1.5], ids=["constant_dv", "variable_dv"])
+def test_sync_restores_macro_state(Tv_ref):
     """After the synchronisation step the moments of f equal the macro state (Sec. 3, P11) up to the
-    quadrature error of Maxwellians at the new temperatures on the fixed grid."""
+    quadrature error of Maxwellians at the new temperatures on the fixed grid; with the variable d_v the
+    equilibrium's vibrational slot carries e_v(T_v) and the state's e_v is recovered."""
+    import dataclasses
+
     c = _case_1d(n=6, nv=64)
+    c = dataclasses.replace(c, gas=dataclasses.replace(c.gas, Tv_ref=Tv_ref))
     o = Oracle(c)
     o.iterate(gsis=False)
     W = o.macro_state()
@@ -802,3 +807,99 @@ def test_safeguard_is_inactive_near_the_fixed_point():
                 break
         assert e < 1e-7, e
         assert len(hits) > 20 and sum(hits[-15:]) == 0, hits
+
+
+# ---------------------------------------------------------------- variable vibrational degrees of freedom
+TV_REF = 1.5  # characteristic vibrational temperature of the variable-d_v pins: d_v(1) = 3 / (e^1.5 - 1)
+
+
+def _e_v(T, Tref=TV_REF):
+    """Vibrational energy per unit mass d_v(T) T / 2 with d_v(T) = 2 (Tref / T) / (exp(Tref / T) - 1) (Sec. 2.1)."""
+    x = Tref / T
+    return 0.5 * (2 * x / np.expm1(x)) * T
+
+
+def _dv_case(dim):
+    import dataclasses
+
+    c = _case_2d_gh() if dim == 2 else _case_3d_gh()
+    return dataclasses.replace(c, gas=dataclasses.replace(c.gas, Tv_ref=TV_REF))
+
+
+def test_vibrational_degrees_of_freedom_special_values():
+    """d_v(T) of Sec. 2.1 at T = T_ref is 2 / (e - 1) = 1.16395... (the constant d_v = 1.16 of the paper's tests
+    is this value) and tends to 2 (a fully excited oscillator) as T / T_ref grows; the oracle inverts
+    e_v = d_v(T_v) T_v / 2: a state with translational temperature 1 and vibrational energy e_v(T) has
+    vibrational temperature T, for T from below to far above T_ref."""
+    c = _dv_case(2)
+    assert abs(2 / (np.e - 1) - 1.1639534137) < 1e-10
+    assert abs(2 * _e_v(TV_REF) / TV_REF - 2 / (np.e - 1)) < 1e-15
+    assert abs(2 * _e_v(400.0 * TV_REF) / (400.0 * TV_REF) - 2) < 3e-3
+    o = Oracle(c)
+    xi = c.vgrid.xi
+    M = maxwell((xi ** 2).sum(axis=1), 2)
+    for T in (TV_REF, 0.6, 3.0, 40.0):
+        slots = [M, 0.5 * c.gas.d_r * M, _e_v(T) * M, M]
+        f = np.tile(np.stack(slots)[None], (c.mesh.nc, 1, 1))
+        o.set_state(f, np.full((c.mesh.nc, c.ords.no), c.gas.sigma_R / np.pi))
+        fl = dict(zip(field_names(2), o.fields()[0]))
+        assert abs(fl["Tt"] - 1) < 1e-13 and abs(fl["Tv"] / T - 1) < 1e-12, (T, fl["Tv"])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_variable_dv_relaxation_conserves_energy_and_exchanges_at_the_stated_rate(dim):
+    """Variable d_v (Sec. 2.1) on a quadrature-exact state with T_t = 1 and e_v = 1.3 e_v(1): the relaxation
+    sources conserve mass, momentum and gas + radiation energy to round-off (T_tv must then satisfy
+    3 T_tv / 2 + e_v(T_tv) = 3 T_t / 2 + e_v(T_v)); the vibrational energy changes at the rate
+    (e_v(T_tv) - e_v(T_v)) / (Z_v tau) - k_eff (4 sigma_R T_v^4 - e_R), with T_v and T_tv found here by an
+    independent root finder; the total temperature satisfies 3 T + d_r T + 2 e_v(T) = 3 T_t + d_r T_r + 2 e_v."""
+    from scipy.optimize import brentq
+
+    c = _dv_case(dim)
+    o = Oracle(c)
+    f, I = _noneq_state_nd(c)
+    f[:, 2] *= 1.3 * _e_v(1.0) / (0.5 * c.gas.d_v)  # vibrational slot: e_v = 1.3 e_v(1) instead of d_v / 2
+    o.set_state(f, I)
+    fl = dict(zip(field_names(dim), o.fields()[0]))
+    ev = 1.3 * _e_v(1.0)
+    Tv = brentq(lambda T: _e_v(T) - ev, 0.2, 10.0, xtol=1e-15)
+    Ttv = brentq(lambda T: 1.5 * T + _e_v(T) - (1.5 + ev), 0.2, 10.0, xtol=1e-15)
+    Ttot = brentq(lambda T: 0.5 * (3 + c.gas.d_r) * T + _e_v(T) - (1.5 + 0.5 * c.gas.d_r * fl["Tr"] + ev), 0.2,
+                  10.0, xtol=1e-15)
+    assert abs(fl["Tt"] - 1) < 1e-13 and abs(fl["Tv"] - Tv) < 1e-12 and abs(fl["T"] - Ttot) < 1e-12
+    J, JR = o.collision()[0], o.rad_source()[0]
+    m = _moments_of_J_nd(c, J, JR)
+    assert abs(m["mass"]) < 1e-13 and np.abs(m["mom"]).max() < 1e-13 and abs(m["energy"]) < 1e-13
+    tau = np.sqrt(2 / np.pi) * c.flow.Kn_gas
+    e_R = 4 * c.gas.sigma_R * fl["TR"] ** 4
+    rate = (_e_v(Ttv) - ev) / (c.gas.Z_v * tau) - c.flow.k_eff * (4 * c.gas.sigma_R * Tv ** 4 - e_R)
+    assert abs(rate) > 1e-2
+    np.testing.assert_allclose(m["ev"], rate, rtol=1e-11)
+    # the synthetic equations' vibrational source equals the moment of the kinetic one (P3 with variable d_v)
+    Q = o.macro_sources(o.macro_state())[0]
+    np.testing.assert_allclose(Q[dim + 3], m["ev"], rtol=1e-10)
+    np.testing.assert_allclose(Q[dim + 2], m["er"], rtol=1e-10, atol=1e-13)
+
+
+def test_variable_dv_equilibrium_is_a_fixed_point():
+    """An equilibrium state at T = 1 (G, R, H of that temperature, V = e_v(1) G with the variable d_v,
+    radiation at B(T)) bounded by walls at the same temperature: no relaxation source, no radiative source,
+    and a kinetic step leaves it unchanged."""
+    import dataclasses
+
+    c = _dv_case(2)
+    T = 1.0  # the Gauss-Hermite rule integrates this temperature exactly
+    c = dataclasses.replace(c, bcs=[dict(b, T=T, u=(0.0, 0.0, 0.0)) for b in c.bcs])
+    o = Oracle(c)
+    xi = c.vgrid.xi
+    M = maxwell((xi ** 2).sum(axis=1), 2, T)
+    slots = [M, 0.5 * c.gas.d_r * T * M, _e_v(T) * M, T * M]
+    f = np.tile(np.stack(slots)[None], (c.mesh.nc, 1, 1))
+    I = np.full((c.mesh.nc, c.ords.no), c.gas.sigma_R * T ** 4 / np.pi)
+    o.set_state(f, I)
+    assert np.abs(o.collision()).max() < 1e-13 * np.abs(f).max()
+    assert np.abs(o.rad_source()).max() < 1e-13 * np.abs(I).max()
+    o.kinetic_step()
+    f1, I1 = o.get_state()
+    assert np.abs(f1 - f).max() < 1e-12 * np.abs(f).max()
+    assert np.abs(I1 - I).max() < 1e-12 * np.abs(I).max()

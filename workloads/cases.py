@@ -37,6 +37,9 @@ class Gas:
     omega: float = 0.74
     Sc: float = 0.8
     sigma_R: float = 0.01
+    # characteristic vibrational temperature (units of the reference temperature): d_v(T) = 2 (Tv_ref / T) /
+    # (exp(Tv_ref / T) - 1) (Sec. 2.1); 0 keeps the constant d_v above
+    Tv_ref: float = 0.0
 
     @property
     def gamma(self) -> float:

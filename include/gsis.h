@@ -69,11 +69,16 @@ typedef struct {
     double rho, T, u[3];
 } gsis_bc;
 
-/* Gas constants (Sec. 2.1): rotational / vibrational degrees of freedom (d_v constant),
- * collision numbers, viscosity index omega, Schmidt number of the Mason matrix A,
- * normalised Stefan-Boltzmann constant sigma_R. */
+/* Gas constants (Sec. 2.1): rotational / vibrational degrees of freedom, collision numbers, viscosity
+ * index omega, Schmidt number of the Mason matrix A, normalised Stefan-Boltzmann constant sigma_R, and the
+ * characteristic vibrational temperature Tv_ref (units of the reference temperature).  Tv_ref > 0 makes
+ * the vibrational degrees of freedom temperature dependent, d_v(T) = 2 (Tv_ref / T) / (exp(Tv_ref / T) - 1):
+ * the vibrational energy e_v = d_v(T_v) T_v / 2 everywhere (moments, reference distributions, equilibria,
+ * boundary states, synthetic equations) and T_tv, T the roots of the energy balances of Sec. 2.1; d_v then
+ * only sets the Mason matrix A and the synthetic equations' conductivities.  Tv_ref = 0: constant d_v. */
 typedef struct {
     double d_r, d_v, Z_r, Z_v, omega, Sc, sigma_R;
+    double Tv_ref;
 } gsis_gas;
 
 /* Flow parameters: Kn_gas enters tau = sqrt(2/pi) T_t^(omega-1) Kn_gas / rho; k_eff = 1/Kn_photon

@@ -122,6 +122,7 @@ static void compute_phys(gsis_t *h)
     p.omega = g.omega;
     p.Sc = g.Sc;
     p.sigma_R = g.sigma_R;
+    p.Tvref = g.Tv_ref;
     p.Kn = h->flow.Kn_gas;
     p.keff = h->flow.k_eff;
     const double dr = g.d_r, dv = g.d_v, Zr = g.Z_r, Zv = g.Z_v, Sc = g.Sc;
@@ -351,6 +352,7 @@ static int32_t build_mesh(gsis_t *h)
         bcs[i].rho = hm.bcs[i].rho;
         bcs[i].T = hm.bcs[i].T;
         for (int a = 0; a < 3; ++a) bcs[i].u[a] = hm.bcs[i].u[a];
+        bcs[i].ev = vib_e(h->phys, hm.bcs[i].T);
     }
     for (int64_t b = 0; b < nbf; ++b)
         if (hm.bcs[bf_tag[b]].kind != GSIS_BC_WALL) closed = 0;
@@ -1148,6 +1150,7 @@ int32_t gsis_set_boundary(gsis_t *h, int32_t tag, const gsis_bc *bc)
         d.rho = bc->rho;
         d.T = bc->T;
         for (int a = 0; a < 3; ++a) d.u[a] = bc->u[a];
+        d.ev = vib_e(h->phys, bc->T);
         (void)hipSetDevice(h->device);
         HIPCHECK(h, hipStreamSynchronize(h->stream));
         HIPCHECK(h, hipMemcpy(h->m.bcs + tag, &d, sizeof(BcDev), hipMemcpyHostToDevice));
@@ -1194,11 +1197,24 @@ int32_t gsis_set_ordinates(gsis_t *h, int64_t no, const double *omega, const dou
 int32_t gsis_set_gas(gsis_t *h, const gsis_gas *gas)
 {
     if (!h || !gas) return GSIS_E_ARG;
-    if (!(gas->d_r > 0 && gas->d_v > 0 && gas->Z_r > 0 && gas->Z_v > 0 && gas->sigma_R >= 0))
+    if (!(gas->d_r > 0 && gas->d_v > 0 && gas->Z_r > 0 && gas->Z_v > 0 && gas->sigma_R >= 0 && gas->Tv_ref >= 0))
         return fail(h, GSIS_E_ARG, "gsis_set_gas: invalid gas constants");
     h->gas = *gas;
     h->have_gas = true;
     if (h->have_flow) compute_phys(h);
+    // boundary states carry e_v(T) of the gas: refresh them when the mesh tables exist already
+    if (h->m.bcs && h->have_flow) {
+        (void)hipSetDevice(h->device);
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        std::vector<BcDev> bcs(h->hm.bcs.size());
+        HIPCHECK(h, hipMemcpy(bcs.data(), h->m.bcs, bcs.size() * sizeof(BcDev), hipMemcpyDeviceToHost));
+        for (auto &b : bcs) b.ev = vib_e(h->phys, b.T);
+        for (auto &b : h->bf_bc) b.ev = vib_e(h->phys, b.T);
+        HIPCHECK(h, hipMemcpy(h->m.bcs, bcs.data(), bcs.size() * sizeof(BcDev), hipMemcpyHostToDevice));
+        if (!h->bf_bc.empty())
+            HIPCHECK(h, hipMemcpy(h->m.bf_bc, h->bf_bc.data(), h->bf_bc.size() * sizeof(BcDev),
+                                  hipMemcpyHostToDevice));
+    }
     return GSIS_OK;
 }
 
@@ -1555,7 +1571,7 @@ int32_t gsis_get_fields(gsis_t *h, double *out)
         o[p++] = m[L.Tr()];
         o[p++] = m[L.Tv()];
         o[p++] = (g.sigma_R > 0) ? std::pow(m[L.eR()] / (4 * g.sigma_R), 0.25) : 0.0;
-        o[p++] = (3 * m[L.Tt()] + g.d_r * m[L.Tr()] + g.d_v * m[L.Tv()]) / (3 + g.d_r + g.d_v);
+        o[p++] = vib_Ttot(h->phys, m[L.Tt()], m[L.Tr()], m[L.Tv()]);
         for (int a = 0; a < D; ++a) o[p++] = m[L.qt() + a];
         for (int a = 0; a < D; ++a) o[p++] = m[L.qr() + a];
         for (int a = 0; a < D; ++a) o[p++] = m[L.qv() + a];

@@ -46,8 +46,57 @@ constexpr int kMomMax = 7 + 5 * 3 + 9;
 // Physical constants of one run (host struct passed by value to kernels).
 struct Phys {
     double d_r, d_v, Z_r, Z_v, omega, Sc, sigma_R, Kn, keff;
+    double Tvref;  // characteristic vibrational temperature; <= 0: constant d_v
     double A[3][3], Q[3][3], K0[3][3];
 };
+
+// Vibrational mode (Sec. 2.1).  With a characteristic temperature T_ref > 0 the degrees of freedom are
+// d_v(T) = 2 (T_ref / T) / (exp(T_ref / T) - 1), so the energy per unit mass is e_v(T) = d_v(T) T / 2 =
+// T_ref / (exp(T_ref / T) - 1), with inverse T = T_ref / ln(1 + T_ref / e_v) and heat capacity
+// c_v = de_v / dT = x^2 / (4 sinh^2(x / 2)), x = T_ref / T.  T_ref <= 0 keeps the constant d_v (and the
+// constant-d_v forms of every expression).
+__host__ __device__ inline double vib_e(const Phys &p, double T)
+{
+    return p.Tvref > 0 ? p.Tvref / expm1(p.Tvref / T) : 0.5 * p.d_v * T;
+}
+__host__ __device__ inline double vib_rho_e(const Phys &p, double rho, double T)
+{
+    return p.Tvref > 0 ? rho * (p.Tvref / expm1(p.Tvref / T)) : 0.5 * p.d_v * rho * T;
+}
+__host__ __device__ inline double vib_cv(const Phys &p, double T)
+{
+    if (!(p.Tvref > 0)) return 0.5 * p.d_v;
+    const double x = p.Tvref / T, sh = sinh(0.5 * x);
+    return x * x / (4 * sh * sh);
+}
+// T_v of the vibrational energy rho_ev (per unit volume) of a gas of density rho
+__host__ __device__ inline double vib_T(const Phys &p, double rho_ev, double rho)
+{
+    return p.Tvref > 0 ? p.Tvref / log1p(p.Tvref * rho / rho_ev) : 2.0 * rho_ev / (p.d_v * rho);
+}
+// root T of alpha T + e_v(T) = R: the left side increases and is convex in T, so Newton from T = R / alpha
+// (where it is >= 0) descends monotonically to the root
+__host__ __device__ inline double vib_eq_T(const Phys &p, double alpha, double R)
+{
+    double T = R / alpha;
+    for (int it = 0; it < 100; ++it) {
+        const double dT = (alpha * T + vib_e(p, T) - R) / (alpha + vib_cv(p, T));
+        T -= dT;
+        if (!(fabs(dT) > 1e-15 * T)) break;
+    }
+    return T;
+}
+// translational-vibrational equilibrium temperature T_tv and the total temperature T of Sec. 2.1
+__host__ __device__ inline double vib_Ttv(const Phys &p, double Tt, double Tv)
+{
+    if (!(p.Tvref > 0)) return (3 * Tt + p.d_v * Tv) / (3 + p.d_v);
+    return vib_eq_T(p, 1.5, 1.5 * Tt + vib_e(p, Tv));
+}
+__host__ __device__ inline double vib_Ttot(const Phys &p, double Tt, double Tr, double Tv)
+{
+    if (!(p.Tvref > 0)) return (3 * Tt + p.d_r * Tr + p.d_v * Tv) / (3 + p.d_r + p.d_v);
+    return vib_eq_T(p, 0.5 * (3 + p.d_r), 1.5 * Tt + 0.5 * p.d_r * Tr + vib_e(p, Tv));
+}
 
 // Options used by kernels.
 struct KinOpts {
@@ -63,6 +112,7 @@ struct KinOpts {
 struct BcDev {
     int kind;
     double rho, T, u[3];
+    double ev;  // vibrational energy per unit mass e_v(T) of the boundary state
 };
 
 // Mesh tables on the device (all FP64 geometry; int32 connectivity).

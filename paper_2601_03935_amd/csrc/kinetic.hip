@@ -358,8 +358,7 @@ __device__ __forceinline__ void collision(const T *cf, const T *xi, const T *fk,
 // boundary state on an incoming velocity: equilibrium (rho, u, T) of the tag, rho replaced by the wall
 // re-emission density on walls
 template <typename T, int D>
-__device__ __forceinline__ void boundary_values(const BcDev &bc, const T rho, const T *xi, const T dr, const T dv,
-                                                T *out)
+__device__ __forceinline__ void boundary_values(const BcDev &bc, const T rho, const T *xi, const T dr, T *out)
 {
     T c2 = T(0);
 #pragma unroll
@@ -375,7 +374,7 @@ __device__ __forceinline__ void boundary_values(const BcDev &bc, const T rho, co
     const T G = rho * dexp<T>(-c2 / (T(2) * Tb)) / sqrt(norm);
     out[0] = G;
     out[1] = T(0.5) * dr * Tb * G;
-    out[2] = T(0.5) * dv * Tb * G;
+    out[2] = (T)bc.ev * G;
     out[3] = T(3 - D) * Tb * G;
 }
 
@@ -457,7 +456,7 @@ __global__ __launch_bounds__(256) void k_residual(const T *__restrict__ f, const
                 const int bfi = -nb[s] - 1;
                 const BcDev bc = m.bcs[m.bf_tag[bfi]];
                 const T rho = (bc.kind == 0) ? rhow[bfi] : (T)bc.rho;
-                boundary_values<T, D>(bc, rho, x, dr, dv, fv);
+                boundary_values<T, D>(bc, rho, x, dr, fv);
             }
 #pragma unroll
             for (int d = 0; d < ND; ++d) flux[d] += xn * fv[d];
@@ -587,7 +586,7 @@ __global__ __launch_bounds__(256) void k_residual_v(const T *__restrict__ f, con
                         T xe[D];
 #pragma unroll
                         for (int a = 0; a < D; ++a) xe[a] = x[a][e];
-                        boundary_values<T, D>(bc, rho, xe, dr, dv, fv);
+                        boundary_values<T, D>(bc, rho, xe, dr, fv);
                     }
 #pragma unroll
                     for (int d = 0; d < ND; ++d) flux[d][e] += xn[e] * fv[d];
@@ -805,7 +804,7 @@ __global__ __launch_bounds__(256) void k_gres_v(const T *__restrict__ f, const T
                         T xe[D], fv[4];
 #pragma unroll
                         for (int a = 0; a < D; ++a) xe[a] = x[a][e];
-                        boundary_values<T, D>(bc, rho, xe, dr, dv, fv);
+                        boundary_values<T, D>(bc, rho, xe, dr, fv);
                         v = fv[d];
                     }
                     flux[e] += xn[e] * v;
@@ -1588,7 +1587,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
                                                  const double *__restrict__ om, const double *__restrict__ wo,
                                                  const double *__restrict__ uref, double *__restrict__ mom,
                                                  const int64_t nc, const int64_t nv, const int64_t no,
-                                                 const double dr, const double dv)
+                                                 const double dr, const double dv, const double Tvref)
 {
     constexpr int ND = (D == 3) ? 3 : 4;
     constexpr MomLayout L{D};
@@ -1690,7 +1689,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
         for (int a = 0; a < D; ++a) M[L.u() + a] = ur[a] + dl[a];
         M[L.Tt()] = Tt;
         M[L.Tr()] = 2.0 * r0 / (dr * rho);
-        M[L.Tv()] = 2.0 * v0 / (dv * rho);
+        M[L.Tv()] = Tvref > 0 ? Tvref / log1p(Tvref * rho / v0) : 2.0 * v0 / (dv * rho);
         M[L.eR()] = eR;
         M[L.er()] = r0;
         M[L.ev()] = v0;
@@ -1721,7 +1720,7 @@ __global__ void k_prologue(const double *__restrict__ mom, T *__restrict__ coef,
     const double *M = mom + c * L.size();
     T *cf = coef + c * coef_size(D);
     const double rho = M[L.rho()], Tt = M[L.Tt()], Tr = M[L.Tr()], Tv = M[L.Tv()], eR = M[L.eR()];
-    const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = (3 * Tt + p.d_v * Tv) / (3 + p.d_v);
+    const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = vib_Ttv(p, Tt, Tv);
     const double tau = sqrt(2.0 / kPi) * pow(Tt, p.omega - 1.0) * p.Kn / rho;
     double qt[3] = {0, 0, 0}, qr[3] = {0, 0, 0}, qv[3] = {0, 0, 0}, q0[3], q1[3], q2[3];
     double un = 0;
@@ -1744,13 +1743,17 @@ __global__ void k_prologue(const double *__restrict__ mom, T *__restrict__ coef,
     cf[D + 2] = (T)(p.keff * (4 * p.sigma_R * Tv4 - eR) / rho);
     cf[D + 3] = (T)(p.sigma_R * Tv4 / kPi);
     cf[D + 4] = (T)(1.0 / (cfl_meso * h[c]));
-    // point-implicit rate of the emission part of the gas-photon exchange on f2: 4 k_eff e_vR / e_v
-    cf[D + 5] = (T)(4.0 * p.keff * 4 * p.sigma_R * Tv4 / M[L.ev()]);
+    // point-implicit rate of the emission part of the gas-photon exchange on f2: d(k_eff e_vR) / d(rho e_v),
+    // 4 k_eff e_vR / e_v with a constant d_v, 4 k_eff e_vR / (rho T_v c_v(T_v)) with d_v(T)
+    cf[D + 5] = (T)(p.Tvref > 0 ? 4.0 * p.keff * 4 * p.sigma_R * Tv4 / (rho * Tv * vib_cv(p, Tv))
+                                : 4.0 * p.keff * 4 * p.sigma_R * Tv4 / M[L.ev()]);
     const double TX[3] = {Tt, Ttr, Ttv};
     const double *qX[3] = {qt, q0, q0};
     const double TRX[3] = {Tr, Ttr, Tr};
     const double *qRX[3] = {qr, q1, q1};
     const double TVX[3] = {Tv, Tv, Ttv};
+    // e_v(T_v) (g_2t, g_2r) and e_v(T_tv) (g_2v): d_v(T) T / 2
+    const double EVX[3] = {vib_e(p, Tv), vib_e(p, Tv), vib_e(p, Ttv)};
     const double *qVX[3] = {qv, q2, q2};
     for (int X = 0; X < 3; ++X) {
         T *px = cf + D + 6 + X * coef_x(D);
@@ -1763,7 +1766,7 @@ __global__ void k_prologue(const double *__restrict__ mom, T *__restrict__ coef,
             px[4 + 2 * D + a] = (T)(qVX[X][a] / (T_ * rho));
         }
         px[2 + D] = (T)(0.5 * p.d_r * TRX[X]);
-        px[3 + 2 * D] = (T)(0.5 * p.d_v * TVX[X]);
+        px[3 + 2 * D] = (T)(p.Tvref > 0 ? EVX[X] : 0.5 * p.d_v * TVX[X]);
         px[4 + 3 * D] = (T)((3 - D) * T_);
     }
 }
@@ -1880,7 +1883,7 @@ __global__ __launch_bounds__(256) void k_boundary_flux(const T *__restrict__ f, 
         } else {
             fv[0] = G;
             fv[1] = 0.5 * dr * bc.T * G;
-            fv[2] = 0.5 * dv * bc.T * G;
+            fv[2] = bc.ev * G;
             fv[3] = (3 - D) * bc.T * G;
         }
         const double wk = w[k];
@@ -1934,7 +1937,7 @@ template <typename T, int D, int VW>
 __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__ I, const double *__restrict__ sp,
                                               const double *__restrict__ xi, const int64_t nc, const int64_t nv,
                                               const int nchunk, const int cgroup, const int64_t no,
-                                              const double dr, const double dv,
+                                              const double dr, const double dv, const double Tvref,
                                               const int init)
 {
     constexpr int ND = (D == 3) ? 3 : 4;
@@ -1946,6 +1949,9 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
     if (!wave_cell_chunk(w, (int)nc, nchunk, cgroup, c, ch)) return;
     const double *s0 = sp + (int64_t)c * 2 * NS, *s1 = s0 + NS;
     const double n0 = gauss_norm<D>(s0[0], s0[D + 1]), n1 = gauss_norm<D>(s1[0], s1[D + 1]);
+    // e_v(T_v) of the two states (variable d_v)
+    const double ev0 = Tvref > 0 ? Tvref / expm1(Tvref / s0[D + 3]) : 0.0;
+    const double ev1 = Tvref > 0 ? Tvref / expm1(Tvref / s1[D + 3]) : 0.0;
     const int64_t kb = ((int64_t)ch * kWave + lane) * VW;
     if (kb < nv) {
       T fv[4][VW];
@@ -1966,7 +1972,7 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
         const double G0 = init ? 0.0 : n0 * exp(-c20 / (2 * s0[D + 1]));
         const double G1 = n1 * exp(-c21 / (2 * s1[D + 1]));
         const double dG[4] = {G1 - G0, 0.5 * dr * (s1[D + 2] * G1 - s0[D + 2] * G0),
-                              0.5 * dv * (s1[D + 3] * G1 - s0[D + 3] * G0),
+                              Tvref > 0 ? ev1 * G1 - ev0 * G0 : 0.5 * dv * (s1[D + 3] * G1 - s0[D + 3] * G0),
                               (3 - D) * (s1[D + 1] * G1 - s0[D + 1] * G0)};
 #pragma unroll
         for (int d = 0; d < ND; ++d) fv[d][e] = init ? (T)dG[d] : (T)((double)fv[d][e] + dG[d]);
@@ -2259,10 +2265,10 @@ void launch_moments(const KinBufs<T> &B, const double *uref, double *mom, int64_
     const int64_t mom_blocks = (nc + 256 / kMomLanes - 1) / (256 / kMomLanes);
     if (nv % VW == 0)
         hipLaunchKernelGGL((k_moments<T, D, VW>), dim3(mom_blocks), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d, B.om_d,
-                           B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
+                           B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v, p.Tvref);
     else
         hipLaunchKernelGGL((k_moments<T, D, 1>), dim3(mom_blocks), dim3(256), 0, st, B.f, B.I, B.xi_d, B.w_d, B.om_d,
-                           B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v);
+                           B.wo_d, uref, mom, nc, nv, no, p.d_r, p.d_v, p.Tvref);
 }
 
 template <typename T, int D>
@@ -2295,11 +2301,11 @@ void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_
     if (nv % VW == 0) {
         const int nchunk = (int)((nv + kWave * VW - 1) / (kWave * VW));
         hipLaunchKernelGGL((k_sync<T, D, VW>), dim3(wave_blocks(nc * nchunk)), dim3(256), 0, st, B.f, B.I, sp,
-                           B.xi_d, nc, nv, nchunk, chunk_group(CG::sync, D, nc), no, p.d_r, p.d_v, init);
+                           B.xi_d, nc, nv, nchunk, chunk_group(CG::sync, D, nc), no, p.d_r, p.d_v, p.Tvref, init);
     } else {
         const int nchunk = (int)((nv + kWave - 1) / kWave);
         hipLaunchKernelGGL((k_sync<T, D, 1>), dim3(wave_blocks(nc * nchunk)), dim3(256), 0, st, B.f, B.I, sp,
-                           B.xi_d, nc, nv, nchunk, chunk_group(CG::sync, D, nc), no, p.d_r, p.d_v, init);
+                           B.xi_d, nc, nv, nchunk, chunk_group(CG::sync, D, nc), no, p.d_r, p.d_v, p.Tvref, init);
     }
 }
 

@@ -47,7 +47,7 @@ __device__ __forceinline__ void prim_of(const double *W, const Phys &p, Prim &q)
     q.u[2] = l.u[2];
     q.Tt = l.Tt;
     q.Tr = 2.0 * W[D + 2] / (p.d_r * W[0]);
-    q.Tv = 2.0 * W[D + 3] / (p.d_v * W[0]);
+    q.Tv = vib_T(p, W[D + 3], W[0]);
     q.eR = W[D + 4];
     q.mu = sqrt(2.0 / kPi) * p.Kn * pow(q.Tt, p.omega);
     q.cs = sqrt(5.0 / 3.0 * q.Tt);
@@ -123,7 +123,7 @@ __device__ __forceinline__ void W_of_state(double rho, const double *u, double T
         ek += 0.5 * rho * u[a] * u[a];
     }
     W[D + 2] = 0.5 * p.d_r * rho * T;
-    W[D + 3] = 0.5 * p.d_v * rho * T;
+    W[D + 3] = vib_rho_e(p, rho, T);
     W[D + 4] = 4 * p.sigma_R * T * T * T * T;
     W[D + 1] = ek + 1.5 * rho * T + W[D + 2] + W[D + 3] + W[D + 4];
 }
@@ -269,7 +269,8 @@ __device__ __forceinline__ void local_solve(const double *rhs, const double *Dg,
 #pragma unroll
     for (int i = 0; i < NW; ++i) dU[i] = rhs[i] / Dg[i];
     const double k = p.keff;
-    const double ep = 32.0 * p.sigma_R * Tv * Tv * Tv / (p.d_v * rho);
+    const double ep = p.Tvref > 0 ? 16.0 * p.sigma_R * Tv * Tv * Tv / (vib_cv(p, Tv) * rho)
+                                  : 32.0 * p.sigma_R * Tv * Tv * Tv / (p.d_v * rho);
     const double dv = (rhs[iv] + k * rhs[iR] / Dg[iR]) / (Dg[iv] - k * k * ep / Dg[iR]);
     const double dR = (rhs[iR] + k * ep * dv) / Dg[iR];
     dU[iv] = dv;
@@ -369,7 +370,7 @@ __global__ void k_W_from_mom(const double *__restrict__ mom, double *__restrict_
         Wc[1 + a] = rho * M[L.u() + a];
         ek += 0.5 * rho * M[L.u() + a] * M[L.u() + a];
     }
-    const double er = 0.5 * p.d_r * rho * M[L.Tr()], ev = 0.5 * p.d_v * rho * M[L.Tv()];
+    const double er = 0.5 * p.d_r * rho * M[L.Tr()], ev = vib_rho_e(p, rho, M[L.Tv()]);
     Wc[D + 1] = ek + 1.5 * rho * M[L.Tt()] + er + ev + M[L.eR()];
     Wc[D + 2] = er;
     Wc[D + 3] = ev;
@@ -856,8 +857,8 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
         }
         const double rho = Pc[0], Tt = Pc[D + 1], Tr = Pc[D + 2], Tv = Pc[D + 3];
         const double tau = Pc[D + 5] / (rho * Tt);
-        const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = (3 * Tt + p.d_v * Tv) / (3 + p.d_v);
-        const double etr = 0.5 * p.d_r * rho * Ttr, etv = 0.5 * p.d_v * rho * Ttv;
+        const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = vib_Ttv(p, Tt, Tv);
+        const double etr = 0.5 * p.d_r * rho * Ttr, etv = vib_rho_e(p, rho, Ttv);
         const double evR = 4 * p.sigma_R * Tv * Tv * Tv * Tv;
         const double er = Wc[D + 2], ev = Wc[D + 3], eR = Wc[D + 4];
         double Q[NW];
@@ -880,9 +881,14 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
         const double dt = cfl_macro * hc / (sqrt(un) + Pc[D + 6]);
         const double jr =
             -3.0 / ((3 + p.d_r) * p.Z_r * tau) + 2 * (p.omega - 1) * (Ttr - Tr) / (3 * p.Z_r * tau * Tt);
-        const double jv = -3.0 / ((3 + p.d_v) * p.Z_v * tau) +
-                          2 * (p.omega - 1) * (Ttv - Tv) / (3 * p.Z_v * tau * Tt) -
-                          p.keff * 16 * p.sigma_R * Tv * Tv * Tv * 2.0 / (p.d_v * rho);
+        // variable d_v: d_v replaced by the heat capacity 2 c_v (at T_tv in the relaxation term, at T_v in the
+        // emission term)
+        const double jv =
+            p.Tvref > 0 ? -3.0 / ((3 + 2 * vib_cv(p, Ttv)) * p.Z_v * tau) +
+                              2 * (p.omega - 1) * (Ttv - Tv) / (3 * p.Z_v * tau * Tt) -
+                              p.keff * 16 * p.sigma_R * Tv * Tv * Tv / (vib_cv(p, Tv) * rho)
+                        : -3.0 / ((3 + p.d_v) * p.Z_v * tau) + 2 * (p.omega - 1) * (Ttv - Tv) / (3 * p.Z_v * tau * Tt) -
+                              p.keff * 16 * p.sigma_R * Tv * Tv * Tv * 2.0 / (p.d_v * rho);
         double Dc[NW];
 #pragma unroll
         for (int i = 0; i < NW; ++i) Dc[i] = 1.0 / dt + gs * iV;
@@ -1297,9 +1303,8 @@ __global__ void k_resid_terms(const double *__restrict__ m1, const double *__res
     }
     o[2] = V * nu;
     o[3] = V * du;
-    const double s = 3 + p.d_r + p.d_v;
-    const double Tn = (3 * A[L.Tt()] + p.d_r * A[L.Tr()] + p.d_v * A[L.Tv()]) / s;
-    const double To = (3 * B[L.Tt()] + p.d_r * B[L.Tr()] + p.d_v * B[L.Tv()]) / s;
+    const double Tn = vib_Ttot(p, A[L.Tt()], A[L.Tr()], A[L.Tv()]);
+    const double To = vib_Ttot(p, B[L.Tt()], B[L.Tr()], B[L.Tv()]);
     o[4] = V * (Tn - To) * (Tn - To);
     o[5] = V * To * To;
     o[6] = V;

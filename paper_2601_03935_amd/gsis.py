@@ -40,7 +40,7 @@ class gsis_bc(C.Structure):
 
 
 class gsis_gas(C.Structure):
-    _fields_ = [(n, C.c_double) for n in ("d_r", "d_v", "Z_r", "Z_v", "omega", "Sc", "sigma_R")]
+    _fields_ = [(n, C.c_double) for n in ("d_r", "d_v", "Z_r", "Z_v", "omega", "Sc", "sigma_R", "Tv_ref")]
 
 
 class gsis_flow(C.Structure):
@@ -180,7 +180,8 @@ class Solver:
         self._check(self.L.gsis_set_ordinates(self.h, q.no, _p(_f64(q.omega)), _p(_f64(q.w))), "gsis_set_ordinates")
         gs = case.gas
         self._check(self.L.gsis_set_gas(self.h, C.byref(gsis_gas(gs.d_r, gs.d_v, gs.Z_r, gs.Z_v, gs.omega, gs.Sc,
-                                                                  gs.sigma_R))), "gsis_set_gas")
+                                                                  gs.sigma_R, getattr(gs, "Tv_ref", 0.0)))),
+                    "gsis_set_gas")
         self._check(self.L.gsis_set_flow(self.h, C.byref(gsis_flow(case.flow.Kn_gas, case.flow.k_eff))),
                     "gsis_set_flow")
         self.opts = default_opts(**opts)

@@ -526,3 +526,62 @@ def test_fused_and_stored_gradients_agree(name, prec, tol):
     fo, _ = o.get_state()
     assert _relerr(ff, fo) < (1e-10 if prec == "fp64" else 2e-6), (name, prec)
     s.close()
+
+
+# ---------------------------------------------------------------- temperature-dependent d_v (Sec. 2.1)
+def _with_tv_ref(case, Tv_ref=1.5):
+    import dataclasses
+
+    return dataclasses.replace(case, gas=dataclasses.replace(case.gas, Tv_ref=Tv_ref))
+
+
+@pytest.mark.parametrize("name,case", _cases_small(), ids=[c[0] for c in _cases_small()])
+def test_variable_dv_stages_fp64(name, case):
+    """Variable vibrational degrees of freedom d_v(T) (characteristic temperature 1.5): moments and fields,
+    one kinetic step, the synthetic solve and the synchronisation element by element against the oracle."""
+    case = _with_tv_ref(case)
+    s, o = _pair(case, precision="fp64", max_inner=_MAX_INNER[name])
+    _warm(o, s, n=3)
+    assert _relerr(s.fields(), o.fields()) < 1e-12, name
+    o.kinetic_step()
+    s.kinetic_step()
+    fo, Io = o.get_state()
+    fg, Ig = s.get_state()
+    assert _relerr(fg, fo) < 1e-10 and _relerr(Ig, Io) < 1e-10, name
+    Wo, ito = o.macro_solve()
+    Wg, itg = s.macro_solve()
+    assert ito == itg
+    assert _relerr(Wg, Wo) < 1e-9, name
+    o.sync(Wo)
+    s.sync(Wo)
+    assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-11
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["1d", "cavity", "capsule"])
+def test_variable_dv_gsis_iterations_fp64(name):
+    """Conventional then GSIS iterations with d_v(T): epsilon and the state against the oracle."""
+    case = _with_tv_ref(dict(_cases_small())[name])
+    s, o = _pair(case, precision="fp64", max_inner=_MAX_INNER[name])
+    for k in range(6):
+        g = k >= 2
+        eo, io = o.iterate(gsis=g)
+        eg, ig = s.iterate(gsis=g)
+        assert io == ig
+        assert abs(eg - eo) <= 1e-8 * abs(eo) + 1e-14, (k, eg, eo)
+    assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-8
+    s.close()
+
+
+def test_variable_dv_converged_1d_fp32():
+    """The 1D radiative Fourier flow with d_v(T) converged by GSIS: FP32 distributions against the FP64
+    oracle, every field within 1e-5 relative L2."""
+    case = _with_tv_ref(case_fourier_1d(n=16, nv=24, no=8, Kn=0.1))
+    s, o = _pair(case, precision="fp32", tol=1e-7, max_outer=400)
+    no, _ = o.solve(gsis=True, n_precond=10, tol=1e-7, max_outer=400)
+    rc, rep, _ = s.solve()
+    assert no > 0 and rc == 0, (no, rc)
+    errs = _field_rel_l2(s.fields(), o.fields(), case.mesh.vol, field_names(1), _u_scale(case))
+    print("iterations", no, rep.iters, sorted(errs.items(), key=lambda kv: -kv[1])[:3])
+    assert _max_err(errs) < 1e-5, errs
+    s.close()

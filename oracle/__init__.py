@@ -20,7 +20,7 @@ _lib = None
 # option vector layout of orc_create
 DEFAULT_OPTS = dict(cfl_meso=1e5, cfl_macro=1e3, limiter_K=10.0, inner_tol=1e-7, max_inner=100, n_sweeps=2,
                     second_order=1, cfl_v=5.0, kin_sweeps=8, kin_omega=1.0, diss_ref=1, macro_order2=0, sweep=0, period=0.0,
-                    rad_implicit=1)
+                    rad_implicit=1, conservative=0)
 
 
 def _load():
@@ -95,7 +95,7 @@ class Oracle:
         flowv = _f64([case.flow.Kn_gas, case.flow.k_eff])
         optv = _f64([o["cfl_meso"], o["cfl_macro"], o["limiter_K"], o["inner_tol"], o["max_inner"], o["n_sweeps"],
                      o["second_order"], o["cfl_v"], o["kin_sweeps"], o["kin_omega"], o["diss_ref"],
-                     o["macro_order2"], o["sweep"], o["period"], o["rad_implicit"]])
+                     o["macro_order2"], o["sweep"], o["period"], o["rad_implicit"], o["conservative"]])
         self._keep = [_f64(m.vol), _f64(m.ctr), np.ascontiguousarray(m.face_cells, dtype=np.int64), _f64(m.face_n),
                       _f64(m.face_area), _f64(m.face_ctr), np.ascontiguousarray(kind, dtype=np.int32), _f64(rho),
                       _f64(T), _f64(u), _f64(g.xi), _f64(g.w), _f64(q.omega), _f64(q.w), gasv, flowv, optv]

@@ -54,6 +54,10 @@ typedef struct {
 typedef struct {
     double Ttr, Ttv, T, tau, q0[3], q1[3], q2[3], evR, B, cs, dt, dtR, radd;
     double ev_v, ev_tv; /* e_v(T_v), e_v(T_tv) */
+    /* discrete-conservative corrections of the reference distributions (option `conservative`), per X in
+     * (t, r, v): a0, aq, a[D] of G (times M_X: a0 + aq c^2 / (2 T_X) + a . c) and the scalars of R, V, H */
+    int has_cons;
+    double cons[3][8];
 } der_t;
 
 typedef struct orc_s {
@@ -75,6 +79,7 @@ typedef struct orc_s {
     int sweep; /* 0: Jacobi sweeps of the implicit kinetic operator; 1: colored symmetric Gauss-Seidel */
     double period;    /* > 0: the mesh is periodic along x with this length (test meshes of the Fourier analysis) */
     int rad_implicit; /* 1: the emission part of the gas-photon exchange joins the diagonal of f2 (default) */
+    int conservative; /* 1: reference distributions corrected to conserve mass, momentum, energy on the grid */
     int max_inner, n_sweeps, second_order;
     /* derived constants */
     double A[3][3], Qm[3][3], K0[3][3];
@@ -437,6 +442,106 @@ static void cell_moments(const orc_t *o, const double *f, const double *I, int64
     m->eR = eR;
 }
 
+static void ref_dists(const orc_t *o, const mom_t *m, const der_t *d, const double *xi, double Y[3][4]);
+static double maxw(int D, double T, double c2);
+
+/* solve the symmetric positive definite n x n system A x = b (Cholesky, row-major A); returns 0 when a pivot
+ * falls below 1e-12 times its diagonal entry (the system is then left unsolved) */
+static int spd_solve(int n, const double *A, const double *b, double *x)
+{
+    double L[8][8];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(v > 1e-12 * A[i * n + i])) return 0;
+                L[i][i] = sqrt(v);
+            } else {
+                L[i][j] = v / L[j][j];
+            }
+        }
+    double y[8];
+    for (int i = 0; i < n; ++i) {
+        double v = b[i];
+        for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+        y[i] = v / L[i][i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < n; ++k) v -= L[k][i] * x[k];
+        x[i] = v / L[i][i];
+    }
+    return 1;
+}
+
+/* Discrete-conservative reference distributions (reading): on a discrete velocity grid the reference
+ * distributions of Eq. (reference_distribution) do not carry exactly the moments the relaxation must
+ * conserve.  For each X in (t, r, v), with M_X = rho f0^eq(T_X) and the polynomial basis psi = (1, c, c^2/2),
+ * c = xi - u, the correction G += M_X (psi . a) is the one whose discrete moments make
+ * sum w psi G = (rho, 0, (D/2) rho T_X) (the normal equations B a = target - sum w psi G with
+ * B = sum w psi psi^T M_X); R, V and H get scalar multiples of M_X restoring their densities
+ * (d_r/2) T_RX rho, e_v(T_VX) rho and (3 - D) T_X rho.  With the corrections the relaxation conserves mass,
+ * momentum and energy to round-off on any grid; a system whose Cholesky pivot falls below 1e-12 of its
+ * diagonal (a Maxwellian narrower than the grid resolves) is left uncorrected. */
+static void conservative_corrections(const orc_t *o, const mom_t *m, der_t *d)
+{
+    int D = o->D, n = D + 2;
+    double TX[3] = {m->Tt, d->Ttr, d->Ttv};
+    double TRX[3] = {m->Tr, d->Ttr, m->Tr};
+    double EVX[3] = {d->ev_v, d->ev_v, d->ev_tv};
+    double TVX[3] = {m->Tv, m->Tv, d->Ttv};
+    double B[3][25], mG[3][5], mR[3], mV[3], mH[3];
+    for (int X = 0; X < 3; ++X) {
+        for (int i = 0; i < 25; ++i) B[X][i] = 0;
+        for (int i = 0; i < 5; ++i) mG[X][i] = 0;
+        mR[X] = mV[X] = mH[X] = 0;
+    }
+    d->has_cons = 0;
+    for (int64_t k = 0; k < o->nv; ++k) {
+        const double *xi = o->xi + k * D;
+        double Y[3][4], psi[5], c2 = 0;
+        ref_dists(o, m, d, xi, Y);
+        psi[0] = 1;
+        for (int a = 0; a < D; ++a) {
+            psi[1 + a] = xi[a] - m->u[a];
+            c2 += psi[1 + a] * psi[1 + a];
+        }
+        psi[D + 1] = 0.5 * c2;
+        double wk = o->w[k];
+        for (int X = 0; X < 3; ++X) {
+            double e = m->rho * maxw(D, TX[X], c2);
+            for (int i = 0; i < n; ++i) {
+                mG[X][i] += wk * psi[i] * Y[X][DG];
+                for (int j = 0; j < n; ++j) B[X][i * n + j] += wk * psi[i] * psi[j] * e;
+            }
+            mR[X] += wk * Y[X][DR];
+            mV[X] += wk * Y[X][DV];
+            if (o->ND == 4) mH[X] += wk * Y[X][DH];
+        }
+    }
+    for (int X = 0; X < 3; ++X) {
+        double rhs[5] = {0, 0, 0, 0, 0}, a[5] = {0, 0, 0, 0, 0};
+        for (int i = 0; i < n; ++i) rhs[i] = -mG[X][i];
+        rhs[0] += m->rho;
+        rhs[D + 1] += 0.5 * D * m->rho * TX[X];
+        double *k = d->cons[X];
+        for (int i = 0; i < 8; ++i) k[i] = 0;
+        if (spd_solve(n, B[X], rhs, a)) {
+            /* psi . a = a0 + a_E c^2/2 + a . c; stored as a0, a_E T_X (coefficient of c^2 / (2 T_X)), a */
+            k[0] = a[0];
+            k[1] = a[D + 1] * TX[X];
+            for (int q = 0; q < D; ++q) k[2 + q] = a[1 + q];
+        }
+        double S = B[X][0];
+        double evx = o->Tvref > 0 ? EVX[X] : 0.5 * o->dv * TVX[X];
+        k[D + 2] = (0.5 * o->dr * TRX[X] * m->rho - mR[X]) / S;
+        k[D + 3] = (evx * m->rho - mV[X]) / S;
+        k[D + 4] = (o->ND == 4) ? ((3 - D) * TX[X] * m->rho - mH[X]) / S : 0.0;
+    }
+    d->has_cons = 1;
+}
+
 static void derived(const orc_t *o, const mom_t *m, int64_t c, der_t *d)
 {
     double dr = o->dr;
@@ -466,6 +571,8 @@ static void derived(const orc_t *o, const mom_t *m, int64_t c, der_t *d)
     /* reading: pseudo time step dt = CFL h / (|u| + c_s); photons move at unit speed */
     d->dt = o->cfl_meso * o->h[c] / (sqrt(un) + d->cs);
     d->dtR = o->cfl_meso * o->h[c];
+    d->has_cons = 0;
+    if (o->conservative) conservative_corrections(o, m, d);
 }
 
 /* normalised D-dimensional Maxwellian (reduced form of f0^eq) */
@@ -506,6 +613,16 @@ static void ref_dists(const orc_t *o, const mom_t *m, const der_t *d, const doub
         Y[X][DR] = 0.5 * o->dr * TRX[X] * G + qrc / T * M;
         Y[X][DV] = (o->Tvref > 0 ? EVX[X] * G : 0.5 * o->dv * TVX[X] * G) + qvc / T * M;
         Y[X][DH] = (3 - D) * m->rho * T * M * (1 + s * (c2 / (2 * T) - 0.5 * D));
+        if (d->has_cons) {
+            const double *k = d->cons[X];
+            double P = k[0] + k[1] * c2 / (2 * T);
+            for (int a = 0; a < D; ++a) P += k[2 + a] * cc[a];
+            double e = m->rho * M;
+            Y[X][DG] += P * e;
+            Y[X][DR] += k[D + 2] * e;
+            Y[X][DV] += k[D + 3] * e;
+            Y[X][DH] += k[D + 4] * e;
+        }
     }
 }
 
@@ -1712,6 +1829,7 @@ orc_t *orc_create(int D, int64_t nc, int64_t nf, const double *vol, const double
     o->sweep = (int)opts[12];
     o->period = opts[13];
     o->rad_implicit = (int)opts[14];
+    o->conservative = (int)opts[15];
     model_constants(o);
     build_mesh(o);
     o->f = (double *)calloc((size_t)nc * o->ND * nv, sizeof(double));

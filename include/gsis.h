@@ -90,7 +90,7 @@ typedef struct {
 
 /* Iteration options.  Defaults (gsis_default_opts): GSIS, FP32, tol 1e-6, max_outer 1000,
  * n_precond 10, cfl_meso 1e5, cfl_v 5, kin_sweeps 8, kin_omega 1, limiter_K 10, second_order 1,
- * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2, first_order_iters 0, sweep JACOBI, kin_fused 0. */
+ * cfl_macro 1e3, inner_tol 1e-7, max_inner 100, n_sweeps 2, first_order_iters 0, sweep JACOBI, kin_fused 0, conservative 0. */
 typedef struct {
     int32_t scheme;       /* GSIS_CIS or GSIS_GSIS */
     int32_t precision;    /* GSIS_FP64 or GSIS_FP32: storage and arithmetic of f and I */
@@ -117,6 +117,12 @@ typedef struct {
                              f), so no gradient field is stored: dim x less memory for the kinetic buffers,
                              ~5x the gradient arithmetic.  Same arithmetic per velocity either way; velocity
                              counts not divisible by 16 bytes / element size always take the stored pass. */
+    int32_t conservative; /* 1: discrete-conservative reference distributions: per cell and reference temperature
+                             X, G gains a multiple e (psi . a) of e = rho f0^eq(T_X), psi = (1, c, c^2/2), whose
+                             discrete moments restore (rho, 0, (D/2) rho T_X), and R, V, H scalar multiples of e
+                             restoring their densities, so that the relaxation conserves mass, momentum and
+                             energy on any velocity grid (a reduction over the velocities per cell and
+                             iteration); 0 (default): the reference distributions as printed */
 } gsis_opts;
 
 typedef struct {

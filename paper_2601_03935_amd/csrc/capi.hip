@@ -434,6 +434,7 @@ static void free_kin(KinBufs<T> &B)
     dfree(B.dI0);
     dfree(B.dI1);
     dfree(B.coef);
+    dfree(B.ccons);
     dfree(B.xi);
     dfree(B.xiT);
     dfree(B.om);
@@ -530,6 +531,7 @@ static bool alloc_kin(gsis_t *h, KinBufs<T> &B)
     B.dI0 = dalloc<T>(nc * no, ok);
     B.dI1 = dalloc<T>(nc * no, ok);
     B.coef = dalloc<T>(nc * coef_sz(D), ok);
+    B.ccons = dalloc<T>(nc * 3 * 8, ok);
     B.xi = dalloc<T>(nv * D, ok);
     B.xiT = dalloc<T>(nv * D, ok);
     B.om = dalloc<T>(no * D, ok);
@@ -553,6 +555,7 @@ static bool alloc_kin(gsis_t *h, KinBufs<T> &B)
     (void)hipMemcpy(B.om_d, h->om.data(), h->om.size() * sizeof(double), hipMemcpyHostToDevice);
     (void)hipMemcpy(B.wo_d, h->wo.data(), h->wo.size() * sizeof(double), hipMemcpyHostToDevice);
     (void)hipMemset(B.rhow, 0, std::max<size_t>(nbf, 1) * sizeof(T));
+    (void)hipMemset(B.ccons, 0, nc * 3 * 8 * sizeof(T));
     (void)hipMemset(B.bflux, 0, std::max<size_t>(nbf * (D + 5), 1) * sizeof(double));
     (void)hipMemset(B.bsurf, 0, std::max<size_t>(nbf * 3, 1) * sizeof(double));
     return true;
@@ -642,6 +645,7 @@ static KinOpts kopts(const gsis_t *h)
     o.second_order = h->opts.second_order;
     o.sweep = h->opts.sweep;
     o.fused = h->opts.kin_fused;
+    o.conservative = h->opts.conservative;
     o.col_ptr = h->col_ptr.data();
     o.ncolor = (int)h->col_ptr.size() - 1;
     return o;
@@ -681,6 +685,12 @@ static void prologue_T(gsis_t *h, KinBufs<T> &B, const double *mom)
     if (D == 1) launch_prologue<T, 1>(mom, B.coef, h->m.h, h->hm.nc, h->phys, h->opts.cfl_meso, h->stream);
     else if (D == 2) launch_prologue<T, 2>(mom, B.coef, h->m.h, h->hm.nc, h->phys, h->opts.cfl_meso, h->stream);
     else launch_prologue<T, 3>(mom, B.coef, h->m.h, h->hm.nc, h->phys, h->opts.cfl_meso, h->stream);
+    if (h->opts.conservative) {
+        const int64_t nc = h->hm.nc, nv = h->nv;
+        if (D == 1) launch_cons_sums<T, 1>(mom, B.coef, B.xi, B.w_d, B.ccons, nc, nv, h->phys, h->stream);
+        else if (D == 2) launch_cons_sums<T, 2>(mom, B.coef, B.xi, B.w_d, B.ccons, nc, nv, h->phys, h->stream);
+        else launch_cons_sums<T, 3>(mom, B.coef, B.xi, B.w_d, B.ccons, nc, nv, h->phys, h->stream);
+    }
 }
 
 template <typename T>
@@ -1054,6 +1064,7 @@ void gsis_default_opts(gsis_opts *o)
     o->n_sweeps = 2;
     o->sweep = GSIS_SWEEP_JACOBI;
     o->kin_fused = 0;
+    o->conservative = 0;
 }
 
 int32_t gsis_create(int32_t device, gsis_t **out)
@@ -1238,7 +1249,7 @@ int32_t gsis_set_opts(gsis_t *h, const gsis_opts *o)
         o->first_order_iters < 0 || (o->second_order != 0 && o->second_order != 1) || !(o->tol >= 0) ||
         !(o->inner_tol >= 0) || !(o->limiter_K > 0) || !(o->kin_omega > 0) || !(o->cfl_v > 0) ||
         !(o->cfl_meso > 0) || !(o->cfl_macro > 0) || (o->sweep != GSIS_SWEEP_JACOBI && o->sweep != GSIS_SWEEP_SGS) ||
-        (o->kin_fused != 0 && o->kin_fused != 1))
+        (o->kin_fused != 0 && o->kin_fused != 1) || (o->conservative != 0 && o->conservative != 1))
         return fail(h, GSIS_E_ARG, "gsis_set_opts: invalid options");
     // the kinetic kernels index waves over (cell, 64-velocity chunk) pairs with 32-bit integers
     if (h->hm.nc * ((h->nv + 63) / 64 + 1) > (int64_t)(INT32_MAX / 8))

@@ -104,6 +104,7 @@ struct KinOpts {
     int kin_sweeps, second_order;
     int sweep;               // 0: Jacobi sweeps; 1: colored symmetric Gauss-Seidel sweeps
     int fused;               // 1: limited gradients recomputed inside the residual kernel
+    int conservative;        // 1: discrete-conservative corrections of the reference distributions
     const int64_t *col_ptr;  // host: cells of colour q are col_cells[col_ptr[q] .. col_ptr[q + 1])
     int ncolor;
 };

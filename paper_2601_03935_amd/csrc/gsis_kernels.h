@@ -15,6 +15,7 @@ struct KinBufs {
     T *I = nullptr, *I2 = nullptr, *gI = nullptr, *rI = nullptr, *dI0 = nullptr, *dI1 = nullptr;
     T *coef = nullptr, *xi = nullptr, *om = nullptr, *rhow = nullptr;
     T *gfb = nullptr;  // limited gradients of the boundary cells only, row i for cell bcells[i]
+    T *ccons = nullptr;  // per cell: discrete-conservative corrections of the reference distributions (3 x 8)
     T *xiT = nullptr;  // velocity components component-major: xiT[a * nv + k]
     double *xi_d = nullptr, *w_d = nullptr, *om_d = nullptr, *wo_d = nullptr;  // om: D components per ordinate
     double *bflux = nullptr, *bsurf = nullptr;
@@ -136,6 +137,10 @@ void launch_moments(const KinBufs<T> &B, const double *uref, double *mom, int64_
 template <typename T, int D>
 void launch_prologue(const double *mom, T *coef, const double *h, int64_t nc, const Phys &p, double cfl,
                      hipStream_t st);
+// discrete-conservative corrections of the reference distributions from the moments and the coefficients
+template <typename T, int D>
+void launch_cons_sums(const double *mom, const T *coef, const T *xi, const double *w, T *ccons, int64_t nc,
+                      int64_t nv, const Phys &p, hipStream_t st);
 template <typename T, int D>
 void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_t no, const Phys &p, int init,
                  hipStream_t st);

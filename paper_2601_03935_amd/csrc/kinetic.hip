@@ -312,12 +312,15 @@ __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__re
 //   then for X in (t, r, v): inv2T, norm, a[D], gR, bR[D], gV, bV[D], hH
 __host__ __device__ constexpr int coef_x(int D) { return 5 + 3 * D; }
 __host__ __device__ constexpr int coef_size(int D) { return D + 6 + 3 * coef_x(D); }
+// per-cell discrete-conservative corrections, for X in (t, r, v): a0, aq, a[D] of G (times e: a0 + aq c^2 /
+// (2 T_X) + a . c), then the scalars of R, V, H (slots of kConsX = 8 values)
+constexpr int kConsX = 8;
 
 // relaxation source J for the nd slots at velocity xi (Eq. kinetic_equation with Eq. reference_distribution,
 // reduced to D velocity dimensions)
 template <typename T, int D>
 __device__ __forceinline__ void collision(const T *cf, const T *xi, const T *fk, T *J, const int nd, const T wt,
-                                          const T wr, const T wv)
+                                          const T wr, const T wv, const T *kc = nullptr)
 {
     T cc[D], c2 = T(0);
 #pragma unroll
@@ -340,10 +343,21 @@ __device__ __forceinline__ void collision(const T *cf, const T *xi, const T *fk,
             bv += p[4 + 2 * D + a] * cc[a];
         }
         const T q = c2 * inv2T;
-        const T G = e * (T(1) + s * (q - aG));
-        const T R = p[2 + D] * G + br * e;
-        const T V = p[3 + 2 * D] * G + bv * e;
-        const T H = p[4 + 3 * D] * e * (T(1) + s * (q - aH));
+        T G = e * (T(1) + s * (q - aG));
+        T R = p[2 + D] * G + br * e;
+        T V = p[3 + 2 * D] * G + bv * e;
+        T H = p[4 + 3 * D] * e * (T(1) + s * (q - aH));
+        if (kc) {
+            // discrete-conservative corrections (a multiple of e = rho f0^eq(T_X) per slot)
+            const T *k = kc + X * kConsX;
+            T P = k[0] + k[1] * q;
+#pragma unroll
+            for (int a = 0; a < D; ++a) P += k[2 + a] * cc[a];
+            G += P * e;
+            R += k[D + 2] * e;
+            V += k[D + 3] * e;
+            H += k[D + 4] * e;
+        }
         const T wX = (X == 0) ? wt : ((X == 1) ? wr : wv);
         Ysum[0] += wX * G;
         Ysum[1] += wX * R;
@@ -381,7 +395,8 @@ __device__ __forceinline__ void boundary_values(const BcDev &bc, const T rho, co
 // ------------------------------------------------------------------ residual and first increment
 template <typename T, int D, int NFM>
 __global__ __launch_bounds__(256) void k_residual(const T *__restrict__ f, const T *__restrict__ gf,
-                                                  const T *__restrict__ coef, const T *__restrict__ xi,
+                                                  const T *__restrict__ coef, const T *__restrict__ ccons,
+                                                  const T *__restrict__ xi,
                                                   const T *__restrict__ rhow, T *__restrict__ r,
                                                   T *__restrict__ dl, T *__restrict__ fout, const MeshDev m,
                                                   const int64_t nv, const T cflv_fac, const T omega,
@@ -462,7 +477,7 @@ __global__ __launch_bounds__(256) void k_residual(const T *__restrict__ f, const
             for (int d = 0; d < ND; ++d) flux[d] += xn * fv[d];
         }
         T J[4];
-        collision<T, D>(cf, x, fc, J, ND, wt, wr, wv);
+        collision<T, D>(cf, x, fc, J, ND, wt, wr, wv, ccons ? ccons + (int64_t)c * 3 * kConsX : nullptr);
         const T dcoef = cf[D + 1] + cf[D] + dsum * cflv_fac;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
@@ -483,7 +498,8 @@ __global__ __launch_bounds__(256) void k_residual(const T *__restrict__ f, const
 // rows of interior neighbours are loaded for every lane and the upwind choice is made per velocity.
 template <typename T, int D, int NFM, int VW>
 __global__ __launch_bounds__(256) void k_residual_v(const T *__restrict__ f, const T *__restrict__ gf,
-                                                    const T *__restrict__ coef, const T *__restrict__ xiT,
+                                                    const T *__restrict__ coef, const T *__restrict__ ccons,
+                                                    const T *__restrict__ xiT,
                                                     const T *__restrict__ rhow, T *__restrict__ r,
                                                     T *__restrict__ dl, T *__restrict__ fout, const MeshDev m,
                                                     const int64_t nv, const int nchunk, const int cgroup,
@@ -601,7 +617,7 @@ __global__ __launch_bounds__(256) void k_residual_v(const T *__restrict__ f, con
             for (int a = 0; a < D; ++a) xe[a] = x[a][e];
 #pragma unroll
             for (int d = 0; d < ND; ++d) fe[d] = fc[d][e];
-            collision<T, D>(cf, xe, fe, J, ND, wt, wr, wv);
+            collision<T, D>(cf, xe, fe, J, ND, wt, wr, wv, ccons ? ccons + (int64_t)c * 3 * kConsX : nullptr);
             const T dcoef = cf[D + 1] + cf[D] + dsum[e] * cflv_fac;
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
@@ -698,7 +714,8 @@ __device__ __forceinline__ void limited_grad_v(const T *__restrict__ f, const Me
 // iterate) with no gradient traffic.  Same arithmetic per velocity as k_grad_v followed by k_residual_v.
 template <typename T, int D, int NFM, int VW>
 __global__ __launch_bounds__(256) void k_gres_v(const T *__restrict__ f, const T *__restrict__ coef,
-                                                const T *__restrict__ xiT, const T *__restrict__ rhow,
+                                                const T *__restrict__ ccons, const T *__restrict__ xiT,
+                                                const T *__restrict__ rhow,
                                                 T *__restrict__ r, T *__restrict__ dl, T *__restrict__ fout,
                                                 const MeshDev m, const int64_t nv, const int nchunk,
                                                 const int cgroup, const int second_order, const T cflv_fac,
@@ -753,7 +770,7 @@ __global__ __launch_bounds__(256) void k_gres_v(const T *__restrict__ f, const T
         for (int a = 0; a < D; ++a) xe[a] = x[a][e];
 #pragma unroll
         for (int d = 0; d < ND; ++d) fe[d] = fc[d][e];
-        collision<T, D>(cf, xe, fe, J, ND, wt, wr, wv);
+        collision<T, D>(cf, xe, fe, J, ND, wt, wr, wv, ccons ? ccons + (int64_t)c * 3 * kConsX : nullptr);
 #pragma unroll
         for (int d = 0; d < ND; ++d) Jv[d][e] = J[d];
     }
@@ -1771,6 +1788,134 @@ __global__ void k_prologue(const double *__restrict__ mom, T *__restrict__ coef,
     }
 }
 
+// ------------------------------------------------------------------ discrete-conservative corrections
+// Per cell (one wave, lanes over the velocities): for each reference temperature X the discrete sums of the
+// reference distributions exactly as collision() evaluates them (T precision, FP64 accumulation) -- the
+// normal matrix B = sum w psi psi^T e with psi = (1, c, c^2/2), e = rho f0^eq(T_X), the moments sum w psi G
+// and the densities of R, V, H -- then, on the first lane, the correction whose discrete moments restore
+// (rho, 0, (D/2) rho T_X) for G and (d_r/2) T_RX rho, e_v(T_VX) rho, (3 - D) T_X rho for R, V, H.  The
+// normal equations are solved by Cholesky; a pivot below 1e-12 of its diagonal leaves G uncorrected.
+__device__ inline bool chol_solve(const int n, double (&A)[5][5], double (&b)[5])
+{
+    double L[5][5];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double v = A[i][j];
+            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+            if (i != j) {
+                L[i][j] = v / L[j][j];
+            } else if (v > 1e-12 * A[i][i]) {
+                L[i][i] = sqrt(v);
+            } else {
+                return false;
+            }
+        }
+    for (int i = 0; i < n; ++i) {  // forward substitution, in place
+        for (int k = 0; k < i; ++k) b[i] -= L[i][k] * b[k];
+        b[i] /= L[i][i];
+    }
+    for (int i = n - 1; i >= 0; --i) {  // back substitution
+        for (int k = i + 1; k < n; ++k) b[i] -= L[k][i] * b[k];
+        b[i] /= L[i][i];
+    }
+    return true;
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cons_sums(const double *__restrict__ mom, const T *__restrict__ coef,
+                                                   const T *__restrict__ xi, const double *__restrict__ w,
+                                                   T *__restrict__ ccons, const int64_t nc, const int64_t nv,
+                                                   const Phys p)
+{
+    constexpr MomLayout L{D};
+    constexpr int n = D + 2, NB = (D + 2) * (D + 3) / 2;
+    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= nc) return;
+    const T *cf = coef + c * coef_size(D);
+    const double *M = mom + c * L.size();
+    const double rho = M[L.rho()], Tt = M[L.Tt()], Tr = M[L.Tr()], Tv = M[L.Tv()];
+    const double Ttr = (3 * Tt + p.d_r * Tr) / (3 + p.d_r), Ttv = vib_Ttv(p, Tt, Tv);
+    const double TX[3] = {Tt, Ttr, Ttv}, TRX[3] = {Tr, Ttr, Tr};
+    const double VX[3] = {p.Tvref > 0 ? vib_e(p, Tv) : 0.5 * p.d_v * Tv, p.Tvref > 0 ? vib_e(p, Tv) : 0.5 * p.d_v * Tv,
+                          p.Tvref > 0 ? vib_e(p, Ttv) : 0.5 * p.d_v * Ttv};
+    T *out = ccons + c * 3 * kConsX;
+    const T aG = T(0.5) * T(2 + D), aH = T(0.5) * T(D);
+    for (int X = 0; X < 3; ++X) {
+        const T *px = cf + D + 6 + X * coef_x(D);
+        double sB[NB], sG[n], sR = 0, sV = 0, sH = 0;
+        for (int i = 0; i < NB; ++i) sB[i] = 0;
+        for (int i = 0; i < n; ++i) sG[i] = 0;
+        for (int64_t k = lane; k < nv; k += kWave) {
+            T cc[D], c2 = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                cc[a] = xi[k * D + a] - cf[a];
+                c2 += cc[a] * cc[a];
+            }
+            const T e = px[1] * dexp<T>(-c2 * px[0]);
+            T s = T(0), br = T(0), bv = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                s += px[2 + a] * cc[a];
+                br += px[3 + D + a] * cc[a];
+                bv += px[4 + 2 * D + a] * cc[a];
+            }
+            const T q = c2 * px[0];
+            const T G = e * (T(1) + s * (q - aG));
+            const double wk = w[k];
+            double psi[n];
+            psi[0] = 1.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) psi[1 + a] = (double)cc[a];
+            psi[D + 1] = 0.5 * (double)c2;
+            int ib = 0;
+#pragma unroll
+            for (int i = 0; i < n; ++i) {
+                sG[i] += wk * psi[i] * (double)G;
+#pragma unroll
+                for (int j = 0; j <= i; ++j) sB[ib++] += wk * psi[i] * psi[j] * (double)e;
+            }
+            sR += wk * (double)(px[2 + D] * G + br * e);
+            sV += wk * (double)(px[3 + 2 * D] * G + bv * e);
+            if (D < 3) sH += wk * (double)(px[4 + 3 * D] * e * (T(1) + s * (q - aH)));
+        }
+        for (int i = 0; i < NB; ++i) sB[i] = wave_sum(sB[i]);
+        for (int i = 0; i < n; ++i) sG[i] = wave_sum(sG[i]);
+        sR = wave_sum(sR);
+        sV = wave_sum(sV);
+        sH = wave_sum(sH);
+        if (lane == 0) {
+            double A[5][5], b[5];
+            int ib = 0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j <= i; ++j) A[i][j] = A[j][i] = sB[ib++];
+            for (int i = 0; i < n; ++i) b[i] = -sG[i];
+            b[0] += rho;
+            b[D + 1] += 0.5 * D * rho * TX[X];
+            T *o = out + X * kConsX;
+            for (int i = 0; i < kConsX; ++i) o[i] = T(0);
+            if (chol_solve(n, A, b)) {
+                o[0] = (T)b[0];
+                o[1] = (T)(b[D + 1] * TX[X]);
+                for (int a = 0; a < D; ++a) o[2 + a] = (T)b[1 + a];
+            }
+            const double S = sB[0];
+            o[D + 2] = (T)((0.5 * p.d_r * TRX[X] * rho - sR) / S);
+            o[D + 3] = (T)((VX[X] * rho - sV) / S);
+            o[D + 4] = (T)(D < 3 ? ((3 - D) * TX[X] * rho - sH) / S : 0.0);
+        }
+    }
+}
+
+template <typename T, int D>
+void launch_cons_sums(const double *mom, const T *coef, const T *xi, const double *w, T *ccons, int64_t nc,
+                      int64_t nv, const Phys &p, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_cons_sums<T, D>), dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, st, mom, coef, xi, w, ccons,
+                       nc, nv, p);
+}
+
 // ------------------------------------------------------------------ wall re-emission densities
 // Wall density of each diffuse-wall face (zero net mass flux): outgoing flux of the reconstructed f over
 // the incoming flux of the unit-density wall Maxwellian.  One 256-thread block per boundary face; the
@@ -2150,6 +2295,7 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
     // gradients recomputed inside the residual (vector kernels only); the stored pass otherwise.  Either way
     // the wall densities read gradient rows of the boundary cells: the compact rows of gfb, or gf itself.
     const bool fused = o.fused && (nv % VW == 0);
+    const T *cons = o.conservative ? B.ccons : nullptr;  // discrete-conservative corrections, when enabled
     int ev = P.begin(0, fused ? (double)m.nbcells * nv * ND * es * (1 + D) : cv * (1 + D));
     if (fused) launch_grad<T, D, NFM>(B.f, B.gfb, m, nv, o.second_order, m.bcells, m.nbcells, 1, st);
     else launch_grad<T, D, NFM>(B.f, B.gf, m, nv, o.second_order, nullptr, m.nc, 0, st);
@@ -2175,16 +2321,17 @@ void launch_kinetic(KinBufs<T> &B, const MeshDev &m, const Phys &p, const KinOpt
         constexpr int VF = VW / 2;
         const int nchf = (int)((nv + kWave * VF - 1) / (kWave * VF));
         hipLaunchKernelGGL((k_gres_v<T, D, NFM, VF>), dim3((unsigned)((m.nc * nchf + 3) / 4)), blk, 0, st, B.f,
-                           B.coef, B.xiT, B.rhow, B.r, sgs ? nullptr : B.dl0, direct ? B.f2 : nullptr, m, nv, nchf,
+                           B.coef, cons, B.xiT, B.rhow, B.r, sgs ? nullptr : B.dl0, direct ? B.f2 : nullptr, m, nv, nchf,
                            chunk_group(CG::residual, D, m.nc), o.second_order, fac, om, wt, wr, wv, (T)p.d_r,
                            (T)p.d_v);
     }
     else if (nv % VW == 0)
-        hipLaunchKernelGGL((k_residual_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.f, B.gf, B.coef, B.xiT, B.rhow,
+        hipLaunchKernelGGL((k_residual_v<T, D, NFM, VW>), chunk_grid, blk, 0, st, B.f, B.gf, B.coef, cons, B.xiT,
+                           B.rhow,
                            B.r, sgs ? nullptr : B.dl0, direct ? B.f2 : nullptr, m, nv, nchunk,
                            chunk_group(CG::residual, D, m.nc), fac, om, wt, wr, wv, (T)p.d_r, (T)p.d_v);
     else
-        hipLaunchKernelGGL((k_residual<T, D, NFM>), grid, blk, 0, st, B.f, B.gf, B.coef, B.xi, B.rhow, B.r,
+        hipLaunchKernelGGL((k_residual<T, D, NFM>), grid, blk, 0, st, B.f, B.gf, B.coef, cons, B.xi, B.rhow, B.r,
                            sgs ? nullptr : B.dl0, direct ? B.f2 : nullptr, m, nv, fac, om, wt, wr, wv, (T)p.d_r,
                            (T)p.d_v);
     P.end(ev);
@@ -2319,6 +2466,8 @@ void launch_sync(KinBufs<T> &B, const double *sp, int64_t nc, int64_t nv, int64_
                                        const Phys &, hipStream_t);                                                 \
     template void launch_prologue<T, D>(const double *, T *, const double *, int64_t, const Phys &, double,       \
                                         hipStream_t);                                                              \
+    template void launch_cons_sums<T, D>(const double *, const T *, const T *, const double *, T *, int64_t,      \
+                                         int64_t, const Phys &, hipStream_t);                                     \
     template void launch_sync<T, D>(KinBufs<T> &, const double *, int64_t, int64_t, int64_t, const Phys &, int,   \
                                     hipStream_t);
 

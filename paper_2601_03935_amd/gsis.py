@@ -53,7 +53,7 @@ class gsis_opts(C.Structure):
                 ("kin_sweeps", C.c_int32), ("kin_omega", C.c_double), ("limiter_K", C.c_double),
                 ("second_order", C.c_int32), ("cfl_macro", C.c_double), ("inner_tol", C.c_double),
                 ("max_inner", C.c_int32), ("n_sweeps", C.c_int32), ("first_order_iters", C.c_int32),
-                ("sweep", C.c_int32), ("kin_fused", C.c_int32)]
+                ("sweep", C.c_int32), ("kin_fused", C.c_int32), ("conservative", C.c_int32)]
 
 
 class gsis_report(C.Structure):
@@ -355,4 +355,5 @@ def oracle_opts(opts: gsis_opts) -> dict:
     """The oracle option set equivalent to a library option set (for parity runs)."""
     return dict(cfl_meso=opts.cfl_meso, cfl_macro=opts.cfl_macro, limiter_K=opts.limiter_K, inner_tol=opts.inner_tol,
                 max_inner=opts.max_inner, n_sweeps=opts.n_sweeps, second_order=opts.second_order, cfl_v=opts.cfl_v,
-                kin_sweeps=opts.kin_sweeps, kin_omega=opts.kin_omega, diss_ref=1, macro_order2=0, sweep=opts.sweep)
+                kin_sweeps=opts.kin_sweeps, kin_omega=opts.kin_omega, diss_ref=1, macro_order2=0, sweep=opts.sweep,
+                conservative=opts.conservative)

@@ -587,11 +587,11 @@ def fields_vs_fixture(F, case, a):
     if not os.path.exists(path) or a.tol != 1e-6:
         return None
     Fo = np.load(path)["fields"].astype(np.float64)
-    if Fo.shape != F.shape:
+    if Fo.shape[0] != F.shape[0]:
         return None
     w = case.mesh.vol / case.mesh.vol.sum()
     out = {}
-    for i, n in enumerate(FIELDS_2D):
+    for i, n in enumerate(FIELDS_2D[: Fo.shape[1]]):
         num = np.sqrt((w * (F[:, i] - Fo[:, i]) ** 2).sum())
         den = max(np.sqrt((w * Fo[:, i] ** 2).sum()), 0.18 if n[0] == "u" else 1e-2)
         out[n] = float(num / den)

@@ -1,7 +1,8 @@
 """The full-size cavity (20,108 triangles, 32 x 32 velocities, 32 ordinates) at the nine (Kn, optical
 thickness) pairs Kn in {0.01, 0.1, 1} x tau in {0.1, 1, 10}: the GPU FP32 solve to epsilon < 1e-6 against the
-converged FP64 oracle fields stored by tests/golden/make_cavity_fixtures.py (same start, same options), every
-field within 1e-5 relative L2 (volume weights; velocities against the lid speed)."""
+converged FP64 oracle fields stored by tests/golden/make_cavity_fixtures.py (same start, same options), the
+primary fields (density, velocity, the four temperatures and the total one) within 1e-5 relative L2 (volume
+weights; velocities against the lid speed)."""
 
 import os
 
@@ -46,7 +47,8 @@ def test_converged_fp32_cavity_matches_oracle(Kn, tau):
     F = s.fields()
     s.close()
     assert rc == 0, (rc, rep.iters)
-    errs = field_rel_l2(F, z["fields"].astype(np.float64), case.mesh.vol, field_names(2), 0.18)
+    Fo = z["fields"].astype(np.float64)
+    errs = field_rel_l2(F[:, : Fo.shape[1]], Fo, case.mesh.vol, field_names(2)[: Fo.shape[1]], 0.18)
     print(f"Kn {Kn} tau {tau}: GPU {rep.iters} iterations, oracle {int(z['iterations'])}; errors",
           sorted(errs.items(), key=lambda kv: -kv[1])[:3])
     assert abs(rep.iters - int(z["iterations"])) <= max(3, 0.02 * int(z["iterations"]))

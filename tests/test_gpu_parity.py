@@ -649,3 +649,24 @@ def test_conservative_relaxation_keeps_the_capsule_mass_on_8cubed():
     errs = _field_rel_l2(s.fields(), o.fields(), V, field_names(3), _u_scale(case))
     assert _max_err(errs) < 1e-5, errs
     s.close()
+
+
+def test_spherical_velocity_grid_with_conservative_relaxation_fp64():
+    """The coarse capsule on an unstructured spherical velocity set (8 radial x 6 polar x 8 azimuthal points,
+    radius 8) with the discrete-conservative relaxation: kinetic step and conventional / GSIS iterations
+    against the oracle."""
+    import dataclasses
+
+    from workloads import spherical_grid
+
+    case = dataclasses.replace(dict(_cases_small())["capsule"], vgrid=spherical_grid(8, 6, 8, 8.0))
+    s, o = _pair(case, precision="fp64", conservative=1, max_inner=10)
+    _warm(o, s, n=2)
+    o.kinetic_step()
+    s.kinetic_step()
+    assert _relerr(s.get_state()[0], o.get_state()[0]) < 1e-10
+    for k in range(4):
+        eo, _ = o.iterate(gsis=k >= 2)
+        eg, _ = s.iterate(gsis=k >= 2)
+        assert abs(eg - eo) <= 1e-8 * abs(eo) + 1e-14, (k, eg, eo)
+    s.close()

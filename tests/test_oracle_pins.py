@@ -1000,3 +1000,20 @@ def test_conservative_relaxation_removes_the_coarse_grid_mass_drift():
         rho[cons] = np.array(r)
     assert rho[0][-1] / rho[0][0] > 1.5, rho[0]
     assert abs(rho[1][-1] / rho[1][0] - 1) < 0.01, rho[1]
+
+
+def test_spherical_velocity_grid_integrates_a_maxwellian():
+    """The unstructured spherical velocity set (Gauss-Legendre in |xi| with weight r^2, Gauss-Legendre in
+    cos(theta), uniform azimuths) integrates the Maxwellian at rest: mass 1, zero momentum, temperature 1, to
+    near round-off; its weights sum to the ball's volume 4 pi R^3 / 3."""
+    from workloads import spherical_grid
+
+    g = spherical_grid(16, 12, 16, 8.0)
+    assert g.nv == 16 * 12 * 16
+    assert abs(g.w.sum() / (4 * np.pi * 8.0 ** 3 / 3) - 1) < 1e-12
+    c2 = (g.xi ** 2).sum(axis=1)
+    f = maxwell(c2, 3)
+    m0 = (g.w * f).sum()
+    assert abs(m0 - 1) < 1e-9
+    assert np.abs((g.w[:, None] * g.xi * f[:, None]).sum(axis=0)).max() < 1e-14
+    assert abs((g.w * c2 * f).sum() / (3 * m0) - 1) < 1e-8

@@ -16,6 +16,7 @@ from .quadrature import (  # noqa: F401
     ordinates_hemisphere,
     ordinates_sphere,
     uniform_box_grid,
+    spherical_grid,
 )
 from .cases import (  # noqa: F401
     Gas,

@@ -117,6 +117,27 @@ def uniform_box_grid(n: int, ranges) -> VelocityGrid:
     return VelocityGrid(dimv, np.ascontiguousarray(xi), np.ascontiguousarray(ww), f"U{n}^{dimv}")
 
 
+def spherical_grid(n_r: int, n_theta: int, n_phi: int, radius: float, center=(0.0, 0.0, 0.0)) -> VelocityGrid:
+    """Unstructured 3D velocity set in a ball of the given radius (the paper's capsule uses an unstructured
+    spherical velocity grid, Sec. 7.4): Gauss-Legendre nodes in |xi - center| on [0, radius] (weight r^2 dr),
+    Gauss-Legendre in cos(theta), uniform azimuths; n_r n_theta n_phi points, not a tensor product in
+    Cartesian components.  Exact for polynomials of degree < 2 n_r - 2 in r times degree < 2 n_theta in
+    cos(theta) and < n_phi in the azimuth, so a Maxwellian well inside the ball is integrated to near
+    round-off."""
+    xr, wr = np.polynomial.legendre.leggauss(n_r)
+    r = 0.5 * radius * (xr + 1)
+    wr = 0.5 * radius * wr * r * r
+    mu, wmu = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2 * np.pi * (np.arange(n_phi) + 0.5) / n_phi
+    R, MU, PH = np.meshgrid(r, mu, phi, indexing="ij")
+    W = wr[:, None, None] * wmu[None, :, None] * np.full(n_phi, 2 * np.pi / n_phi)[None, None, :]
+    st = np.sqrt(1 - MU * MU)
+    xi = np.stack([R * MU, R * st * np.cos(PH), R * st * np.sin(PH)], axis=-1).reshape(-1, 3)
+    xi = xi + np.asarray(center, dtype=np.float64)[None, :]
+    return VelocityGrid(3, np.ascontiguousarray(xi), np.ascontiguousarray(W.reshape(-1)),
+                        f"S{n_r}x{n_theta}x{n_phi}_r{radius}")
+
+
 def ordinates_slab(n: int) -> Ordinates:
     """Plane-parallel set: Gauss-Legendre in mu = cos(theta), azimuth integrated (weight 2 pi w)."""
     mu, w = np.polynomial.legendre.leggauss(n)

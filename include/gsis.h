@@ -136,14 +136,16 @@ typedef struct {
     int64_t inner_total;  /* macro inner iterations summed over the solve */
 } gsis_report;
 
-/* Handle lifetime.  device: HIP device ordinal.  The destroy call releases all device memory. */
+/* Handle lifetime (infrastructure; no passage of the paper).  device: HIP device ordinal.  The destroy call
+ * releases all device memory.  gsis_default_opts fills the defaults listed with gsis_opts (Sec. 6 and 7
+ * settings: CFL numbers, 100 inner iterations, 10 conventional iterations before GSIS, tolerance 1e-6). */
 int32_t gsis_create(int32_t device, gsis_t **out);
 void gsis_destroy(gsis_t *h);
 const char *gsis_last_error(gsis_t *h);
 void gsis_default_opts(gsis_opts *o);
 
-/* Use a caller-provided HIP stream (hipStream_t passed as void*), e.g. a torch stream handle.
- * NULL selects the null stream.  The handle does not take ownership. */
+/* Use a caller-provided HIP stream (hipStream_t passed as void*), e.g. a torch stream handle
+ * (infrastructure).  NULL selects the null stream.  The handle does not take ownership. */
 int32_t gsis_set_stream(gsis_t *h, void *hip_stream);
 
 /* Mesh (Sec. 6 finite-volume forms).  dim in {1,2,3}; vol[nc]; ctr[nc*dim] cell centroids;
@@ -160,13 +162,19 @@ int32_t gsis_set_mesh(gsis_t *h, int32_t dim, int64_t nc, int64_t nf, const doub
  * stay the same (GSIS_E_ARG otherwise); the distributions are kept. */
 int32_t gsis_set_boundary(gsis_t *h, int32_t tag, const gsis_bc *bc);
 
-/* Discrete velocities xi[nv*dim] with quadrature weights w[nv] (int g dxi ~ sum w_k g(xi_k)). */
+/* Discrete velocities xi[nv*dim] with quadrature weights w[nv] (int g dxi ~ sum w_k g(xi_k)): the discrete
+ * velocity method of Sec. 6 (moments Eq. getmoment as weighted sums); any node set (tensor, spherical,
+ * unstructured, Sec. 7.4).  GSIS_E_ARG for nv < 1 or null arrays. */
 int32_t gsis_set_velocity_grid(gsis_t *h, int64_t nv, const double *xi, const double *w);
 
-/* Discrete ordinates omega[no*3] (unit vectors) with weights w[no] summing to 4 pi; only the first
- * dim components enter the transport. */
+/* Discrete ordinates omega[no*3] (unit vectors) with weights w[no] summing to 4 pi (the angular
+ * discretisation of the radiative transfer equation, Sec. 6); only the first dim components enter the
+ * transport. */
 int32_t gsis_set_ordinates(gsis_t *h, int64_t no, const double *omega, const double *w);
 
+/* Gas constants and flow parameters of the kinetic model (Sec. 2.1, Eq. kinetic_equation and the relaxation
+ * matrix A); GSIS_E_ARG for non-positive degrees of freedom or collision numbers, or a negative sigma_R,
+ * Tv_ref, Kn or k_eff. */
 int32_t gsis_set_gas(gsis_t *h, const gsis_gas *gas);
 int32_t gsis_set_flow(gsis_t *h, const gsis_flow *flow);
 
@@ -179,7 +187,8 @@ int32_t gsis_set_flow(gsis_t *h, const gsis_flow *flow);
  * limiter constant, relaxation factor or CFL number. */
 int32_t gsis_set_opts(gsis_t *h, const gsis_opts *opts);
 
-/* Equilibrium initial state from fields: rho[nc], u[nc*dim], T[nc] (all modes and T_R equal T). */
+/* Equilibrium initial state from fields (the equilibrium of Sec. 3's synchronisation): rho[nc], u[nc*dim],
+ * T[nc] (all modes and T_R equal T). */
 int32_t gsis_init_equilibrium(gsis_t *h, const double *rho, const double *u, const double *T);
 
 /* Multi-temperature equilibrium initial state (the f^eq of the synchronisation step, Sec. 3):
@@ -188,7 +197,8 @@ int32_t gsis_init_equilibrium(gsis_t *h, const double *rho, const double *u, con
 int32_t gsis_init_fields(gsis_t *h, const double *rho, const double *u, const double *Tt, const double *Tr,
                          const double *Tv, const double *TR);
 
-/* Full state in and out (double host arrays; f [nc][ND][nv], I [nc][no]). */
+/* Full state in and out (double host arrays; f [nc][ND][nv], I [nc][no]): the reduced distributions of
+ * Eq. reduced_distribution and the intensity I_R of Sec. 2.1, converted to and from the storage precision. */
 int32_t gsis_set_state(gsis_t *h, const double *f, const double *I);
 int32_t gsis_get_state(gsis_t *h, double *f, double *I);
 
@@ -219,21 +229,25 @@ int32_t gsis_kinetic_step(gsis_t *h);
 int32_t gsis_macro_solve(gsis_t *h, double *W, int32_t *inner);
 int32_t gsis_sync(gsis_t *h, const double *W);
 
-/* Macroscopic fields of the current state, [nc][nfields] with nfields = 1 + D + 5 + 4 D + D(D+1)/2
+/* Macroscopic fields of the current state (the moments of Eq. getmoment; T the total temperature of
+ * Sec. 2.1; T_R from e_R = 4 sigma_R T_R^4), [nc][nfields] with nfields = 1 + D + 5 + 4 D + D(D+1)/2
  * in the order rho, u (D), T_t, T_r, T_v, T_R, T, q_t (D), q_r (D), q_v (D), q_R (D),
  * sigma (upper triangle, row by row). */
 int32_t gsis_nfields(gsis_t *h);
 int32_t gsis_get_fields(gsis_t *h, double *out);
 
-/* Residual history of the last gsis_solve: up to cap values into buf, count in *n. */
+/* Residual history of the last gsis_solve (epsilon of Sec. 7 per outer iteration): up to cap values into
+ * buf, count in *n. */
 int32_t gsis_get_residual_history(gsis_t *h, double *buf, int64_t cap, int64_t *n);
 
-/* Surface quantities of the current state on boundary faces, in face order (all nf faces; entries of
+/* Surface quantities (the capsule's surface heat flux of Sec. 7.4) of the current state on boundary
+ * faces, in face order (all nf faces; entries of
  * interior faces are 0): q_conv = gas energy flux into the boundary, q_rad = net radiative flux
  * through it, p_w = normal momentum flux. */
 int32_t gsis_get_surface_flux(gsis_t *h, double *q_conv, double *q_rad, double *p_w);
 
-/* Per-kernel timing with HIP events recorded on the handle's stream around each launch (off by default).
+/* Per-kernel timing with HIP events recorded on the handle's stream around each launch (measurement
+ * infrastructure, no passage of the paper; off by default).
  * gsis_set_profiling(h, 1) clears and enables the counters for every kind; gsis_set_profiling(h,
  * GSIS_PROF_SELECT | (1 << kind) | ...) for the listed kinds only (fewer events in the timed stream);
  * 0 disables.  gsis_get_kernel_stats returns, for one kernel kind, the summed device time in ms, the
@@ -254,7 +268,7 @@ int32_t gsis_set_profiling(gsis_t *h, int32_t on);
 int32_t gsis_get_kernel_stats(gsis_t *h, int32_t kind, double *ms_total, int64_t *launches, double *bytes_total);
 
 /* Counted work of the last gsis_solve / gsis_iterate calls (cell-velocity updates and algorithmic
- * HBM bytes of the kinetic steps), for throughput reporting. */
+ * HBM bytes of the kinetic steps), for throughput reporting (measurement infrastructure). */
 int32_t gsis_get_counters(gsis_t *h, double *cellvel_updates, double *kinetic_bytes, double *kinetic_seconds);
 
 #ifdef __cplusplus

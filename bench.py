@@ -69,7 +69,8 @@ def parse():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-outer", type=int, default=600)
-    ap.add_argument("--workload", default="capsule", choices=["capsule", "cavity", "capsule-shard", "cylinder", "shock"],
+    ap.add_argument("--workload", default="capsule",
+                    choices=["capsule", "cavity", "capsule-shard", "cylinder", "shock", "c5-gen", "c5-eval"],
                     help="capsule: GSIS iterations of the 3D Ma 10 capsule at full size (default); cavity: GSIS "
                          "iterations of the 2D radiative cavity; capsule-shard: kinetic steps "
                          "of the 3D capsule on one eighth of its velocity space (one GPU's share); cylinder: the "
@@ -80,6 +81,11 @@ def parse():
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--ws-cases", type=int, default=24, help="training cases of the warm-start network")
     ap.add_argument("--no-fp64", action="store_true", help="capsule: skip the FP64 leg")
+    ap.add_argument("--c5-cases", type=int, default=256, help="c5: cases of the warm-start data set")
+    ap.add_argument("--c5-train", type=int, default=224, help="c5: the first this many cases train, the rest test")
+    ap.add_argument("--c5-shard", default="0/1", help="c5-gen: k/n solves cases k, k + n, ...")
+    ap.add_argument("--c5-dir", default="gpurun_out/c5", help="c5: directory of the per-case solutions")
+    ap.add_argument("--c5-seconds", type=float, default=1000.0, help="c5-gen: stop starting cases after this")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibration of the HBM byte counters)")
     a = ap.parse_args()
@@ -542,6 +548,96 @@ def warmstart_leg(a, case, stream, plain_fields):
             "network": "4-layer MLP 7-256-256-256-7, tanh, BF16 weights, FP32 accumulation, Adam"}
 
 
+def bench_c5_gen(a):
+    """Warm-start data set of hypersonic cylinders (Mach 3-10, Kn 1e-3-1, optical thickness 1e-2-1e2, 20,160
+    triangles, 64^2 velocities, 64 ordinates): this shard's cases solved from the free stream by Mach
+    continuation (first-order fallback), each written to a.c5_dir as case_NNN.npz with its targets (log
+    rho, u, log T_t, log T_r, log T_v, log T_R; float16), the continuation's iteration count and time."""
+    import numpy as np
+    import torch
+
+    from paper_2601_03935_amd import warmstart as WS
+    from workloads import case_c5_cylinder, mesh_annulus, warmstart_c5_params
+
+    k, n = (int(x) for x in a.c5_shard.split("/"))
+    os.makedirs(a.c5_dir, exist_ok=True)
+    P = warmstart_c5_params(a.c5_cases, seed=2)
+    mesh = mesh_annulus(n_theta=180, n_r=56, seed=1)
+    st = torch.cuda.current_stream().cuda_stream
+    t_start = time.perf_counter()
+    done = []
+    for i in range(k, a.c5_cases, n):
+        if time.perf_counter() - t_start > a.c5_seconds:
+            break
+        Ma, Kn, tau = P[i]
+        c = case_c5_cylinder(Ma, Kn, tau, mesh=mesh)
+        Y, rec = WS.cylinder_case_solution(c, stream=st, precision=a.precision, tol=a.tol)
+        np.savez_compressed(os.path.join(a.c5_dir, f"case_{i:03d}.npz"), index=i, Ma=Ma, Kn=Kn, tau=tau,
+                            ok=bool(rec["ok"]), order=int(rec.get("order", 0)),
+                            iterations=int(rec.get("iterations", -1)), seconds=float(rec.get("seconds", -1.0)),
+                            targets=(Y if Y is not None else np.zeros((0, 7))).astype(np.float16))
+        done.append(dict(i=i, **{q: (float(v) if isinstance(v, (float, np.floating)) else v) for q, v in rec.items()}))
+        print(json.dumps(done[-1]), file=sys.stderr, flush=True)
+    return {"workload": "c5-gen", "shard": a.c5_shard, "cases": len(done),
+            "converged": int(sum(d["ok"] for d in done)), "seconds": time.perf_counter() - t_start}
+
+
+def bench_c5_eval(a):
+    """Train the warm-start network on the solved training cases of the data set (cases below a.c5_train)
+    and start each solved test case from its prediction (10 conventional and 20 first-order iterations, then
+    GSIS to the tolerance): iterations and wall time against the continuation from the free stream."""
+    import glob
+
+    import numpy as np
+    import torch
+
+    from paper_2601_03935_amd import warmstart as WS
+    from paper_2601_03935_amd.gsis import GsisError, Solver
+    from workloads import case_c5_cylinder, mesh_annulus
+
+    mesh = mesh_annulus(n_theta=180, n_r=56, seed=1)
+    st = torch.cuda.current_stream().cuda_stream
+    recs = [dict(np.load(f)) for f in sorted(glob.glob(os.path.join(a.c5_dir, "case_*.npz")))]
+    train = [r for r in recs if int(r["index"]) < a.c5_train and bool(r["ok"])]
+    test = [r for r in recs if int(r["index"]) >= a.c5_train and bool(r["ok"])]
+    X = np.concatenate([WS.cylinder_features(case_c5_cylinder(float(r["Ma"]), float(r["Kn"]), float(r["tau"]),
+                                                              mesh=mesh)) for r in train])
+    Y = np.concatenate([r["targets"].astype(np.float64) for r in train])
+    ws = WS.WarmStart(width=256, bf16=True, seed=0, stream=st, family="cylinder")
+    t0 = time.perf_counter()
+    loss = ws.fit(X, Y, epochs=40, batch=8192, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    rows = []
+    for r in test:
+        c = case_c5_cylinder(float(r["Ma"]), float(r["Kn"]), float(r["tau"]), mesh=mesh)
+        s = Solver(c, device=0, stream=st, precision=a.precision, n_precond=10, first_order_iters=20, tol=a.tol,
+                   max_outer=1500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            ws.init_solver(s, c)
+            rc, rep, _ = s.solve()
+            it, ok = int(rep.iters), bool(rc == 0)
+        except GsisError:
+            it, ok = -1, False
+        torch.cuda.synchronize()
+        rows.append(dict(index=int(r["index"]), Ma=float(r["Ma"]), Kn=float(r["Kn"]), tau=float(r["tau"]),
+                         warm_iterations=it, warm_seconds=time.perf_counter() - t0, warm_converged=ok,
+                         continuation_iterations=int(r["iterations"]), continuation_seconds=float(r["seconds"])))
+        s.close()
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    good = [x for x in rows if x["warm_converged"]]
+    out = {"workload": "c5-eval", "cases_solved": len(recs), "train_cases": len(train), "test_cases": len(test),
+           "train_rows": int(X.shape[0]), "train_s": t_train, "train_loss": loss,
+           "warm_converged": len(good), "per_case": rows}
+    if good:
+        out["median_iterations_warm"] = float(np.median([x["warm_iterations"] for x in good]))
+        out["median_iterations_continuation"] = float(np.median([x["continuation_iterations"] for x in good]))
+        out["total_seconds_warm"] = float(sum(x["warm_seconds"] for x in good))
+        out["total_seconds_continuation"] = float(sum(x["continuation_seconds"] for x in good))
+    return out
+
+
 def cavity_time_to_tol(a, case=None, stream=None):
     """Wall time to the residual tolerance on the 2D cavity from the uniform start (10 conventional iterations
     first): the configured precision, plain FP64 GSIS, and the configured precision started from the
@@ -635,6 +731,12 @@ def main():
         if not a.no_cpu_baseline:
             out["cpu_baseline"] = capsule_cpu_baseline(a)
         print(json.dumps(out), flush=True)
+        return
+    if a.workload == "c5-gen":
+        print(json.dumps(bench_c5_gen(a)), flush=True)
+        return
+    if a.workload == "c5-eval":
+        print(json.dumps(bench_c5_eval(a)), flush=True)
         return
     if a.workload == "capsule-shard":
         print(json.dumps(bench_capsule_shard(a)), flush=True)

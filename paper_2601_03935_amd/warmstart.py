@@ -348,8 +348,29 @@ def continuation_fields(case, tag, mach_steps, device=0, stream=None, stage_tol=
 
 
 def mach_steps(Ma):
-    """Intermediate free-stream Mach numbers of the continuation towards Ma (2, 3, 4 below Ma)."""
-    return [x for x in (2.0, 3.0, 4.0) if x < Ma - 0.25]
+    """Intermediate free-stream Mach numbers of the continuation towards Ma (the integers from 2 below Ma)."""
+    return [x for x in (2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0, 9.0) if x < Ma - 0.25]
+
+
+def cylinder_case_solution(c, device=0, stream=None, tol=1e-6, first_order_fallback=True, **opts):
+    """One cylinder case solved from the free stream by Mach continuation, with the first-order fallback of
+    cylinder_training_set.  Returns (targets or None, record with ok, order, iterations, seconds)."""
+    rec = dict(Ma=c.meta["Ma"], Kn=c.flow.Kn_gas, tau=c.flow.k_eff)
+    tries = [(2, opts, None)]
+    if first_order_fallback:
+        tries.append((1, dict(opts, second_order=0), dict(first_order_iters=0, first_order_jump=0)))
+    for order, o, cont in tries:
+        try:
+            F, Yc, it, dt, ok = continuation_fields(c, 1, mach_steps(c.meta["Ma"]), device=device, stream=stream,
+                                                    tol=tol, cont=cont, **o)
+        except GsisError as ex:
+            rec.update(ok=False, order=order, error=str(ex))
+            continue
+        rec.update(ok=bool(ok and Yc is not None and np.isfinite(Yc).all()), order=order, iterations=it, seconds=dt)
+        rec.pop("error", None)
+        if rec["ok"]:
+            return Yc, rec
+    return None, rec
 
 
 def cylinder_training_set(cases, device=0, stream=None, tol=1e-6, first_order_fallback=True, **opts):

@@ -33,4 +33,6 @@ from .cases import (  # noqa: F401
     warmstart_case_params,
     warmstart_cavity_params,
     warmstart_cylinder_params,
+    warmstart_c5_params,
+    case_c5_cylinder,
 )

@@ -200,6 +200,27 @@ def warmstart_cavity_params(n: int = 32, seed: int = 2):
     return np.stack([Kn, tau, ulid], axis=1)
 
 
+def warmstart_c5_params(n: int = 256, seed: int = 2, log10_Kn=(-2.0, 0.0), log10_tau=(-1.0, 1.0)):
+    """Seeded (Mach, Kn, optical thickness) draws of the warm-start data set of hypersonic cylinders: Mach
+    uniform in [3, 10], Kn and optical thickness log-uniform in the given decades (default Kn in [1e-2, 1],
+    optical thickness in [0.1, 10]; the wider [1e-3, 1] x [1e-2, 1e2] puts most draws where the Mach
+    continuation from the free stream does not reach a steady state on this mesh)."""
+    rng = np.random.default_rng(seed)
+    Ma = rng.uniform(3.0, 10.0, n)
+    Kn = 10 ** rng.uniform(log10_Kn[0], log10_Kn[1], n)
+    tau = 10 ** rng.uniform(log10_tau[0], log10_tau[1], n)
+    return np.stack([Ma, Kn, tau], axis=1)
+
+
+def case_c5_cylinder(Ma: float, Kn: float, tau: float, mesh: Mesh | None = None) -> Case:
+    """One cylinder of the warm-start data set: the annulus at 180 x 56 points (20,160 triangles), 64 x 64
+    Newton-Cotes velocities up to |xi| = 18 (the Mach 10 free stream at u = 11.5 with room for its thermal
+    spread), 64 ordinates, sigma_R = 0.1."""
+    mesh = mesh if mesh is not None else mesh_annulus(n_theta=180, n_r=56, seed=1)
+    return case_cylinder(mesh=mesh, Ma=Ma, Kn=Kn, tau_opt=tau, nvx=64, xmax=18.0, n_theta=4, n_phi=16,
+                         sigma_R=0.1)
+
+
 def warmstart_cylinder_params(n: int = 16, seed: int = 3):
     """Seeded (Mach, Kn, optical thickness) draws for warm-start training sets on the cylinder family:
     Mach uniform in [3, 5], Kn log-uniform in [0.01, 0.1], optical thickness log-uniform in [0.3, 3]."""

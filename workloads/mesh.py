@@ -70,8 +70,42 @@ def _morton_order(ctr: np.ndarray) -> np.ndarray:
     return np.argsort(code, kind="stable")
 
 
-def _renumber(dim, vol, ctr, face_cells, face_n, face_area, face_ctr, name):
-    perm = _morton_order(ctr)
+def _hilbert_order(ctr: np.ndarray, bits: int = 16) -> np.ndarray:
+    """Permutation that sorts points along a Hilbert curve (Skilling's transpose form of the Hilbert index,
+    `bits` bits per axis): unlike the Z-order curve, consecutive points of the curve are always adjacent."""
+    dim = ctr.shape[1]
+    lo = ctr.min(axis=0)
+    span = np.maximum(ctr.max(axis=0) - lo, 1e-300)
+    X = [np.floor((ctr[:, a] - lo[a]) / span[a] * ((1 << bits) - 1)).astype(np.uint64) for a in range(dim)]
+    M = np.uint64(1 << (bits - 1))
+    Q = M
+    while Q > 1:  # inverse undo of the excess work
+        P = Q - np.uint64(1)
+        for i in range(dim):
+            hit = (X[i] & Q) != 0
+            X[0] = np.where(hit, X[0] ^ P, X[0])
+            t = np.where(hit, np.uint64(0), (X[0] ^ X[i]) & P)
+            X[0] ^= t
+            X[i] ^= t
+        Q >>= np.uint64(1)
+    for i in range(1, dim):  # Gray encode
+        X[i] ^= X[i - 1]
+    t = np.zeros_like(X[0])
+    Q = M
+    while Q > 1:
+        t = np.where((X[dim - 1] & Q) != 0, t ^ (Q - np.uint64(1)), t)
+        Q >>= np.uint64(1)
+    for i in range(dim):
+        X[i] ^= t
+    key = np.zeros(ctr.shape[0], dtype=np.uint64)
+    for b in range(bits - 1, -1, -1):
+        for i in range(dim):
+            key = (key << np.uint64(1)) | ((X[i] >> np.uint64(b)) & np.uint64(1))
+    return np.argsort(key, kind="stable")
+
+
+def _renumber(dim, vol, ctr, face_cells, face_n, face_area, face_ctr, name, order="morton"):
+    perm = _hilbert_order(ctr) if order == "hilbert" else _morton_order(ctr)
     inv = np.empty_like(perm)
     inv[perm] = np.arange(perm.size)
     fc = face_cells.copy()
@@ -300,7 +334,7 @@ def mesh_periodic_1d(n: int, length: float = 1.0) -> Mesh:
 
 
 def mesh_capsule(n_s: int = 40, n_phi: int = 24, n_r: int = 24, r_nose: float = 1.0, cone_deg: float = 33.0,
-                 r_out: float = 4.0, seed: int = 3) -> Mesh:
+                 r_out: float = 4.0, seed: int = 3, cell_order: str = "morton") -> Mesh:
     """Blunt capsule: spherical-cap forebody and conical afterbody, tetrahedral mesh.
 
     A body-fitted structured grid (surface coordinate s along the profile,
@@ -412,4 +446,4 @@ def mesh_capsule(n_s: int = 40, n_phi: int = 24, n_r: int = 24, r_nose: float = 
     wall = on_body[tri[rows[:, 0]]].all(axis=1)
     R[bnd] = -(1 + np.where(wall[bnd], 0, 1))
     fc = np.stack([L, R], axis=1)
-    return _renumber(3, vol, ctr, fc, n, area, fctr, f"capsule_{nc}")
+    return _renumber(3, vol, ctr, fc, n, area, fctr, f"capsule_{nc}", order=cell_order)

@@ -603,6 +603,10 @@ def bench_c5_eval(a):
     X = np.concatenate([WS.cylinder_features(case_c5_cylinder(float(r["Ma"]), float(r["Kn"]), float(r["tau"]),
                                                               mesh=mesh)) for r in train])
     Y = np.concatenate([r["targets"].astype(np.float64) for r in train])
+    rows_all = int(X.shape[0])
+    if rows_all > 2_000_000:  # one training call takes at most ~2.1M rows: a seeded subset of the cells
+        keep = np.sort(np.random.default_rng(0).choice(rows_all, 2_000_000, replace=False))
+        X, Y = X[keep], Y[keep]
     ws = WS.WarmStart(width=256, bf16=True, seed=0, stream=st, family="cylinder")
     t0 = time.perf_counter()
     loss = ws.fit(X, Y, epochs=40, batch=8192, lr=2e-3)
@@ -610,26 +614,37 @@ def bench_c5_eval(a):
     rows = []
     for r in test:
         c = case_c5_cylinder(float(r["Ma"]), float(r["Kn"]), float(r["tau"]), mesh=mesh)
-        s = Solver(c, device=0, stream=st, precision=a.precision, n_precond=10, first_order_iters=20, tol=a.tol,
-                   max_outer=1500)
-        torch.cuda.synchronize()
+        # second order after 20 first-order iterations; where that fails, first order throughout (the order the
+        # data set falls back to for cases whose second-order shock does not settle on this mesh)
         t0 = time.perf_counter()
-        try:
-            ws.init_solver(s, c)
-            rc, rep, _ = s.solve()
-            it, ok = int(rep.iters), bool(rc == 0)
-        except GsisError:
-            it, ok = -1, False
-        torch.cuda.synchronize()
+        it, ok, order = -1, False, 0
+        for so in (1, 0):
+            s = Solver(c, device=0, stream=st, precision=a.precision, n_precond=10, first_order_iters=20,
+                       second_order=so, tol=a.tol, max_outer=1500)
+            try:
+                ws.init_solver(s, c)
+                rc, rep, _ = s.solve()
+                it, ok, order = int(rep.iters), bool(rc == 0), 2 if so else 1
+            except GsisError:
+                it, ok = -1, False
+            torch.cuda.synchronize()
+            s.close()
+            if ok:
+                break
         rows.append(dict(index=int(r["index"]), Ma=float(r["Ma"]), Kn=float(r["Kn"]), tau=float(r["tau"]),
                          warm_iterations=it, warm_seconds=time.perf_counter() - t0, warm_converged=ok,
+                         warm_order=order, continuation_order=int(r["order"]),
                          continuation_iterations=int(r["iterations"]), continuation_seconds=float(r["seconds"])))
-        s.close()
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     good = [x for x in rows if x["warm_converged"]]
     out = {"workload": "c5-eval", "cases_solved": len(recs), "train_cases": len(train), "test_cases": len(test),
-           "train_rows": int(X.shape[0]), "train_s": t_train, "train_loss": loss,
+           "train_rows": int(X.shape[0]), "train_rows_available": rows_all, "train_s": t_train, "train_loss": loss,
            "warm_converged": len(good), "per_case": rows}
+    # freestream start (the continuation) as the fallback where the warm start does not converge
+    out["total_seconds_warm_with_fallback"] = float(sum(x["warm_seconds"] +
+                                                        (0.0 if x["warm_converged"] else x["continuation_seconds"])
+                                                        for x in rows))
+    out["total_seconds_continuation_all"] = float(sum(x["continuation_seconds"] for x in rows))
     if good:
         out["median_iterations_warm"] = float(np.median([x["warm_iterations"] for x in good]))
         out["median_iterations_continuation"] = float(np.median([x["continuation_iterations"] for x in good]))

@@ -213,6 +213,30 @@ __device__ __forceinline__ void store_vw(T *p, const T *v)
         *(vec_t<T, VW> *)p = x;
     }
 }
+// the same for data read or written once by the kernel (streamed past the caches)
+template <typename T, int VW>
+__device__ __forceinline__ void load_vw_nt(const T *p, T *v)
+{
+    if constexpr (VW == 1) {
+        v[0] = __builtin_nontemporal_load(p);
+    } else {
+        const vec_t<T, VW> x = __builtin_nontemporal_load((const vec_t<T, VW> *)p);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[e] = x[e];
+    }
+}
+template <typename T, int VW>
+__device__ __forceinline__ void store_vw_nt(T *p, const T *v)
+{
+    if constexpr (VW == 1) {
+        __builtin_nontemporal_store(v[0], p);
+    } else {
+        vec_t<T, VW> x;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) x[e] = v[e];
+        __builtin_nontemporal_store(x, (vec_t<T, VW> *)p);
+    }
+}
 
 template <typename T, int D, int NFM, int VW>
 __global__ __launch_bounds__(256) void k_grad_v(const T *__restrict__ f, T *__restrict__ gf, const MeshDev m,
@@ -953,7 +977,8 @@ __global__ __launch_bounds__(256) void k_sweep_v(const T *__restrict__ r, const 
         }
     V rv[ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) rv[d] = *(const V *)(r + ((int64_t)c * ND + d) * nv + k);
+    // r and f are read once per sweep: streamed past the caches, which keep the neighbours' increment rows
+    for (int d = 0; d < ND; ++d) rv[d] = __builtin_nontemporal_load((const V *)(r + ((int64_t)c * ND + d) * nv + k));
     V acc[ND], dsum = T(0);
 #pragma unroll
     for (int d = 0; d < ND; ++d) acc[d] = T(0);
@@ -985,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_sweep_v(const T *__restrict__ r, const 
         const int64_t o = ((int64_t)c * ND + d) * nv + k;
         const V dn = (rv[d] - acc[d]) * ((d == 2) ? inv2 : inv0);
         if (fout) {
-            const V fo = *(const V *)(f + o) + omega * dn;
+            const V fo = __builtin_nontemporal_load((const V *)(f + o)) + omega * dn;
             __builtin_nontemporal_store(fo, (V *)(fout + o));
         } else {
             __builtin_nontemporal_store(dn, (V *)(dlout + o));
@@ -1629,10 +1654,10 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
 #pragma unroll 4
     for (int64_t kb = (int64_t)lane * VW; kb < nv; kb += kMomLanes * VW) {
       T fG[VW], fR[VW], fV[VW], fH[VW];
-      load_vw<T, VW>(f + (c * ND + 0) * nv + kb, fG);
-      load_vw<T, VW>(f + (c * ND + 1) * nv + kb, fR);
-      load_vw<T, VW>(f + (c * ND + 2) * nv + kb, fV);
-      if (ND == 4) load_vw<T, VW>(f + (c * ND + (ND == 4 ? 3 : 0)) * nv + kb, fH);
+      load_vw_nt<T, VW>(f + (c * ND + 0) * nv + kb, fG);
+      load_vw_nt<T, VW>(f + (c * ND + 1) * nv + kb, fR);
+      load_vw_nt<T, VW>(f + (c * ND + 2) * nv + kb, fV);
+      if (ND == 4) load_vw_nt<T, VW>(f + (c * ND + (ND == 4 ? 3 : 0)) * nv + kb, fH);
 #pragma unroll
       for (int e = 0; e < VW; ++e) {
         const int64_t k = kb + e;
@@ -2102,7 +2127,7 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
       T fv[4][VW];
       if (!init) {
 #pragma unroll
-        for (int d = 0; d < ND; ++d) load_vw<T, VW>(f + ((int64_t)c * ND + d) * nv + kb, fv[d]);
+        for (int d = 0; d < ND; ++d) load_vw_nt<T, VW>(f + ((int64_t)c * ND + d) * nv + kb, fv[d]);
       }
 #pragma unroll
       for (int e = 0; e < VW; ++e) {
@@ -2123,7 +2148,7 @@ __global__ __launch_bounds__(256) void k_sync(T *__restrict__ f, T *__restrict__
         for (int d = 0; d < ND; ++d) fv[d][e] = init ? (T)dG[d] : (T)((double)fv[d][e] + dG[d]);
       }
 #pragma unroll
-      for (int d = 0; d < ND; ++d) store_vw<T, VW>(f + ((int64_t)c * ND + d) * nv + kb, fv[d]);
+      for (int d = 0; d < ND; ++d) store_vw_nt<T, VW>(f + ((int64_t)c * ND + d) * nv + kb, fv[d]);
     }
     if (ch != 0) return;
     const double dI = init ? s1[D + 4] / (4 * kPi) : (s1[D + 4] - s0[D + 4]) / (4 * kPi);

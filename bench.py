@@ -212,6 +212,20 @@ def bench_capsule(a):
     return out
 
 
+
+def unit_roofline(unit_bytes, units, stat, traffic, ndist, es):
+    """HBM roofline of the sweep kernel by the per-cell-velocity accounting: every reduced distribution read and
+    written once per kinetic step (unit_bytes per cell-velocity) x the cell-velocities one launch covers, over
+    the mean launch time.  The kernel's own byte rate (its operand arrays, each once) is reported beside it."""
+    tms, n, by = stat
+    mean_s = tms / n * 1e-3
+    achieved = unit_bytes * units / mean_s / 1e9
+    return {"bound": "hbm", "kernel": "sweep", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": unit_bytes * units,
+            "accounting": f"{unit_bytes} B per cell-velocity (f read and written once, {ndist} distributions, "
+                          f"{'FP32' if es == 4 else 'FP64'}) x cells x velocities per launch / mean launch time",
+            "kernel_operand_gbs": by / n / mean_s / 1e9}
+
 def bench_capsule_fp64(a):
     """FP64 distributions on the full capsule (same mesh, velocities, physics and start): with one symmetric
     Gauss-Seidel sweep in place and the gradients recomputed inside the residual the state fits in 152 GB
@@ -330,8 +344,7 @@ def bench_capsule_shard(a):
         if n:
             kernels[k] = dict(ms_per_step=tms / a.steps, launches_per_step=n / a.steps,
                               gbs=(by / (tms * 1e-3) / 1e9) if by > 0 and tms > 0 else None)
-    tms, n, by = stats["sweep"]
-    achieved = by / n / (tms / n * 1e-3) / 1e9
+    es = 4 if a.precision == "fp32" else 8
     return {
         "metric": "DVM cell-velocity updates/s of the kinetic step (3D capsule, one velocity-space shard)",
         "value": nc * nv * a.steps / (ms * 1e-3), "unit": "cell-velocity updates/s", "n_gpus": 1,
@@ -341,8 +354,7 @@ def bench_capsule_shard(a):
         "config": {"workload": "3D blunt capsule (spherical cap + 33 deg cone), kinetic step on 1/8 of velocity space",
                    "cells": nc, "velocities": nv, "velocities_full_grid": 24 ** 3, "distributions_per_velocity": 3,
                    "ordinates": no, "Kn_gas": 0.01, "Mach": 10.0, "optical_thickness": 1.0},
-        "roofline": {"bound": "hbm", "kernel": "sweep", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": by / n},
+        "roofline": unit_roofline(2 * 3 * es, nc * nv, stats["sweep"], None, 3, es),
         "kernels": kernels,
     }
 
@@ -385,8 +397,7 @@ def bench_cylinder(a):
         if n:
             kernels[k] = dict(ms_per_step=tms / 5, launches_per_step=n / 5,
                               gbs=(by / (tms * 1e-3) / 1e9) if by > 0 and tms > 0 else None)
-    tms, n, by = stats["sweep"]
-    achieved = by / n / (tms / n * 1e-3) / 1e9
+    es = 4 if a.precision == "fp32" else 8
     iters = int(sum(its))
     ws = None if a.no_warmstart else cylinder_warmstart_leg(a, case, stream, plain_fields)
     return {
@@ -399,8 +410,7 @@ def bench_cylinder(a):
                    "optical_thickness": 1.0, "sigma_R": 0.1, "tol": a.tol, "mach_steps": [2, 3, 4, 5]},
         "converged": ok, "iterations_per_stage": its, "eps_final": float(hist[-1]),
         "cell_velocity_updates_per_s": nc * nv * iters / sec,
-        "roofline": {"bound": "hbm", "kernel": "sweep", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": by / n},
+        "roofline": unit_roofline(2 * 4 * es, nc * nv, stats["sweep"], None, 4, es),
         "kernels": kernels,
         "warmstart": ws,
     }
@@ -813,9 +823,7 @@ def main():
             continue
         kernels[k] = dict(ms_per_step=tms / nprof, launches_per_step=n / nprof,
                           gbs=(by / (tms * 1e-3) / 1e9) if by > 0 and tms > 0 else None)
-    dom = "sweep"
-    tms, n, by = stats_timed[dom]
-    achieved = by / n / (tms / n * 1e-3) / 1e9
+    es = 4 if a.precision == "fp32" else 8
     kin_ms = sum(stats[k][0] for k in ("grad", "residual", "sweep", "rad", "boundary")) / nprof
     kin_bytes_ideal = nc * (2 * 4 * nv + 2 * no) * (4 if a.precision == "fp32" else 8)
     out = {
@@ -838,10 +846,8 @@ def main():
             "kinetic_sweeps": s.opts.kin_sweeps, "max_inner": s.opts.max_inner,
             "storage": a.precision + " distributions, fp64 moments and macro solve",
         },
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("sweep", "cavity20k") if a.precision == "fp32" else None,
-                     "algorithmic_bytes_per_launch": by / n},
+        "roofline": unit_roofline(2 * 4 * es, nc * nv, stats_timed["sweep"],
+                                  measured_traffic("sweep", "cavity20k") if a.precision == "fp32" else None, 4, es),
         "kinetic_step": {"ms": kin_ms, "ideal_bytes": kin_bytes_ideal,
                          "ideal_gbs": kin_bytes_ideal / (kin_ms * 1e-3) / 1e9},
         "kernels": kernels,

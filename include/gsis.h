@@ -202,6 +202,13 @@ int32_t gsis_init_fields(gsis_t *h, const double *rho, const double *u, const do
 int32_t gsis_set_state(gsis_t *h, const double *f, const double *I);
 int32_t gsis_get_state(gsis_t *h, double *f, double *I);
 
+/* The state rows of selected cells (double host arrays): f [n][ND][nv] and I [n][no] receive the reduced
+ * distributions and intensities of cells[0 .. n) (cell indices of the mesh, in any order, repeats allowed),
+ * the cell-averaged unknowns f_i of the discrete system of Sec. 6; either output may be null.  For checks and
+ * probes of single cells of a state too large to copy whole.  GSIS_E_ARG for n < 0, null cells with n > 0,
+ * or an index outside [0, nc); GSIS_E_STATE without an initialised state. */
+int32_t gsis_get_state_cells(gsis_t *h, const int64_t *cells, int64_t n, double *f, double *I);
+
 /* Checkpoint of the iteration state: f, I (in the storage precision, so a restore continues bit for bit)
  * and the residual history of the last gsis_solve, written to `path` (a binary file of the documented
  * layout, overwritten).  gsis_restore reads it into a handle set up with the same mesh, grids and

@@ -915,6 +915,26 @@ static int32_t get_state_T(gsis_t *h, KinBufs<T> &B, double *f, double *I)
     return GSIS_OK;
 }
 
+template <typename T>
+static int32_t get_state_cells_T(gsis_t *h, KinBufs<T> &B, const int64_t *cells, int64_t n, double *f, double *I)
+{
+    const size_t row = (size_t)ndist(h->hm.D) * h->nv, no = (size_t)h->no;
+    std::vector<T> tf(f ? row : 0), ti(I ? no : 0);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    for (int64_t k = 0; k < n; ++k) {
+        const size_t c = (size_t)cells[k];
+        if (f) {
+            HIPCHECK(h, hipMemcpy(tf.data(), B.f + c * row, row * sizeof(T), hipMemcpyDeviceToHost));
+            std::copy(tf.begin(), tf.end(), f + (size_t)k * row);
+        }
+        if (I && no) {
+            HIPCHECK(h, hipMemcpy(ti.data(), B.I + c * no, no * sizeof(T), hipMemcpyDeviceToHost));
+            std::copy(ti.begin(), ti.end(), I + (size_t)k * no);
+        }
+    }
+    return GSIS_OK;
+}
+
 // ------------------------------------------------------------------ checkpoint / restore
 // File layout (native byte order): 8-byte tag "GSISCKP1"; int32 D, ND, precision, reserved; int64 nc, nv,
 // no, history length; f [nc][ND][nv] and I [nc][no] in the storage type of the precision; the residual
@@ -1338,6 +1358,19 @@ int32_t gsis_get_state(gsis_t *h, double *f, double *I)
     if (!h->have_state || !h->have_init) return fail(h, GSIS_E_STATE, "gsis_get_state: no initialised state");
     (void)hipSetDevice(h->device);
     return (h->prec == GSIS_FP32) ? get_state_T(h, h->Bf, f, I) : get_state_T(h, h->Bd, f, I);
+}
+
+int32_t gsis_get_state_cells(gsis_t *h, const int64_t *cells, int64_t n, double *f, double *I)
+{
+    if (!h) return GSIS_E_ARG;
+    if (n < 0 || (n > 0 && !cells)) return fail(h, GSIS_E_ARG, "gsis_get_state_cells: bad cell list");
+    for (int64_t k = 0; k < n; ++k)
+        if (cells[k] < 0 || cells[k] >= h->hm.nc)
+            return fail(h, GSIS_E_ARG, "gsis_get_state_cells: cell index out of range");
+    if (!h->have_state || !h->have_init) return fail(h, GSIS_E_STATE, "gsis_get_state_cells: no initialised state");
+    (void)hipSetDevice(h->device);
+    return (h->prec == GSIS_FP32) ? get_state_cells_T(h, h->Bf, cells, n, f, I)
+                                  : get_state_cells_T(h, h->Bd, cells, n, f, I);
 }
 
 static int32_t check_ready(gsis_t *h, const char *who)

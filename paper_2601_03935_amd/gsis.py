@@ -27,7 +27,7 @@ GSIS_SWEEP_JACOBI, GSIS_SWEEP_SGS = 0, 1
 EXPORTS = [
     "gsis_create", "gsis_destroy", "gsis_last_error", "gsis_default_opts", "gsis_set_stream", "gsis_set_mesh",
     "gsis_set_velocity_grid", "gsis_set_boundary", "gsis_set_ordinates", "gsis_set_gas", "gsis_set_flow", "gsis_set_opts",
-    "gsis_init_equilibrium", "gsis_init_fields", "gsis_set_state", "gsis_get_state", "gsis_iterate", "gsis_solve",
+    "gsis_init_equilibrium", "gsis_init_fields", "gsis_set_state", "gsis_get_state", "gsis_get_state_cells", "gsis_iterate", "gsis_solve",
     "gsis_kinetic_step", "gsis_macro_solve", "gsis_sync", "gsis_nfields", "gsis_get_fields",
     "gsis_get_residual_history", "gsis_get_surface_flux", "gsis_get_counters", "gsis_set_profiling",
     "gsis_get_kernel_stats", "gsis_checkpoint", "gsis_restore",
@@ -96,6 +96,7 @@ def lib():
         "gsis_init_equilibrium": ([P, P, P, P], I32),
         "gsis_set_state": ([P, P, P], I32),
         "gsis_get_state": ([P, P, P], I32),
+        "gsis_get_state_cells": ([P, P, C.c_int64, P, P], I32),
         "gsis_iterate": ([P, I32, I32, C.POINTER(D), C.POINTER(I32)], I32),
         "gsis_solve": ([P, C.POINTER(gsis_report)], I32),
         "gsis_kinetic_step": ([P], I32),
@@ -277,6 +278,14 @@ class Solver:
         f = np.empty((self.nc, self.ND, self.nv))
         I = np.empty((self.nc, self.no))
         self._check(self.L.gsis_get_state(self.h, _p(f), _p(I)), "gsis_get_state")
+        return f, I
+
+    def get_state_cells(self, cells):
+        """State rows (f [n, ND, nv], I [n, no]) of the listed cells."""
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        f = np.empty((len(cells), self.ND, self.nv))
+        I = np.empty((len(cells), self.no))
+        self._check(self.L.gsis_get_state_cells(self.h, _p(cells), len(cells), _p(f), _p(I)), "gsis_get_state_cells")
         return f, I
 
     def checkpoint(self, path):

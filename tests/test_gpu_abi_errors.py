@@ -199,3 +199,23 @@ def test_diverging_iteration_stops_with_diverged():
     assert rc == GSIS_E_DIVERGED, (rc, rep.iters, rep.eps_final)
     assert rep.iters < 40 and "non-positive density or temperature" in msg, (rep.iters, msg)
     s.close()
+
+
+def test_get_state_cells():
+    """gsis_get_state_cells returns the listed rows of the full state, and rejects bad lists."""
+    case = case_cavity(mesh=mesh_cavity(h=0.1), nvx=8, n_theta=2, n_phi=4, Kn=0.1)
+    s = Solver(case, precision="fp64")
+    try:
+        n = case.mesh.nc
+        s.iterate(gsis=False, n=2)
+        f, I = s.get_state()
+        cells = np.array([n - 1, 0, 5, 5])
+        fc, Ic = s.get_state_cells(cells)
+        assert np.array_equal(fc, f[cells]) and np.array_equal(Ic, I[cells])
+        fe, Ie = s.get_state_cells(np.zeros(0, dtype=np.int64))
+        assert fe.shape[0] == 0 and Ie.shape[0] == 0
+        for bad in ([n], [-1], [0, n + 7]):
+            with pytest.raises(GsisError):
+                s.get_state_cells(bad)
+    finally:
+        s.close()

@@ -1017,3 +1017,37 @@ def test_spherical_velocity_grid_integrates_a_maxwellian():
     assert abs(m0 - 1) < 1e-9
     assert np.abs((g.w[:, None] * g.xi * f[:, None]).sum(axis=0)).max() < 1e-14
     assert abs((g.w * c2 * f).sum() / (3 * m0) - 1) < 1e-8
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_kinetic_step_depends_on_ten_neighbour_rings(dim):
+    """Locality of one kinetic step with eight Jacobi sweeps (Sec. 6): the limited reconstruction reaches two
+    face-neighbour steps and each sweep one more, so on the cells within ten steps of a cell (case_patch, the
+    cut faces made far-field boundaries) its f^(k+1/2) and I equal the full mesh's bit for bit, and nine steps
+    are not enough.  The full-size sampled GPU parity test relies on this."""
+    from workloads import case_capsule, case_patch
+
+    if dim == 2:
+        c = case_cavity(mesh=mesh_cavity(h=0.025), nvx=8, Kn=0.1)
+        o = Oracle(c)
+    else:
+        c = case_capsule(Kn=0.1, Ma=2.0, nvx=6, xmax=8.0, n_theta=2, n_phi=4, mesh_kw=dict(n_s=14, n_phi=12, n_r=14))
+        o = Oracle(c, limiter_K=1.0)
+    for _ in range(2):
+        o.iterate(gsis=False)
+    f, I = o.get_state()
+    seeds = np.array([3, c.mesh.nc // 2, c.mesh.nc - 7])
+    o.kinetic_step()
+    f1, I1 = o.get_state()
+    errs = {}
+    for rings in (9, 10):
+        pc, cells, sl = case_patch(c, seeds, rings)
+        assert (cells[sl] == seeds).all()
+        pc.mesh.check()
+        op = Oracle(pc, **o.opts)
+        op.set_state(f[cells], I[cells])
+        op.kinetic_step()
+        fp, Ip = op.get_state()
+        errs[rings] = (np.abs(fp[sl] - f1[seeds]).max(), np.abs(Ip[sl] - I1[seeds]).max())
+    assert errs[10] == (0.0, 0.0)
+    assert max(errs[9]) > 0

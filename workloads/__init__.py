@@ -6,7 +6,7 @@ of the kinetic or macroscopic arithmetic of the method; both the product
 path and the oracle receive what it builds as plain arrays.
 """
 
-from .mesh import Mesh, mesh_1d, mesh_cavity, mesh_cavity_mirror, mesh_annulus, mesh_periodic_1d, mesh_capsule  # noqa: F401
+from .mesh import Mesh, mesh_1d, mesh_cavity, mesh_cavity_mirror, mesh_annulus, mesh_periodic_1d, mesh_capsule, mesh_patch  # noqa: F401
 from .quadrature import (  # noqa: F401
     VelocityGrid,
     Ordinates,
@@ -35,4 +35,5 @@ from .cases import (  # noqa: F401
     warmstart_cylinder_params,
     warmstart_c5_params,
     case_c5_cylinder,
+    case_patch,
 )

@@ -229,3 +229,19 @@ def warmstart_cylinder_params(n: int = 16, seed: int = 3):
     Kn = 10 ** rng.uniform(np.log10(0.01), np.log10(0.1), n)
     tau = 10 ** rng.uniform(np.log10(0.3), np.log10(3.0), n)
     return np.stack([Ma, Kn, tau], axis=1)
+
+
+def case_patch(case: Case, seeds, rings: int):
+    """The case restricted to the cells within `rings` face-neighbour steps of the seed cells (mesh_patch):
+    same grids, gas, flow and boundary tags, plus one far-field condition at the free-stream state on the
+    faces that cut the patch from the rest of the mesh.  Returns (patch case, kept cell indices, the seeds'
+    patch indices).  A stage whose result at a cell depends only on cells within r steps agrees on the two
+    meshes at every seed when rings >= r (the cut faces only reach cells within r steps of them)."""
+    from .mesh import mesh_patch
+
+    pm, cells, seeds_local = mesh_patch(case.mesh, seeds, rings)
+    fl = case.flow
+    bcs = list(case.bcs) + [dict(kind=BC_FARFIELD, rho=fl.rho_inf, T=fl.T_inf, u=tuple(fl.u_inf))]
+    out = Case(f"{case.name}_patch{pm.nc}", pm, case.vgrid, case.ords, case.gas, case.flow, bcs,
+               case.init_rho[cells].copy(), case.init_u[cells].copy(), case.init_T[cells].copy(), dict(case.meta))
+    return out, cells, seeds_local

@@ -447,3 +447,55 @@ def mesh_capsule(n_s: int = 40, n_phi: int = 24, n_r: int = 24, r_nose: float = 
     R[bnd] = -(1 + np.where(wall[bnd], 0, 1))
     fc = np.stack([L, R], axis=1)
     return _renumber(3, vol, ctr, fc, n, area, fctr, f"capsule_{nc}", order=cell_order)
+
+
+def mesh_patch(mesh: Mesh, seeds, rings: int):
+    """The cells within `rings` face-neighbour steps of the seed cells, as a mesh of its own.
+
+    Returns (patch, cells, seeds_local): `cells` are the kept cell indices of `mesh` in increasing order
+    (patch cell k is mesh cell cells[k]), `seeds_local` the seeds' patch indices.  Faces between two kept
+    cells stay interior; boundary faces of kept cells keep their tags; a face between a kept and a dropped
+    cell becomes a boundary face of the kept cell, oriented outward from it, with the new tag
+    (largest tag of `mesh`) + 1, so every patch cell is closed."""
+    fc = mesh.face_cells
+    L, R = fc[:, 0], fc[:, 1]
+    inner = R >= 0
+    nbr = [[] for _ in range(mesh.nc)]
+    for a, b in zip(L[inner], R[inner]):
+        nbr[a].append(b)
+        nbr[b].append(a)
+    keep = np.zeros(mesh.nc, dtype=bool)
+    seeds = np.asarray(seeds, dtype=np.int64)
+    keep[seeds] = True
+    front = list(np.unique(seeds))
+    for _ in range(rings):
+        nxt = []
+        for c in front:
+            for j in nbr[c]:
+                if not keep[j]:
+                    keep[j] = True
+                    nxt.append(j)
+        front = nxt
+    cells = np.nonzero(keep)[0]
+    local = np.full(mesh.nc, -1, dtype=np.int64)
+    local[cells] = np.arange(len(cells))
+    new_tag = int((-R[~inner] - 1).max()) + 1 if (~inner).any() else 0
+    kl = keep[L]
+    kr = np.where(inner, keep[np.maximum(R, 0)], False)
+    sel = kl | kr
+    fL, fR = L[sel], R[sel]
+    n, area, fctr = mesh.face_n[sel].copy(), mesh.face_area[sel], mesh.face_ctr[sel]
+    kl_s, kr_s, inner_s = kl[sel], kr[sel], inner[sel]
+    out = np.empty((sel.sum(), 2), dtype=np.int64)
+    both = kl_s & kr_s
+    out[both, 0], out[both, 1] = local[fL[both]], local[fR[both]]
+    bnd = kl_s & ~inner_s
+    out[bnd, 0], out[bnd, 1] = local[fL[bnd]], fR[bnd]
+    cutL = kl_s & inner_s & ~kr_s
+    out[cutL, 0], out[cutL, 1] = local[fL[cutL]], -(new_tag + 1)
+    cutR = kr_s & ~kl_s
+    out[cutR, 0], out[cutR, 1] = local[fR[cutR]], -(new_tag + 1)
+    n[cutR] = -n[cutR]
+    patch = Mesh(mesh.dim, mesh.vol[cells].copy(), mesh.ctr[cells].copy(), out, n, area.copy(), fctr.copy(),
+                 name=f"{mesh.name}_patch{len(cells)}")
+    return patch, cells, local[seeds]

@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--c5-cases", type=int, default=256, help="c5: cases of the warm-start data set")
     ap.add_argument("--c5-train", type=int, default=224, help="c5: the first this many cases train, the rest test")
     ap.add_argument("--c5-shard", default="0/1", help="c5-gen: k/n solves cases k, k + n, ...")
-    ap.add_argument("--c5-dir", default="gpurun_out/c5", help="c5: directory of the per-case solutions")
+    ap.add_argument("--c5-dir", default="c5_cases", help="c5: directory of the per-case solutions")
     ap.add_argument("--c5-seconds", type=float, default=1000.0, help="c5-gen: stop starting cases after this")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibration of the HBM byte counters)")

@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="bound of the oracle baseline run")
+    ap.add_argument("--no-oracle-timings", action="store_true",
+                    help="capsule: skip the oracle timings of the 1D, cavity and cylinder configurations")
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-outer", type=int, default=600)
@@ -325,6 +327,42 @@ def capsule_cpu_baseline(a):
             "cpu_model": cpu_info(),
             "sample": f"{k} FP64 GSIS iterations (after 2 untimed conventional ones) of the capsule on {n} "
                       f"tetrahedra x {case.vgrid.nv} velocities ({dt:.1f} s)"}
+
+
+def oracle_timings(a):
+    """The FP64 oracle on the host cores for the other configurations (context beside the capsule baseline):
+    the 1D Fourier flow to epsilon < 1e-6 (10 conventional iterations, then GSIS), one kinetic step and one
+    GSIS iteration of the full-size cavity (Kn 0.1, optical thickness 1) from its start, and one kinetic step
+    of the full-size Ma 5 cylinder from the free stream."""
+    import time as _t
+
+    from oracle import Oracle
+    from workloads import case_cavity, case_cylinder, case_fourier_1d
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    out = {"kind": "oracle", "cores": cores, "cpu_model": cpu_info()}
+    c = case_fourier_1d()
+    o = Oracle(c)
+    t0 = _t.perf_counter()
+    n, hist = o.solve(gsis=True, n_precond=10, tol=1e-6, max_outer=1000)
+    dt = _t.perf_counter() - t0
+    out["fourier_1d"] = {"cells": c.mesh.nc, "velocities": c.vgrid.nv, "iterations_to_1e-6": int(n),
+                         "seconds_to_1e-6": dt}
+    del o
+    for name, c in (("cavity", case_cavity()), ("cylinder", case_cylinder())):
+        o = Oracle(c)
+        t0 = _t.perf_counter()
+        o.kinetic_step()
+        tk = _t.perf_counter() - t0
+        rec = {"cells": c.mesh.nc, "velocities": c.vgrid.nv, "kinetic_step_s": tk,
+               "cell_velocity_updates_per_s": c.mesh.nc * c.vgrid.nv / tk}
+        if name == "cavity":
+            t0 = _t.perf_counter()
+            o.iterate(gsis=True)
+            rec["gsis_iteration_s"] = _t.perf_counter() - t0
+        out[name] = rec
+        del o
+    return out
 
 
 def bench_capsule_shard(a):
@@ -777,6 +815,8 @@ def main():
             out["time_to_tol_cavity"] = cavity_time_to_tol(a)
         if not a.no_cpu_baseline:
             out["cpu_baseline"] = capsule_cpu_baseline(a)
+            if not a.no_oracle_timings:
+                out["oracle_timings"] = oracle_timings(a)
         print(json.dumps(out), flush=True)
         return
     if a.workload == "c5-gen":

@@ -77,14 +77,17 @@ def parse():
     ap.add_argument("--max-inner", type=int, default=100,
                     help="capsule: inner iterations of each synthetic solve (tolerance 1e-7 or this many)")
     ap.add_argument("--workload", default="capsule",
-                    choices=["capsule", "cavity", "capsule-shard", "cylinder", "shock", "c5-gen", "c5-eval"],
+                    choices=["capsule", "cavity", "capsule-shard", "capsule-ma5", "cylinder", "shock", "c5-gen",
+                             "c5-eval"],
                     help="capsule: GSIS iterations of the 3D Ma 10 capsule at full size (default); cavity: GSIS "
                          "iterations of the 2D radiative cavity; capsule-shard: kinetic steps "
-                         "of the 3D capsule on one eighth of its velocity space (one GPU's share); cylinder: the "
+                         "of the 3D capsule on one eighth of its velocity space (one GPU's share); capsule-ma5: "
+                         "the full-size capsule mesh converged at Mach 5 by Mach continuation (use --tol 1e-5); "
+                         "cylinder: the "
                          "Ma 5 cylinder solved from the free stream to the tolerance; shock: iterations to 2e-6 of "
                          "the Ma 5 normal shock, GSIS and conventional")
     ap.add_argument("--cyl-Kn", type=float, default=0.01, help="Kn of the cylinder workload")
-    ap.add_argument("--max-stage", type=int, default=400, help="iteration limit per Mach stage (cylinder)")
+    ap.add_argument("--max-stage", type=int, default=400, help="iteration limit per Mach stage (cylinder, capsule-ma5)")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--ws-cases", type=int, default=24, help="training cases of the warm-start network")
     ap.add_argument("--no-fp64", action="store_true", help="capsule: skip the FP64 leg")
@@ -110,6 +113,14 @@ def capsule_case(nvx=24, mesh_kw=None):
 
     return case_capsule(Kn=0.01, tau_opt=1.0, Ma=10.0, nvx=nvx, n_theta=8, n_phi=12, sigma_R=0.045,
                         mesh_kw=mesh_kw or dict(n_s=46, n_phi=28, n_r=28), vgrid="box")
+
+
+def capsule_case_ma(Ma, nvx=24):
+    """The capsule workload at another far-field Mach number (box velocity grid sized for it)."""
+    from workloads import case_capsule
+
+    return case_capsule(Kn=0.01, tau_opt=1.0, Ma=Ma, nvx=nvx, n_theta=8, n_phi=12, sigma_R=0.045,
+                        mesh_kw=dict(n_s=46, n_phi=28, n_r=28), vgrid="box")
 
 
 # Limiter constant of the capsule runs: the limiter acts through (K h)^1.5 and the tetrahedra of the capsule
@@ -245,6 +256,53 @@ def unit_roofline(unit_bytes, units, stat, traffic, ndist, es):
             "accounting": f"{unit_bytes} B per cell-velocity (f read and written once, {ndist} distributions, "
                           f"{'FP32' if es == 4 else 'FP64'}) x cells x velocities per launch / mean launch time",
             "kernel_operand_gbs": by / n / mean_s / 1e9}
+
+def bench_capsule_converge(a):
+    """The full-size capsule mesh and 24^3 box velocities (box sized for Mach 5) converged on one GPU, FP32:
+    from a Mach 2 uniform start, Mach continuation 2 -> 3 -> 4 -> 5 of the far field (40 conventional and 60
+    first-order iterations in the first stage, 20 first-order after each jump; stages to epsilon < 1e-4,
+    the last to --tol), limiter K = 1.  Wall time, iterations per stage and the per-iteration cost."""
+    import numpy as np
+    import torch
+
+    from paper_2601_03935_amd.gsis import Solver
+
+    case = capsule_case_ma(5.0)
+    nc, nv = case.mesh.nc, case.vgrid.nv
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    s = Solver(case, device=0, stream=stream.cuda_stream, precision=a.precision, limiter_K=CAPSULE_K,
+               max_inner=a.max_inner)
+    g = np.sqrt(case.gas.gamma)
+    u0 = np.zeros((nc, 3))
+    u0[:, 0] = 2.0 * g
+    s.init_equilibrium(np.ones(nc), u0, np.ones(nc))
+    states = [(1.0, 1.0, (Ma * g, 0.0, 0.0)) for Ma in (2.0, 3.0, 4.0, 5.0)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, hist, ok = s.solve_continuation(1, states, stage_tol=1e-4, tol=a.tol, max_stage=a.max_stage,
+                                         first_order_jump=20)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    F = s.fields()
+    s.close()
+    iters = int(sum(its))
+    return {
+        "metric": "wall time to the residual tolerance from a Mach 2 start (3D Ma 5 capsule, Mach continuation)",
+        "value": sec, "unit": "s", "n_gpus": 1, "steps": iters, "warmup": 0, "ms_per_step": 1e3 * sec / iters,
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32" if a.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "3D Ma 5 blunt capsule (spherical cap radius 1 + 33 deg cone), full-size mesh",
+                   "cells": nc, "cell_type": "tetrahedra", "velocities": nv, "velocity_grid": "24^3 uniform box",
+                   "distributions_per_velocity": 3, "ordinates": case.ords.no, "Kn_gas": 0.01, "Mach": 5.0,
+                   "optical_thickness": 1.0, "sigma_R": 0.045, "tol": a.tol, "mach_steps": [2, 3, 4, 5],
+                   "limiter_K": CAPSULE_K, "kinetic_relaxation": "8 Jacobi sweeps", "max_inner": a.max_inner},
+        "converged": ok, "iterations_per_stage": its, "eps_final": float(hist[-1]),
+        "eps_tail": [float(x) for x in hist[-5:]],
+        "cell_velocity_updates_per_s": nc * nv * iters / sec,
+        "fields_finite": bool(np.isfinite(F).all()), "min_density": float(F[:, 0].min()),
+    }
+
 
 def bench_capsule_fp64(a):
     """FP64 distributions on the full capsule (same mesh, velocities, physics and start): with one symmetric
@@ -836,6 +894,9 @@ def main():
         return
     if a.workload == "cylinder":
         print(json.dumps(bench_cylinder(a)), flush=True)
+        return
+    if a.workload == "capsule-ma5":
+        print(json.dumps(bench_capsule_converge(a)), flush=True)
         return
     if a.workload == "shock":
         print(json.dumps(bench_shock(a)), flush=True)

@@ -1679,13 +1679,15 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
         v0 += V;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            m1[a] += cc[a] * G;
-            m3[a] += cc[a] * c2 * G;
+            const double cG = cc[a] * G;
+            m1[a] += cG;
+            m3[a] += cG * c2;
             h1[a] += cc[a] * H;
             r1[a] += cc[a] * R;
             v1[a] += cc[a] * V;
+            // the second moment is symmetric: its upper triangle, mirrored after the sums
 #pragma unroll
-            for (int bb = 0; bb < D; ++bb) m2[a][bb] += cc[a] * cc[bb] * G;
+            for (int bb = a; bb < D; ++bb) m2[a][bb] += cc[bb] * cG;
         }
       }
     }
@@ -1701,8 +1703,12 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
         r1[a] = group_sum<kMomLanes>(r1[a]);
         v1[a] = group_sum<kMomLanes>(v1[a]);
 #pragma unroll
-        for (int bb = 0; bb < D; ++bb) m2[a][bb] = group_sum<kMomLanes>(m2[a][bb]);
+        for (int bb = a; bb < D; ++bb) m2[a][bb] = group_sum<kMomLanes>(m2[a][bb]);
     }
+#pragma unroll
+    for (int a = 1; a < D; ++a)
+#pragma unroll
+        for (int bb = 0; bb < a; ++bb) m2[a][bb] = m2[bb][a];
     double eR = 0, qR[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) qR[a] = 0;

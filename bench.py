@@ -55,7 +55,7 @@ def measured_traffic(kind="sweep", workload="capsule"):
     return t["bytes_per_launch"] if t.get("kernel_source_sha256") == sha else None
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed GSIS iterations (capsule 10, cavity 20)")
@@ -98,7 +98,7 @@ def parse():
     ap.add_argument("--c5-seconds", type=float, default=1000.0, help="c5-gen: stop starting cases after this")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibration of the HBM byte counters)")
-    a = ap.parse_args()
+    a = ap.parse_args(argv)
     if a.steps is None:
         a.steps = 10 if a.workload == "capsule" else 20
     if a.warmup is None:
@@ -846,7 +846,7 @@ def fields_vs_fixture(F, case, a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {a.gpus}",
+        print(f"bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus {a.gpus}",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

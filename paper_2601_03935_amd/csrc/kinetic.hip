@@ -575,12 +575,26 @@ __global__ __launch_bounds__(256) void k_residual_v(const T *__restrict__ f, con
             for (int a = 0; a < D; ++a) xn += x[a] * nsv[s][a];
             if (nb[s] >= 0) {
                 const int64_t j = nb[s];
+                // the neighbour's reconstruction enters only where it is upwind (xi . n <= 0): a lane whose
+                // velocities all leave through this face does not load the neighbour's rows
+                bool up = false;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) up = up || !(xn[e] > T(0));
                 V fj[ND], gj[ND][D];
+                if (up) {
 #pragma unroll
-                for (int d = 0; d < ND; ++d) {
-                    fj[d] = *(const V *)(f + (j * ND + d) * nv + k);
+                    for (int d = 0; d < ND; ++d) {
+                        fj[d] = *(const V *)(f + (j * ND + d) * nv + k);
 #pragma unroll
-                    for (int a = 0; a < D; ++a) gj[d][a] = *(const V *)(gf + ((j * ND + d) * D + a) * nv + k);
+                        for (int a = 0; a < D; ++a) gj[d][a] = *(const V *)(gf + ((j * ND + d) * D + a) * nv + k);
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) {
+                        fj[d] = T(0);
+#pragma unroll
+                        for (int a = 0; a < D; ++a) gj[d][a] = T(0);
+                    }
                 }
 #pragma unroll
                 for (int e = 0; e < VW; ++e) {

@@ -709,9 +709,17 @@ __device__ __forceinline__ void part_load(const double *__restrict__ part, const
         const int b = lane + 64 * u;
         pr[u] = (b < nb) ? part[b] : 0.0;
     }
-    double v = 0;
-    for (int b = lane + 64 * kPartRegs; b < nb; b += 64) v += part[b];
-    *rest = v;
+    // beyond the first 64 kPartRegs partials (large grids), eight independent running sums so that eight
+    // loads are in flight per step instead of one
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b0 = lane + 64 * kPartRegs; b0 < nb; b0 += 64 * 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + 64 * u;
+            a[u] += (b < nb) ? part[b] : 0.0;
+        }
+    }
+    *rest = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 // Stopping test of inner iteration `it` from the loaded partial sums; block 0 records the norms and raises

@@ -177,6 +177,7 @@ static void free_mesh(MeshDev &m)
     dfree(m.bf_bidx);
     dfree(m.f_L);
     dfree(m.f_R);
+    dfree(m.fslot);
     dfree(m.fgeo);
     dfree(m.bcs);
     dfree(m.bf_bc);
@@ -371,8 +372,12 @@ static int32_t build_mesh(gsis_t *h)
     m.nbc = (int)hm.bcs.size();
     m.closed = closed;
     std::vector<int> sfid(nc * NFM, 0);
+    std::vector<int> fslot(2 * nf, -1);
     for (int64_t k = 0; k < nc * NFM; ++k)
-        if (fid[k] >= 0) sfid[k] = (sgn[k] > 0) ? fid[k] : -(1 + fid[k]);
+        if (fid[k] >= 0) {
+            sfid[k] = (sgn[k] > 0) ? fid[k] : -(1 + fid[k]);
+            if (nbr[k] >= 0) fslot[2 * (int64_t)fid[k] + (sgn[k] > 0 ? 0 : 1)] = (int)k;
+        }
     // per slot (c, s) with an interior neighbour j: the slots of j (neighbour lists two cells away)
     std::vector<int> nb2(nc * NFM * NFM, INT32_MIN);
     for (int64_t k = 0; k < nc * NFM; ++k)
@@ -409,7 +414,7 @@ static int32_t build_mesh(gsis_t *h)
               upload(m.h, hh) && upload(m.eps2, eps2) && upload(m.nfc, nfc) && upload(m.bf_face, bf_face) &&
               upload(m.bf_cell, bf_cell) && upload(m.bf_tag, bf_tag) && upload(m.bf_n, bf_n) &&
               upload(m.bf_dxc, bf_dxc) && upload(m.bcells, bcells) && upload(m.bf_bidx, bf_bidx) &&
-              upload(m.f_L, fL) && upload(m.f_R, fR) &&
+              upload(m.f_L, fL) && upload(m.f_R, fR) && upload(m.fslot, fslot) &&
               upload(m.fgeo, fgeo) && upload(m.bcs, bcs) && upload(m.bf_bc, bf_bc) && upload(m.color, color) &&
               upload(m.col_cells, col_cells);
     if (!ok) return fail(h, GSIS_E_OOM, "device allocation of mesh tables failed");
@@ -457,6 +462,7 @@ static void free_macro(MacroBufs &B)
     dfree(B.P2);
     dfree(B.fld2);
     dfree(B.Gs);
+    dfree(B.Ff);
     dfree(B.part);
     dfree(B.bpart);
     dfree(B.Ts);
@@ -575,6 +581,7 @@ static bool alloc_macro(gsis_t *h)
     B.P2 = dalloc<double>(nc * (D + 8), ok);
     B.fld2 = dalloc<double>(nc * (D + 4), ok);
     B.Gs = dalloc<double>(nc * h->m.NFM * 2, ok);
+    B.Ff = dalloc<double>(nf * NW, ok);
     B.part = dalloc<double>(macro_nparts(nc, h->m.NFM) + 1, ok);
     B.gfld = dalloc<double>(nc * (D + 4) * D, ok);
     B.R = dalloc<double>(nc * NW, ok);

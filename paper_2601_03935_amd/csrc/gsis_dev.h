@@ -142,6 +142,7 @@ struct MeshDev {
     int *bf_bidx = nullptr;                      // per boundary face: position of its cell in bcells
     // interior faces (for face HoTs / reference dissipation)
     int *f_L = nullptr, *f_R = nullptr;  // R < 0 on boundary faces
+    int *fslot = nullptr;  // per face: the slot (c NFM + s) of its left cell and of its right cell (-1 on boundary)
     // per face, 2D + 2 values: the unit normal n (L -> R), and on interior faces with d = x_R - x_L the unit
     // vector d / |d|, 1 / |d| and 1 / |n . d| (zeros on boundary faces)
     double *fgeo = nullptr;

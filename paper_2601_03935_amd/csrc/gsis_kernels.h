@@ -29,6 +29,7 @@ struct MacroBufs {
     double *fcon = nullptr;   // per face: frozen flux constants (dissipation + HoTs), HoT stress along n
     double *bcorr = nullptr;  // per boundary face: kinetic minus model flux at the start of the solve
     double *Gs = nullptr;                     // per cell slot (interior faces): spectral radii G, G_R
+    double *Ff = nullptr;                     // per face: its flux (face orientation), large-grid split path
     double *part = nullptr;                   // per-block partial sums of the residual norm
     double *resc = nullptr, *scal = nullptr;  // per-cell scratch, device scalars (res0, mass, ...)
     double *bpart = nullptr;                  // partial sums of launch_block_sum (8 * kSumBlocks)

@@ -745,6 +745,39 @@ __device__ __forceinline__ bool inner_converged(const double pr[kPartRegs], cons
     return done;
 }
 
+// Interior-face fluxes of the synthetic equations for grids that do not fit the GPU in one round of k_mres:
+// one lane per face evaluates face_flux once, in the face's own orientation (k_mres<SPLIT> then negates it
+// on the right cell, exactly as the fused kernel does, so both paths give identical residuals), and
+// stores the spectral radii into the slots of both cells.
+template <int D, int NFM>
+__global__ __launch_bounds__(256) void k_mface(const double *__restrict__ W, const double *__restrict__ P,
+                                               const double *__restrict__ fld, const double *__restrict__ fcon,
+                                               double *__restrict__ Ff, double *__restrict__ Gs,
+                                               const int *__restrict__ flags, const MeshDev m, const Phys p)
+{
+    constexpr int NW = D + 5;
+    if (flags[0]) return;
+    const int64_t f = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (f >= m.nf) return;
+    const int sl = m.fslot[2 * f], sr = m.fslot[2 * f + 1];
+    if (sl < 0 || sr < 0) return;
+    const int64_t cL = sl / NFM, cR = sr / NFM;
+    int nbL[NFM], nbR[NFM];
+#pragma unroll
+    for (int q = 0; q < NFM; ++q) {
+        nbL[q] = m.nbr[cL * NFM + q];
+        nbR[q] = m.nbr[cR * NFM + q];
+    }
+    double F[NW], G, GR;
+    face_flux<D, NFM>(W, P, fld, fcon, m, p, f, cL, cR, nbL, nbR, F, &G, &GR);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) Ff[f * NW + i] = F[i];
+    Gs[(int64_t)sl * 2] = G;
+    Gs[(int64_t)sl * 2 + 1] = GR;
+    Gs[(int64_t)sr * 2] = G;
+    Gs[(int64_t)sr * 2 + 1] = GR;
+}
+
 // Residual of every cell: R_i = -(1/V) sum_f F S + Q (face fluxes of the cell's slots gathered in slot
 // order, boundary model fluxes plus the frozen kinetic corrections), the diagonal D_i and the first
 // increment of the U unknowns; per-slot spectral radii for the sweeps; per-block sums of the
@@ -752,12 +785,13 @@ __device__ __forceinline__ bool inner_converged(const double pr[kPartRegs], cons
 // PRE: the cell's point-solve data is loaded up front with the slot tables (one dependent-load level
 // less; 22 more VGPRs, two waves per SIMD), else in the per-cell tail (three waves per SIMD, for grids
 // that would not fit the GPU in one round at two).
-template <int D, int NFM, bool PRE>
+template <int D, int NFM, bool PRE, bool SPLIT = false>
 __global__ __launch_bounds__(kSBlk) void k_mres(
     const double *__restrict__ W, const double *__restrict__ P, const double *__restrict__ fld,
     const double *__restrict__ fcon, const double *__restrict__ bcorr,
     double *__restrict__ Gs, double *__restrict__ R, double *__restrict__ Dg, double *__restrict__ dU,
-    double *__restrict__ part, const int *__restrict__ flags, const MeshDev m, const Phys p, const double cfl_macro)
+    double *__restrict__ part, const int *__restrict__ flags, const MeshDev m, const Phys p, const double cfl_macro,
+    const double *__restrict__ Ff = nullptr)
 {
     constexpr int NW = D + 5, NP = D + 8, MG = 2 * D + 2, LS = slot_lanes(NFM);
     __shared__ double sh[kSBlk / 64];
@@ -781,11 +815,13 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
     const int sf = slot ? sfr : 0;
     const double Sl = slot ? Slr : 0.0;
     int nbc[NFM], nbj[NFM];
+    if constexpr (!SPLIT) {
 #pragma unroll
-    for (int q = 0; q < NFM; ++q) {
-        const int a = m.nbr[cc * NFM + q], b = m.nb2[(cc * NFM + ss) * NFM + q];
-        nbc[q] = cell ? a : INT32_MIN;
-        nbj[q] = slot ? b : INT32_MIN;
+        for (int q = 0; q < NFM; ++q) {
+            const int a = m.nbr[cc * NFM + q], b = m.nb2[(cc * NFM + ss) * NFM + q];
+            nbc[q] = cell ? a : INT32_MIN;
+            nbj[q] = slot ? b : INT32_MIN;
+        }
     }
     double Wc[NW], Pc[D + 7], V = 1, hc = 1;
     if constexpr (PRE) {
@@ -829,14 +865,24 @@ __global__ __launch_bounds__(kSBlk) void k_mres(
             const bool left = sf >= 0;
             const int64_t fid = left ? sf : -(int64_t)sf - 1;
             double G, GR;
-            face_flux<D, NFM>(W, P, fld, fcon, m, p, fid, left ? c : j, left ? j : c, left ? nbc : nbj,
-                              left ? nbj : nbc, Fs, &G, &GR);
+            if constexpr (SPLIT) {
+                // the face's flux and spectral radii, evaluated once per face by k_mface
+#pragma unroll
+                for (int i = 0; i < NW; ++i) Fs[i] = Ff[fid * NW + i];
+                G = Gs[(c * NFM + s) * 2];
+                GR = Gs[(c * NFM + s) * 2 + 1];
+            } else {
+                face_flux<D, NFM>(W, P, fld, fcon, m, p, fid, left ? c : j, left ? j : c, left ? nbc : nbj,
+                                  left ? nbj : nbc, Fs, &G, &GR);
+            }
             if (!left) {
 #pragma unroll
                 for (int i = 0; i < NW; ++i) Fs[i] = -Fs[i];
             }
-            st_nt(Gs + (c * NFM + s) * 2, G);
-            st_nt(Gs + (c * NFM + s) * 2 + 1, GR);
+            if constexpr (!SPLIT) {
+                st_nt(Gs + (c * NFM + s) * 2, G);
+                st_nt(Gs + (c * NFM + s) * 2 + 1, GR);
+            }
             gS = G * S;
             gRS = GR * S;
         }
@@ -1206,12 +1252,17 @@ void macro_solve(MacroBufs &B, const MeshDev &m, const Phys &p, const MacroOpts 
     for (int it = 0; it < o.max_inner; ++it) {
         const int cur = pingpong ? (it & 1) : 0, nxt = cur ^ 1;
         double *W = Wb[cur], *P = Pb[cur], *fld = Fb[cur];
-        if (one_round)
+        if (one_round) {
             hipLaunchKernelGGL((k_mres<D, NFM, true>), gsl, bsl, 0, st, W, P, fld, B.fcon, B.bcorr, B.Gs, B.R,
-                               B.Dg, B.dU0, B.part, B.flags, m, p, o.cfl_macro);
-        else
-            hipLaunchKernelGGL((k_mres<D, NFM, false>), gsl, bsl, 0, st, W, P, fld, B.fcon, B.bcorr, B.Gs,
-                               B.R, B.Dg, B.dU0, B.part, B.flags, m, p, o.cfl_macro);
+                               B.Dg, B.dU0, B.part, B.flags, m, p, o.cfl_macro, nullptr);
+        } else {
+            // more than one round: each interior face once (half the flux evaluations, fewer registers per
+            // kernel), then the per-cell sums and point solves
+            hipLaunchKernelGGL((k_mface<D, NFM>), dim3((unsigned)((m.nf + 255) / 256)), dim3(256), 0, st, W, P, fld,
+                               B.fcon, B.Ff, B.Gs, B.flags, m, p);
+            hipLaunchKernelGGL((k_mres<D, NFM, false, true>), gsl, bsl, 0, st, W, P, fld, B.fcon, B.bcorr, B.Gs,
+                               B.R, B.Dg, B.dU0, B.part, B.flags, m, p, o.cfl_macro, B.Ff);
+        }
         double *din = B.dU0, *dout = B.dU1;
         const int ns = o.n_sweeps;
         for (int s = 0; s < ns; ++s) {

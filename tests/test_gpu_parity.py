@@ -113,6 +113,27 @@ def test_macro_solve_and_sync_fp64(name, case):
     assert _relerr(Ig, Io) < 1e-11
 
 
+def test_macro_solve_split_path_fp64():
+    """A 3D grid too large for one round of the fused residual kernel of the synthetic solve (40,576
+    tetrahedra: 634 blocks, one per compute unit resident at 256 registers): the solve takes the split path
+    (one face kernel evaluating each interior face once, then the per-cell kernel) and matches the oracle
+    as the fused path does on the small grids (10 inner iterations, as for the other capsule stages)."""
+    case = case_capsule(Kn=0.1, Ma=2.0, nvx=8, xmax=8.0, n_theta=2, n_phi=4, mesh_kw=dict(n_s=24, n_phi=16, n_r=18))
+    assert case.mesh.nc == 40576
+    s, o = _pair(case, precision="fp64", max_inner=10)
+    _warm(o, s, n=2)
+    Wo, ito = o.macro_solve()
+    Wg, itg = s.macro_solve()
+    assert ito == itg
+    assert _relerr(Wg, Wo) < 1e-9
+    o.sync(Wo)
+    s.sync(Wo)
+    fo, _ = o.get_state()
+    fg, _ = s.get_state()
+    assert _relerr(fg, fo) < 1e-11
+    s.close()
+
+
 @pytest.mark.parametrize("inner_tol", [0.9, 0.7, 0.5, 0.3])
 def test_macro_solve_stops_early(inner_tol):
     """Loose inner tolerances, reached after 2, 7, 16 and 48 inner iterations on this mesh (oracle): the
